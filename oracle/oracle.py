@@ -1,0 +1,256 @@
+"""ctypes wrapper of the FP64 C oracle in ``hgs_oracle.c``.
+
+Test infrastructure only: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the GPU library.  Every array handed to
+the C code is widened from the stored FP32 values to FP64 here; the oracle then
+computes in FP64 throughout.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hgs_oracle.c")
+LIB = os.path.join(HERE, "_build", "liboracle.so")
+
+NPARAM = 59
+NSPLAT = 20
+MAX_ALT = 4
+ALPHA_MIN = 1.0 / 255.0
+T_MIN = 1e-4
+
+# parameter slots of the gradient array
+SLOTS = dict(mean=(0, 3), scale=(3, 6), rot=(6, 10), opacity=(10, 11), sh=(11, 59))
+
+
+def build() -> str:
+    os.makedirs(os.path.dirname(LIB), exist_ok=True)
+    tmp = LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                           "-shared", "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.POINTER
+        d, i32, i64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+        L.or_granularity_all.argtypes = [P(_OHier), P(_OView), P(d)]
+        L.or_cut.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64]
+        L.or_cut.restype = i64
+        L.or_project.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(d)]
+        L.or_render.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(i64), i64, P(d), P(d), P(i32),
+                                P(i32), P(d), P(d)]
+        L.or_render.restype = i64
+        L.or_signature.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64]
+        L.or_signature.restype = ctypes.c_uint64
+        L.or_backward.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(d), P(d), P(d), P(d)]
+        L.or_sh_basis.argtypes = [P(d), P(d)]
+        _lib = L
+    return _lib
+
+
+class _OHier(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64),
+                ("parent", ctypes.POINTER(ctypes.c_int32)),
+                ("child_begin", ctypes.POINTER(ctypes.c_int32)),
+                ("child_count", ctypes.POINTER(ctypes.c_int32)),
+                ("bmin", ctypes.POINTER(ctypes.c_double)),
+                ("bmax", ctypes.POINTER(ctypes.c_double)),
+                ("mean", ctypes.POINTER(ctypes.c_double)),
+                ("scale", ctypes.POINTER(ctypes.c_double)),
+                ("rot", ctypes.POINTER(ctypes.c_double)),
+                ("opacity", ctypes.POINTER(ctypes.c_double)),
+                ("sh", ctypes.POINTER(ctypes.c_double))]
+
+
+class _OView(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double * 9), ("eye", ctypes.c_double * 3),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("z_near", ctypes.c_double), ("tau", ctypes.c_double)]
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+class Hier:
+    """FP64 copy of a hierarchy (values widened from the FP32 storage)."""
+
+    FIELDS = ("mean", "scale", "rot", "opacity", "sh")
+
+    def __init__(self, h):
+        a = h.arrays() if hasattr(h, "arrays") else dict(h)
+        self.parent = np.ascontiguousarray(a["parent"], np.int32)
+        self.child_begin = np.ascontiguousarray(a["child_begin"], np.int32)
+        self.child_count = np.ascontiguousarray(a["child_count"], np.int32)
+        self.bmin = np.ascontiguousarray(a["bmin"], np.float64)
+        self.bmax = np.ascontiguousarray(a["bmax"], np.float64)
+        for f in self.FIELDS:
+            setattr(self, f, np.ascontiguousarray(a[f], np.float64))
+        self.n = self.parent.shape[0]
+
+    def struct(self):
+        s = _OHier()
+        s.n = self.n
+        s.parent = _p(self.parent, ctypes.c_int32)
+        s.child_begin = _p(self.child_begin, ctypes.c_int32)
+        s.child_count = _p(self.child_count, ctypes.c_int32)
+        s.bmin = _p(self.bmin, ctypes.c_double)
+        s.bmax = _p(self.bmax, ctypes.c_double)
+        for f in self.FIELDS:
+            setattr(s, f, _p(getattr(self, f), ctypes.c_double))
+        return s
+
+    def copy(self):
+        c = Hier.__new__(Hier)
+        for k in ("parent", "child_begin", "child_count", "bmin", "bmax") + self.FIELDS:
+            setattr(c, k, getattr(self, k).copy())
+        c.n = self.n
+        return c
+
+    def param_flat(self, slot: int) -> np.ndarray:
+        """View of gradient slot ``slot`` (0..58) in the parameter arrays."""
+        if slot < 3:
+            return self.mean[slot]
+        if slot < 6:
+            return self.scale[slot - 3]
+        if slot < 10:
+            return self.rot[slot - 6]
+        if slot == 10:
+            return self.opacity
+        return self.sh[slot - 11]
+
+
+def view_struct(v) -> _OView:
+    s = _OView()
+    R = np.asarray(v.R, np.float32).astype(np.float64).reshape(9)
+    for k in range(9):
+        s.R[k] = R[k]
+    e = np.asarray(v.eye, np.float32).astype(np.float64)
+    for k in range(3):
+        s.eye[k] = e[k]
+    f32 = lambda x: float(np.float32(x))  # noqa: E731  (the values the GPU sees)
+    s.fx, s.fy, s.cx, s.cy = f32(v.fx), f32(v.fy), f32(v.cx), f32(v.cy)
+    s.width, s.height = int(v.width), int(v.height)
+    s.z_near, s.tau = f32(v.z_near), f32(v.tau)
+    return s
+
+
+def _H(h):
+    return h if isinstance(h, Hier) else Hier(h)
+
+
+def granularity(h, v) -> np.ndarray:
+    H = _H(h)
+    out = np.empty(H.n, np.float64)
+    hs, vs = H.struct(), view_struct(v)
+    lib().or_granularity_all(ctypes.byref(hs), ctypes.byref(vs), _p(out, ctypes.c_double))
+    return out
+
+
+def cut(h, v):
+    """(ids int32 ascending, t float64) of the cut for view v."""
+    H = _H(h)
+    hs, vs = H.struct(), view_struct(v)
+    ids = np.empty(max(H.n, 1), np.int32)
+    t = np.empty(max(H.n, 1), np.float64)
+    c = lib().or_cut(ctypes.byref(hs), ctypes.byref(vs), _p(ids, ctypes.c_int32), _p(t, ctypes.c_double), H.n)
+    return ids[:c].copy(), t[:c].copy()
+
+
+SPLAT_COLS = ("valid", "u", "v", "depth", "ca", "cb", "cc", "kappa", "A_n", "A_p", "t", "K",
+              "r", "g", "b", "x0", "x1", "y0", "y1", "depth32")
+
+
+def project(h, v, ids, t) -> dict:
+    H = _H(h)
+    ids = np.ascontiguousarray(ids, np.int32)
+    t = np.ascontiguousarray(t, np.float64)
+    out = np.zeros((ids.shape[0], NSPLAT), np.float64)
+    hs, vs = H.struct(), view_struct(v)
+    lib().or_project(ctypes.byref(hs), ctypes.byref(vs), _p(ids, ctypes.c_int32), _p(t, ctypes.c_double),
+                     ids.shape[0], _p(out, ctypes.c_double))
+    return {k: out[:, i] for i, k in enumerate(SPLAT_COLS)}
+
+
+def render(h, v, ids=None, t=None, pix=None, alternatives=True) -> dict:
+    """Render view v (all pixels, or the linear pixel indices ``pix``)."""
+    H = _H(h)
+    if ids is None:
+        ids, t = cut(H, v)
+    ids = np.ascontiguousarray(ids, np.int32)
+    t = np.ascontiguousarray(t, np.float64)
+    if pix is None:
+        pix = np.arange(v.width * v.height, dtype=np.int64)
+    pix = np.ascontiguousarray(pix, np.int64)
+    m = pix.shape[0]
+    rgb = np.zeros((m, 3))
+    T = np.zeros(m)
+    nb = np.zeros(m, np.int32)
+    nalt = np.zeros(m, np.int32)
+    alt_rgb = np.zeros((m, MAX_ALT, 3))
+    alt_T = np.zeros((m, MAX_ALT))
+    hs, vs = H.struct(), view_struct(v)
+    P = ctypes.POINTER
+    total = lib().or_render(ctypes.byref(hs), ctypes.byref(vs), _p(ids, ctypes.c_int32), _p(t, ctypes.c_double),
+                            ids.shape[0], _p(pix, ctypes.c_int64), m, _p(rgb, ctypes.c_double),
+                            _p(T, ctypes.c_double), _p(nb, ctypes.c_int32),
+                            _p(nalt, ctypes.c_int32) if alternatives else P(ctypes.c_int32)(),
+                            _p(alt_rgb, ctypes.c_double) if alternatives else P(ctypes.c_double)(),
+                            _p(alt_T, ctypes.c_double) if alternatives else P(ctypes.c_double)())
+    return dict(rgb=rgb, T=T, nblend=nb, nalt=nalt, alt_rgb=alt_rgb, alt_T=alt_T, blended=int(total),
+                pix=pix, ids=ids, t=t)
+
+
+def render_image(h, v, ids=None, t=None):
+    r = render(h, v, ids, t, alternatives=False)
+    return r["rgb"].reshape(v.height, v.width, 3), r["T"].reshape(v.height, v.width)
+
+
+def signature(h, v, ids, t) -> int:
+    H = _H(h)
+    hs, vs = H.struct(), view_struct(v)
+    ids = np.ascontiguousarray(ids, np.int32)
+    t = np.ascontiguousarray(t, np.float64)
+    return int(lib().or_signature(ctypes.byref(hs), ctypes.byref(vs), _p(ids, ctypes.c_int32),
+                                  _p(t, ctypes.c_double), ids.shape[0]))
+
+
+def backward(h, v, ids, t, dL_drgb) -> dict:
+    """Vector-Jacobian product of the rendered image with dL_drgb[H, W, 3].
+    Returns grad[59, n] (no leaf masking), dt per cut node and the per-node
+    screen-space adjoints [count, 11]."""
+    H = _H(h)
+    ids = np.ascontiguousarray(ids, np.int32)
+    t = np.ascontiguousarray(t, np.float64)
+    g = np.ascontiguousarray(dL_drgb, np.float64).reshape(-1)
+    assert g.shape[0] == v.width * v.height * 3
+    grad = np.zeros((NPARAM, H.n))
+    dt = np.zeros(ids.shape[0])
+    scr = np.zeros((ids.shape[0], 11))
+    hs, vs = H.struct(), view_struct(v)
+    lib().or_backward(ctypes.byref(hs), ctypes.byref(vs), _p(ids, ctypes.c_int32), _p(t, ctypes.c_double),
+                      ids.shape[0], _p(g, ctypes.c_double), _p(grad, ctypes.c_double), _p(dt, ctypes.c_double),
+                      _p(scr, ctypes.c_double))
+    return dict(grad=grad, dt=dt, screen=scr)
+
+
+def sh_basis(d) -> np.ndarray:
+    d = np.ascontiguousarray(d, np.float64)
+    Y = np.zeros(16)
+    lib().or_sh_basis(_p(d, ctypes.c_double), _p(Y, ctypes.c_double))
+    return Y
