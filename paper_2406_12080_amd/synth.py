@@ -472,7 +472,12 @@ def build_hierarchy(leaves: dict, collapse_chains: bool = False) -> Hierarchy:
 
     # boxes: leaf = mean +- 3 sqrt(diag cov), rounded outward to FP32;
     # interior = union of its children's boxes (= union over its leaves)
-    ext = 3.0 * np.sqrt(np.maximum(np.einsum("nii->ni", cov[is_leaf]), 0.0))
+    # (from the stored FP32 scale and rotation of each leaf)
+    q32 = q.astype(np.float32).astype(np.float64)
+    q32 /= np.linalg.norm(q32, axis=1, keepdims=True)
+    Rl = quat_to_mat(q32[is_leaf])
+    s32 = scale[is_leaf].astype(np.float32).astype(np.float64)
+    ext = 3.0 * np.sqrt(np.einsum("nij,nj->ni", Rl ** 2, s32 ** 2))
     bmin = np.zeros((N, 3), np.float32)
     bmax = np.zeros((N, 3), np.float32)
     bmin[is_leaf] = _round_down32(mean[is_leaf] - ext)

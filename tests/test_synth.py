@@ -32,8 +32,9 @@ def test_boxes_nest_and_contain_leaf_3sigma(h):
     var = np.einsum("nij,nj->ni", R ** 2, s ** 2)
     ext = 3 * np.sqrt(var)
     m = h.mean[:, leaf].T.astype(np.float64)
-    assert np.all(h.bmin[:, leaf].T <= m - ext + 1e-6 * np.abs(m - ext))
-    assert np.all(h.bmax[:, leaf].T >= m + ext - 1e-6 * np.abs(m + ext))
+    tol = 1e-6 * ext
+    assert np.all(h.bmin[:, leaf].T <= m - ext + tol)
+    assert np.all(h.bmax[:, leaf].T >= m + ext - tol)
 
 
 def test_merge_moments(h):
