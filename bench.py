@@ -1,0 +1,305 @@
+#!/usr/bin/env python3
+"""Throughput of the hierarchical-Gaussian cut + splatting path on one MI355X.
+
+One step = the whole path for one batch of views: the per-view cut and
+interpolation weights, preprocess (interpolation, EWA projection, SH
+colour), visibility compaction and depth sort, pair duplication, (tile,
+depth) sort, tile ranges, alpha blending, and the backward (blend backward
+plus preprocess backward to every interior node's parameters).  The batch
+is rendered in one call (one graph launch); the same views rendered one call
+per view are reported as the plain comparison.
+
+Prints one JSON line (see the "metric" field); progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "views/s and Gaussian-pixel blends/s at 1080p tau=6px, batched vs plain; fwd+bwd"
+
+WORKLOADS = {
+    # 30M leaves along a 3 km corridor, 32 views of 1920x1080 at tau = 6 px
+    "corridor30m_32x1080p_tau6": dict(config=5, headline=True),
+    # 8M leaves along a 1 km corridor, 64 views of 1920x1080 at tau = 6 px
+    "corridor8m_64x1080p_tau6": dict(config=3, headline=True),
+    # 1M leaves in a 100x100x20 m box with a dense core, one 1920x1080 view at tau = 6 px
+    "box1m_1x1080p_tau6": dict(config=2, tau=6.0),
+    # 2M leaves, 8 views of 1280x720 at tau = 6 px
+    "box2m_8x720p_tau6": dict(config=4),
+}
+DEFAULT = "corridor30m_32x1080p_tau6"
+
+# Algorithmic FP32 operations per (pixel, splat) pair of the blend kernels
+# (transcendentals counted as one); see the design notes for the breakdown.
+F_EVAL, F_EVAL_T, F_BLEND = 15, 11, 10
+F_BWD_CONTRIB, F_BWD_CONTRIB_T = 47, 10
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU, 2.4 GHz)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(name: str, leaves: int | None = None):
+    from paper_2406_12080_amd import synth
+    w = WORKLOADS[name]
+    cfg = w["config"]
+    t0 = time.time()
+    h = synth.make_scene(cfg, n_leaves=leaves)
+    if cfg in (3, 5):
+        views = synth.make_views(cfg, headline=True)
+    else:
+        views = synth.make_views(cfg, tau=w.get("tau"))
+    log(f"[bench] scene {name}: {h.info} views={len(views)} ({time.time() - t0:.1f}s)")
+    return h, views
+
+
+def autotune(r, views, step, reps=1):
+    """Pick the (tile, batch) with the fastest fwd+bwd step; images are
+    bit-identical across choices."""
+    import torch
+    from paper_2406_12080_amd import hgs  # noqa: F401
+    best = None
+    for tw, th, b in [(8, 8, 64), (8, 8, 128), (16, 8, 128), (16, 8, 256), (16, 16, 256), (16, 16, 512),
+                      (32, 16, 512)]:
+        r.set_tuning(tw, th, b)
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        log(f"[bench] autotune tile {tw}x{th} batch {b}: {dt * 1e3:.2f} ms")
+        if best is None or dt < best[0]:
+            best = (dt, tw, th, b)
+    r.set_tuning(best[1], best[2], best[3])
+    return dict(tile_w=best[1], tile_h=best[2], batch=best[3])
+
+
+def cpu_baseline(h, view, row_stride: int = 16):
+    """The FP64 oracle on the host cores: one view's full cut and projection
+    plus compositing and backward on every `row_stride`-th pixel row; the
+    row-proportional part is scaled to the whole image."""
+    import numpy as np
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    H = O.Hier(h)
+    t_prep = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ids, t = O.cut(H, view)
+    t_cut = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.project(H, view, ids, t)
+    t_proj = time.perf_counter() - t0
+    rows = np.arange(0, view.height, row_stride)
+    pix = (rows[:, None] * view.width + np.arange(view.width)[None, :]).reshape(-1)
+    frac = pix.size / float(view.width * view.height)
+    t0 = time.perf_counter()
+    O.render(H, view, ids, t, pix=pix, alternatives=False)
+    t_render = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    dL = np.zeros((view.height * view.width, 3))
+    dL[pix] = rng.normal(size=(pix.size, 3))
+    t0 = time.perf_counter()
+    O.backward(H, view, ids, t, dL, pix=pix)
+    t_bwd = time.perf_counter() - t0
+    per_row_part = max(t_render + t_bwd - 2.0 * t_proj, 0.0)
+    t_view = t_cut + t_proj + per_row_part / frac
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=1.0 / t_view, unit="views/s", cores=cores, kind="oracle",
+                sample=(f"1 view ({view.width}x{view.height}, tau={view.tau:g}): full cut ({len(ids)} nodes, "
+                        f"{t_cut:.2f}s) and projection ({t_proj:.2f}s), forward+backward compositing on every "
+                        f"{row_stride}th pixel row ({frac:.4f} of the pixels, {t_render + t_bwd:.2f}s), "
+                        f"row-proportional time scaled to the full image; FP64 widening of the hierarchy "
+                        f"({t_prep:.1f}s) not counted"),
+                seconds=dict(cut=t_cut, project=t_proj, render_sample=t_render, backward_sample=t_bwd,
+                             full_view_estimate=t_view))
+
+
+def kernel_source_sha() -> str:
+    p = os.path.join(ROOT, "paper_2406_12080_amd", "csrc", "k_blend.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 --pmc
+    summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("source_sha") != kernel_source_sha():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--leaves", type=int, default=None, help="override the leaf count (smaller runs)")
+    ap.add_argument("--tile", default=None, help="WxHxB, skips the autotuner (e.g. 16x16x256)")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-row-stride", type=int, default=16)
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(views shard across GPUs with no communication in the forward; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2406_12080_amd import hgs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    h, views = build_workload(args.workload, args.leaves)
+    nv = len(views)
+    dev = torch.device("cuda", 0)
+    r = hgs.Renderer(0)
+    t0 = time.time()
+    r.upload(h)
+    P = hgs.params_to_device(h, dev)
+    r.bind(*[P[k] for k in hgs.PARAM_FIELDS])
+    grads = {k: torch.zeros_like(P[k]) for k in hgs.PARAM_FIELDS}
+    gen = torch.Generator(device=dev).manual_seed(1234)
+    dL = [torch.randn((v.height, v.width, 3), device=dev, generator=gen) for v in views]
+    imgs = [torch.empty((v.height, v.width, 3), device=dev) for v in views]
+    log(f"[bench] upload + buffers {time.time() - t0:.1f}s")
+
+    def step_batched():
+        r.render(views, out=imgs)
+        r.backward(dL, grads)
+
+    def step_plain():
+        for k, v in enumerate(views):
+            r.render([v], out=[imgs[k]])
+            r.backward([dL[k]], grads)
+
+    def fwd_batched():
+        r.render(views, out=imgs)
+
+    step_batched()  # sizes the workspaces
+    torch.cuda.synchronize()
+    if args.tile:
+        tw, th, b = (int(x) for x in args.tile.split("x"))
+        r.set_tuning(tw, th, b)
+        tuning = dict(tile_w=tw, tile_h=th, batch=b)
+    else:
+        tuning = autotune(r, views, step_batched)
+    log(f"[bench] tuning {tuning}")
+
+    r.set_profiling(True)  # the blend then runs right after the graph, bracketed by events
+    for _ in range(max(args.warmup, 1)):
+        step_batched()
+    torch.cuda.synchronize()
+    r.set_profiling(True)  # resets the kernel totals; the captured graph stays valid
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_batched()
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / args.steps
+    k_ms = {k: r.kernel_time(k) for k in (hgs.K_BLEND, hgs.K_BLEND_BWD, hgs.K_PREPROCESS_BWD)}
+    r.set_profiling(False)
+    ctr = r.counters()
+    log(f"[bench] batched fwd+bwd {t_batched * 1e3:.2f} ms/step, counters {ctr}")
+
+    # forward only, batched
+    fwd_batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd_batched()
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / args.steps
+
+    t_plain = None
+    if not args.no_plain:
+        step_plain()
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 2))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step_plain()
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - t0) / reps
+        log(f"[bench] plain fwd+bwd {t_plain * 1e3:.2f} ms/step")
+
+    # roofline of the dominant kernel (the longer of blend and blend backward)
+    ms_blend, n_blend = k_ms[hgs.K_BLEND]
+    ms_bwd, n_bwd = k_ms[hgs.K_BLEND_BWD]
+    flops_fwd = F_EVAL * ctr["evaluated"] + F_EVAL_T * ctr["evaluated_t"] + F_BLEND * ctr["blended"]
+    tfrac = ctr["bwd_evaluated_t"] / max(ctr["bwd_evaluated"], 1)
+    flops_bwd = (F_EVAL * ctr["bwd_evaluated"] + F_EVAL_T * ctr["bwd_evaluated_t"] +
+                 (F_BWD_CONTRIB + F_BWD_CONTRIB_T * tfrac) * ctr["bwd_contrib"])
+    if ms_bwd >= ms_blend:
+        kname, avg_ms, flops = "k_blend_bwd", ms_bwd / max(n_bwd, 1), flops_bwd
+    else:
+        kname, avg_ms, flops = "k_blend", ms_blend / max(n_blend, 1), flops_fwd
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    traffic = load_traffic(args.workload, kname)
+    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=traffic, kernel=kname,
+                    avg_launch_ms=round(avg_ms, 4), flops_per_launch=int(flops),
+                    other_kernels_avg_ms={"k_blend": round(ms_blend / max(n_blend, 1), 4),
+                                          "k_blend_bwd": round(ms_bwd / max(n_bwd, 1), 4),
+                                          "k_preprocess_bwd": round(k_ms[hgs.K_PREPROCESS_BWD][0] /
+                                                                    max(k_ms[hgs.K_PREPROCESS_BWD][1], 1), 4)})
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline ...")
+        cpu = cpu_baseline(h, views[0], args.cpu_row_stride)
+        log(f"[bench] cpu {cpu}")
+
+    v0 = views[0]
+    out = {
+        "metric": METRIC,
+        "value": round(nv / t_batched, 3),
+        "unit": "views/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_batched * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "leaves": h.n_leaves, "nodes": h.n_nodes, "views": nv,
+                   "width": v0.width, "height": v0.height, "tau": v0.tau, "mode": "batched fwd+bwd",
+                   "tuning": tuning},
+        "blends_per_s": round(ctr["blended"] / t_batched, 1),
+        "views_per_s_plain": round(nv / t_plain, 3) if t_plain else None,
+        "views_per_s_fwd_batched": round(nv / t_fwd, 3),
+        "blends_per_s_fwd_batched": round(ctr["blended"] / t_fwd, 1),
+        "ms_per_step_plain": round(t_plain * 1e3, 3) if t_plain else None,
+        "counters_per_step": ctr,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    r.close()
+
+
+if __name__ == "__main__":
+    main()

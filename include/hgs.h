@@ -1,0 +1,204 @@
+/*
+ * hgs.h - C ABI of the MI355X (gfx950) hierarchical 3D-Gaussian cut and
+ * splatting library.
+ *
+ * The library implements the per-view hot path of "A Hierarchical 3D
+ * Gaussian Representation for Real-Time Rendering of Very Large Datasets"
+ * (Kerbl et al., ACM TOG 43(4), 2024):
+ *   - the level-of-detail cut of Sec. 4.2 ("Hierarchy Cut Selection and
+ *     Level Switching"): granularity = projected size of the largest
+ *     dimension of a node's leaf bounding box; a node is selected when it
+ *     meets the target granularity tau and its parent does not;
+ *   - the interpolation weight of Eq. (t_interp), used as the parent's weight
+ *     in the lerp of position, scale, rotation and SH (Sec. 4.2) and in the
+ *     opacity transition of Eq. (alphap) generalised to K children
+ *     (Sec. 5.2);
+ *   - tile-based splatting (Sec. 3 "Background", Eq. (alpha) and the
+ *     projected Gaussian G): EWA projection with the anti-aliasing low-pass
+ *     of Sec. 5.1, degree-3 SH colour, (tile, depth) ordering and
+ *     front-to-back compositing with alpha clamped to 0.99 (Sec. 7.3);
+ *   - the backward pass to every node's parameters (Sec. 5.1, Sec. 6.1
+ *     "Implementation"), with an absolute-value opacity activation and no
+ *     opacity gradient through the 0.99 clamp (Sec. 7.3).
+ *
+ * Conventions (all calls):
+ *   - every function returns hgs_status; nothing throws across the ABI;
+ *     hgs_last_error(ctx) returns the message of the last failure on ctx;
+ *   - "device pointer" means memory on the ctx's device (hipMalloc or a
+ *     torch CUDA tensor); "host pointer" means ordinary host memory;
+ *   - work is queued on the stream given to hgs_create (NULL = the default
+ *     stream) unless a call is documented to synchronise;
+ *   - a ctx must not be used from two threads at once.
+ *
+ * Hierarchy layout (structure of arrays, FP32, component index major):
+ *   nodes in BFS order, root = 0, parent[i] < i, the children of a node
+ *   contiguous starting at child_begin; child_count == 0 <=> leaf;
+ *   bmin/bmax [3][N] axis-aligned box over the node's leaves;
+ *   mean [3][N]; scale [3][N] (activated, world units);
+ *   rot [4][N] quaternion (w, x, y, z);
+ *   opacity [N]: opacity of a leaf, "falloff" (may exceed 1) of an interior
+ *   node; the renderer uses |opacity|;
+ *   sh [48][N]: row 3*k + c = coefficient of real SH basis function k
+ *   (k = l*l + l + m, degree <= 3) for colour channel c.
+ */
+#ifndef HGS_H
+#define HGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HGS_OK = 0,
+    HGS_ERR_INVALID_ARG = 1, /* bad pointer, size, view or topology */
+    HGS_ERR_OOM = 2,         /* device allocation failed */
+    HGS_ERR_HIP = 3,         /* a HIP runtime call failed */
+    HGS_ERR_STATE = 4,       /* call order violated (e.g. backward before render) */
+    HGS_ERR_CAPACITY = 5     /* caller's output buffer too small; *out_count holds the size needed */
+} hgs_status;
+
+typedef struct hgs_ctx hgs_ctx;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (may be NULL for the default stream); it is borrowed, not owned.
+ * On success *out receives a library-owned context.
+ * Errors: HGS_ERR_INVALID_ARG (out == NULL, bad device), HGS_ERR_HIP. */
+hgs_status hgs_create(hgs_ctx **out, int device, void *hip_stream);
+
+/* Release every device buffer of ctx.  NULL is accepted and ignored. */
+void hgs_destroy(hgs_ctx *ctx);
+
+/* Message of the last failing call on ctx (never NULL; "" if none).  The
+ * string is owned by ctx and valid until its next call. */
+const char *hgs_last_error(const hgs_ctx *ctx);
+
+/* Point the ctx at another stream (borrowed). */
+hgs_status hgs_set_stream(hgs_ctx *ctx, void *hip_stream);
+
+typedef struct {
+    int64_t n_nodes;
+    int32_t sh_degree;                               /* must be 3 */
+    const int32_t *parent, *child_begin, *child_count; /* [N] */
+    const float *bmin, *bmax;                        /* [3][N] */
+    const float *mean, *scale, *rot, *opacity, *sh;  /* [3][N] [3][N] [4][N] [N] [48][N] */
+} hgs_hierarchy_desc;
+
+/* Copy a hierarchy into library-owned device memory.  `src_on_device` = 0:
+ * every pointer in desc is a host pointer; 1: every pointer is a device
+ * pointer.  The topology is validated (parent < child, children contiguous
+ * and consistent with parent, child ranges in bounds, boxes ordered);
+ * a malformed hierarchy returns HGS_ERR_INVALID_ARG and leaves ctx without a
+ * hierarchy.  Synchronises the ctx stream.  Replaces any earlier hierarchy
+ * and unbinds parameters bound with hgs_bind_params.  Leaf boxes must contain
+ * the granularity box the caller intends (the library does not recompute
+ * boxes from the Gaussians). */
+hgs_status hgs_upload(hgs_ctx *ctx, const hgs_hierarchy_desc *desc, int src_on_device);
+
+/* Render from caller-owned device parameter arrays instead of the copies
+ * made by hgs_upload (same layouts, N = n_nodes).  Pointers stay owned by the
+ * caller and must stay valid while used.  Passing all NULL reverts to the
+ * library's copies.  Invalidates the state kept for hgs_render_backward. */
+hgs_status hgs_bind_params(hgs_ctx *ctx, float *mean, float *scale, float *rot, float *opacity, float *sh);
+
+/* One pinhole camera.  R (row-major 3x3) rows are the camera's right, down
+ * and forward axes in world coordinates: p_cam = R (x - eye).  Pixel (i, j)
+ * samples the image-plane point (i + 1/2, j + 1/2) with
+ * u = fx p.x / p.z + cx, v = fy p.y / p.z + cy.  Splats with p.z <= z_near
+ * are culled.  tau is the target granularity in pixels (>= 0). */
+typedef struct {
+    float R[9];
+    float eye[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float z_near, tau;
+} hgs_view;
+
+/* The cut of Sec. 4.2 for one view (host pointer `view`).
+ * out_ids (device, int32[capacity]) receives the selected node ids in
+ * ascending order; out_t (device, float[capacity], may be NULL) the
+ * interpolation weight of each (the parent's weight; 0 for the root, for
+ * leaves coarser than tau, and where eps(parent) <= eps(node) or the eye is
+ * inside the parent's box).  The predicate and t are evaluated in FP64.
+ * *out_count (host) receives the cut size; if it exceeds capacity nothing is
+ * written and HGS_ERR_CAPACITY is returned.  Synchronises the ctx stream. */
+hgs_status hgs_cut(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *out_t, int64_t capacity,
+                   int64_t *out_count);
+
+typedef struct {
+    int64_t cut;        /* cut nodes, all views */
+    int64_t visible;    /* splats with a non-empty footprint */
+    int64_t pairs;      /* (tile, splat) pairs */
+    int64_t evaluated;  /* (pixel, splat) pairs whose alpha was computed */
+    int64_t blended;    /* (pixel, splat) pairs that passed alpha >= 1/255 and were composited */
+    float ms[8];        /* stage times when requested: cut, preprocess, visible+depth sort,
+                           duplicate, tile sort, ranges, blend, total (0 when not timed) */
+} hgs_stats;
+
+/* Render n_views views (host array `views`) into out_rgb[v] (host array of
+ * device pointers; each float[height][width][3], overwritten).  n_views == 1
+ * launches the stages one by one; n_views > 1 runs every view through one
+ * sequence of launches (all cuts, one preprocess, one sort, one blend over
+ * the tiles of every view) captured once into a HIP graph and replayed while
+ * the view sizes stay the same.  `stats` (host, may be NULL) receives counts;
+ * stats->ms is filled when stats->ms[0] < 0 on entry (costs event syncs).
+ * Keeps the state hgs_render_backward needs.  Synchronises the ctx stream
+ * once at the end (capacity check); grows internal buffers and replays when
+ * a capacity was exceeded. */
+hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, float *const *out_rgb,
+                      hgs_stats *stats);
+
+typedef struct {
+    float *mean, *scale, *rot, *opacity, *sh; /* device, same layouts as the parameters; accumulated (+=) */
+    float *dt;                                /* device, may be NULL: dL/dt per cut entry of the last render */
+} hgs_grads;
+
+/* Backward of the last hgs_render on this ctx: dL_drgb[v] (host array of
+ * device pointers, float[height][width][3]) is dL/d(out_rgb[v]).  Gradients
+ * of every node's parameters are ADDED to `out`; leaves get none (they are
+ * frozen, Sec. 6.1); opacity gradients include the sign of the
+ * absolute-value activation and are zero where the 0.99 clamp is active.
+ * Per-tile blending state is recomputed from the final transmittance and
+ * the index of the last contributor of each pixel (no per-pixel lists).
+ * Errors: HGS_ERR_STATE without a preceding render (or after the parameters
+ * were rebound / re-uploaded).  Does not synchronise. */
+hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_grads *out);
+
+/* Tuning knobs of the blend stage (chosen by the autotuner): tile edge
+ * tile_w x tile_h in {8x8, 16x8, 16x16, 32x16} and splats staged per batch
+ * (a multiple of 64 up to 1024; 0 = one per thread).  Changing them keeps
+ * images bit-identical.  HGS_ERR_INVALID_ARG for other values. */
+hgs_status hgs_set_tuning(hgs_ctx *ctx, int32_t tile_w, int32_t tile_h, int32_t batch);
+
+/* Kernel timing for benchmarks: with profiling on, selected launches are
+ * bracketed by HIP events on the stream they run on (in a multi-view render
+ * the blend then runs right after the graph instead of inside it).
+ * hgs_set_profiling resets the totals.  hgs_kernel_time synchronises and
+ * returns the summed milliseconds and launch count of kernel `which`:
+ * 0 blend, 1 blend backward, 2 preprocess backward. */
+hgs_status hgs_set_profiling(hgs_ctx *ctx, int32_t on);
+hgs_status hgs_kernel_time(hgs_ctx *ctx, int32_t which, double *total_ms, int64_t *launches);
+
+/* Counters of the last render and backward (synchronises): out[0..8] =
+ * cut, visible, pairs, evaluated, blended, evaluated with t > 0,
+ * backward evaluated, backward evaluated with t > 0, backward contributing
+ * pairs.  At most n values are written. */
+hgs_status hgs_counters(hgs_ctx *ctx, int64_t *out, int32_t n);
+
+/* Read-only access to internal state of the last render/backward (device
+ * pointers, valid until the next render on ctx), for tests and tools.
+ * which: 0 cut node ids (int32, all views, view-major), 1 cut t (float),
+ * 2 final transmittance per pixel (float, views concatenated, row-major),
+ * 3 contributors processed per pixel (uint32: index within its tile's list
+ * after the last blended splat, + 1; 0 if none), 4 blended splats per pixel
+ * (uint32), 5 screen-space gradients of the last backward (double[cut][12]:
+ * du, dv, dconic(3), dA_n, dA_p, drgb(3), dt_alpha, unused), 6 cut offsets
+ * per view (uint32[n_views + 1]).  *count receives the element count. */
+hgs_status hgs_get_buffer(hgs_ctx *ctx, int32_t which, const void **dev_ptr, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGS_H */

@@ -785,21 +785,19 @@ static void splat_backward(const or_hier *h, const or_view *v, const or_splat *S
     if (dt_out) *dt_out = (p >= 0) ? dt : 0.0;
 }
 
-/* Gradient of L = sum over pixels and channels of dL_drgb * rgb, i.e. the
- * vector-Jacobian product with dL_drgb[H*W*3] (row-major, channel last).
+/* Gradient of L = sum over the listed pixels pix[npix] (linear indices
+ * y*W + x) and channels of dL_drgb[k*3 + c] * rgb, i.e. the vector-Jacobian
+ * product with a cotangent that is zero on every other pixel.
  * grad[OR_NPARAM * n] accumulates; dt[count] (optional) receives dL/dt for
  * each cut node; screen[count*11] (optional) receives the screen-space
  * adjoints du, dv, dconic(3), dA_n, dA_p, drgb(3), dt_alpha of each cut node
  * (A_n = kappa o_n, A_p = kappa o_p, dt_alpha = the part of dL/dt that flows
  * through alpha alone). */
 void or_backward(const or_hier *h, const or_view *v, const int32_t *ids, const double *t, int64_t count,
-                 const double *dL_drgb, double *grad, double *dt, double *screen)
+                 const int64_t *pix, int64_t npix, const double *dL_drgb, double *grad, double *dt, double *screen)
 {
     or_frame F;
     frame_build(h, v, ids, t, count, &F);
-    const int64_t npix = (int64_t)v->width * v->height;
-    int64_t *pix = (int64_t *)malloc(sizeof(int64_t) * npix);
-    for (int64_t k = 0; k < npix; ++k) pix[k] = k;
     or_lists L;
     lists_build(&F, v, pix, npix, &L);
     or_sgrad *sg = (or_sgrad *)calloc((size_t)(count > 0 ? count : 1), sizeof(or_sgrad));
@@ -808,7 +806,7 @@ void or_backward(const or_hier *h, const or_view *v, const int32_t *ids, const d
     double *alph = NULL, *Tb = NULL;
     int64_t cap = 0;
     for (int64_t k = 0; k < npix; ++k) {
-        const int px = (int)(k % v->width), py = (int)(k / v->width);
+        const int px = (int)(pix[k] % v->width), py = (int)(pix[k] / v->width);
         const int32_t *items = L.items + L.start[k];
         const int64_t m = L.start[k + 1] - L.start[k];
         const double *gC = dL_drgb + 3 * k;
@@ -897,6 +895,5 @@ void or_backward(const or_hier *h, const or_view *v, const int32_t *ids, const d
     free(sg);
     lists_free(&L);
     frame_free(&F);
-    free(pix);
 }
 

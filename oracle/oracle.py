@@ -56,7 +56,7 @@ def lib():
         L.or_render.restype = i64
         L.or_signature.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64]
         L.or_signature.restype = ctypes.c_uint64
-        L.or_backward.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(d), P(d), P(d), P(d)]
+        L.or_backward.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(i64), i64, P(d), P(d), P(d), P(d)]
         L.or_sh_basis.argtypes = [P(d), P(d)]
         _lib = L
     return _lib
@@ -230,22 +230,27 @@ def signature(h, v, ids, t) -> int:
                                   _p(t, ctypes.c_double), ids.shape[0]))
 
 
-def backward(h, v, ids, t, dL_drgb) -> dict:
-    """Vector-Jacobian product of the rendered image with dL_drgb[H, W, 3].
-    Returns grad[59, n] (no leaf masking), dt per cut node and the per-node
-    screen-space adjoints [count, 11]."""
+def backward(h, v, ids, t, dL_drgb, pix=None) -> dict:
+    """Vector-Jacobian product of the rendered image with dL_drgb[H, W, 3]
+    (restricted to the linear pixel indices ``pix`` when given; the cotangent
+    is zero elsewhere).  Returns grad[59, n] (no leaf masking), dt per cut
+    node and the per-node screen-space adjoints [count, 11]."""
     H = _H(h)
     ids = np.ascontiguousarray(ids, np.int32)
     t = np.ascontiguousarray(t, np.float64)
-    g = np.ascontiguousarray(dL_drgb, np.float64).reshape(-1)
-    assert g.shape[0] == v.width * v.height * 3
+    g = np.ascontiguousarray(dL_drgb, np.float64).reshape(-1, 3)
+    assert g.shape[0] == v.width * v.height
+    if pix is None:
+        pix = np.arange(v.width * v.height, dtype=np.int64)
+    pix = np.ascontiguousarray(pix, np.int64)
+    gp = np.ascontiguousarray(g[pix])
     grad = np.zeros((NPARAM, H.n))
     dt = np.zeros(ids.shape[0])
     scr = np.zeros((ids.shape[0], 11))
     hs, vs = H.struct(), view_struct(v)
     lib().or_backward(ctypes.byref(hs), ctypes.byref(vs), _p(ids, ctypes.c_int32), _p(t, ctypes.c_double),
-                      ids.shape[0], _p(g, ctypes.c_double), _p(grad, ctypes.c_double), _p(dt, ctypes.c_double),
-                      _p(scr, ctypes.c_double))
+                      ids.shape[0], _p(pix, ctypes.c_int64), pix.shape[0], _p(gp, ctypes.c_double),
+                      _p(grad, ctypes.c_double), _p(dt, ctypes.c_double), _p(scr, ctypes.c_double))
     return dict(grad=grad, dt=dt, screen=scr)
 
 

@@ -1,0 +1,852 @@
+// Host side of the C ABI declared in include/hgs.h: context, hierarchy
+// upload and validation, workspace management, the launch sequence of the
+// cut -> preprocess -> sort -> blend pipeline (direct for one view, captured
+// in a HIP graph for several), and the backward.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hgs.h"
+#include "hgs_internal.h"
+
+using namespace hgs;
+
+namespace {
+
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+};
+
+constexpr int kTimedKernels = 4;  // blend, blend backward, preprocess backward, preprocess
+
+struct RenderKey {
+    int nv = -1;
+    std::vector<int> wh;
+    int tw = 0, th = 0, batch = 0;
+    uint64_t layout = 0;
+    bool profiled = false;
+    bool operator==(const RenderKey &o) const
+    {
+        return nv == o.nv && wh == o.wh && tw == o.tw && th == o.th && batch == o.batch && layout == o.layout &&
+               profiled == o.profiled;
+    }
+};
+
+}  // namespace
+
+struct hgs_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;   // caller's (borrowed)
+    hipStream_t gstream = nullptr;  // library-owned, for graph capture/launch
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::string err;
+
+    // hierarchy
+    bool has_hier = false;
+    int64_t n = 0, n_leaves = 0;
+    uint32_t *pinfo = nullptr;
+    float *box = nullptr;
+    int32_t *child_count = nullptr;
+    float *own[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    float *bound[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool use_bound = false;
+    uint64_t param_gen = 1;
+
+    int tile_w = 16, tile_h = 16, batch = 0;
+
+    // workspaces
+    uint64_t layout_gen = 1;
+    std::vector<void *> allocs;
+    DevView *views_dev = nullptr;
+    DevView *views_host = nullptr;  // pinned
+    Counters *ctr = nullptr;
+    Counters *ctr_host = nullptr;   // pinned
+    uint32_t cut_cap = 0, pair_cap = 0;
+    size_t pix_cap = 0, tile_cap = 0;
+    int nblocks_cap = 0, nv_cap = 0;
+    uint64_t *masks = nullptr;
+    uint32_t *blk_counts = nullptr, *blk_offsets = nullptr, *cut_base = nullptr;
+    int32_t *cut_ids = nullptr;
+    float *cut_t = nullptr;
+    SplatRec *recs = nullptr;
+    uint32_t *depth_key = nullptr, *ntiles = nullptr;
+    uint2 *rect = nullptr;
+    uint64_t *vis_mask = nullptr;
+    uint32_t *vis_counts = nullptr, *vis_offsets = nullptr;
+    uint32_t *skeys = nullptr, *svals = nullptr, *pair_offsets = nullptr;
+    uint32_t *pkeys = nullptr, *pvals = nullptr;
+    uint32_t *k2 = nullptr, *v2 = nullptr;
+    uint32_t *hist = nullptr, *hist_scan = nullptr, *partial = nullptr, *scan_total = nullptr;
+    uint2 *ranges = nullptr;
+    float *T_final = nullptr;
+    uint32_t *n_last = nullptr, *n_blend = nullptr;
+    double *sgrad = nullptr;
+
+    // state of the last render
+    bool have_render = false;
+    uint64_t render_param_gen = 0;
+    int last_nv = 0;
+    uint32_t last_tiles = 0;
+    uint32_t last_cut = 0;
+    size_t last_pix = 0;
+    bool pairs_in_scratch = false;
+    bool g_pairs_in_scratch = false;
+    int r_tw = 16, r_th = 16, r_batch = 0;
+
+    // graph
+    hipGraphExec_t gexec = nullptr;
+    RenderKey gkey;
+    bool g_profiled = false;
+
+    // kernel timing (HIP events around selected launches)
+    bool profile = false;
+    struct Pending {
+        int which;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    double k_ms[kTimedKernels] = {};
+    int64_t k_launches[kTimedKernels] = {};
+};
+
+namespace {
+
+hgs_status fail(hgs_ctx *c, hgs_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPC(call)                                                                                     \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(ctx, HGS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+hgs_status dalloc(hgs_ctx *ctx, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, HGS_ERR_OOM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    ctx->allocs.push_back(*p);
+    return HGS_OK;
+}
+
+void dfree(hgs_ctx *ctx, void *p)
+{
+    if (!p) return;
+    auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
+    if (it != ctx->allocs.end()) ctx->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+template <typename T>
+hgs_status realloc_buf(hgs_ctx *ctx, T *&p, size_t count)
+{
+    dfree(ctx, p);
+    p = nullptr;
+    void *q = nullptr;
+    hgs_status s = dalloc(ctx, &q, count * sizeof(T));
+    p = (T *)q;
+    return s;
+}
+
+hipEvent_t take_event(hgs_ctx *ctx)
+{
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one launch with events when profiling is on.
+struct KernelTimer {
+    hgs_ctx *ctx;
+    int which;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    KernelTimer(hgs_ctx *c, int w, hipStream_t s) : ctx(c), which(w), st(s)
+    {
+        if (!ctx->profile) return;
+        a = take_event(ctx);
+        b = take_event(ctx);
+        if (a) (void)hipEventRecord(a, st);
+    }
+    ~KernelTimer()
+    {
+        if (!a || !b) return;
+        (void)hipEventRecord(b, st);
+        ctx->pending.push_back({which, a, b});
+    }
+};
+
+void collect_times(hgs_ctx *ctx)
+{
+    for (auto &p : ctx->pending) {
+        (void)hipEventSynchronize(p.b);
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            ctx->k_ms[p.which] += ms;
+            ctx->k_launches[p.which] += 1;
+        }
+        ctx->event_pool.push_back(p.a);
+        ctx->event_pool.push_back(p.b);
+    }
+    ctx->pending.clear();
+}
+
+DevHier dev_hier(const hgs_ctx *c)
+{
+    DevHier h;
+    h.n = c->n;
+    h.pinfo = c->pinfo;
+    h.box = c->box;
+    h.child_count = c->child_count;
+    float *const *P = c->use_bound ? c->bound : c->own;
+    h.mean = P[0];
+    h.scale = P[1];
+    h.rot = P[2];
+    h.opacity = P[3];
+    h.sh = P[4];
+    return h;
+}
+
+int cut_blocks(int64_t n) { return (int)((n + kCutBlock - 1) / kCutBlock); }
+
+bool finite_view(const hgs_view &v)
+{
+    for (float x : v.R)
+        if (!std::isfinite(x)) return false;
+    for (float x : v.eye)
+        if (!std::isfinite(x)) return false;
+    return std::isfinite(v.fx) && std::isfinite(v.fy) && std::isfinite(v.cx) && std::isfinite(v.cy) &&
+           std::isfinite(v.z_near) && std::isfinite(v.tau) && v.fx > 0 && v.fy > 0 && v.tau >= 0 &&
+           v.width > 0 && v.height > 0 && v.width <= 32768 && v.height <= 32768;
+}
+
+// Per-view device records and global tile/pixel bases.
+hgs_status setup_views(hgs_ctx *ctx, const hgs_view *views, int nv, float *const *out_rgb, uint32_t &n_tiles,
+                       size_t &n_pix)
+{
+    n_tiles = 0;
+    n_pix = 0;
+    for (int v = 0; v < nv; ++v) {
+        const hgs_view &s = views[v];
+        if (!finite_view(s)) return fail(ctx, HGS_ERR_INVALID_ARG, "view " + std::to_string(v) + " is invalid");
+        DevView &d = ctx->views_host[v];
+        memcpy(d.R, s.R, sizeof d.R);
+        memcpy(d.eye, s.eye, sizeof d.eye);
+        d.fx = s.fx;
+        d.fy = s.fy;
+        d.cx = s.cx;
+        d.cy = s.cy;
+        d.W = s.width;
+        d.H = s.height;
+        d.z_near = s.z_near;
+        d.tau = s.tau;
+        d.tiles_x = (s.width + ctx->tile_w - 1) / ctx->tile_w;
+        d.tiles_y = (s.height + ctx->tile_h - 1) / ctx->tile_h;
+        d.tile_base = n_tiles;
+        d.pix_base = (uint32_t)n_pix;
+        d.out_rgb = out_rgb ? out_rgb[v] : nullptr;
+        d.dL = nullptr;
+        const uint64_t nt = (uint64_t)d.tiles_x * d.tiles_y;
+        if ((uint64_t)n_tiles + nt >= (1ull << 31)) return fail(ctx, HGS_ERR_INVALID_ARG, "too many tiles");
+        n_tiles += (uint32_t)nt;
+        n_pix += (size_t)s.width * s.height;
+        if (n_pix >= (1ull << 32)) return fail(ctx, HGS_ERR_INVALID_ARG, "too many pixels");
+    }
+    return HGS_OK;
+}
+
+hgs_status ensure_fixed(hgs_ctx *ctx, int nv, uint32_t n_tiles, size_t n_pix)
+{
+    hgs_status s;
+    const int nb = cut_blocks(ctx->n);
+    if (nv > ctx->nv_cap || nb > ctx->nblocks_cap) {
+        const int nvc = std::max(nv, ctx->nv_cap), nbc = std::max(nb, ctx->nblocks_cap);
+        const size_t words = (size_t)((ctx->n + 63) / 64);
+        if ((s = realloc_buf(ctx, ctx->masks, words * nvc + 1))) return s;
+        if ((s = realloc_buf(ctx, ctx->blk_counts, (size_t)nbc * nvc))) return s;
+        if ((s = realloc_buf(ctx, ctx->blk_offsets, (size_t)nbc * nvc))) return s;
+        if ((s = realloc_buf(ctx, ctx->cut_base, (size_t)nvc + 1))) return s;
+        ctx->nv_cap = nvc;
+        ctx->nblocks_cap = nbc;
+        ctx->layout_gen++;
+    }
+    if (n_tiles > ctx->tile_cap) {
+        if ((s = realloc_buf(ctx, ctx->ranges, n_tiles))) return s;
+        ctx->tile_cap = n_tiles;
+        ctx->layout_gen++;
+    }
+    if (n_pix > ctx->pix_cap) {
+        if ((s = realloc_buf(ctx, ctx->T_final, n_pix))) return s;
+        if ((s = realloc_buf(ctx, ctx->n_last, n_pix))) return s;
+        if ((s = realloc_buf(ctx, ctx->n_blend, n_pix))) return s;
+        ctx->pix_cap = n_pix;
+        ctx->layout_gen++;
+    }
+    return HGS_OK;
+}
+
+hgs_status ensure_cut_cap(hgs_ctx *ctx, uint32_t cap)
+{
+    if (cap <= ctx->cut_cap) return HGS_OK;
+    hgs_status s;
+    if ((s = realloc_buf(ctx, ctx->cut_ids, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->cut_t, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->recs, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->depth_key, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->ntiles, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->rect, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->vis_mask, (size_t)cap / 64 + 8))) return s;
+    if ((s = realloc_buf(ctx, ctx->vis_counts, (size_t)cap / 256 + 2))) return s;
+    if ((s = realloc_buf(ctx, ctx->vis_offsets, (size_t)cap / 256 + 2))) return s;
+    if ((s = realloc_buf(ctx, ctx->skeys, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->svals, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->pair_offsets, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->sgrad, (size_t)cap * 12))) return s;
+    ctx->cut_cap = cap;
+    const size_t scratch = std::max<size_t>(ctx->cut_cap, ctx->pair_cap);
+    if ((s = realloc_buf(ctx, ctx->k2, scratch))) return s;
+    if ((s = realloc_buf(ctx, ctx->v2, scratch))) return s;
+    ctx->layout_gen++;
+    return HGS_OK;
+}
+
+hgs_status ensure_pair_cap(hgs_ctx *ctx, uint32_t cap)
+{
+    if (cap <= ctx->pair_cap) return HGS_OK;
+    hgs_status s;
+    if ((s = realloc_buf(ctx, ctx->pkeys, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->pvals, cap))) return s;
+    ctx->pair_cap = cap;
+    const size_t scratch = std::max<size_t>(ctx->cut_cap, ctx->pair_cap);
+    if ((s = realloc_buf(ctx, ctx->k2, scratch))) return s;
+    if ((s = realloc_buf(ctx, ctx->v2, scratch))) return s;
+    ctx->layout_gen++;
+    return HGS_OK;
+}
+
+int bits_for(uint32_t n)
+{
+    int b = 1;
+    while (b < 32 && (1ull << b) < n) ++b;
+    return b;
+}
+
+// The whole forward for nv views, queued on st.  `ev` (9 events, optional)
+// marks stage boundaries.
+void enqueue_blend(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st)
+{
+    const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
+    launch_blend(ctx->views_dev, nv, n_tiles, ctx->ranges, vals, ctx->recs, ctx->T_final, ctx->n_last, ctx->n_blend,
+                 ctx->ctr, ctx->tile_w, ctx->tile_h, ctx->batch, st);
+}
+
+void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hipEvent_t *ev, bool with_blend)
+{
+    const DevHier h = dev_hier(ctx);
+    const int nb = cut_blocks(ctx->n);
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], st);
+    };
+    mark(0);
+    launch_fill_u32((uint32_t *)ctx->ctr, 0u, sizeof(Counters) / 4, st);
+    launch_cut_flags(h, ctx->views_dev, nv, ctx->masks, ctx->blk_counts, nb, st);
+    launch_scan(ctx->blk_counts, nullptr, (uint32_t)(nb * nv), nullptr, ctx->blk_offsets, &ctx->ctr->cut_total,
+                ctx->partial, st);
+    launch_cut_emit(h, ctx->views_dev, nv, ctx->masks, ctx->blk_offsets, nb, ctx->cut_ids, ctx->cut_t, ctx->cut_cap,
+                    st);
+    launch_cut_finish(ctx->blk_offsets, ctx->blk_counts, nb, nv, ctx->cut_base, ctx->ctr, st);
+    mark(1);
+    launch_preprocess(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t, &ctx->ctr->cut_total,
+                      ctx->cut_cap, ctx->recs, ctx->depth_key, ctx->rect, ctx->ntiles, ctx->vis_mask,
+                      ctx->vis_counts, ctx->tile_w, ctx->tile_h, st);
+    mark(2);
+    const uint32_t vblocks = (ctx->cut_cap + 255) / 256;
+    launch_scan(ctx->vis_counts, nullptr, vblocks, nullptr, ctx->vis_offsets, &ctx->ctr->vis_total, ctx->partial, st);
+    launch_compact_visible(ctx->vis_mask, ctx->vis_offsets, &ctx->ctr->cut_total, ctx->cut_cap, ctx->depth_key,
+                           ctx->skeys, ctx->svals, st);
+    SortScratch sc{ctx->k2, ctx->v2, ctx->hist, ctx->hist_scan, ctx->partial, ctx->scan_total};
+    launch_radix_sort(ctx->skeys, ctx->svals, ctx->cut_cap, &ctx->ctr->vis_total, 32, sc, st);  // 4 passes: in place
+    mark(3);
+    launch_scan(ctx->ntiles, ctx->svals, ctx->cut_cap, &ctx->ctr->vis_total, ctx->pair_offsets, &ctx->ctr->pair_total,
+                ctx->partial, st);
+    launch_duplicate(ctx->rect, ctx->views_dev, nv, ctx->cut_base, ctx->svals, ctx->pair_offsets,
+                     &ctx->ctr->vis_total, ctx->cut_cap, &ctx->ctr->pair_total, ctx->pair_cap, ctx->pkeys,
+                     ctx->pvals, ctx->ctr, st);
+    mark(4);
+    ctx->pairs_in_scratch =
+        launch_radix_sort(ctx->pkeys, ctx->pvals, ctx->pair_cap, &ctx->ctr->pair_total, bits_for(n_tiles), sc, st);
+    mark(5);
+    const uint32_t *keys = ctx->pairs_in_scratch ? ctx->k2 : ctx->pkeys;
+    const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
+    launch_fill_u32((uint32_t *)ctx->ranges, 0u, (size_t)n_tiles * 2, st);
+    launch_ranges(keys, &ctx->ctr->pair_total, ctx->pair_cap, ctx->ranges, st);
+    (void)vals;
+    mark(6);
+    if (with_blend) {
+        KernelTimer kt(ctx, 0, st);
+        enqueue_blend(ctx, nv, n_tiles, st);
+    }
+    mark(7);
+}
+
+}  // namespace
+
+extern "C" {
+
+hgs_status hgs_create(hgs_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return HGS_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return HGS_ERR_INVALID_ARG;
+    }
+    hgs_ctx *ctx = new hgs_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    hgs_status s = HGS_OK;
+    do {
+        if (hipSetDevice(device) != hipSuccess) { s = HGS_ERR_HIP; break; }
+        if (hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess) { s = HGS_ERR_HIP; break; }
+        if (hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess) { s = HGS_ERR_HIP; break; }
+        if (hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess) { s = HGS_ERR_HIP; break; }
+        if (hipHostMalloc((void **)&ctx->views_host, sizeof(DevView) * kMaxViews, hipHostMallocDefault) != hipSuccess) {
+            s = HGS_ERR_OOM;
+            break;
+        }
+        if (hipHostMalloc((void **)&ctx->ctr_host, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+            s = HGS_ERR_OOM;
+            break;
+        }
+        if ((s = dalloc(ctx, (void **)&ctx->views_dev, sizeof(DevView) * kMaxViews))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->ctr, sizeof(Counters)))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->hist, sizeof(uint32_t) * 256 * kSortBlocksMax))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->hist_scan, sizeof(uint32_t) * 256 * kSortBlocksMax))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->partial, sizeof(uint32_t) * kScanBlocks))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->scan_total, sizeof(uint32_t) * 4))) break;
+    } while (0);
+    if (s != HGS_OK) {
+        hgs_destroy(ctx);
+        return s;
+    }
+    *out = ctx;
+    return HGS_OK;
+}
+
+void hgs_destroy(hgs_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->gstream) (void)hipStreamSynchronize(ctx->gstream);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    collect_times(ctx);
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+    for (void *p : ctx->allocs) (void)hipFree(p);
+    ctx->allocs.clear();
+    if (ctx->views_host) (void)hipHostFree(ctx->views_host);
+    if (ctx->ctr_host) (void)hipHostFree(ctx->ctr_host);
+    if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
+    delete ctx;
+}
+
+const char *hgs_last_error(const hgs_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+hgs_status hgs_set_stream(hgs_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return HGS_OK;
+}
+
+hgs_status hgs_set_tuning(hgs_ctx *ctx, int32_t tile_w, int32_t tile_h, int32_t batch)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!blend_supported(tile_w, tile_h, batch))
+        return fail(ctx, HGS_ERR_INVALID_ARG, "unsupported tile/batch combination");
+    ctx->tile_w = tile_w;
+    ctx->tile_h = tile_h;
+    ctx->batch = batch == tile_w * tile_h ? 0 : batch;
+    ctx->have_render = false;
+    return HGS_OK;
+}
+
+hgs_status hgs_upload(hgs_ctx *ctx, const hgs_hierarchy_desc *d, int src_on_device)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!d) return fail(ctx, HGS_ERR_INVALID_ARG, "desc is NULL");
+    HIPC(hipSetDevice(ctx->device));
+    const int64_t N = d->n_nodes;
+    if (N <= 0 || N >= (int64_t)kRootParent) return fail(ctx, HGS_ERR_INVALID_ARG, "n_nodes out of range");
+    if (d->sh_degree != 3) return fail(ctx, HGS_ERR_INVALID_ARG, "only sh_degree 3 is supported");
+    const void *ptrs[] = {d->parent, d->child_begin, d->child_count, d->bmin, d->bmax,
+                          d->mean,   d->scale,       d->rot,         d->opacity, d->sh};
+    for (const void *p : ptrs)
+        if (!p) return fail(ctx, HGS_ERR_INVALID_ARG, "NULL array in desc");
+    // topology and boxes to the host for validation
+    std::vector<int32_t> par(N), cb(N), cc(N);
+    std::vector<float> bmin(3 * N), bmax(3 * N);
+    const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    HIPC(hipMemcpy(par.data(), d->parent, 4 * N, kind));
+    HIPC(hipMemcpy(cb.data(), d->child_begin, 4 * N, kind));
+    HIPC(hipMemcpy(cc.data(), d->child_count, 4 * N, kind));
+    HIPC(hipMemcpy(bmin.data(), d->bmin, 12 * N, kind));
+    HIPC(hipMemcpy(bmax.data(), d->bmax, 12 * N, kind));
+    ctx->has_hier = false;
+    ctx->have_render = false;
+    if (par[0] != -1) return fail(ctx, HGS_ERR_INVALID_ARG, "parent[0] must be -1 (root first)");
+    int64_t kids = 0, leaves = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        if (i > 0 && (par[i] < 0 || par[i] >= i))
+            return fail(ctx, HGS_ERR_INVALID_ARG, "parent[" + std::to_string(i) + "] must lie in [0, i)");
+        if (cc[i] < 0) return fail(ctx, HGS_ERR_INVALID_ARG, "negative child_count");
+        if (cc[i] == 0) {
+            ++leaves;
+        } else {
+            if (cb[i] <= i || (int64_t)cb[i] + cc[i] > N)
+                return fail(ctx, HGS_ERR_INVALID_ARG, "child range of node " + std::to_string(i) + " out of bounds");
+            for (int32_t k = 0; k < cc[i]; ++k)
+                if (par[cb[i] + k] != i)
+                    return fail(ctx, HGS_ERR_INVALID_ARG,
+                                "children of node " + std::to_string(i) + " are not contiguous");
+            kids += cc[i];
+        }
+        for (int k = 0; k < 3; ++k) {
+            const float lo = bmin[k * N + i], hi = bmax[k * N + i];
+            if (!(lo <= hi) || !std::isfinite(lo) || !std::isfinite(hi))
+                return fail(ctx, HGS_ERR_INVALID_ARG, "box of node " + std::to_string(i) + " is invalid");
+        }
+    }
+    if (kids != N - 1) return fail(ctx, HGS_ERR_INVALID_ARG, "child counts do not cover every non-root node once");
+    std::vector<uint32_t> pinfo(N);
+    for (int64_t i = 0; i < N; ++i)
+        pinfo[i] = (i == 0 ? kRootParent : (uint32_t)par[i]) | (cc[i] == 0 ? kLeafBit : 0u);
+
+    // (re)allocate hierarchy buffers
+    for (int k = 0; k < 5; ++k) {
+        dfree(ctx, ctx->own[k]);
+        ctx->own[k] = nullptr;
+        ctx->bound[k] = nullptr;
+    }
+    dfree(ctx, ctx->pinfo);
+    dfree(ctx, ctx->box);
+    dfree(ctx, ctx->child_count);
+    ctx->pinfo = nullptr;
+    ctx->box = nullptr;
+    ctx->child_count = nullptr;
+    ctx->use_bound = false;
+    hgs_status s;
+    if ((s = dalloc(ctx, (void **)&ctx->pinfo, 4 * N))) return s;
+    if ((s = dalloc(ctx, (void **)&ctx->box, 24 * N))) return s;
+    if ((s = dalloc(ctx, (void **)&ctx->child_count, 4 * N))) return s;
+    const size_t comp[5] = {3, 3, 4, 1, 48};
+    const float *src[5] = {d->mean, d->scale, d->rot, d->opacity, d->sh};
+    for (int k = 0; k < 5; ++k)
+        if ((s = dalloc(ctx, (void **)&ctx->own[k], 4 * comp[k] * N))) return s;
+    HIPC(hipMemcpy(ctx->pinfo, pinfo.data(), 4 * N, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->box, bmin.data(), 12 * N, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->box + 3 * N, bmax.data(), 12 * N, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->child_count, cc.data(), 4 * N, hipMemcpyHostToDevice));
+    const hipMemcpyKind k2 = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    for (int k = 0; k < 5; ++k) HIPC(hipMemcpy(ctx->own[k], src[k], 4 * comp[k] * N, k2));
+    HIPC(hipDeviceSynchronize());
+    ctx->n = N;
+    ctx->n_leaves = leaves;
+    ctx->has_hier = true;
+    ctx->param_gen++;
+    ctx->layout_gen++;
+    // cut workspace sized for the hierarchy (the grid of the cut sweep depends on N)
+    ctx->nblocks_cap = 0;
+    ctx->nv_cap = 0;
+    return HGS_OK;
+}
+
+hgs_status hgs_bind_params(hgs_ctx *ctx, float *mean, float *scale, float *rot, float *opacity, float *sh)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy uploaded");
+    float *p[5] = {mean, scale, rot, opacity, sh};
+    bool same = true;
+    for (int k = 0; k < 5; ++k) same = same && ctx->bound[k] == p[k];
+    if (same && ctx->use_bound == (p[0] != nullptr)) return HGS_OK;  // nothing changes
+    int nn = 0;
+    for (float *q : p) nn += q == nullptr;
+    if (nn != 0 && nn != 5) return fail(ctx, HGS_ERR_INVALID_ARG, "bind all five parameter arrays or none");
+    for (int k = 0; k < 5; ++k) ctx->bound[k] = p[k];
+    ctx->use_bound = nn == 0;
+    ctx->param_gen++;
+    ctx->layout_gen++;
+    ctx->have_render = false;
+    return HGS_OK;
+}
+
+hgs_status hgs_cut(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *out_t, int64_t capacity,
+                   int64_t *out_count)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy uploaded");
+    if (!view || !out_count || capacity < 0 || (capacity > 0 && !out_ids))
+        return fail(ctx, HGS_ERR_INVALID_ARG, "bad arguments");
+    HIPC(hipSetDevice(ctx->device));
+    ctx->have_render = false;  // shares the cut workspace and counters
+    uint32_t n_tiles;
+    size_t n_pix;
+    hgs_status s;
+    if ((s = setup_views(ctx, view, 1, nullptr, n_tiles, n_pix))) return s;
+    if ((s = ensure_fixed(ctx, 1, 0, 0))) return s;
+    hipStream_t st = ctx->stream;
+    HIPC(hipMemcpyAsync(ctx->views_dev, ctx->views_host, sizeof(DevView), hipMemcpyHostToDevice, st));
+    const DevHier h = dev_hier(ctx);
+    const int nb = cut_blocks(ctx->n);
+    launch_fill_u32((uint32_t *)ctx->ctr, 0u, sizeof(Counters) / 4, st);
+    launch_cut_flags(h, ctx->views_dev, 1, ctx->masks, ctx->blk_counts, nb, st);
+    launch_scan(ctx->blk_counts, nullptr, (uint32_t)nb, nullptr, ctx->blk_offsets, &ctx->ctr->cut_total, ctx->partial,
+                st);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(ctx->ctr_host, ctx->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    *out_count = ctx->ctr_host->cut_total;
+    if (*out_count > capacity)
+        return fail(ctx, HGS_ERR_CAPACITY, "cut has " + std::to_string(*out_count) + " nodes, capacity " +
+                                               std::to_string(capacity));
+    if (*out_count > 0)
+        launch_cut_emit(h, ctx->views_dev, 1, ctx->masks, ctx->blk_offsets, nb, out_ids, out_t, (uint32_t)capacity, st);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(st));
+    return HGS_OK;
+}
+
+hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, float *const *out_rgb, hgs_stats *stats)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy uploaded");
+    if (!views || n_views <= 0 || n_views > kMaxViews || !out_rgb)
+        return fail(ctx, HGS_ERR_INVALID_ARG, "bad views / n_views / out_rgb");
+    for (int v = 0; v < n_views; ++v)
+        if (!out_rgb[v]) return fail(ctx, HGS_ERR_INVALID_ARG, "out_rgb[" + std::to_string(v) + "] is NULL");
+    HIPC(hipSetDevice(ctx->device));
+    ctx->have_render = false;
+    uint32_t n_tiles;
+    size_t n_pix;
+    hgs_status s;
+    if ((s = setup_views(ctx, views, n_views, out_rgb, n_tiles, n_pix))) return s;
+    if ((s = ensure_fixed(ctx, n_views, n_tiles, n_pix))) return s;
+    const bool timed = stats && stats->ms[0] < 0.0f && n_views == 1;
+    if (ctx->cut_cap == 0) {
+        const uint64_t guess = std::min<uint64_t>((uint64_t)n_views * (uint64_t)std::min<int64_t>(ctx->n_leaves, 1 << 21),
+                                                  0x7FFFFFFFull);
+        if ((s = ensure_cut_cap(ctx, (uint32_t)std::max<uint64_t>(guess, 4096)))) return s;
+    }
+    if (ctx->pair_cap == 0) {
+        const uint64_t guess = std::min<uint64_t>((uint64_t)n_pix * 4 + 65536, 0x7FFFFFFFull);
+        if ((s = ensure_pair_cap(ctx, (uint32_t)guess))) return s;
+    }
+    hipEvent_t ev[8] = {};
+    if (timed)
+        for (auto &e : ev) HIPC(hipEventCreate(&e));
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        const bool graph = n_views > 1;
+        hipStream_t st = graph ? ctx->gstream : ctx->stream;
+        if (graph) {
+            HIPC(hipEventRecord(ctx->ev_in, ctx->stream));
+            HIPC(hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
+        }
+        HIPC(hipMemcpyAsync(ctx->views_dev, ctx->views_host, sizeof(DevView) * n_views, hipMemcpyHostToDevice, st));
+        if (graph) {
+            RenderKey key;
+            key.nv = n_views;
+            for (int v = 0; v < n_views; ++v) {
+                key.wh.push_back(views[v].width);
+                key.wh.push_back(views[v].height);
+            }
+            key.tw = ctx->tile_w;
+            key.th = ctx->tile_h;
+            key.batch = ctx->batch;
+            key.layout = ctx->layout_gen * 1000003ull + ctx->param_gen;
+            key.profiled = ctx->profile;
+            if (!ctx->gexec || !(key == ctx->gkey)) {
+                if (ctx->gexec) {
+                    HIPC(hipGraphExecDestroy(ctx->gexec));
+                    ctx->gexec = nullptr;
+                }
+                hipGraph_t g = nullptr;
+                HIPC(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
+                enqueue_forward(ctx, n_views, n_tiles, ctx->gstream, nullptr, !ctx->profile);
+                HIPC(hipStreamEndCapture(ctx->gstream, &g));
+                hipError_t e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return fail(ctx, HGS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+                ctx->gkey = key;
+                ctx->g_pairs_in_scratch = ctx->pairs_in_scratch;
+            }
+            ctx->pairs_in_scratch = ctx->g_pairs_in_scratch;
+            HIPC(hipGraphLaunch(ctx->gexec, ctx->gstream));
+            if (ctx->profile) {
+                // timed blend outside the graph
+                KernelTimer kt(ctx, 0, ctx->gstream);
+                enqueue_blend(ctx, n_views, n_tiles, ctx->gstream);
+            }
+        } else {
+            enqueue_forward(ctx, n_views, n_tiles, st, timed ? ev : nullptr, true);
+        }
+        HIPC(hipGetLastError());
+        HIPC(hipMemcpyAsync(ctx->ctr_host, ctx->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        const Counters c = *ctx->ctr_host;
+        bool grow = false;
+        if (c.cut_total > ctx->cut_cap) {
+            if ((s = ensure_cut_cap(ctx, (uint32_t)std::min<uint64_t>((uint64_t)c.cut_total * 5 / 4 + 1024, 0x7FFFFFFFull))))
+                return s;
+            grow = true;
+        }
+        if (!grow && c.pair_total > ctx->pair_cap) {
+            if ((s = ensure_pair_cap(ctx, (uint32_t)std::min<uint64_t>((uint64_t)c.pair_total * 5 / 4 + 4096, 0x7FFFFFFFull))))
+                return s;
+            grow = true;
+        }
+        if (grow) continue;
+        ctx->have_render = true;
+        ctx->render_param_gen = ctx->param_gen;
+        ctx->last_nv = n_views;
+        ctx->last_tiles = n_tiles;
+        ctx->last_cut = c.cut_total;
+        ctx->last_pix = n_pix;
+        ctx->r_tw = ctx->tile_w;
+        ctx->r_th = ctx->tile_h;
+        ctx->r_batch = ctx->batch;
+        if (stats) {
+            stats->cut = c.cut_total;
+            stats->visible = c.vis_total;
+            stats->pairs = c.pair_total;
+            stats->evaluated = (int64_t)c.evaluated;
+            stats->blended = (int64_t)c.blended;
+            for (int k = 0; k < 8; ++k) stats->ms[k] = 0.0f;
+            if (timed) {
+                for (int k = 0; k < 7; ++k) (void)hipEventElapsedTime(&stats->ms[k], ev[k], ev[k + 1]);
+                (void)hipEventElapsedTime(&stats->ms[7], ev[0], ev[7]);
+            }
+        }
+        if (timed)
+            for (auto &e : ev) (void)hipEventDestroy(e);
+        return HGS_OK;
+    }
+    if (timed)
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    return fail(ctx, HGS_ERR_CAPACITY, "render did not fit after growing buffers");
+}
+
+hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_grads *out)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->have_render || ctx->render_param_gen != ctx->param_gen)
+        return fail(ctx, HGS_ERR_STATE, "render_backward needs a render with the current parameters");
+    if (!dL_drgb || !out || !out->mean || !out->scale || !out->rot || !out->opacity || !out->sh)
+        return fail(ctx, HGS_ERR_INVALID_ARG, "bad gradient arguments");
+    const int nv = ctx->last_nv;
+    for (int v = 0; v < nv; ++v) {
+        if (!dL_drgb[v]) return fail(ctx, HGS_ERR_INVALID_ARG, "dL_drgb[" + std::to_string(v) + "] is NULL");
+        ctx->views_host[v].dL = dL_drgb[v];
+    }
+    HIPC(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    HIPC(hipMemcpyAsync(ctx->views_dev, ctx->views_host, sizeof(DevView) * nv, hipMemcpyHostToDevice, st));
+    const uint32_t cut = std::min(ctx->last_cut, ctx->cut_cap);
+    launch_fill_u32((uint32_t *)ctx->sgrad, 0u, (size_t)cut * 24, st);
+    launch_fill_u32((uint32_t *)&ctx->ctr->bwd_evaluated, 0u, 6, st);
+    const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
+    {
+        KernelTimer kt(ctx, 1, st);
+        launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->ranges, vals, ctx->recs, ctx->T_final,
+                              ctx->n_last, ctx->sgrad, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch, st);
+    }
+    const DevHier h = dev_hier(ctx);
+    {
+        KernelTimer kt(ctx, 2, st);
+        launch_preprocess_backward(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t,
+                                   &ctx->ctr->cut_total, ctx->cut_cap, ctx->ntiles, ctx->sgrad, out->mean, out->scale,
+                                   out->rot, out->opacity, out->sh, out->dt, st);
+    }
+    HIPC(hipGetLastError());
+    // host copy of views keeps dL for nothing else
+    for (int v = 0; v < nv; ++v) ctx->views_host[v].dL = nullptr;
+    return HGS_OK;
+}
+
+hgs_status hgs_counters(hgs_ctx *ctx, int64_t *out, int32_t n)
+{
+    if (!ctx || !out || n <= 0) return HGS_ERR_INVALID_ARG;
+    HIPC(hipSetDevice(ctx->device));
+    HIPC(hipMemcpyAsync(ctx->ctr_host, ctx->ctr, sizeof(Counters), hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    const Counters &c = *ctx->ctr_host;
+    const int64_t v[] = {c.cut_total, c.vis_total, c.pair_total, (int64_t)c.evaluated, (int64_t)c.blended,
+                         (int64_t)c.evaluated_t, (int64_t)c.bwd_evaluated, (int64_t)c.bwd_evaluated_t,
+                         (int64_t)c.bwd_contrib};
+    for (int32_t k = 0; k < n && k < (int32_t)(sizeof v / sizeof v[0]); ++k) out[k] = v[k];
+    return HGS_OK;
+}
+
+hgs_status hgs_set_profiling(hgs_ctx *ctx, int32_t on)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    HIPC(hipSetDevice(ctx->device));
+    collect_times(ctx);
+    ctx->profile = on != 0;
+    for (int k = 0; k < kTimedKernels; ++k) {
+        ctx->k_ms[k] = 0.0;
+        ctx->k_launches[k] = 0;
+    }
+    return HGS_OK;
+}
+
+hgs_status hgs_kernel_time(hgs_ctx *ctx, int32_t which, double *total_ms, int64_t *launches)
+{
+    if (!ctx || !total_ms || !launches || which < 0 || which >= kTimedKernels) return HGS_ERR_INVALID_ARG;
+    HIPC(hipSetDevice(ctx->device));
+    collect_times(ctx);
+    *total_ms = ctx->k_ms[which];
+    *launches = ctx->k_launches[which];
+    return HGS_OK;
+}
+
+hgs_status hgs_get_buffer(hgs_ctx *ctx, int32_t which, const void **dev_ptr, int64_t *count)
+{
+    if (!ctx || !dev_ptr || !count) return HGS_ERR_INVALID_ARG;
+    if (!ctx->have_render) return fail(ctx, HGS_ERR_STATE, "no render yet");
+    switch (which) {
+    case 0: *dev_ptr = ctx->cut_ids; *count = ctx->last_cut; break;
+    case 1: *dev_ptr = ctx->cut_t; *count = ctx->last_cut; break;
+    case 2: *dev_ptr = ctx->T_final; *count = (int64_t)ctx->last_pix; break;
+    case 3: *dev_ptr = ctx->n_last; *count = (int64_t)ctx->last_pix; break;
+    case 4: *dev_ptr = ctx->n_blend; *count = (int64_t)ctx->last_pix; break;
+    case 5: *dev_ptr = ctx->sgrad; *count = (int64_t)ctx->last_cut * 12; break;
+    case 6: *dev_ptr = ctx->cut_base; *count = ctx->last_nv + 1; break;
+    default: return fail(ctx, HGS_ERR_INVALID_ARG, "unknown buffer");
+    }
+    return HGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hgs {
+
+// Conventions of the splatting stage (3D Gaussian splatting defaults that the
+// paper's renderer builds on; the 0.99 clamp is the one of Sec. 7.3).
+constexpr float kAlphaMin = 1.0f / 255.0f;  // a splat with alpha below this is skipped
+constexpr float kTMin = 1e-4f;              // stop before transmittance would fall below
+constexpr float kAlphaMax = 0.99f;          // alpha clamp
+constexpr double kDilation = 0.3;           // EWA screen-space low-pass variance (px^2)
+constexpr int kMaxViews = 1024;
+
+constexpr uint32_t kRootParent = 0x7FFFFFFFu;
+constexpr uint32_t kLeafBit = 0x80000000u;
+
+struct DevView {
+    float R[9];
+    float eye[3];
+    float fx, fy, cx, cy;
+    int32_t W, H;
+    float z_near, tau;
+    int32_t tiles_x, tiles_y;
+    uint32_t tile_base;  // first global tile id of this view
+    uint32_t pix_base;   // first pixel of this view in per-pixel state arrays
+    float *out_rgb;      // [H][W][3]
+    const float *dL;     // [H][W][3], backward only
+};
+
+struct DevHier {
+    int64_t n;
+    const uint32_t *pinfo;  // parent index | leaf bit
+    const float *box;       // [6][n]: bmin x y z, bmax x y z
+    const int32_t *child_count;
+    const float *mean, *scale, *rot, *opacity, *sh;
+};
+
+// Blend record of one splat (64 bytes).  The mean is kept as an integer pixel
+// anchor plus an FP32 fraction.  The conic (inverse dilated 2D covariance)
+// is stored through its eigen-axes scaled so that, for a pixel offset d from
+// the mean, u_i = w_i . d and G = exp2(-(u_1^2 + u_2^2)) = exp(-d^T conic d / 2):
+// a sum of squares, which FP32 evaluates without the cancellation the
+// expanded quadratic form suffers for thin splats far from their centre.
+struct __align__(16) SplatRec {
+    int32_t ax, ay;
+    float fx, fy;          // mean - anchor
+    float w1x, w1y, w2x, w2y;
+    float An, Ap;          // kappa |o_n|, kappa |o_p|
+    float t, invK;
+    float r, g, b;
+    uint32_t node;
+};
+// 1/2 log2(e): exp(-q/2) = exp2(-kHalfLog2e q)
+constexpr double kHalfLog2e = 0.72134752044448170368;
+static_assert(sizeof(SplatRec) == 64, "record layout");
+
+// Device-side counters of one render.
+struct Counters {
+    uint32_t cut_total;
+    uint32_t vis_total;
+    uint32_t pair_total;
+    uint32_t overflow;
+    unsigned long long evaluated;
+    unsigned long long blended;
+    unsigned long long evaluated_t;      // evaluated pairs of interpolated splats (t > 0)
+    unsigned long long bwd_evaluated;    // backward: pairs re-evaluated
+    unsigned long long bwd_evaluated_t;
+    unsigned long long bwd_contrib;      // backward: pairs that contributed
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers queue work on `st`; sizes that only the device knows are read
+// from device memory (`*_dev`) and clamped to the host-side capacity.
+
+// cut: per-node predicate over all views, bitmask + per-block counts
+constexpr int kCutThreads = 256;
+constexpr int kCutItems = 4;
+constexpr int kCutBlock = kCutThreads * kCutItems;  // nodes per block
+void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *masks, uint32_t *block_counts,
+                      int nblocks, hipStream_t st);
+void launch_cut_emit(const DevHier &h, const DevView *views, int nv, const uint64_t *masks,
+                     const uint32_t *block_offsets, int nblocks, int32_t *out_ids, float *out_t, uint32_t cap,
+                     hipStream_t st);
+void launch_cut_finish(const uint32_t *block_offsets, const uint32_t *block_counts, int nblocks, int nv,
+                       uint32_t *cut_base, Counters *ctr, hipStream_t st);
+
+// exclusive scan of uint32 (optionally in[idx[i]]); writes *total
+void launch_scan(const uint32_t *in, const uint32_t *idx, uint32_t n_host, const uint32_t *n_dev, uint32_t *out,
+                 uint32_t *total, uint32_t *partial, hipStream_t st);
+constexpr int kScanBlocks = 512;
+
+// stable LSD radix sort of (uint32 key, uint32 value) over bit range [0, bits)
+struct SortScratch {
+    uint32_t *k2, *v2;   // ping-pong buffers (capacity elements)
+    uint32_t *hist;      // 256 * kSortBlocksMax
+    uint32_t *hist_scan; // 256 * kSortBlocksMax
+    uint32_t *partial;   // kScanBlocks
+    uint32_t *total;     // 1
+};
+constexpr int kSortBlocksMax = 1024;
+// Returns true when the sorted result is in (s.k2, s.v2) (odd pass count).
+bool launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t cap, const uint32_t *n_dev, int bits,
+                       const SortScratch &s, hipStream_t st);
+
+// preprocess: interpolation, EWA projection, SH colour, footprint, per cut entry
+void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
+                       const int32_t *cut_ids, const float *cut_t, const uint32_t *cut_total, uint32_t cap,
+                       SplatRec *recs, uint32_t *depth_key, uint2 *rect, uint32_t *ntiles, uint64_t *vis_mask,
+                       uint32_t *vis_block_counts, int tile_w, int tile_h, hipStream_t st);
+void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
+                            uint32_t cap, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals,
+                            hipStream_t st);
+void launch_duplicate(const uint2 *rect, const DevView *views, int nv, const uint32_t *cut_base,
+                      const uint32_t *sorted_vals, const uint32_t *pair_offsets, const uint32_t *vis_total,
+                      uint32_t vis_cap, const uint32_t *pair_total, uint32_t pair_cap, uint32_t *pair_keys,
+                      uint32_t *pair_vals, Counters *ctr, hipStream_t st);
+void launch_ranges(const uint32_t *pair_keys, const uint32_t *pair_total, uint32_t pair_cap, uint2 *ranges,
+                   hipStream_t st);
+void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
+
+// blend (tile_w x tile_h pixels per workgroup, `batch` records staged per step)
+bool blend_supported(int tw, int th, int batch);
+void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges, const uint32_t *pair_vals,
+                  const SplatRec *recs, float *T_final, uint32_t *n_last, uint32_t *n_blend, Counters *ctr, int tw,
+                  int th, int batch, hipStream_t st);
+
+// backward
+void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges,
+                           const uint32_t *pair_vals, const SplatRec *recs, const float *T_final,
+                           const uint32_t *n_last, double *sgrad, Counters *ctr, int tw, int th, int batch,
+                           hipStream_t st);
+void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
+                                const int32_t *cut_ids, const float *cut_t, const uint32_t *cut_total, uint32_t cap,
+                                const uint32_t *ntiles, const double *sgrad, float *g_mean, float *g_scale,
+                                float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st);
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+}  // namespace hgs

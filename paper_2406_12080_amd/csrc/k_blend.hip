@@ -1,0 +1,413 @@
+// Per-tile alpha blending (forward) and its backward.
+//
+// One workgroup per tile of TW x TH pixels; each 64-lane wave owns an 8x8
+// sub-tile, one lane per pixel.  The tile's splats (sorted front to back)
+// are staged through LDS in batches of BATCH records; every lane walks the
+// batch in order.  Per pixel and splat (Sec. 3 Eq. (alpha) with the
+// projected Gaussian G; Eq. (alphap) generalised to K children, Sec. 5.2;
+// the weight t of Eq. (t_interp) as the parent's weight; clamp of Sec. 7.3):
+//   G     = exp(-q/2),  q = d^T conic d  (d = pixel centre - mean), evaluated
+//           as exp2(-(u1^2 + u2^2)) with u_i = w_i . d on the conic's scaled
+//           eigen-axes (see SplatRec)
+//   a_n   = min(0.99, A_n G),  a_p = min(0.99, A_p G)
+//   alpha = (1 - t) a_n + t (1 - (1 - a_p)^(1/K))     (= a_n when t = 0)
+//   skip when alpha < 1/255; stop before T (1 - alpha) < 1e-4;
+//   C += c alpha T;  T *= 1 - alpha.
+// The backward walks each tile back to front from the final transmittance
+// and the index of the last contributor of each pixel, recovering the
+// transmittance in front of every splat by division (no per-pixel lists),
+// reduces each splat's gradient over the wave and the workgroup, and adds it
+// once per tile to the splat's screen-space gradient.
+#include "hgs_internal.h"
+
+namespace hgs {
+
+namespace {
+
+struct AlphaEval {
+    float G, an, ap, apr, alpha, u1, u2;
+    bool cn, cp;
+};
+
+// Staged splat, per 8x8 block of the tile: c = w . (block corner + 1/2 - mean)
+// in FP64, so that a lane only adds w . (its offset inside the block): the
+// result depends on the pixel alone, not on the tile size.
+__device__ __forceinline__ void block_offsets(const SplatRec &r, int bx, int by, float &c1, float &c2, float &dx0,
+                                              float &dy0)
+{
+#pragma clang fp contract(off)
+    const double dx = ((double)(bx - r.ax) + 0.5) - (double)r.fx;
+    const double dy = ((double)(by - r.ay) + 0.5) - (double)r.fy;
+    c1 = (float)(dx * (double)r.w1x + dy * (double)r.w1y);
+    c2 = (float)(dx * (double)r.w2x + dy * (double)r.w2y);
+    dx0 = (float)dx;
+    dy0 = (float)dy;
+}
+
+// Identical instruction sequence in forward and backward (explicit FMAs, no
+// other contraction), so that the backward reproduces the forward's
+// decisions bit for bit.
+__device__ __forceinline__ void eval_alpha(const float4 &W, const float4 &O, float2 c, float lx, float ly,
+                                           AlphaEval &e)
+{
+#pragma clang fp contract(off)
+    e.u1 = fmaf(ly, W.y, fmaf(lx, W.x, c.x));
+    e.u2 = fmaf(ly, W.w, fmaf(lx, W.z, c.y));
+    const float s = fmaf(e.u1, e.u1, e.u2 * e.u2);
+    e.G = __builtin_amdgcn_exp2f(-s);
+    const float an = O.x * e.G;
+    e.cn = an > kAlphaMax;
+    e.an = e.cn ? kAlphaMax : an;
+    e.alpha = e.an;
+    e.ap = 0.0f;
+    e.apr = 0.0f;
+    e.cp = false;
+    if (O.z > 0.0f) {
+        const float ap = O.y * e.G;
+        e.cp = ap > kAlphaMax;
+        e.ap = e.cp ? kAlphaMax : ap;
+        e.apr = 1.0f - __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(1.0f - e.ap) * O.w);
+        e.alpha = (1.0f - O.z) * e.an + O.z * e.apr;
+    }
+}
+
+__device__ __forceinline__ int view_of_tile(const DevView *views, int nv, uint32_t tile)
+{
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_base <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int TW, int TH, int BATCH>
+__global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ views, int nv,
+                                                  const uint2 *__restrict__ ranges,
+                                                  const uint32_t *__restrict__ pair_vals,
+                                                  const SplatRec *__restrict__ recs, float *__restrict__ T_final,
+                                                  uint32_t *__restrict__ n_last, uint32_t *__restrict__ n_blend,
+                                                  Counters *__restrict__ ctr)
+{
+    constexpr int NT = TW * TH;
+    constexpr int SX = TW / 8;
+    constexpr int NB = (TW / 8) * (TH / 8);
+    __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
+    __shared__ float2 s_u[NB][BATCH];
+    const uint32_t tile = blockIdx.x;
+    const int vi = view_of_tile(views, nv, tile);
+    const DevView &V = views[vi];
+    const uint32_t lt = tile - V.tile_base;
+    const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ox = tx * TW, oy = ty * TH;
+    const int px = ox + (w % SX) * 8 + (lane & 7), py = oy + (w / SX) * 8 + (lane >> 3);
+    const bool inside = px < V.W && py < V.H;
+    const float lx = (float)(lane & 7), ly = (float)(lane >> 3);
+    const uint2 rg = ranges[tile];
+
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    uint32_t last = 0, nb = 0, ne = 0, net = 0;
+    bool done = !inside;
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
+        if (__syncthreads_count(!done) == 0) break;
+        for (int j = threadIdx.x; j < BATCH; j += NT) {
+            const uint32_t idx = b0 + j;
+            if (idx < rg.y) {
+                const SplatRec r = recs[pair_vals[idx]];
+                s_w[j] = make_float4(r.w1x, r.w1y, r.w2x, r.w2y);
+                s_o[j] = make_float4(r.An, r.Ap, r.t, r.invK);
+                s_c[j] = make_float4(r.r, r.g, r.b, 0.0f);
+#pragma unroll
+                for (int bk = 0; bk < NB; ++bk) {
+                    float c1, c2, d0, d1;
+                    block_offsets(r, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
+                    s_u[bk][j] = make_float2(c1, c2);
+                }
+            }
+        }
+        __syncthreads();
+        if (!done) {
+            const int cnt = (int)min((uint32_t)BATCH, rg.y - b0);
+            for (int j = 0; j < cnt; ++j) {
+                const float4 Wv = s_w[j], Ov = s_o[j];
+                AlphaEval e;
+                eval_alpha(Wv, Ov, s_u[w][j], lx, ly, e);
+                ++ne;
+                net += Ov.z > 0.0f;
+                if (e.alpha < kAlphaMin) continue;
+                const float Tn = T * (1.0f - e.alpha);
+                if (Tn < kTMin) {
+                    done = true;
+                    break;
+                }
+                const float4 Cc = s_c[j];
+                const float wgt = e.alpha * T;
+                C0 += Cc.x * wgt;
+                C1 += Cc.y * wgt;
+                C2 += Cc.z * wgt;
+                T = Tn;
+                last = b0 - rg.x + (uint32_t)j + 1u;
+                ++nb;
+            }
+        }
+    }
+    if (inside) {
+        const size_t p = (size_t)py * V.W + px;
+        float *o = V.out_rgb + 3 * p;
+        o[0] = C0;
+        o[1] = C1;
+        o[2] = C2;
+        const size_t g = (size_t)V.pix_base + p;
+        T_final[g] = T;
+        n_last[g] = last;
+        n_blend[g] = nb;
+    }
+    unsigned long long e64 = ne, b64 = nb, t64 = net;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        e64 += __shfl_xor(e64, d, 64);
+        b64 += __shfl_xor(b64, d, 64);
+        t64 += __shfl_xor(t64, d, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&ctr->evaluated, e64);
+        atomicAdd(&ctr->blended, b64);
+        atomicAdd(&ctr->evaluated_t, t64);
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float x)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+constexpr int kG = 12;  // floats per splat in the screen-space gradient
+
+template <int TW, int TH, int BATCH>
+__global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict__ views, int nv,
+                                                      const uint2 *__restrict__ ranges,
+                                                      const uint32_t *__restrict__ pair_vals,
+                                                      const SplatRec *__restrict__ recs,
+                                                      const float *__restrict__ T_final,
+                                                      const uint32_t *__restrict__ n_last,
+                                                      double *__restrict__ sgrad, Counters *__restrict__ ctr)
+{
+    constexpr int NT = TW * TH;
+    constexpr int SX = TW / 8;
+    constexpr int NB = (TW / 8) * (TH / 8);
+    constexpr float kInvHL2e = (float)(1.0 / kHalfLog2e);
+    __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
+    __shared__ float4 s_u[NB][BATCH];  // c1, c2, dx0, dy0
+    __shared__ uint32_t s_id[BATCH];
+    __shared__ double s_g[BATCH][kG];
+    __shared__ uint32_t s_max;
+    const uint32_t tile = blockIdx.x;
+    const int vi = view_of_tile(views, nv, tile);
+    const DevView &V = views[vi];
+    const uint32_t lt = tile - V.tile_base;
+    const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ox = tx * TW, oy = ty * TH;
+    const int px = ox + (w % SX) * 8 + (lane & 7), py = oy + (w / SX) * 8 + (lane >> 3);
+    const bool inside = px < V.W && py < V.H;
+    const float lx = (float)(lane & 7), ly = (float)(lane >> 3);
+    const uint2 rg = ranges[tile];
+
+    float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+    uint32_t last = 0;
+    if (inside) {
+        const size_t p = (size_t)py * V.W + px;
+        const size_t g = (size_t)V.pix_base + p;
+        T = T_final[g];
+        last = n_last[g];
+        g0 = V.dL[3 * p];
+        g1 = V.dL[3 * p + 1];
+        g2 = V.dL[3 * p + 2];
+    }
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    uint32_t wm = last;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) wm = max(wm, (uint32_t)__shfl_xor((int)wm, d, 64));
+    if (lane == 0) atomicMax(&s_max, wm);
+    __syncthreads();
+    const uint32_t end = rg.x + s_max;
+    float R0 = 0.0f, R1 = 0.0f, R2 = 0.0f;  // colour composited behind the current splat
+    uint32_t ne = 0, net = 0, nc = 0;
+
+    for (uint32_t hi = end; hi > rg.x;) {
+        const uint32_t lo = hi - rg.x > (uint32_t)BATCH ? hi - BATCH : rg.x;
+        const int cnt = (int)(hi - lo);
+        for (int j = threadIdx.x; j < cnt; j += NT) {
+            const uint32_t sidx = pair_vals[lo + j];
+            const SplatRec r = recs[sidx];
+            s_id[j] = sidx;
+            s_w[j] = make_float4(r.w1x, r.w1y, r.w2x, r.w2y);
+            s_o[j] = make_float4(r.An, r.Ap, r.t, r.invK);
+            s_c[j] = make_float4(r.r, r.g, r.b, 0.0f);
+#pragma unroll
+            for (int bk = 0; bk < NB; ++bk) {
+                float c1, c2, d0, d1;
+                block_offsets(r, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
+                s_u[bk][j] = make_float4(c1, c2, d0, d1);
+            }
+#pragma unroll
+            for (int q = 0; q < kG; ++q) s_g[j][q] = 0.0;
+        }
+        __syncthreads();
+        for (int j = cnt - 1; j >= 0; --j) {
+            const uint32_t li = lo - rg.x + (uint32_t)j;
+            const float4 Wv = s_w[j], Ov = s_o[j];
+            const float4 U = s_u[w][j];
+            AlphaEval e;
+            bool contrib = false;
+            if (li < last) {
+                eval_alpha(Wv, Ov, make_float2(U.x, U.y), lx, ly, e);
+                contrib = e.alpha >= kAlphaMin;
+                ++ne;
+                net += Ov.z > 0.0f;
+                nc += contrib;
+            }
+            if (__ballot(contrib) == 0ull) continue;
+            float v[11];
+#pragma unroll
+            for (int q = 0; q < 11; ++q) v[q] = 0.0f;
+            if (contrib) {
+                const float4 Cc = s_c[j];
+                const float a = e.alpha;
+                T = T / (1.0f - a);
+                const float dal = T * ((Cc.x - R0) * g0 + (Cc.y - R1) * g1 + (Cc.z - R2) * g2);
+                const float aT = a * T;
+                v[7] = aT * g0;
+                v[8] = aT * g1;
+                v[9] = aT * g2;
+                R0 = a * Cc.x + (1.0f - a) * R0;
+                R1 = a * Cc.y + (1.0f - a) * R1;
+                R2 = a * Cc.z + (1.0f - a) * R2;
+                float dan = dal, dap = 0.0f;
+                if (Ov.z > 0.0f) {
+                    dan = (1.0f - Ov.z) * dal;
+                    const float dapr = Ov.z * dal;
+                    v[10] = (e.apr - e.an) * dal;
+                    dap = dapr * Ov.w *
+                          __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(1.0f - e.ap) * (Ov.w - 1.0f));
+                }
+                float dG = 0.0f;
+                if (!e.cn) {
+                    v[5] = dan * e.G;
+                    dG += dan * Ov.x;
+                }
+                if (Ov.z > 0.0f && !e.cp) {
+                    v[6] = dap * e.G;
+                    dG += dap * Ov.y;
+                }
+                // G = exp(-q/2), q = d^T conic d, d = pixel - mean
+                const float dq = -0.5f * e.G * dG;
+                const float dx = U.z + lx, dy = U.w + ly;
+                v[2] = dq * dx * dx;
+                v[3] = 2.0f * dq * dx * dy;
+                v[4] = dq * dy * dy;
+                // conic d = (u1 w1 + u2 w2) / kHalfLog2e; dq/dmean = -2 conic d
+                const float k2 = -2.0f * kInvHL2e * dq;
+                v[0] = k2 * (e.u1 * Wv.x + e.u2 * Wv.z);
+                v[1] = k2 * (e.u1 * Wv.y + e.u2 * Wv.w);
+            }
+#pragma unroll
+            for (int q = 0; q < 11; ++q) {
+                const float sm = wave_sum(v[q]);
+                if (lane == 0 && sm != 0.0f) atomicAdd(&s_g[j][q], (double)sm);
+            }
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < cnt * 11; idx += NT) {
+            const int j = idx / 11, q = idx % 11;
+            const double sm = s_g[j][q];
+            if (sm != 0.0) unsafeAtomicAdd(&sgrad[(size_t)s_id[j] * kG + q], sm);
+        }
+        __syncthreads();
+        hi = lo;
+    }
+    unsigned long long e64 = ne, t64 = net, c64 = nc;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        e64 += __shfl_xor(e64, d, 64);
+        t64 += __shfl_xor(t64, d, 64);
+        c64 += __shfl_xor(c64, d, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&ctr->bwd_evaluated, e64);
+        atomicAdd(&ctr->bwd_evaluated_t, t64);
+        atomicAdd(&ctr->bwd_contrib, c64);
+    }
+}
+
+template <int TW, int TH, int BATCH>
+void launch_blend_t(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges, const uint32_t *pair_vals,
+                    const SplatRec *recs, float *T_final, uint32_t *n_last, uint32_t *n_blend, Counters *ctr,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL((k_blend<TW, TH, BATCH>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, ranges, pair_vals,
+                       recs, T_final, n_last, n_blend, ctr);
+}
+
+template <int TW, int TH, int BATCH>
+void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges,
+                        const uint32_t *pair_vals, const SplatRec *recs, const float *T_final,
+                        const uint32_t *n_last, double *sgrad, Counters *ctr, hipStream_t st)
+{
+    // the backward stages at most 256 splats per step (its LDS holds FP64 partial sums)
+    constexpr int B = BATCH < 256 ? BATCH : 256;
+    hipLaunchKernelGGL((k_blend_bwd<TW, TH, B>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, ranges,
+                       pair_vals, recs, T_final, n_last, sgrad, ctr);
+}
+
+}  // namespace
+
+// Supported (tile, batch) combinations; batch 0 means one record per thread.
+#define HGS_BLEND_CASES(X)                                                                                            \
+    X(8, 8, 64) X(8, 8, 128) X(8, 8, 256) X(16, 8, 128) X(16, 8, 256) X(16, 16, 256) X(16, 16, 512) X(32, 16, 512)
+
+bool blend_supported(int tw, int th, int batch)
+{
+    if (batch == 0) batch = tw * th;
+#define X(a, b, c) \
+    if (tw == a && th == b && batch == c) return true;
+    HGS_BLEND_CASES(X)
+#undef X
+    return false;
+}
+
+void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges, const uint32_t *pair_vals,
+                  const SplatRec *recs, float *T_final, uint32_t *n_last, uint32_t *n_blend, Counters *ctr, int tw,
+                  int th, int batch, hipStream_t st)
+{
+    if (batch == 0) batch = tw * th;
+    if (!n_tiles) return;
+#define X(a, b, c)                                                                                           \
+    if (tw == a && th == b && batch == c)                                                                    \
+        return launch_blend_t<a, b, c>(views, nv, n_tiles, ranges, pair_vals, recs, T_final, n_last, n_blend, \
+                                       ctr, st);
+    HGS_BLEND_CASES(X)
+#undef X
+}
+
+void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges,
+                           const uint32_t *pair_vals, const SplatRec *recs, const float *T_final,
+                           const uint32_t *n_last, double *sgrad, Counters *ctr, int tw, int th, int batch,
+                           hipStream_t st)
+{
+    if (batch == 0) batch = tw * th;
+    if (!n_tiles) return;
+#define X(a, b, c)                                                                                                 \
+    if (tw == a && th == b && batch == c)                                                                          \
+        return launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, ranges, pair_vals, recs, T_final, n_last, sgrad, ctr, \
+                                           st);
+    HGS_BLEND_CASES(X)
+#undef X
+}
+
+}  // namespace hgs

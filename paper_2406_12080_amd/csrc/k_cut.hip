@@ -1,0 +1,187 @@
+// Level-of-detail cut (Sec. 4.2, "Hierarchy Cut Selection and Level
+// Switching") and the interpolation weight of Eq. (t_interp).
+//
+// A node n meets the target granularity tau when it is a leaf or when the
+// projected size of the largest dimension of its leaf bounding box,
+// eps(n) = f L(n) / d(n) (d = distance from the eye to the box), is at most
+// tau.  The cut is every node that meets it while its parent does not: a
+// constant-time test per node, run here as a coalesced sweep over the
+// structure-of-arrays boxes with one thread per node and every view handled
+// by the thread that holds the node (the node's box is read once per batch
+// of views).  Selected nodes are compacted in ascending id order with a
+// 64-lane ballot bitmask per wave, a per-block count, one exclusive scan over
+// (view, block), and an emit pass that writes ids and weights.
+//
+// eps and t are evaluated in FP64 with contraction disabled, from the FP32
+// stored boxes, so that the selection does not depend on FP32 rounding.
+#include "hgs_internal.h"
+
+namespace hgs {
+
+__device__ __forceinline__ double granularity(const float b[6], const DevView &V)
+{
+#pragma clang fp contract(off)
+    double L = 0.0;
+    double dd[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double lo = b[k], hi = b[3 + k];
+        const double ext = hi - lo;
+        if (ext > L) L = ext;
+        const double e = V.eye[k];
+        const double c = e < lo ? lo : (e > hi ? hi : e);
+        dd[k] = e - c;
+    }
+    const double d2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2];
+    const double d = sqrt(d2);
+    if (d == 0.0) return __builtin_inf();
+    const double f = V.fx > V.fy ? (double)V.fx : (double)V.fy;
+    return (f * L) / d;
+}
+
+__device__ __forceinline__ void load_box(const DevHier &h, int64_t i, float b[6])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) b[k] = h.box[k * h.n + i];
+}
+
+__global__ __launch_bounds__(kCutThreads) void k_cut_flags(DevHier h, const DevView *__restrict__ views, int nv,
+                                                           uint64_t *__restrict__ masks,
+                                                           uint32_t *__restrict__ block_counts, int nblocks)
+{
+    __shared__ uint32_t s_cnt[kMaxViews];
+    for (int v = threadIdx.x; v < nv; v += kCutThreads) s_cnt[v] = 0;
+    __syncthreads();
+    const int64_t n = h.n;
+    const int64_t words = (n + 63) >> 6;
+    const int lane = threadIdx.x & 63;
+#pragma unroll 1
+    for (int it = 0; it < kCutItems; ++it) {
+        const int64_t i0 = (int64_t)blockIdx.x * kCutBlock + it * kCutThreads + (threadIdx.x & ~63);
+        const int64_t i = i0 + lane;
+        const bool valid = i < n;
+        float b[6] = {0, 0, 0, 0, 0, 0}, pb[6] = {0, 0, 0, 0, 0, 0};
+        uint32_t pi = kRootParent;
+        if (valid) {
+            load_box(h, i, b);
+            pi = h.pinfo[i];
+        }
+        const bool leaf = (pi & kLeafBit) != 0;
+        const uint32_t par = pi & ~kLeafBit;
+        const bool root = par == kRootParent;
+        if (valid && !root) load_box(h, par, pb);
+#pragma unroll 1
+        for (int v = 0; v < nv; ++v) {
+            const DevView &V = views[v];
+            const double tau = V.tau;
+            bool in = false;
+            if (valid) {
+                const bool Fn = leaf || granularity(b, V) <= tau;
+                if (Fn) in = root || !(granularity(pb, V) <= tau);
+            }
+            const uint64_t m = __ballot(in);
+            if (lane == 0 && i0 < n) {
+                masks[(int64_t)v * words + (i0 >> 6)] = m;
+                if (m) atomicAdd(&s_cnt[v], (uint32_t)__popcll(m));
+            }
+        }
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < nv; v += kCutThreads) block_counts[(int64_t)v * nblocks + blockIdx.x] = s_cnt[v];
+}
+
+__device__ __forceinline__ float cut_weight(const DevHier &h, const DevView &V, int64_t i)
+{
+#pragma clang fp contract(off)
+    const uint32_t par = h.pinfo[i] & ~kLeafBit;
+    if (par == kRootParent) return 0.0f;
+    float b[6], pb[6];
+    load_box(h, i, b);
+    load_box(h, par, pb);
+    const double en = granularity(b, V);
+    const double ep = granularity(pb, V);
+    if (__builtin_isinf(ep) || !(ep > en)) return 0.0f;
+    double t = ((double)V.tau - en) / (ep - en);
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    return (float)t;
+}
+
+__global__ __launch_bounds__(kCutThreads) void k_cut_emit(DevHier h, const DevView *__restrict__ views,
+                                                          const uint64_t *__restrict__ masks,
+                                                          const uint32_t *__restrict__ block_offsets, int nblocks,
+                                                          int32_t *__restrict__ out_ids, float *__restrict__ out_t,
+                                                          uint32_t cap)
+{
+    constexpr int W = kCutBlock / 64;
+    __shared__ uint64_t s_word[W];
+    __shared__ uint32_t s_pre[W];
+    __shared__ int s_any;
+    const int v = blockIdx.y;
+    const int64_t n = h.n;
+    const int64_t words = (n + 63) >> 6;
+    const int64_t w0 = (int64_t)blockIdx.x * W;
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    if (threadIdx.x < W) {
+        const int64_t w = w0 + threadIdx.x;
+        const uint64_t m = w < words ? masks[(int64_t)v * words + w] : 0ull;
+        s_word[threadIdx.x] = m;
+        if (m) s_any = 1;
+    }
+    __syncthreads();
+    if (!s_any) return;
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int k = 0; k < W; ++k) {
+            s_pre[k] = acc;
+            acc += (uint32_t)__popcll(s_word[k]);
+        }
+    }
+    __syncthreads();
+    const uint32_t off = block_offsets[(int64_t)v * nblocks + blockIdx.x];
+    const DevView &V = views[v];
+#pragma unroll 1
+    for (int it = 0; it < kCutItems; ++it) {
+        const int local = it * kCutThreads + threadIdx.x;
+        const int w = local >> 6, bit = local & 63;
+        const uint64_t m = s_word[w];
+        if (!((m >> bit) & 1ull)) continue;
+        const uint32_t pos = off + s_pre[w] + (uint32_t)__popcll(m & ((1ull << bit) - 1ull));
+        if (pos >= cap) continue;
+        const int64_t i = (int64_t)blockIdx.x * kCutBlock + local;
+        out_ids[pos] = (int32_t)i;
+        if (out_t) out_t[pos] = cut_weight(h, V, i);
+    }
+}
+
+__global__ void k_cut_finish(const uint32_t *__restrict__ block_offsets, int nblocks, int nv,
+                             uint32_t *__restrict__ cut_base, const uint32_t *__restrict__ total)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < nv) cut_base[v] = block_offsets[(int64_t)v * nblocks];
+    if (v == nv) cut_base[nv] = *total;
+}
+
+void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *masks, uint32_t *block_counts,
+                      int nblocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cut_flags, dim3(nblocks), dim3(kCutThreads), 0, st, h, views, nv, masks, block_counts,
+                       nblocks);
+}
+
+void launch_cut_emit(const DevHier &h, const DevView *views, int nv, const uint64_t *masks,
+                     const uint32_t *block_offsets, int nblocks, int32_t *out_ids, float *out_t, uint32_t cap,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cut_emit, dim3(nblocks, nv), dim3(kCutThreads), 0, st, h, views, masks, block_offsets,
+                       nblocks, out_ids, out_t, cap);
+}
+
+void launch_cut_finish(const uint32_t *block_offsets, const uint32_t *, int nblocks, int nv, uint32_t *cut_base,
+                       Counters *ctr, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cut_finish, dim3((nv + 1 + 255) / 256), dim3(256), 0, st, block_offsets, nblocks, nv,
+                       cut_base, &ctr->cut_total);
+}
+
+}  // namespace hgs

@@ -1,0 +1,434 @@
+// Preprocess (one thread per cut entry, FP64): interpolation, EWA projection,
+// SH colour, footprint, tile rectangle; then visibility compaction, tile
+// counts, pair emission and per-tile ranges.  Also the preprocess backward.
+#include "hgs_internal.h"
+#include "project.h"
+
+namespace hgs {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr double kAlphaMinD = 1.0 / 255.0;
+
+__device__ __forceinline__ int view_of(const uint32_t *cut_base, int nv, uint32_t k)
+{
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cut_base[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kT) void k_preprocess(DevHier h, const DevView *__restrict__ views, int nv,
+                                                   const uint32_t *__restrict__ cut_base,
+                                                   const int32_t *__restrict__ cut_ids,
+                                                   const float *__restrict__ cut_t,
+                                                   const uint32_t *__restrict__ cut_total, uint32_t cap,
+                                                   SplatRec *__restrict__ recs, uint32_t *__restrict__ depth_key,
+                                                   uint2 *__restrict__ rect, uint32_t *__restrict__ ntiles,
+                                                   uint64_t *__restrict__ vis_mask,
+                                                   uint32_t *__restrict__ vis_block_counts, int tile_w, int tile_h)
+{
+    __shared__ uint32_t s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    const uint32_t total = min(*cut_total, cap);
+    const uint32_t k = blockIdx.x * kT + threadIdx.x;
+    bool vis = false;
+    uint32_t nt = 0;
+    if (k < total) {
+        const int vi = view_of(cut_base, nv, k);
+        const DevView &V = views[vi];
+        Proj P;
+        project_splat(h, V, (uint32_t)cut_ids[k], cut_t[k], P, true);
+        if (P.ok) {
+            // footprint: alpha <= min(0.99, A G) with A = kappa((1-t)o_n + t o_p);
+            // alpha_min can only be reached inside d^T Sigma2'^-1 d <= 2 ln(A/alpha_min)
+            const double A = P.kappa * ((1.0 - P.t) * P.o_n + P.t * P.o_p);
+            if (A >= kAlphaMinD && fabs(P.u) < 1e9 && fabs(P.v) < 1e9) {
+                const double r2 = 2.0 * log(A / kAlphaMinD);
+                const double hx = sqrt(r2 * (P.a + kDilation)), hy = sqrt(r2 * (P.c + kDilation));
+                double x0 = ceil(P.u - hx - 0.5), x1 = floor(P.u + hx - 0.5);
+                double y0 = ceil(P.v - hy - 0.5), y1 = floor(P.v + hy - 0.5);
+                x0 = fmax(x0, 0.0);
+                y0 = fmax(y0, 0.0);
+                x1 = fmin(x1, (double)(V.W - 1));
+                y1 = fmin(y1, (double)(V.H - 1));
+                if (x1 >= x0 && y1 >= y0) {
+                    vis = true;
+                    const uint32_t tx0 = (uint32_t)x0 / tile_w, tx1 = (uint32_t)x1 / tile_w;
+                    const uint32_t ty0 = (uint32_t)y0 / tile_h, ty1 = (uint32_t)y1 / tile_h;
+                    nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+                    rect[k] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+                    SplatRec r;
+                    const double fu = floor(P.u), fv = floor(P.v);
+                    r.ax = (int32_t)fu;
+                    r.ay = (int32_t)fv;
+                    r.fx = (float)(P.u - fu);
+                    r.fy = (float)(P.v - fv);
+                    // eigen-axes of the conic [[ca, cb], [cb, cc]]
+                    const double ca = P.conic[0], cb = P.conic[1], cc = P.conic[2];
+                    const double th = 0.5 * atan2(2.0 * cb, ca - cc);
+                    const double cs = cos(th), sn = sin(th);
+                    const double l1 = ca * cs * cs + 2.0 * cb * sn * cs + cc * sn * sn;
+                    const double l2 = ca * sn * sn - 2.0 * cb * sn * cs + cc * cs * cs;
+                    const double s1 = sqrt(fmax(l1, 0.0) * kHalfLog2e), s2 = sqrt(fmax(l2, 0.0) * kHalfLog2e);
+                    r.w1x = (float)(s1 * cs);
+                    r.w1y = (float)(s1 * sn);
+                    r.w2x = (float)(-s2 * sn);
+                    r.w2y = (float)(s2 * cs);
+                    r.An = (float)(P.kappa * P.o_n);
+                    r.Ap = (float)(P.kappa * P.o_p);
+                    r.t = (float)P.t;
+                    r.invK = (float)(1.0 / (double)P.K);
+                    r.r = (float)fmax(P.raw[0], 0.0);
+                    r.g = (float)fmax(P.raw[1], 0.0);
+                    r.b = (float)fmax(P.raw[2], 0.0);
+                    r.node = P.node;
+                    recs[k] = r;
+                    depth_key[k] = __float_as_uint((float)P.pc[2]);
+                }
+            }
+        }
+        ntiles[k] = nt;
+    }
+    const uint64_t m = __ballot(vis);
+    const uint32_t k0 = blockIdx.x * kT + (threadIdx.x & ~63u);
+    if ((threadIdx.x & 63) == 0) {
+        if (k0 < cap) vis_mask[k0 >> 6] = m;
+        if (m) atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) vis_block_counts[blockIdx.x] = s_cnt;
+}
+
+__global__ __launch_bounds__(kT) void k_compact_visible(const uint64_t *__restrict__ vis_mask,
+                                                        const uint32_t *__restrict__ offsets,
+                                                        const uint32_t *__restrict__ cut_total, uint32_t cap,
+                                                        const uint32_t *__restrict__ depth_key,
+                                                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    const uint32_t total = min(*cut_total, cap);
+    const uint32_t k = blockIdx.x * kT + threadIdx.x;
+    if (blockIdx.x * kT >= total) return;
+    __shared__ uint32_t s_pre[kT / 64];
+    __shared__ uint64_t s_m[kT / 64];
+    if (threadIdx.x < kT / 64) s_m[threadIdx.x] = vis_mask[blockIdx.x * (kT / 64) + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int w = 0; w < kT / 64; ++w) {
+            s_pre[w] = acc;
+            acc += (uint32_t)__popcll(s_m[w]);
+        }
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, bit = threadIdx.x & 63;
+    const uint64_t m = s_m[w];
+    if (k < total && ((m >> bit) & 1ull)) {
+        const uint32_t pos = offsets[blockIdx.x] + s_pre[w] + (uint32_t)__popcll(m & ((1ull << bit) - 1ull));
+        keys[pos] = depth_key[k];
+        vals[pos] = k;
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_duplicate(const uint2 *__restrict__ rect, const DevView *__restrict__ views,
+                                                  int nv, const uint32_t *__restrict__ cut_base,
+                                                  const uint32_t *__restrict__ sorted_vals,
+                                                  const uint32_t *__restrict__ offsets,
+                                                  const uint32_t *__restrict__ vis_total, uint32_t vis_cap,
+                                                  const uint32_t *__restrict__ pair_total, uint32_t pair_cap,
+                                                  uint32_t *__restrict__ pair_keys, uint32_t *__restrict__ pair_vals,
+                                                  Counters *__restrict__ ctr)
+{
+    const uint32_t nvis = min(*vis_total, vis_cap);
+    const uint32_t i = blockIdx.x * kT + threadIdx.x;
+    if (i == 0 && *pair_total > pair_cap) atomicOr(&ctr->overflow, 4u);
+    if (i >= nvis) return;
+    const uint32_t s = sorted_vals[i];
+    const uint2 r = rect[s];
+    const int v = view_of(cut_base, nv, s);
+    const uint32_t base = views[v].tile_base, tx_n = (uint32_t)views[v].tiles_x;
+    const uint32_t tx0 = r.x & 0xFFFFu, tx1 = r.x >> 16, ty0 = r.y & 0xFFFFu, ty1 = r.y >> 16;
+    uint32_t o = offsets[i];
+    for (uint32_t ty = ty0; ty <= ty1; ++ty)
+        for (uint32_t tx = tx0; tx <= tx1; ++tx, ++o) {
+            if (o < pair_cap) {
+                pair_keys[o] = base + ty * tx_n + tx;
+                pair_vals[o] = s;
+            }
+        }
+}
+
+__global__ __launch_bounds__(kT) void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ total,
+                                               uint32_t cap, uint2 *__restrict__ ranges)
+{
+    const uint32_t n = min(*total, cap);
+    const uint32_t i = blockIdx.x * kT + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t t = keys[i];
+    if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
+    if (i == n - 1 || keys[i + 1] != t) ranges[t].y = i + 1;
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// ------------------------------------------------------------------ backward
+__device__ __forceinline__ void add(float *p, double v)
+{
+    if (v != 0.0) unsafeAtomicAdd(p, (float)v);
+}
+
+__global__ __launch_bounds__(kT) void k_preprocess_bwd(DevHier h, const DevView *__restrict__ views, int nv,
+                                                       const uint32_t *__restrict__ cut_base,
+                                                       const int32_t *__restrict__ cut_ids,
+                                                       const float *__restrict__ cut_t,
+                                                       const uint32_t *__restrict__ cut_total, uint32_t cap,
+                                                       const uint32_t *__restrict__ ntiles,
+                                                       const double *__restrict__ sgrad, float *__restrict__ g_mean,
+                                                       float *__restrict__ g_scale, float *__restrict__ g_rot,
+                                                       float *__restrict__ g_op, float *__restrict__ g_sh,
+                                                       float *__restrict__ g_dt)
+{
+    const uint32_t total = min(*cut_total, cap);
+    const uint32_t k = blockIdx.x * kT + threadIdx.x;
+    if (k >= total) return;
+    if (ntiles[k] == 0) {
+        if (g_dt) g_dt[k] = 0.0f;
+        return;
+    }
+    const double *sg = sgrad + (size_t)k * 12;
+    const double du = sg[0], dv = sg[1], gca = sg[2], gcb = sg[3], gcc = sg[4], dAn = sg[5], dAp = sg[6];
+    const double drgb[3] = {sg[7], sg[8], sg[9]};
+    double dt = sg[10];
+    const int vi = view_of(cut_base, nv, k);
+    const DevView &V = views[vi];
+    Proj P;
+    project_splat(h, V, (uint32_t)cut_ids[k], cut_t[k], P, true);
+    if (!P.ok) return;
+    const int64_t n = h.n;
+    const uint32_t node = P.node, par = P.par;
+    const bool node_leaf = (h.pinfo[node] & kLeafBit) != 0;
+    const bool use_par = P.has_par && P.t > 0.0;
+    const double t = P.t, w0 = 1.0 - t;
+
+    // colour: rgb = max(0, raw)
+    double gr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gr[c] = P.raw[c] > 0.0 ? drgb[c] : 0.0;
+    double Y[16], Bw[16];
+    sh_eval(P.dir[0], P.dir[1], P.dir[2], Y);
+#pragma unroll 2
+    for (int kk = 0; kk < 16; ++kk) {
+        Bw[kk] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int row = 3 * kk + c;
+            const double cn = h.sh[row * n + node];
+            const double cp = use_par ? (double)h.sh[row * n + par] : cn;
+            const double sht = w0 * cn + t * cp;
+            const double dsh = gr[c] * Y[kk];
+            Bw[kk] += gr[c] * sht;
+            if (!node_leaf) add(&g_sh[row * n + node], w0 * dsh);
+            if (use_par) {
+                add(&g_sh[row * n + par], t * dsh);
+                dt += dsh * (cp - cn);
+            }
+        }
+    }
+    double ddir[3];
+    sh_grad_dot(P.dir[0], P.dir[1], P.dir[2], Bw, ddir);
+    double dmu[3];
+    {
+        const double dd = P.dir[0] * ddir[0] + P.dir[1] * ddir[1] + P.dir[2] * ddir[2];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) dmu[m] = (ddir[m] - P.dir[m] * dd) / P.rlen;
+    }
+
+    // A_n = kappa o_n, A_p = kappa o_p
+    const double dkappa = dAn * P.o_n + dAp * P.o_p;
+    const double don = dAn * P.kappa, dop = dAp * P.kappa;
+
+    // conic = inverse of Sigma2 + hI, kappa = sqrt(det Sigma2 / det(Sigma2 + hI))
+    const double a = P.a, b = P.b, c = P.c;
+    const double ad = a + kDilation, cd = c + kDilation;
+    const double Dd = P.Dd, D = P.D, iD2 = 1.0 / (Dd * Dd);
+    double da = gca * (-cd * cd * iD2) + gcb * (b * cd * iD2) + gcc * (1.0 / Dd - ad * cd * iD2);
+    double dc = gca * (1.0 / Dd - ad * cd * iD2) + gcb * (b * ad * iD2) + gcc * (-ad * ad * iD2);
+    double db = gca * (2.0 * b * cd * iD2) + gcb * (-1.0 / Dd - 2.0 * b * b * iD2) + gcc * (2.0 * b * ad * iD2);
+    if (D > 0.0 && P.kappa > 0.0) {
+        const double hk = 0.5 * P.kappa * dkappa;
+        da += hk * (c / D - cd / Dd);
+        dc += hk * (a / D - ad / Dd);
+        db += hk * (2.0 * b / Dd - 2.0 * b / D);
+    }
+
+    // Sigma2 = Tm Sigma3 Tm^T
+    const double *T0 = P.Tm, *T1 = P.Tm + 3;
+    const double *S = P.cov3;
+    const double Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
+    double T0S[3], T1S[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        T0S[j] = T0[0] * Sf[j] + T0[1] * Sf[3 + j] + T0[2] * Sf[6 + j];
+        T1S[j] = T1[0] * Sf[j] + T1[1] * Sf[3 + j] + T1[2] * Sf[6 + j];
+    }
+    double dS[9];  // gradient w.r.t. Sigma3 as a general matrix
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dS[3 * i + j] = da * T0[i] * T0[j] + db * T0[i] * T1[j] + dc * T1[i] * T1[j];
+    double dT0[3], dT1[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        dT0[j] = 2.0 * da * T0S[j] + db * T1S[j];
+        dT1[j] = db * T0S[j] + 2.0 * dc * T1S[j];
+    }
+    // Tm = J R: row 0 = J00 R0 + J02 R2, row 1 = J11 R1 + J12 R2
+    double R[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) R[q] = V.R[q];
+    const double dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
+    const double dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
+    const double dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
+    const double dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
+    const double x = P.pc[0], y = P.pc[1], z = P.pc[2];
+    const double iz = 1.0 / z, iz2 = iz * iz, iz3 = iz2 * iz;
+    const double fx = V.fx, fy = V.fy;
+    double dp[3];
+    dp[0] = dJ02 * (-fx * iz2) + du * fx * iz;
+    dp[1] = dJ12 * (-fy * iz2) + dv * fy * iz;
+    dp[2] = dJ00 * (-fx * iz2) + dJ02 * (2.0 * fx * x * iz3) + dJ11 * (-fy * iz2) + dJ12 * (2.0 * fy * y * iz3) -
+            du * fx * x * iz2 - dv * fy * y * iz2;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) dmu[m] += R[m] * dp[0] + R[3 + m] * dp[1] + R[6 + m] * dp[2];
+
+    // Sigma3 = M M^T, M = Rq diag(s)
+    double Rq[9];
+    quat_rot(P.q, Rq);
+    double M[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) M[3 * r + cc] = Rq[3 * r + cc] * P.s[cc];
+    double ds[3] = {0.0, 0.0, 0.0}, dR[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc += (dS[3 * i + q] + dS[3 * q + i]) * M[3 * q + j];
+            ds[j] += acc * Rq[3 * i + j];
+            dR[3 * i + j] = acc * P.s[j];
+        }
+    const double qw = P.q[0], qx = P.q[1], qy = P.q[2], qz = P.q[3];
+    double dq[4];
+    dq[0] = 2.0 * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+    dq[1] = 2.0 * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0 * qx * dR[4] - qw * dR[5] + qz * dR[6] + qw * dR[7] -
+                   2.0 * qx * dR[8]);
+    dq[2] = 2.0 * (-2.0 * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] + qz * dR[7] -
+                   2.0 * qy * dR[8]);
+    dq[3] = 2.0 * (-2.0 * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0 * qz * dR[4] + qy * dR[5] +
+                   qx * dR[6] + qy * dR[7]);
+    const double qd = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
+    double dqr[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dqr[m] = (dq[m] - P.q[m] * qd) / P.qlen;
+
+    // interpolation: node (1 - t), parent t; leaves are frozen
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        if (!node_leaf) {
+            add(&g_mean[m * n + node], w0 * dmu[m]);
+            add(&g_scale[m * n + node], w0 * ds[m]);
+        }
+        if (use_par) {
+            add(&g_mean[m * n + par], t * dmu[m]);
+            add(&g_scale[m * n + par], t * ds[m]);
+            dt += dmu[m] * ((double)h.mean[m * n + par] - (double)h.mean[m * n + node]);
+            dt += ds[m] * ((double)h.scale[m * n + par] - (double)h.scale[m * n + node]);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (!node_leaf) add(&g_rot[m * n + node], w0 * dqr[m]);
+        if (use_par) {
+            add(&g_rot[m * n + par], t * dqr[m]);
+            dt += dqr[m] * ((double)h.rot[m * n + par] - (double)h.rot[m * n + node]);
+        }
+    }
+    // opacity through |o|
+    if (!node_leaf) add(&g_op[node], (P.on_raw > 0.0 ? 1.0 : (P.on_raw < 0.0 ? -1.0 : 0.0)) * don);
+    if (use_par) add(&g_op[par], (P.op_raw > 0.0 ? 1.0 : (P.op_raw < 0.0 ? -1.0 : 0.0)) * dop);
+    if (g_dt) g_dt[k] = use_par ? (float)dt : 0.0f;
+}
+
+}  // namespace
+
+void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
+                       const int32_t *cut_ids, const float *cut_t, const uint32_t *cut_total, uint32_t cap,
+                       SplatRec *recs, uint32_t *depth_key, uint2 *rect, uint32_t *ntiles, uint64_t *vis_mask,
+                       uint32_t *vis_block_counts, int tile_w, int tile_h, hipStream_t st)
+{
+    const uint32_t blocks = (cap + kT - 1) / kT;
+    if (!blocks) return;
+    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(kT), 0, st, h, views, nv, cut_base, cut_ids, cut_t, cut_total,
+                       cap, recs, depth_key, rect, ntiles, vis_mask, vis_block_counts, tile_w, tile_h);
+}
+
+void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
+                            uint32_t cap, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals,
+                            hipStream_t st)
+{
+    const uint32_t blocks = (cap + kT - 1) / kT;
+    if (!blocks) return;
+    hipLaunchKernelGGL(k_compact_visible, dim3(blocks), dim3(kT), 0, st, vis_mask, vis_block_offsets, cut_total, cap,
+                       depth_key, keys, vals);
+}
+
+void launch_duplicate(const uint2 *rect, const DevView *views, int nv, const uint32_t *cut_base,
+                      const uint32_t *sorted_vals, const uint32_t *pair_offsets, const uint32_t *vis_total,
+                      uint32_t vis_cap, const uint32_t *pair_total, uint32_t pair_cap, uint32_t *pair_keys,
+                      uint32_t *pair_vals, Counters *ctr, hipStream_t st)
+{
+    const uint32_t blocks = (vis_cap + kT - 1) / kT;
+    if (!blocks) return;
+    hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(kT), 0, st, rect, views, nv, cut_base, sorted_vals,
+                       pair_offsets, vis_total, vis_cap, pair_total, pair_cap, pair_keys, pair_vals, ctr);
+}
+
+void launch_ranges(const uint32_t *pair_keys, const uint32_t *pair_total, uint32_t pair_cap, uint2 *ranges,
+                   hipStream_t st)
+{
+    const uint32_t blocks = (pair_cap + kT - 1) / kT;
+    if (!blocks) return;
+    hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(kT), 0, st, pair_keys, pair_total, pair_cap, ranges);
+}
+
+void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st)
+{
+    if (!n) return;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, value, n);
+}
+
+void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
+                                const int32_t *cut_ids, const float *cut_t, const uint32_t *cut_total, uint32_t cap,
+                                const uint32_t *ntiles, const double *sgrad, float *g_mean, float *g_scale,
+                                float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st)
+{
+    const uint32_t blocks = (cap + kT - 1) / kT;
+    if (!blocks) return;
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(kT), 0, st, h, views, nv, cut_base, cut_ids, cut_t,
+                       cut_total, cap, ntiles, sgrad, g_mean, g_scale, g_rot, g_opacity, g_sh, g_dt);
+}
+
+}  // namespace hgs

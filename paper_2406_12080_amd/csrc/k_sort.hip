@@ -1,0 +1,182 @@
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits,
+// LDS-staged.  A fixed grid of G blocks each owns one contiguous chunk of the
+// input (so the element count may be a device value and the launches can be
+// captured in a graph):
+//   hist    : per-block digit histogram -> hist[digit * G + block]
+//   scan    : exclusive scan of hist (digit-major) = first output slot of
+//             every (digit, block)
+//   scatter : each block walks its chunk in tiles of 2048 keys, ranks keys
+//             stably inside the tile (64-lane digit match from 8 ballots,
+//             per-wave running counts in LDS), regroups the tile by digit in
+//             LDS, and writes runs of equal digits contiguously.
+// Ranking order inside a tile is (wave, item, lane) = input order, so equal
+// keys keep their input order.
+#include <algorithm>
+
+#include "hgs_internal.h"
+
+namespace hgs {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kWaves = kT / 64;
+constexpr int kItems = 8;
+constexpr int kTile = kT * kItems;
+constexpr int kRadix = 256;
+
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
+{
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+__device__ __forceinline__ void chunk_of(uint32_t n, int G, uint32_t &b0, uint32_t &b1)
+{
+    const uint32_t chunk = (n + G - 1) / G;
+    b0 = min(n, blockIdx.x * chunk);
+    b1 = min(n, b0 + chunk);
+}
+
+__global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *__restrict__ keys, uint32_t cap,
+                                                const uint32_t *__restrict__ n_dev, int shift,
+                                                uint32_t *__restrict__ hist, int G)
+{
+    __shared__ uint32_t s_h[kRadix];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t n = min(*n_dev, cap);
+    uint32_t b0, b1;
+    chunk_of(n, G, b0, b1);
+    const uint64_t lt = lanemask_lt();
+    for (uint32_t base = b0; base < b1; base += kT) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < b1;
+        const uint32_t d = valid ? (keys[i] >> shift) & 0xFFu : 0u;
+        const uint64_t peers = match_digit(d, valid);
+        if (valid && (peers & lt) == 0) atomicAdd(&s_h[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * G + blockIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                   uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                   uint32_t cap, const uint32_t *__restrict__ n_dev, int shift,
+                                                   const uint32_t *__restrict__ offsets, int G)
+{
+    __shared__ uint32_t s_keys[kTile];
+    __shared__ uint32_t s_vals[kTile];
+    __shared__ uint32_t s_wcnt[kWaves][kRadix];
+    __shared__ uint32_t s_run[kRadix];
+    __shared__ uint32_t s_start[kRadix];
+    __shared__ uint32_t s_tot[kRadix];
+    __shared__ uint32_t s_w[kWaves];
+
+    const uint32_t n = min(*n_dev, cap);
+    uint32_t b0, b1;
+    chunk_of(n, G, b0, b1);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
+    s_run[threadIdx.x] = offsets[(int64_t)threadIdx.x * G + blockIdx.x];
+
+    for (uint32_t base = b0; base < b1; base += kTile) {
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) s_wcnt[k][threadIdx.x] = 0;
+        __syncthreads();
+        uint32_t key[kItems], val[kItems], rank[kItems];
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const uint32_t i = base + (uint32_t)(w * 64 * kItems + it * 64 + lane);
+            const bool valid = i < b1;
+            key[it] = valid ? kin[i] : 0u;
+            val[it] = valid ? vin[i] : 0u;
+            const uint32_t d = (key[it] >> shift) & 0xFFu;
+            const uint64_t peers = match_digit(d, valid);
+            const uint32_t before = s_wcnt[w][d];
+            rank[it] = before + (uint32_t)__popcll(peers & lt);
+            if (valid && (peers & lt) == 0) s_wcnt[w][d] = before + (uint32_t)__popcll(peers);
+            if (!valid) rank[it] = 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        // per digit: wave offsets and tile total
+        {
+            const int d = threadIdx.x;
+            uint32_t acc = 0;
+#pragma unroll
+            for (int k = 0; k < kWaves; ++k) {
+                const uint32_t c = s_wcnt[k][d];
+                s_wcnt[k][d] = acc;
+                acc += c;
+            }
+            s_tot[d] = acc;
+            // exclusive scan of tile totals over digits (one digit per thread)
+            uint32_t x = acc;
+            uint32_t inc = x;
+#pragma unroll
+            for (int dd = 1; dd < 64; dd <<= 1) {
+                const uint32_t y = __shfl_up(inc, dd, 64);
+                if (lane >= dd) inc += y;
+            }
+            if (lane == 63) s_w[w] = inc;
+            __syncthreads();
+            uint32_t wb = 0;
+#pragma unroll
+            for (int k = 0; k < kWaves; ++k) wb += k < w ? s_w[k] : 0u;
+            s_start[d] = wb + inc - x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            if (rank[it] == 0xFFFFFFFFu) continue;
+            const uint32_t d = (key[it] >> shift) & 0xFFu;
+            const uint32_t lp = s_start[d] + s_wcnt[w][d] + rank[it];
+            s_keys[lp] = key[it];
+            s_vals[lp] = val[it];
+        }
+        __syncthreads();
+        const uint32_t cnt = min((uint32_t)kTile, b1 - base);
+        for (uint32_t j = threadIdx.x; j < cnt; j += kT) {
+            const uint32_t k2 = s_keys[j];
+            const uint32_t d = (k2 >> shift) & 0xFFu;
+            const uint32_t g = s_run[d] + (j - s_start[d]);
+            kout[g] = k2;
+            vout[g] = s_vals[j];
+        }
+        __syncthreads();
+        s_run[threadIdx.x] += s_tot[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+// Sorts (keys, vals) over bits [0, bits) with ceil(bits / 8) passes that
+// ping-pong between (keys, vals) and the scratch pair.  Returns true when the
+// pass count is odd, i.e. the sorted result is in (s.k2, s.v2).
+bool launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t cap, const uint32_t *n_dev, int bits,
+                       const SortScratch &s, hipStream_t st)
+{
+    if (cap == 0 || bits <= 0) return false;
+    const int passes = (bits + 7) / 8;
+    const int G = (int)std::min<uint32_t>(kSortBlocksMax, std::max<uint32_t>(1u, (cap + 16383u) / 16384u));
+    uint32_t *ki = keys, *vi = vals, *ko = s.k2, *vo = s.v2;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * 8;
+        hipLaunchKernelGGL(k_rs_hist, dim3(G), dim3(kT), 0, st, ki, cap, n_dev, shift, s.hist, G);
+        launch_scan(s.hist, nullptr, (uint32_t)(kRadix * G), nullptr, s.hist_scan, s.total, s.partial, st);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(G), dim3(kT), 0, st, ki, vi, ko, vo, cap, n_dev, shift, s.hist_scan,
+                           G);
+        std::swap(ki, ko);
+        std::swap(vi, vo);
+    }
+    return (passes & 1) != 0;
+}
+
+}  // namespace hgs

@@ -1,0 +1,283 @@
+"""Thin Python binding of the C ABI in ``include/hgs.h`` (ctypes).
+
+Argument marshalling only: every stage of the cut and splatting path runs in
+the HIP library ``libhgs.so``.  PyTorch provides device memory and the
+stream.  Importing this module does not need a GPU; creating a
+:class:`Renderer` does, and fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhgs.so")
+
+OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_CAPACITY = range(6)
+_NAMES = {0: "HGS_OK", 1: "HGS_ERR_INVALID_ARG", 2: "HGS_ERR_OOM", 3: "HGS_ERR_HIP", 4: "HGS_ERR_STATE",
+          5: "HGS_ERR_CAPACITY"}
+EXPORTS = ("hgs_create", "hgs_destroy", "hgs_last_error", "hgs_set_stream", "hgs_upload", "hgs_bind_params",
+           "hgs_cut", "hgs_render", "hgs_render_backward", "hgs_set_tuning", "hgs_get_buffer",
+           "hgs_set_profiling", "hgs_kernel_time", "hgs_counters")
+COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t", "bwd_evaluated",
+                 "bwd_evaluated_t", "bwd_contrib")
+K_BLEND, K_BLEND_BWD, K_PREPROCESS_BWD = range(3)
+
+BUF_CUT_IDS, BUF_CUT_T, BUF_T_FINAL, BUF_N_LAST, BUF_N_BLEND, BUF_SGRAD, BUF_CUT_BASE = range(7)
+
+
+class HgsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class HierarchyDesc(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("sh_degree", ctypes.c_int32),
+                ("parent", ctypes.c_void_p), ("child_begin", ctypes.c_void_p), ("child_count", ctypes.c_void_p),
+                ("bmin", ctypes.c_void_p), ("bmax", ctypes.c_void_p), ("mean", ctypes.c_void_p),
+                ("scale", ctypes.c_void_p), ("rot", ctypes.c_void_p), ("opacity", ctypes.c_void_p),
+                ("sh", ctypes.c_void_p)]
+
+
+class View(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("eye", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("z_near", ctypes.c_float),
+                ("tau", ctypes.c_float)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("cut", ctypes.c_int64), ("visible", ctypes.c_int64), ("pairs", ctypes.c_int64),
+                ("evaluated", ctypes.c_int64), ("blended", ctypes.c_int64), ("ms", ctypes.c_float * 8)]
+
+    def as_dict(self):
+        return dict(cut=self.cut, visible=self.visible, pairs=self.pairs, evaluated=self.evaluated,
+                    blended=self.blended, ms=list(self.ms))
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("mean", ctypes.c_void_p), ("scale", ctypes.c_void_p), ("rot", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("dt", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libhgs.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2406_12080_amd.build` "
+                               "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, c_int, vp = ctypes.POINTER, ctypes.c_int, ctypes.c_void_p
+        L.hgs_create.argtypes = [P(vp), c_int, vp]
+        L.hgs_destroy.argtypes = [vp]
+        L.hgs_destroy.restype = None
+        L.hgs_last_error.argtypes = [vp]
+        L.hgs_last_error.restype = ctypes.c_char_p
+        L.hgs_set_stream.argtypes = [vp, vp]
+        L.hgs_upload.argtypes = [vp, P(HierarchyDesc), c_int]
+        L.hgs_bind_params.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.hgs_cut.argtypes = [vp, P(View), vp, vp, ctypes.c_int64, P(ctypes.c_int64)]
+        L.hgs_render.argtypes = [vp, P(View), ctypes.c_int32, P(vp), P(Stats)]
+        L.hgs_render_backward.argtypes = [vp, P(vp), P(Grads)]
+        L.hgs_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.hgs_get_buffer.argtypes = [vp, ctypes.c_int32, P(vp), P(ctypes.c_int64)]
+        L.hgs_set_profiling.argtypes = [vp, ctypes.c_int32]
+        L.hgs_counters.argtypes = [vp, P(ctypes.c_int64), ctypes.c_int32]
+        L.hgs_kernel_time.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
+        for f in EXPORTS:
+            if f not in ("hgs_destroy", "hgs_last_error"):
+                getattr(L, f).restype = c_int
+        _lib = L
+    return _lib
+
+
+def make_view(v) -> View:
+    """hgs_view from any object with R, eye, fx, fy, cx, cy, width, height,
+    z_near, tau (e.g. ``synth.View``)."""
+    out = View()
+    R = np.asarray(v.R, np.float32).reshape(9)
+    for k in range(9):
+        out.R[k] = float(R[k])
+    e = np.asarray(v.eye, np.float32).reshape(3)
+    for k in range(3):
+        out.eye[k] = float(e[k])
+    out.fx, out.fy, out.cx, out.cy = float(v.fx), float(v.fy), float(v.cx), float(v.cy)
+    out.width, out.height = int(v.width), int(v.height)
+    out.z_near, out.tau = float(v.z_near), float(v.tau)
+    return out
+
+
+_hip = None
+
+
+def _hip_memcpy_d2d(dst: int, src: int, nbytes: int) -> None:
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    r = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3)  # device to device
+    if r != 0:
+        raise RuntimeError(f"hipMemcpy failed: {r}")
+
+
+PARAM_FIELDS = ("mean", "scale", "rot", "opacity", "sh")
+
+
+class Renderer:
+    """One library context on one device (``hgs_create``)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._stream = stream
+        self.L = lib()
+        h = ctypes.c_void_p()
+        st = self.L.hgs_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != OK:
+            raise HgsError(st, "hgs_create failed")
+        self.h = h
+        self.n_nodes = 0
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.hgs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != OK:
+            raise HgsError(st, self.L.hgs_last_error(self.h).decode())
+
+    # -- hierarchy ---------------------------------------------------------
+    def upload(self, hier) -> None:
+        """Upload a hierarchy: a ``synth.Hierarchy`` / dict of numpy arrays
+        (host) or of CUDA tensors (device)."""
+        a = hier.arrays() if hasattr(hier, "arrays") else dict(hier)
+        torch = self.torch
+        on_dev = isinstance(a["mean"], torch.Tensor) and a["mean"].is_cuda
+        keep = {}
+        for k, dt in (("parent", np.int32), ("child_begin", np.int32), ("child_count", np.int32),
+                      ("bmin", np.float32), ("bmax", np.float32), ("mean", np.float32), ("scale", np.float32),
+                      ("rot", np.float32), ("opacity", np.float32), ("sh", np.float32)):
+            x = a[k]
+            if on_dev:
+                x = x.contiguous()
+                assert x.dtype == (torch.int32 if dt == np.int32 else torch.float32), k
+                keep[k] = (x, x.data_ptr())
+            else:
+                x = np.ascontiguousarray(x, dt)
+                keep[k] = (x, x.ctypes.data)
+        d = HierarchyDesc()
+        d.n_nodes = int(keep["parent"][0].shape[0])
+        d.sh_degree = 3
+        for k in keep:
+            setattr(d, k, keep[k][1])
+        self._check(self.L.hgs_upload(self.h, ctypes.byref(d), 1 if on_dev else 0))
+        self.n_nodes = d.n_nodes
+
+    def bind(self, mean, scale, rot, opacity, sh) -> None:
+        ts = (mean, scale, rot, opacity, sh)
+        for t in ts:
+            assert t.is_cuda and t.is_contiguous() and t.dtype == self.torch.float32
+        self._bound = ts
+        self._check(self.L.hgs_bind_params(self.h, *[ctypes.c_void_p(t.data_ptr()) for t in ts]))
+
+    def unbind(self) -> None:
+        self._bound = None
+        self._check(self.L.hgs_bind_params(self.h, None, None, None, None, None))
+
+    def set_tuning(self, tile_w: int, tile_h: int, batch: int = 0) -> None:
+        self._check(self.L.hgs_set_tuning(self.h, tile_w, tile_h, batch))
+
+    # -- cut -----------------------------------------------------------------
+    def cut(self, view, capacity: int | None = None):
+        torch = self.torch
+        cap = capacity if capacity is not None else self.n_nodes
+        ids = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        t = torch.empty(max(cap, 1), dtype=torch.float32, device=self.device)
+        cnt = ctypes.c_int64()
+        hv = make_view(view)
+        self._check(self.L.hgs_cut(self.h, ctypes.byref(hv), ctypes.c_void_p(ids.data_ptr()),
+                                   ctypes.c_void_p(t.data_ptr()), cap, ctypes.byref(cnt)))
+        return ids[:cnt.value], t[:cnt.value]
+
+    # -- render ----------------------------------------------------------------
+    def render(self, views, out=None, timed: bool = False):
+        """Render a list of views; returns (images, stats dict).  ``out`` may
+        hold preallocated float32 [H, W, 3] CUDA tensors."""
+        torch = self.torch
+        views = list(views)
+        nv = len(views)
+        arr = (View * nv)(*[make_view(v) for v in views])
+        if out is None:
+            out = [torch.empty((v.height, v.width, 3), dtype=torch.float32, device=self.device) for v in views]
+        ptrs = (ctypes.c_void_p * nv)(*[o.data_ptr() for o in out])
+        st = Stats()
+        if timed:
+            st.ms[0] = -1.0
+        self._check(self.L.hgs_render(self.h, arr, nv, ptrs, ctypes.byref(st)))
+        self._last_views = views
+        return out, st.as_dict()
+
+    def backward(self, dL, grads: dict, dt=None) -> None:
+        """Accumulate parameter gradients of the last render into ``grads``
+        (dict of CUDA tensors keyed like the parameters)."""
+        dL = [g.contiguous() for g in dL]
+        ptrs = (ctypes.c_void_p * len(dL))(*[g.data_ptr() for g in dL])
+        g = Grads()
+        for k in PARAM_FIELDS:
+            setattr(g, k, grads[k].data_ptr())
+        g.dt = dt.data_ptr() if dt is not None else None
+        self._keep = dL
+        self._check(self.L.hgs_render_backward(self.h, ptrs, ctypes.byref(g)))
+
+    def counters(self) -> dict:
+        out = (ctypes.c_int64 * len(COUNTER_NAMES))()
+        self._check(self.L.hgs_counters(self.h, out, len(COUNTER_NAMES)))
+        return dict(zip(COUNTER_NAMES, list(out)))
+
+    def set_profiling(self, on: bool) -> None:
+        self._check(self.L.hgs_set_profiling(self.h, 1 if on else 0))
+
+    def kernel_time(self, which: int):
+        """(total milliseconds, launches) of kernel `which` since profiling was switched on."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.L.hgs_kernel_time(self.h, which, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def buffer(self, which: int, dtype):
+        """Copy of an internal buffer of the last render (see hgs_get_buffer)."""
+        torch = self.torch
+        p = ctypes.c_void_p()
+        n = ctypes.c_int64()
+        self._check(self.L.hgs_get_buffer(self.h, which, ctypes.byref(p), ctypes.byref(n)))
+        out = torch.empty(max(n.value, 1), dtype=dtype, device=self.device)
+        torch.cuda.synchronize(self.device)
+        if n.value:
+            _hip_memcpy_d2d(out.data_ptr(), p.value, n.value * out.element_size())
+        return out[:n.value]
+
+
+def params_to_device(hier, device="cuda"):
+    """The five parameter arrays of a hierarchy as contiguous CUDA tensors."""
+    import torch
+    a = hier.arrays() if hasattr(hier, "arrays") else hier
+    return {k: torch.as_tensor(np.ascontiguousarray(a[k], np.float32)).to(device) for k in PARAM_FIELDS}

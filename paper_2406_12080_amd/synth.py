@@ -35,6 +35,8 @@ contiguous; structure-of-arrays FP32 with the component index major
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -196,50 +198,68 @@ def _cov_from(scale: np.ndarray, R: np.ndarray) -> np.ndarray:
 # ----------------------------------------------------------------------------
 # leaves
 # ----------------------------------------------------------------------------
-def _box_positions(rng, n, lo, hi):
-    lo = np.asarray(lo, np.float64)
-    hi = np.asarray(hi, np.float64)
-    return lo + (hi - lo) * rng.random((n, 3))
+_CHUNK = 1 << 20
 
 
-def _corridor_positions(rng, n, length):
-    x = rng.random(n) * length
-    y = -20.0 + 40.0 * rng.random(n)
-    # exponential with 3 m scale, truncated to [0, 20] by inverse CDF
-    u = rng.random(n)
-    cap = 1.0 - math.exp(-20.0 / 3.0)
-    z = -3.0 * np.log1p(-u * cap)
-    return np.stack([x, y, z], 1)
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _par(fn, n: int, chunk: int = _CHUNK) -> None:
+    """Run fn(start, stop) over [0, n) in chunks on a thread pool (numpy
+    releases the GIL inside its kernels); fn writes disjoint slices."""
+    spans = [(a, min(n, a + chunk)) for a in range(0, n, chunk)]
+    if len(spans) <= 1:
+        for a, b in spans:
+            fn(a, b)
+        return
+    with ThreadPoolExecutor(_workers()) as ex:
+        list(ex.map(lambda ab: fn(*ab), spans))
 
 
 def make_leaves(n: int, layout: str, seed: int) -> dict:
-    """Leaf Gaussians.  Independent PCG64 sub-streams per attribute."""
+    """Leaf Gaussians (FP32), drawn in chunks of 2^20 leaves from PCG64
+    streams spawned per attribute and per chunk (deterministic in seed and n)."""
     ss = np.random.SeedSequence(seed)
-    r_pos, r_scale, r_rot, r_op, r_sh = [np.random.Generator(np.random.PCG64(s))
-                                         for s in ss.spawn(5)]
-    if layout == "cube":
-        pos = _box_positions(r_pos, n, (-1, -1, -1), (1, 1, 1))
-    elif layout == "box_core":
-        n_core = n // 5
-        a = _box_positions(r_pos, n - n_core, (-50, -50, 0), (50, 50, 20))
-        b = _box_positions(r_pos, n_core, (-10, -10, 0), (10, 10, 5))
-        pos = np.concatenate([a, b], 0)
-    elif layout.startswith("corridor"):
+    s_pos, s_scale, s_rot, s_op, s_sh = ss.spawn(5)
+    nch = max(1, (n + _CHUNK - 1) // _CHUNK)
+    seeds = {k: v.spawn(nch) for k, v in dict(pos=s_pos, scale=s_scale, rot=s_rot, op=s_op, sh=s_sh).items()}
+    pos = np.empty((n, 3), np.float32)
+    scale = np.empty((n, 3), np.float32)
+    rot = np.empty((n, 4), np.float32)
+    op = np.empty(n, np.float32)
+    sh = np.empty((n, 3 * SH_COEFFS), np.float32)
+    if layout.startswith("corridor"):
         length = float(layout.split(":")[1]) if ":" in layout else 1000.0
-        pos = _corridor_positions(r_pos, n, length)
-    else:
+    elif layout not in ("cube", "box_core"):
         raise ValueError(layout)
-    scale = np.exp(r_scale.normal(-4.0, 0.5, (n, 3)))
-    q = r_rot.normal(0.0, 1.0, (n, 4))
-    q /= np.linalg.norm(q, axis=1, keepdims=True)
-    op = 1.0 / (1.0 + np.exp(-r_op.normal(0.0, 1.0, n)))
-    sh = r_sh.normal(0.0, 0.3, (n, 3 * SH_COEFFS))
-    # quantise to the FP32 storage every consumer sees
-    return dict(pos=pos.astype(np.float32).astype(np.float64),
-                scale=scale.astype(np.float32).astype(np.float64),
-                rot=q.astype(np.float32).astype(np.float64),
-                opacity=op.astype(np.float32).astype(np.float64),
-                sh=sh.astype(np.float32).astype(np.float64))
+    n_core = n // 5 if layout == "box_core" else 0
+
+    def fill(a, b):
+        c = a // _CHUNK
+        m = b - a
+        g = lambda k: np.random.Generator(np.random.PCG64(seeds[k][c]))  # noqa: E731
+        rp = g("pos")
+        u = rp.random((m, 3))
+        if layout == "cube":
+            P = -1.0 + 2.0 * u
+        elif layout == "box_core":
+            core = (np.arange(a, b) >= n - n_core)[:, None]
+            big = np.array([-50.0, -50.0, 0.0]) + np.array([100.0, 100.0, 20.0]) * u
+            small = np.array([-10.0, -10.0, 0.0]) + np.array([20.0, 20.0, 5.0]) * u
+            P = np.where(core, small, big)
+        else:
+            cap = 1.0 - math.exp(-20.0 / 3.0)
+            P = np.stack([u[:, 0] * length, -20.0 + 40.0 * u[:, 1], -3.0 * np.log1p(-u[:, 2] * cap)], 1)
+        pos[a:b] = P
+        scale[a:b] = np.exp(g("scale").normal(-4.0, 0.5, (m, 3)))
+        q = g("rot").normal(0.0, 1.0, (m, 4))
+        rot[a:b] = q / np.linalg.norm(q, axis=1, keepdims=True)
+        op[a:b] = 1.0 / (1.0 + np.exp(-g("op").normal(0.0, 1.0, m)))
+        sh[a:b] = g("sh").standard_normal((m, 3 * SH_COEFFS), dtype=np.float32) * np.float32(0.3)
+
+    _par(fill, n)
+    return dict(pos=pos, scale=scale, rot=rot, opacity=op, sh=sh)
 
 
 # ----------------------------------------------------------------------------
@@ -291,18 +311,19 @@ def build_topology(codes: np.ndarray, collapse_chains: bool = False):
 
 
 def _split_starts(codes, plo, phi, d):
-    n = codes.shape[0]
+    """First leaf of every non-empty child cell (Morton level d) of the
+    multi-leaf ranges [plo, phi); past the last Morton level, groups of at most
+    8 consecutive leaves."""
     if d <= MORTON_BITS:
         shift = np.uint64(3 * (MORTON_BITS - d))
-        mark = np.zeros(n + 1, np.int64)
-        np.add.at(mark, plo + 1, 1)
-        np.add.at(mark, phi, -1)
-        inside = np.cumsum(mark[:n]) > 0
-        key = codes >> shift
-        diff = np.zeros(n, bool)
-        diff[1:] = key[1:] != key[:-1]
-        cand = np.nonzero(inside & diff)[0]
-        return np.union1d(plo, cand)
+        lens = phi - plo - 1
+        tot = int(lens.sum())
+        if tot == 0:
+            return plo.copy()
+        base = np.repeat(plo + 1 - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+        idx = np.arange(tot, dtype=np.int64) + base
+        diff = (codes[idx] >> shift) != (codes[idx - 1] >> shift)
+        return np.sort(np.concatenate([plo, idx[diff]]))
     st = []
     for a, b in zip(plo.tolist(), phi.tolist()):
         m = b - a
@@ -383,105 +404,166 @@ def _octree_levels_collapsed(codes):
 # ----------------------------------------------------------------------------
 # merges, orientation matching, boxes
 # ----------------------------------------------------------------------------
+def _cov6(scale, R):
+    """Symmetric covariance R diag(s^2) R^T as [6, M] (xx xy xz yy yz zz)."""
+    s2 = scale * scale
+    out = np.empty((6, scale.shape[0]))
+    for k, (i, j) in enumerate(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))):
+        out[k] = (R[:, i, :] * R[:, j, :] * s2).sum(1)
+    return out
+
+
+def _full(c6):
+    """[6, M] -> [M, 3, 3]."""
+    M = np.empty((c6.shape[1], 3, 3))
+    M[:, 0, 0], M[:, 0, 1], M[:, 0, 2] = c6[0], c6[1], c6[2]
+    M[:, 1, 0], M[:, 1, 1], M[:, 1, 2] = c6[1], c6[3], c6[4]
+    M[:, 2, 0], M[:, 2, 1], M[:, 2, 2] = c6[2], c6[4], c6[5]
+    return M
+
+
+def _perm_trace_index():
+    """trace(C P) for the 24 proper signed permutations as sums of 3 signed
+    entries of C: (flat index [24, 3], sign [24, 3])."""
+    idx = np.zeros((24, 3), np.int64)
+    sg = np.zeros((24, 3))
+    for p in range(24):
+        P = _PERMS[p]
+        for col in range(3):
+            row = int(np.nonzero(P[:, col])[0][0])
+            # (C P)_{col,col} = sum_j C[col, j] P[j, col] = C[col, row] * P[row, col]
+            idx[p, col] = 3 * col + row
+            sg[p, col] = P[row, col]
+    return idx, sg
+
+
+_PT_IDX, _PT_SG = _perm_trace_index()
+
+
 def build_hierarchy(leaves: dict, collapse_chains: bool = False) -> Hierarchy:
-    pos = leaves["pos"]
+    pos = np.asarray(leaves["pos"], np.float64)
     n = pos.shape[0]
     codes = _morton(pos)
     order = np.argsort(codes, kind="stable")
     codes = codes[order]
-    L = {k: v[order] for k, v in leaves.items()}
 
     parent, child_begin, child_count, lo_all, hi_all, first = build_topology(codes, collapse_chains)
     N = parent.shape[0]
     is_leaf = child_count == 0
-    leaf_of = np.full(N, -1, np.int64)
-    leaf_of[is_leaf] = lo_all[is_leaf]
-    assert np.all(hi_all[is_leaf] - lo_all[is_leaf] == 1)
+    leaf_nodes = np.nonzero(is_leaf)[0]
+    assert np.all(hi_all[leaf_nodes] - lo_all[leaf_nodes] == 1)
+    src = order[lo_all[leaf_nodes]]  # original leaf index of each leaf node
 
-    mean = np.zeros((N, 3))
-    cov = np.zeros((N, 3, 3))
-    sh = np.zeros((N, 3 * SH_COEFFS))
+    # component-major working arrays (segment sums run along contiguous rows)
+    mean = np.zeros((3, N))
+    cov = np.zeros((6, N))
+    sh = np.zeros((3 * SH_COEFFS, N), np.float32)
     op = np.zeros(N)
     surf = np.zeros(N)
-    scale = np.zeros((N, 3))
+    scale = np.zeros((3, N))
     Rm = np.zeros((N, 3, 3))
 
-    li = leaf_of[is_leaf]
-    mean[is_leaf] = L["pos"][li]
-    Rl = quat_to_mat(L["rot"][li])
-    cov[is_leaf] = _cov_from(L["scale"][li], Rl)
-    sh[is_leaf] = L["sh"][li]
-    op[is_leaf] = L["opacity"][li]
-    scale[is_leaf] = L["scale"][li]
-    Rm[is_leaf] = Rl
-    surf[is_leaf] = _ellipsoid_surface(L["scale"][li])
+    def leaf_fill(a, b):
+        nd, sr = leaf_nodes[a:b], src[a:b]
+        mean[:, nd] = pos[sr].T
+        q = np.asarray(leaves["rot"][sr], np.float64)
+        s_ = np.asarray(leaves["scale"][sr], np.float64)
+        R = quat_to_mat(q)
+        cov[:, nd] = _cov6(s_, R)
+        sh[:, nd] = leaves["sh"][sr].T
+        op[nd] = leaves["opacity"][sr]
+        scale[:, nd] = s_.T
+        Rm[nd] = R
+        surf[nd] = _ellipsoid_surface(s_)
+
+    _par(leaf_fill, leaf_nodes.shape[0])
 
     nlev = len(first) - 1
-    # bottom-up merge, one level at a time (children live on the next level)
+    # bottom-up merge, one level at a time (children live on the next level),
+    # each level in chunks of parents whose children are contiguous
     for lv in range(nlev - 2, -1, -1):
         ids = np.arange(first[lv], first[lv + 1])
         inner = ids[child_count[ids] > 0]
         if inner.shape[0] == 0:
             continue
-        cb = child_begin[inner].astype(np.int64)
-        cc = child_count[inner].astype(np.int64)
-        c0 = int(cb[0])
-        c1 = int(cb[-1] + cc[-1])
-        ch = np.arange(c0, c1)
-        seg = cb - c0
-        wp = op[ch] * surf[ch]                       # unnormalised weights
-        wsum = np.add.reduceat(wp, seg)
-        wn = wp / np.repeat(wsum, cc)
-        mu = np.add.reduceat(wn[:, None] * mean[ch], seg, axis=0)
-        dmu = mean[ch] - np.repeat(mu, cc, axis=0)
-        cv = np.add.reduceat(wn[:, None, None] * (cov[ch] + dmu[:, :, None] * dmu[:, None, :]),
-                             seg, axis=0)
-        shm = np.add.reduceat(wn[:, None] * sh[ch], seg, axis=0)
-        cv = 0.5 * (cv + np.swapaxes(cv, 1, 2))
-        lam, V = np.linalg.eigh(cv)
-        lam = np.maximum(lam, 1e-20)
-        det = np.linalg.det(V)
-        V[det < 0, :, 2] *= -1.0
-        s = np.sqrt(lam)
-        sp = _ellipsoid_surface(s)
-        mean[inner] = mu
-        cov[inner] = cv
-        sh[inner] = shm
-        scale[inner] = s
-        Rm[inner] = V
-        surf[inner] = sp
-        op[inner] = wsum / sp                        # falloff, may exceed 1
+
+        def merge(a, b, inner=inner):
+            nd = inner[a:b]
+            cb = child_begin[nd].astype(np.int64)
+            cc = child_count[nd].astype(np.int64)
+            c0, c1 = int(cb[0]), int(cb[-1] + cc[-1])
+            seg = cb - c0
+            ch = slice(c0, c1)
+            wp = op[ch] * surf[ch]                       # unnormalised weights o_i S_i
+            wsum = np.add.reduceat(wp, seg)
+            wn = wp / np.repeat(wsum, cc)
+            mu = np.add.reduceat(wn * mean[:, ch], seg, axis=1)
+            dmu = mean[:, ch] - np.repeat(mu, cc, axis=1)
+            outer = np.stack([dmu[0] * dmu[0], dmu[0] * dmu[1], dmu[0] * dmu[2],
+                              dmu[1] * dmu[1], dmu[1] * dmu[2], dmu[2] * dmu[2]], 0)
+            cv = np.add.reduceat(wn * (cov[:, ch] + outer), seg, axis=1)
+            shm = np.add.reduceat(wn.astype(np.float32) * sh[:, ch], seg, axis=1)
+            lam, V = np.linalg.eigh(_full(cv))
+            lam = np.maximum(lam, 1e-20)
+            V[np.linalg.det(V) < 0, :, 2] *= -1.0
+            s_ = np.sqrt(lam)
+            sp = _ellipsoid_surface(s_)
+            mean[:, nd] = mu
+            cov[:, nd] = cv
+            sh[:, nd] = shm
+            scale[:, nd] = s_.T
+            Rm[nd] = V
+            surf[nd] = sp
+            op[nd] = wsum / sp                           # falloff, may exceed 1
+
+        _par(merge, inner.shape[0], chunk=1 << 18)
 
     # top-down orientation matching
     for lv in range(1, nlev):
-        ids = np.arange(first[lv], first[lv + 1])
-        par = parent[ids]
-        C = np.swapaxes(Rm[par], 1, 2) @ Rm[ids]     # R_p^T R_c
-        tr = np.einsum("nkj,pjk->np", C, _PERMS)
-        best = np.argmax(tr, axis=1)
-        P = _PERMS[best]
-        Rm[ids] = Rm[ids] @ P
-        # new axis k takes the scale of old axis pi(k): s' = |P|^T s
-        scale[ids] = np.einsum("njk,nj->nk", np.abs(P), scale[ids])
+        lo, hi = int(first[lv]), int(first[lv + 1])
 
-    q = mat_to_quat(Rm)
+        def match(a, b, lo=lo):
+            ids = np.arange(lo + a, lo + b)
+            C = (np.swapaxes(Rm[parent[ids]], 1, 2) @ Rm[ids]).reshape(-1, 9)  # R_p^T R_c
+            tr = (C[:, _PT_IDX] * _PT_SG).sum(2)
+            P = _PERMS[np.argmax(tr, axis=1)]
+            Rm[ids] = Rm[ids] @ P
+            # new axis k takes the scale of old axis pi(k): s' = |P|^T s
+            scale[:, ids] = np.einsum("njk,jn->kn", np.abs(P), scale[:, ids])
+
+        _par(match, hi - lo, chunk=1 << 18)
+
+    q = np.empty((N, 4))
+
+    def quats(a, b):
+        q[a:b] = mat_to_quat(Rm[a:b])
+
+    _par(quats, N)
     for lv in range(1, nlev):
         ids = np.arange(first[lv], first[lv + 1])
         dots = np.einsum("ni,ni->n", q[ids], q[parent[ids]])
         q[ids[dots < 0]] *= -1.0
+    del Rm
 
-    # boxes: leaf = mean +- 3 sqrt(diag cov), rounded outward to FP32;
-    # interior = union of its children's boxes (= union over its leaves)
-    # (from the stored FP32 scale and rotation of each leaf)
-    q32 = q.astype(np.float32).astype(np.float64)
-    q32 /= np.linalg.norm(q32, axis=1, keepdims=True)
-    Rl = quat_to_mat(q32[is_leaf])
-    s32 = scale[is_leaf].astype(np.float32).astype(np.float64)
-    ext = 3.0 * np.sqrt(np.einsum("nij,nj->ni", Rl ** 2, s32 ** 2))
+    # boxes: leaf = mean +- 3 sqrt(diag cov) from the stored FP32 scale and
+    # rotation, rounded outward to FP32; interior = union of its children
     bmin = np.zeros((N, 3), np.float32)
     bmax = np.zeros((N, 3), np.float32)
-    bmin[is_leaf] = _round_down32(mean[is_leaf] - ext)
-    bmax[is_leaf] = _round_up32(mean[is_leaf] + ext)
+    scale32 = scale.astype(np.float32)   # [3, N]
+    q32 = q.astype(np.float32)
+
+    def leaf_box(a, b):
+        nd = leaf_nodes[a:b]
+        qq = q32[nd].astype(np.float64)
+        qq /= np.linalg.norm(qq, axis=1, keepdims=True)
+        R = quat_to_mat(qq)
+        s32 = scale32[:, nd].T.astype(np.float64)
+        ext = 3.0 * np.sqrt(np.einsum("nij,nj->ni", R ** 2, s32 ** 2))
+        m = mean[:, nd].T
+        bmin[nd] = _round_down32(m - ext)
+        bmax[nd] = _round_up32(m + ext)
+
+    _par(leaf_box, leaf_nodes.shape[0])
     for lv in range(nlev - 2, -1, -1):
         ids = np.arange(first[lv], first[lv + 1])
         inner = ids[child_count[ids] > 0]
@@ -497,13 +579,13 @@ def build_hierarchy(leaves: dict, collapse_chains: bool = False) -> Hierarchy:
     f32 = np.float32
     h = Hierarchy(parent=parent, child_begin=np.where(child_count > 0, child_begin, 0).astype(np.int32),
                   child_count=child_count,
-                  bmin=np.ascontiguousarray(bmin.T.astype(f32)),
-                  bmax=np.ascontiguousarray(bmax.T.astype(f32)),
-                  mean=np.ascontiguousarray(mean.T.astype(f32)),
-                  scale=np.ascontiguousarray(scale.T.astype(f32)),
-                  rot=np.ascontiguousarray(q.T.astype(f32)),
+                  bmin=np.ascontiguousarray(bmin.T),
+                  bmax=np.ascontiguousarray(bmax.T),
+                  mean=mean.astype(f32),
+                  scale=scale32,
+                  rot=np.ascontiguousarray(q32.T),
                   opacity=op.astype(f32),
-                  sh=np.ascontiguousarray(sh.T.astype(f32)))
+                  sh=sh)
     h.info = dict(n_nodes=int(N), n_leaves=int(n), n_interior=int(N - n), levels=int(nlev),
                   single_child=int(np.count_nonzero(child_count == 1)),
                   max_children=int(child_count.max()))

@@ -1,0 +1,62 @@
+"""Shared parity checks of the GPU path against the oracle (test-side only)."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+
+PIX_TOL = 2e-4   # max abs per pixel channel
+GRAD_REL = 1e-3  # relative L2 per parameter group
+
+
+def safe_tau(h, v, rel=1e-9):
+    """Nudge tau (in FP32 steps) until no interior node's granularity lies
+    within a relative `rel` of it, so that the selection never hinges on the
+    last bit of an FP64 evaluation.  Returns the (possibly) new view."""
+    H = h if isinstance(h, O.Hier) else O.Hier(h)
+    inner = H.child_count > 0
+    for _ in range(64):
+        eps = O.granularity(H, v)[inner]
+        tau = float(np.float32(v.tau))
+        if tau == 0.0 or not np.any(np.abs(eps / tau - 1.0) < rel):
+            return v
+        v = v.replace(tau=float(np.nextafter(np.float32(tau), np.float32(np.inf))))
+    raise AssertionError("could not move tau away from every granularity")
+
+
+def check_pixels(gpu_rgb, gpu_T, o, tol=PIX_TOL):
+    """Two-branch acceptance: a pixel passes when it is within `tol` of the
+    oracle's nominal value or of one of its single-flip alternatives (a
+    decision within a relative 1e-4 of the 1/255 skip or the 1e-4 stop
+    threshold, inverted).  gpu_rgb [m, 3], gpu_T [m] at o['pix']."""
+    nom = np.abs(gpu_rgb - o["rgb"]).max(-1)
+    nomT = np.abs(gpu_T - o["T"])
+    ok = (nom <= tol) & (nomT <= tol)
+    alt_used = np.zeros_like(ok)
+    for k in range(O.MAX_ALT):
+        has = o["nalt"] > k
+        ea = np.abs(gpu_rgb - o["alt_rgb"][:, k]).max(-1)
+        eT = np.abs(gpu_T - o["alt_T"][:, k])
+        hit = has & (ea <= tol) & (eT <= tol) & ~ok
+        alt_used |= hit
+        ok |= hit
+    bad = np.nonzero(~ok)[0]
+    return dict(ok=bool(ok.all()), n_bad=int(bad.size), bad=bad[:10], max_nominal=float(nom.max(initial=0.0)),
+                n_alt=int(alt_used.sum()), n_ambiguous=int((o["nalt"] > 0).sum()), m=int(ok.size))
+
+
+def check_grads(gpu: dict, og: np.ndarray, leaf_mask, rel=GRAD_REL):
+    """Per parameter group: relative L2 error <= rel and per element
+    |diff| <= rel * max(|g|, 1e-3 rms(group))."""
+    out = {}
+    for name, (a, b) in O.SLOTS.items():
+        ref = og[a:b].copy()
+        ref[:, leaf_mask] = 0.0
+        g = np.asarray(gpu[name], np.float64).reshape(b - a, -1)
+        nrm = np.linalg.norm(ref)
+        err = np.linalg.norm(g - ref)
+        rms = nrm / np.sqrt(ref.size)
+        elem = np.abs(g - ref) <= rel * np.maximum(np.abs(ref), 1e-3 * rms) + 1e-30
+        out[name] = dict(rel=float(err / max(nrm, 1e-30)), elem_ok=float(elem.mean()), norm=float(nrm),
+                         worst=float((np.abs(g - ref) / np.maximum(np.abs(ref), 1e-3 * rms + 1e-30)).max()))
+    return out
