@@ -55,7 +55,7 @@ def build_workload(name: str, leaves: int | None = None):
     w = WORKLOADS[name]
     cfg = w["config"]
     t0 = time.time()
-    h = synth.make_scene(cfg, n_leaves=leaves)
+    h = synth.make_scene(cfg, n_leaves=leaves, progress=lambda m: log(f"[bench] scene: {m} ({time.time() - t0:.1f}s)"))
     if cfg in (3, 5):
         views = synth.make_views(cfg, headline=True)
     else:

@@ -188,12 +188,13 @@ hgs_status hgs_counters(hgs_ctx *ctx, int64_t *out, int32_t n);
 
 /* Read-only access to internal state of the last render/backward (device
  * pointers, valid until the next render on ctx), for tests and tools.
- * which: 0 cut node ids (int32, all views, view-major), 1 cut t (float),
+ * which: 0 cut node ids (int32, all views, view-major), 1 cut t (double),
  * 2 final transmittance per pixel (float, views concatenated, row-major),
  * 3 contributors processed per pixel (uint32: index within its tile's list
  * after the last blended splat, + 1; 0 if none), 4 blended splats per pixel
  * (uint32), 5 screen-space gradients of the last backward (double[cut][12]:
- * du, dv, dconic(3), dA_n, dA_p, drgb(3), dt_alpha, unused), 6 cut offsets
+ * du, dv, dL/d(a, b, c) of the 2D covariance through the conic, dA_n, dA_p,
+ * drgb(3), dt_alpha, unused), 6 cut offsets
  * per view (uint32[n_views + 1]).  *count receives the element count. */
 hgs_status hgs_get_buffer(hgs_ctx *ctx, int32_t which, const void **dev_ptr, int64_t *count);
 

@@ -72,8 +72,9 @@ struct hgs_ctx {
     uint64_t *masks = nullptr;
     uint32_t *blk_counts = nullptr, *blk_offsets = nullptr, *cut_base = nullptr;
     int32_t *cut_ids = nullptr;
-    float *cut_t = nullptr;
+    double *cut_t = nullptr;
     SplatRec *recs = nullptr;
+    double4 *axes = nullptr;
     uint32_t *depth_key = nullptr, *ntiles = nullptr;
     uint2 *rect = nullptr;
     uint64_t *vis_mask = nullptr;
@@ -311,6 +312,7 @@ hgs_status ensure_cut_cap(hgs_ctx *ctx, uint32_t cap)
     if ((s = realloc_buf(ctx, ctx->cut_ids, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->cut_t, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->recs, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->axes, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->depth_key, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->ntiles, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->rect, cap))) return s;
@@ -355,8 +357,8 @@ int bits_for(uint32_t n)
 void enqueue_blend(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st)
 {
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
-    launch_blend(ctx->views_dev, nv, n_tiles, ctx->ranges, vals, ctx->recs, ctx->T_final, ctx->n_last, ctx->n_blend,
-                 ctx->ctr, ctx->tile_w, ctx->tile_h, ctx->batch, st);
+    launch_blend(ctx->views_dev, nv, n_tiles, ctx->ranges, vals, ctx->recs, ctx->axes, ctx->T_final, ctx->n_last,
+                 ctx->n_blend, ctx->ctr, ctx->tile_w, ctx->tile_h, ctx->batch, st);
 }
 
 void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hipEvent_t *ev, bool with_blend)
@@ -371,12 +373,12 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     launch_cut_flags(h, ctx->views_dev, nv, ctx->masks, ctx->blk_counts, nb, st);
     launch_scan(ctx->blk_counts, nullptr, (uint32_t)(nb * nv), nullptr, ctx->blk_offsets, &ctx->ctr->cut_total,
                 ctx->partial, st);
-    launch_cut_emit(h, ctx->views_dev, nv, ctx->masks, ctx->blk_offsets, nb, ctx->cut_ids, ctx->cut_t, ctx->cut_cap,
-                    st);
+    launch_cut_emit(h, ctx->views_dev, nv, ctx->masks, ctx->blk_offsets, nb, ctx->cut_ids, nullptr, ctx->cut_t,
+                    ctx->cut_cap, st);
     launch_cut_finish(ctx->blk_offsets, ctx->blk_counts, nb, nv, ctx->cut_base, ctx->ctr, st);
     mark(1);
     launch_preprocess(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t, &ctx->ctr->cut_total,
-                      ctx->cut_cap, ctx->recs, ctx->depth_key, ctx->rect, ctx->ntiles, ctx->vis_mask,
+                      ctx->cut_cap, ctx->recs, ctx->axes, ctx->depth_key, ctx->rect, ctx->ntiles, ctx->vis_mask,
                       ctx->vis_counts, ctx->tile_w, ctx->tile_h, st);
     mark(2);
     const uint32_t vblocks = (ctx->cut_cap + 255) / 256;
@@ -633,7 +635,8 @@ hgs_status hgs_cut(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *
         return fail(ctx, HGS_ERR_CAPACITY, "cut has " + std::to_string(*out_count) + " nodes, capacity " +
                                                std::to_string(capacity));
     if (*out_count > 0)
-        launch_cut_emit(h, ctx->views_dev, 1, ctx->masks, ctx->blk_offsets, nb, out_ids, out_t, (uint32_t)capacity, st);
+        launch_cut_emit(h, ctx->views_dev, 1, ctx->masks, ctx->blk_offsets, nb, out_ids, out_t, nullptr,
+                        (uint32_t)capacity, st);
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(st));
     return HGS_OK;
@@ -779,7 +782,7 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_gr
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
     {
         KernelTimer kt(ctx, 1, st);
-        launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->ranges, vals, ctx->recs, ctx->T_final,
+        launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->ranges, vals, ctx->recs, ctx->axes, ctx->T_final,
                               ctx->n_last, ctx->sgrad, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch, st);
     }
     const DevHier h = dev_hier(ctx);

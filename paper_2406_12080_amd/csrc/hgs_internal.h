@@ -53,6 +53,10 @@ struct __align__(16) SplatRec {
     float r, g, b;
     uint32_t node;
 };
+// The FP64 axes (w1x, w1y, w2x, w2y) are kept beside the record: the
+// per-8x8-block offsets w . (corner - mean) are formed from them in FP64, since
+// a splat's centre can lie far off screen, where the FP32 rounding of the
+// axis direction alone would move the evaluated position by whole 1e-4s.
 // 1/2 log2(e): exp(-q/2) = exp2(-kHalfLog2e q)
 constexpr double kHalfLog2e = 0.72134752044448170368;
 static_assert(sizeof(SplatRec) == 64, "record layout");
@@ -82,8 +86,8 @@ constexpr int kCutBlock = kCutThreads * kCutItems;  // nodes per block
 void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *masks, uint32_t *block_counts,
                       int nblocks, hipStream_t st);
 void launch_cut_emit(const DevHier &h, const DevView *views, int nv, const uint64_t *masks,
-                     const uint32_t *block_offsets, int nblocks, int32_t *out_ids, float *out_t, uint32_t cap,
-                     hipStream_t st);
+                     const uint32_t *block_offsets, int nblocks, int32_t *out_ids, float *out_t, double *out_t64,
+                     uint32_t cap, hipStream_t st);
 void launch_cut_finish(const uint32_t *block_offsets, const uint32_t *block_counts, int nblocks, int nv,
                        uint32_t *cut_base, Counters *ctr, hipStream_t st);
 
@@ -107,9 +111,9 @@ bool launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t cap, const uint3
 
 // preprocess: interpolation, EWA projection, SH colour, footprint, per cut entry
 void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
-                       const int32_t *cut_ids, const float *cut_t, const uint32_t *cut_total, uint32_t cap,
-                       SplatRec *recs, uint32_t *depth_key, uint2 *rect, uint32_t *ntiles, uint64_t *vis_mask,
-                       uint32_t *vis_block_counts, int tile_w, int tile_h, hipStream_t st);
+                       const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
+                       SplatRec *recs, double4 *axes, uint32_t *depth_key, uint2 *rect, uint32_t *ntiles,
+                       uint64_t *vis_mask, uint32_t *vis_block_counts, int tile_w, int tile_h, hipStream_t st);
 void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
                             uint32_t cap, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals,
                             hipStream_t st);
@@ -124,16 +128,16 @@ void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
 // blend (tile_w x tile_h pixels per workgroup, `batch` records staged per step)
 bool blend_supported(int tw, int th, int batch);
 void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges, const uint32_t *pair_vals,
-                  const SplatRec *recs, float *T_final, uint32_t *n_last, uint32_t *n_blend, Counters *ctr, int tw,
-                  int th, int batch, hipStream_t st);
+                  const SplatRec *recs, const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend,
+                  Counters *ctr, int tw, int th, int batch, hipStream_t st);
 
 // backward
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges,
-                           const uint32_t *pair_vals, const SplatRec *recs, const float *T_final,
+                           const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                            const uint32_t *n_last, double *sgrad, Counters *ctr, int tw, int th, int batch,
                            hipStream_t st);
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
-                                const int32_t *cut_ids, const float *cut_t, const uint32_t *cut_total, uint32_t cap,
+                                const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
                                 const uint32_t *ntiles, const double *sgrad, float *g_mean, float *g_scale,
                                 float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st);
 

@@ -32,14 +32,14 @@ struct AlphaEval {
 // Staged splat, per 8x8 block of the tile: c = w . (block corner + 1/2 - mean)
 // in FP64, so that a lane only adds w . (its offset inside the block): the
 // result depends on the pixel alone, not on the tile size.
-__device__ __forceinline__ void block_offsets(const SplatRec &r, int bx, int by, float &c1, float &c2, float &dx0,
-                                              float &dy0)
+__device__ __forceinline__ void block_offsets(const SplatRec &r, const double4 &W, int bx, int by, float &c1,
+                                              float &c2, float &dx0, float &dy0)
 {
 #pragma clang fp contract(off)
     const double dx = ((double)(bx - r.ax) + 0.5) - (double)r.fx;
     const double dy = ((double)(by - r.ay) + 0.5) - (double)r.fy;
-    c1 = (float)(dx * (double)r.w1x + dy * (double)r.w1y);
-    c2 = (float)(dx * (double)r.w2x + dy * (double)r.w2y);
+    c1 = (float)(dx * W.x + dy * W.y);
+    c2 = (float)(dx * W.z + dy * W.w);
     dx0 = (float)dx;
     dy0 = (float)dy;
 }
@@ -86,7 +86,8 @@ template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ views, int nv,
                                                   const uint2 *__restrict__ ranges,
                                                   const uint32_t *__restrict__ pair_vals,
-                                                  const SplatRec *__restrict__ recs, float *__restrict__ T_final,
+                                                  const SplatRec *__restrict__ recs,
+                                                  const double4 *__restrict__ axes, float *__restrict__ T_final,
                                                   uint32_t *__restrict__ n_last, uint32_t *__restrict__ n_blend,
                                                   Counters *__restrict__ ctr)
 {
@@ -115,14 +116,16 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
         for (int j = threadIdx.x; j < BATCH; j += NT) {
             const uint32_t idx = b0 + j;
             if (idx < rg.y) {
-                const SplatRec r = recs[pair_vals[idx]];
+                const uint32_t sidx = pair_vals[idx];
+                const SplatRec r = recs[sidx];
+                const double4 W64 = axes[sidx];
                 s_w[j] = make_float4(r.w1x, r.w1y, r.w2x, r.w2y);
                 s_o[j] = make_float4(r.An, r.Ap, r.t, r.invK);
                 s_c[j] = make_float4(r.r, r.g, r.b, 0.0f);
 #pragma unroll
                 for (int bk = 0; bk < NB; ++bk) {
                     float c1, c2, d0, d1;
-                    block_offsets(r, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
+                    block_offsets(r, W64, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
                     s_u[bk][j] = make_float2(c1, c2);
                 }
             }
@@ -192,6 +195,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                                                       const uint2 *__restrict__ ranges,
                                                       const uint32_t *__restrict__ pair_vals,
                                                       const SplatRec *__restrict__ recs,
+                                                      const double4 *__restrict__ axes,
                                                       const float *__restrict__ T_final,
                                                       const uint32_t *__restrict__ n_last,
                                                       double *__restrict__ sgrad, Counters *__restrict__ ctr)
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
     constexpr int NB = (TW / 8) * (TH / 8);
     constexpr float kInvHL2e = (float)(1.0 / kHalfLog2e);
     __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
-    __shared__ float4 s_u[NB][BATCH];  // c1, c2, dx0, dy0
+    __shared__ float2 s_u[NB][BATCH];  // c1, c2
     __shared__ uint32_t s_id[BATCH];
     __shared__ double s_g[BATCH][kG];
     __shared__ uint32_t s_max;
@@ -245,6 +249,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
         for (int j = threadIdx.x; j < cnt; j += NT) {
             const uint32_t sidx = pair_vals[lo + j];
             const SplatRec r = recs[sidx];
+            const double4 W64 = axes[sidx];
             s_id[j] = sidx;
             s_w[j] = make_float4(r.w1x, r.w1y, r.w2x, r.w2y);
             s_o[j] = make_float4(r.An, r.Ap, r.t, r.invK);
@@ -252,8 +257,8 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
 #pragma unroll
             for (int bk = 0; bk < NB; ++bk) {
                 float c1, c2, d0, d1;
-                block_offsets(r, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
-                s_u[bk][j] = make_float4(c1, c2, d0, d1);
+                block_offsets(r, W64, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
+                s_u[bk][j] = make_float2(c1, c2);
             }
 #pragma unroll
             for (int q = 0; q < kG; ++q) s_g[j][q] = 0.0;
@@ -262,11 +267,11 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
         for (int j = cnt - 1; j >= 0; --j) {
             const uint32_t li = lo - rg.x + (uint32_t)j;
             const float4 Wv = s_w[j], Ov = s_o[j];
-            const float4 U = s_u[w][j];
+            const float2 U = s_u[w][j];
             AlphaEval e;
             bool contrib = false;
             if (li < last) {
-                eval_alpha(Wv, Ov, make_float2(U.x, U.y), lx, ly, e);
+                eval_alpha(Wv, Ov, U, lx, ly, e);
                 contrib = e.alpha >= kAlphaMin;
                 ++ne;
                 net += Ov.z > 0.0f;
@@ -305,16 +310,18 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                     v[6] = dap * e.G;
                     dG += dap * Ov.y;
                 }
-                // G = exp(-q/2), q = d^T conic d, d = pixel - mean
+                // G = exp(-q/2), q = d^T conic d, d = pixel - mean.  With g = conic d
+                // = (u1 w1 + u2 w2) / kHalfLog2e:  dq/dmean = -2 g, and through the
+                // conic (the inverse of Sigma2'), dL/dSigma2' = -sum dL/dq g g^T;
+                // accumulated as (a, b, c) = (xx, 2 xy, yy) of that symmetric matrix.
                 const float dq = -0.5f * e.G * dG;
-                const float dx = U.z + lx, dy = U.w + ly;
-                v[2] = dq * dx * dx;
-                v[3] = 2.0f * dq * dx * dy;
-                v[4] = dq * dy * dy;
-                // conic d = (u1 w1 + u2 w2) / kHalfLog2e; dq/dmean = -2 conic d
-                const float k2 = -2.0f * kInvHL2e * dq;
-                v[0] = k2 * (e.u1 * Wv.x + e.u2 * Wv.z);
-                v[1] = k2 * (e.u1 * Wv.y + e.u2 * Wv.w);
+                const float gx = kInvHL2e * (e.u1 * Wv.x + e.u2 * Wv.z);
+                const float gy = kInvHL2e * (e.u1 * Wv.y + e.u2 * Wv.w);
+                v[0] = -2.0f * dq * gx;
+                v[1] = -2.0f * dq * gy;
+                v[2] = -dq * gx * gx;
+                v[3] = -2.0f * dq * gx * gy;
+                v[4] = -dq * gy * gy;
             }
 #pragma unroll
             for (int q = 0; q < 11; ++q) {
@@ -347,22 +354,22 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
 
 template <int TW, int TH, int BATCH>
 void launch_blend_t(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges, const uint32_t *pair_vals,
-                    const SplatRec *recs, float *T_final, uint32_t *n_last, uint32_t *n_blend, Counters *ctr,
-                    hipStream_t st)
+                    const SplatRec *recs, const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend,
+                    Counters *ctr, hipStream_t st)
 {
     hipLaunchKernelGGL((k_blend<TW, TH, BATCH>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, ranges, pair_vals,
-                       recs, T_final, n_last, n_blend, ctr);
+                       recs, axes, T_final, n_last, n_blend, ctr);
 }
 
 template <int TW, int TH, int BATCH>
 void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges,
-                        const uint32_t *pair_vals, const SplatRec *recs, const float *T_final,
+                        const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                         const uint32_t *n_last, double *sgrad, Counters *ctr, hipStream_t st)
 {
     // the backward stages at most 256 splats per step (its LDS holds FP64 partial sums)
     constexpr int B = BATCH < 256 ? BATCH : 256;
     hipLaunchKernelGGL((k_blend_bwd<TW, TH, B>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, ranges,
-                       pair_vals, recs, T_final, n_last, sgrad, ctr);
+                       pair_vals, recs, axes, T_final, n_last, sgrad, ctr);
 }
 
 }  // namespace
@@ -382,21 +389,21 @@ bool blend_supported(int tw, int th, int batch)
 }
 
 void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges, const uint32_t *pair_vals,
-                  const SplatRec *recs, float *T_final, uint32_t *n_last, uint32_t *n_blend, Counters *ctr, int tw,
-                  int th, int batch, hipStream_t st)
+                  const SplatRec *recs, const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend,
+                  Counters *ctr, int tw, int th, int batch, hipStream_t st)
 {
     if (batch == 0) batch = tw * th;
     if (!n_tiles) return;
 #define X(a, b, c)                                                                                           \
     if (tw == a && th == b && batch == c)                                                                    \
-        return launch_blend_t<a, b, c>(views, nv, n_tiles, ranges, pair_vals, recs, T_final, n_last, n_blend, \
-                                       ctr, st);
+        return launch_blend_t<a, b, c>(views, nv, n_tiles, ranges, pair_vals, recs, axes, T_final, n_last, \
+                                       n_blend, ctr, st);
     HGS_BLEND_CASES(X)
 #undef X
 }
 
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges,
-                           const uint32_t *pair_vals, const SplatRec *recs, const float *T_final,
+                           const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                            const uint32_t *n_last, double *sgrad, Counters *ctr, int tw, int th, int batch,
                            hipStream_t st)
 {
@@ -404,8 +411,8 @@ void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const
     if (!n_tiles) return;
 #define X(a, b, c)                                                                                                 \
     if (tw == a && th == b && batch == c)                                                                          \
-        return launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, ranges, pair_vals, recs, T_final, n_last, sgrad, ctr, \
-                                           st);
+        return launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, ranges, pair_vals, recs, axes, T_final, n_last, \
+                                           sgrad, ctr, st);
     HGS_BLEND_CASES(X)
 #undef X
 }

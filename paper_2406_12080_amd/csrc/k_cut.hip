@@ -90,27 +90,26 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_flags(DevHier h, const DevV
     for (int v = threadIdx.x; v < nv; v += kCutThreads) block_counts[(int64_t)v * nblocks + blockIdx.x] = s_cnt[v];
 }
 
-__device__ __forceinline__ float cut_weight(const DevHier &h, const DevView &V, int64_t i)
+__device__ __forceinline__ double cut_weight(const DevHier &h, const DevView &V, int64_t i)
 {
 #pragma clang fp contract(off)
     const uint32_t par = h.pinfo[i] & ~kLeafBit;
-    if (par == kRootParent) return 0.0f;
+    if (par == kRootParent) return 0.0;
     float b[6], pb[6];
     load_box(h, i, b);
     load_box(h, par, pb);
     const double en = granularity(b, V);
     const double ep = granularity(pb, V);
-    if (__builtin_isinf(ep) || !(ep > en)) return 0.0f;
+    if (__builtin_isinf(ep) || !(ep > en)) return 0.0;
     double t = ((double)V.tau - en) / (ep - en);
-    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-    return (float)t;
+    return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
 }
 
 __global__ __launch_bounds__(kCutThreads) void k_cut_emit(DevHier h, const DevView *__restrict__ views,
                                                           const uint64_t *__restrict__ masks,
                                                           const uint32_t *__restrict__ block_offsets, int nblocks,
                                                           int32_t *__restrict__ out_ids, float *__restrict__ out_t,
-                                                          uint32_t cap)
+                                                          double *__restrict__ out_t64, uint32_t cap)
 {
     constexpr int W = kCutBlock / 64;
     __shared__ uint64_t s_word[W];
@@ -150,7 +149,11 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_emit(DevHier h, const DevVi
         if (pos >= cap) continue;
         const int64_t i = (int64_t)blockIdx.x * kCutBlock + local;
         out_ids[pos] = (int32_t)i;
-        if (out_t) out_t[pos] = cut_weight(h, V, i);
+        if (out_t || out_t64) {
+            const double t = cut_weight(h, V, i);
+            if (out_t) out_t[pos] = (float)t;
+            if (out_t64) out_t64[pos] = t;
+        }
     }
 }
 
@@ -170,11 +173,11 @@ void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *
 }
 
 void launch_cut_emit(const DevHier &h, const DevView *views, int nv, const uint64_t *masks,
-                     const uint32_t *block_offsets, int nblocks, int32_t *out_ids, float *out_t, uint32_t cap,
-                     hipStream_t st)
+                     const uint32_t *block_offsets, int nblocks, int32_t *out_ids, float *out_t, double *out_t64,
+                     uint32_t cap, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cut_emit, dim3(nblocks, nv), dim3(kCutThreads), 0, st, h, views, masks, block_offsets,
-                       nblocks, out_ids, out_t, cap);
+                       nblocks, out_ids, out_t, out_t64, cap);
 }
 
 void launch_cut_finish(const uint32_t *block_offsets, const uint32_t *, int nblocks, int nv, uint32_t *cut_base,

@@ -25,9 +25,10 @@ __device__ __forceinline__ int view_of(const uint32_t *cut_base, int nv, uint32_
 __global__ __launch_bounds__(kT) void k_preprocess(DevHier h, const DevView *__restrict__ views, int nv,
                                                    const uint32_t *__restrict__ cut_base,
                                                    const int32_t *__restrict__ cut_ids,
-                                                   const float *__restrict__ cut_t,
+                                                   const double *__restrict__ cut_t,
                                                    const uint32_t *__restrict__ cut_total, uint32_t cap,
-                                                   SplatRec *__restrict__ recs, uint32_t *__restrict__ depth_key,
+                                                   SplatRec *__restrict__ recs, double4 *__restrict__ axes,
+                                                   uint32_t *__restrict__ depth_key,
                                                    uint2 *__restrict__ rect, uint32_t *__restrict__ ntiles,
                                                    uint64_t *__restrict__ vis_mask,
                                                    uint32_t *__restrict__ vis_block_counts, int tile_w, int tile_h)
@@ -76,10 +77,12 @@ __global__ __launch_bounds__(kT) void k_preprocess(DevHier h, const DevView *__r
                     const double l1 = ca * cs * cs + 2.0 * cb * sn * cs + cc * sn * sn;
                     const double l2 = ca * sn * sn - 2.0 * cb * sn * cs + cc * cs * cs;
                     const double s1 = sqrt(fmax(l1, 0.0) * kHalfLog2e), s2 = sqrt(fmax(l2, 0.0) * kHalfLog2e);
-                    r.w1x = (float)(s1 * cs);
-                    r.w1y = (float)(s1 * sn);
-                    r.w2x = (float)(-s2 * sn);
-                    r.w2y = (float)(s2 * cs);
+                    const double4 ax4 = make_double4(s1 * cs, s1 * sn, -s2 * sn, s2 * cs);
+                    axes[k] = ax4;
+                    r.w1x = (float)ax4.x;
+                    r.w1y = (float)ax4.y;
+                    r.w2x = (float)ax4.z;
+                    r.w2y = (float)ax4.w;
                     r.An = (float)(P.kappa * P.o_n);
                     r.Ap = (float)(P.kappa * P.o_p);
                     r.t = (float)P.t;
@@ -189,7 +192,7 @@ __device__ __forceinline__ void add(float *p, double v)
 __global__ __launch_bounds__(kT) void k_preprocess_bwd(DevHier h, const DevView *__restrict__ views, int nv,
                                                        const uint32_t *__restrict__ cut_base,
                                                        const int32_t *__restrict__ cut_ids,
-                                                       const float *__restrict__ cut_t,
+                                                       const double *__restrict__ cut_t,
                                                        const uint32_t *__restrict__ cut_total, uint32_t cap,
                                                        const uint32_t *__restrict__ ntiles,
                                                        const double *__restrict__ sgrad, float *__restrict__ g_mean,
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(kT) void k_preprocess_bwd(DevHier h, const DevView 
         return;
     }
     const double *sg = sgrad + (size_t)k * 12;
-    const double du = sg[0], dv = sg[1], gca = sg[2], gcb = sg[3], gcc = sg[4], dAn = sg[5], dAp = sg[6];
+    const double du = sg[0], dv = sg[1], dAn = sg[5], dAp = sg[6];
     const double drgb[3] = {sg[7], sg[8], sg[9]};
     double dt = sg[10];
     const int vi = view_of(cut_base, nv, k);
@@ -256,13 +259,13 @@ __global__ __launch_bounds__(kT) void k_preprocess_bwd(DevHier h, const DevView 
     const double dkappa = dAn * P.o_n + dAp * P.o_p;
     const double don = dAn * P.kappa, dop = dAp * P.kappa;
 
-    // conic = inverse of Sigma2 + hI, kappa = sqrt(det Sigma2 / det(Sigma2 + hI))
+    // dL/d(a, b, c) of Sigma2 through the conic arrives accumulated per pixel
+    // (the blend backward sums -dL/dq (conic d)(conic d)^T); add the part
+    // through kappa = sqrt(det Sigma2 / det(Sigma2 + hI))
     const double a = P.a, b = P.b, c = P.c;
     const double ad = a + kDilation, cd = c + kDilation;
-    const double Dd = P.Dd, D = P.D, iD2 = 1.0 / (Dd * Dd);
-    double da = gca * (-cd * cd * iD2) + gcb * (b * cd * iD2) + gcc * (1.0 / Dd - ad * cd * iD2);
-    double dc = gca * (1.0 / Dd - ad * cd * iD2) + gcb * (b * ad * iD2) + gcc * (-ad * ad * iD2);
-    double db = gca * (2.0 * b * cd * iD2) + gcb * (-1.0 / Dd - 2.0 * b * b * iD2) + gcc * (2.0 * b * ad * iD2);
+    const double Dd = P.Dd, D = P.D;
+    double da = sg[2], db = sg[3], dc = sg[4];
     if (D > 0.0 && P.kappa > 0.0) {
         const double hk = 0.5 * P.kappa * dkappa;
         da += hk * (c / D - cd / Dd);
@@ -374,14 +377,14 @@ __global__ __launch_bounds__(kT) void k_preprocess_bwd(DevHier h, const DevView 
 }  // namespace
 
 void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
-                       const int32_t *cut_ids, const float *cut_t, const uint32_t *cut_total, uint32_t cap,
-                       SplatRec *recs, uint32_t *depth_key, uint2 *rect, uint32_t *ntiles, uint64_t *vis_mask,
-                       uint32_t *vis_block_counts, int tile_w, int tile_h, hipStream_t st)
+                       const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
+                       SplatRec *recs, double4 *axes, uint32_t *depth_key, uint2 *rect, uint32_t *ntiles,
+                       uint64_t *vis_mask, uint32_t *vis_block_counts, int tile_w, int tile_h, hipStream_t st)
 {
     const uint32_t blocks = (cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(kT), 0, st, h, views, nv, cut_base, cut_ids, cut_t, cut_total,
-                       cap, recs, depth_key, rect, ntiles, vis_mask, vis_block_counts, tile_w, tile_h);
+                       cap, recs, axes, depth_key, rect, ntiles, vis_mask, vis_block_counts, tile_w, tile_h);
 }
 
 void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
@@ -421,7 +424,7 @@ void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st)
 }
 
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
-                                const int32_t *cut_ids, const float *cut_t, const uint32_t *cut_total, uint32_t cap,
+                                const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
                                 const uint32_t *ntiles, const double *sgrad, float *g_mean, float *g_scale,
                                 float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st)
 {

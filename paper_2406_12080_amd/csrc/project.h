@@ -94,7 +94,7 @@ struct Proj {
 
 // Gathers node and parent, interpolates, projects; computes the colour only
 // when with_colour (the backward recomputes it on the fly).
-__device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V, uint32_t node, float t_in,
+__device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V, uint32_t node, double t_in,
                                               Proj &P, bool with_colour)
 {
     const int64_t n = h.n;
@@ -102,7 +102,7 @@ __device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V
     const uint32_t pi = h.pinfo[node];
     const uint32_t par = pi & ~kLeafBit;
     P.has_par = par != kRootParent;
-    P.t = P.has_par ? (double)t_in : 0.0;
+    P.t = P.has_par ? t_in : 0.0;
     const bool use_par = P.has_par && P.t > 0.0;
     P.par = P.has_par ? par : node;
     P.K = P.has_par ? h.child_count[par] : 1;

@@ -440,7 +440,8 @@ def _perm_trace_index():
 _PT_IDX, _PT_SG = _perm_trace_index()
 
 
-def build_hierarchy(leaves: dict, collapse_chains: bool = False) -> Hierarchy:
+def build_hierarchy(leaves: dict, collapse_chains: bool = False, progress=None) -> Hierarchy:
+    say = progress or (lambda msg: None)
     pos = np.asarray(leaves["pos"], np.float64)
     n = pos.shape[0]
     codes = _morton(pos)
@@ -449,6 +450,7 @@ def build_hierarchy(leaves: dict, collapse_chains: bool = False) -> Hierarchy:
 
     parent, child_begin, child_count, lo_all, hi_all, first = build_topology(codes, collapse_chains)
     N = parent.shape[0]
+    say(f"topology: {N} nodes in {len(first) - 1} levels")
     is_leaf = child_count == 0
     leaf_nodes = np.nonzero(is_leaf)[0]
     assert np.all(hi_all[leaf_nodes] - lo_all[leaf_nodes] == 1)
@@ -517,6 +519,7 @@ def build_hierarchy(leaves: dict, collapse_chains: bool = False) -> Hierarchy:
             op[nd] = wsum / sp                           # falloff, may exceed 1
 
         _par(merge, inner.shape[0], chunk=1 << 18)
+        say(f"merged level {lv} ({inner.shape[0]} interior nodes)")
 
     # top-down orientation matching
     for lv in range(1, nlev):
@@ -533,6 +536,7 @@ def build_hierarchy(leaves: dict, collapse_chains: bool = False) -> Hierarchy:
 
         _par(match, hi - lo, chunk=1 << 18)
 
+    say("orientation matching done")
     q = np.empty((N, 4))
 
     def quats(a, b):
@@ -642,11 +646,14 @@ CONFIGS = {
 
 
 def make_scene(config: int, seed: int | None = None, n_leaves: int | None = None,
-               collapse_chains: bool = False) -> Hierarchy:
+               collapse_chains: bool = False, progress=None) -> Hierarchy:
     c = CONFIGS[config]
     n = n_leaves if n_leaves is not None else c["leaves"]
     seed = config if seed is None else seed
-    return build_hierarchy(make_leaves(n, c["layout"], seed), collapse_chains=collapse_chains)
+    leaves = make_leaves(n, c["layout"], seed)
+    if progress:
+        progress(f"{n} leaves drawn")
+    return build_hierarchy(leaves, collapse_chains=collapse_chains, progress=progress)
 
 
 def make_views(config: int, seed: int | None = None, headline: bool = False,
