@@ -87,6 +87,8 @@ struct hgs_ctx {
     float *T_final = nullptr;
     uint32_t *n_last = nullptr, *n_blend = nullptr;
     double *sgrad = nullptr;
+    float *pgrad = nullptr;  // per cut entry, 32 floats
+    float *cjac = nullptr;   // per cut entry, 12 floats: d colour / d dir, parent - node colour
 
     // state of the last render
     bool have_render = false;
@@ -323,6 +325,8 @@ hgs_status ensure_cut_cap(hgs_ctx *ctx, uint32_t cap)
     if ((s = realloc_buf(ctx, ctx->svals, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->pair_offsets, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->sgrad, (size_t)cap * 12))) return s;
+    if ((s = realloc_buf(ctx, ctx->pgrad, (size_t)cap * 32))) return s;
+    if ((s = realloc_buf(ctx, ctx->cjac, (size_t)cap * 12))) return s;
     ctx->cut_cap = cap;
     const size_t scratch = std::max<size_t>(ctx->cut_cap, ctx->pair_cap);
     if ((s = realloc_buf(ctx, ctx->k2, scratch))) return s;
@@ -378,7 +382,8 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     launch_cut_finish(ctx->blk_offsets, ctx->blk_counts, nb, nv, ctx->cut_base, ctx->ctr, st);
     mark(1);
     launch_preprocess(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t, &ctx->ctr->cut_total,
-                      ctx->cut_cap, ctx->recs, ctx->axes, ctx->depth_key, ctx->rect, ctx->ntiles, ctx->vis_mask,
+                      ctx->cut_cap, ctx->recs, ctx->axes, ctx->depth_key, ctx->rect, ctx->ntiles, ctx->cjac,
+                      ctx->vis_mask,
                       ctx->vis_counts, ctx->tile_w, ctx->tile_h, st);
     mark(2);
     const uint32_t vblocks = (ctx->cut_cap + 255) / 256;
@@ -789,8 +794,9 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_gr
     {
         KernelTimer kt(ctx, 2, st);
         launch_preprocess_backward(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t,
-                                   &ctx->ctr->cut_total, ctx->cut_cap, ctx->ntiles, ctx->sgrad, out->mean, out->scale,
-                                   out->rot, out->opacity, out->sh, out->dt, st);
+                                   &ctx->ctr->cut_total, ctx->cut_cap, ctx->ntiles, ctx->recs, ctx->cjac, ctx->sgrad,
+                                   ctx->pgrad, out->mean,
+                                   out->scale, out->rot, out->opacity, out->sh, out->dt, st);
     }
     HIPC(hipGetLastError());
     // host copy of views keeps dL for nothing else

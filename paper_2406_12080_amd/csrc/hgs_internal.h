@@ -113,7 +113,8 @@ bool launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t cap, const uint3
 void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                        const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
                        SplatRec *recs, double4 *axes, uint32_t *depth_key, uint2 *rect, uint32_t *ntiles,
-                       uint64_t *vis_mask, uint32_t *vis_block_counts, int tile_w, int tile_h, hipStream_t st);
+                       float *cjac, uint64_t *vis_mask, uint32_t *vis_block_counts, int tile_w, int tile_h,
+                       hipStream_t st);
 void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
                             uint32_t cap, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals,
                             hipStream_t st);
@@ -138,8 +139,9 @@ void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const
                            hipStream_t st);
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
-                                const uint32_t *ntiles, const double *sgrad, float *g_mean, float *g_scale,
-                                float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st);
+                                const uint32_t *ntiles, const SplatRec *recs, const float *cjac, const double *sgrad,
+                                float *pg, float *g_mean, float *g_scale, float *g_rot, float *g_opacity, float *g_sh,
+                                float *g_dt, hipStream_t st);
 
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ uint64_t lanemask_lt()

@@ -16,8 +16,8 @@
 // The backward walks each tile back to front from the final transmittance
 // and the index of the last contributor of each pixel, recovering the
 // transmittance in front of every splat by division (no per-pixel lists),
-// reduces each splat's gradient over the wave and the workgroup, and adds it
-// once per tile to the splat's screen-space gradient.
+// reduces each splat's gradient over the wave (FP32) and the workgroup, and
+// adds it once per tile, in FP64, to the splat's screen-space gradient.
 #include "hgs_internal.h"
 
 namespace hgs {
@@ -181,11 +181,37 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
     }
 }
 
-__device__ __forceinline__ float wave_sum(float x)
+// Reduce-scatter of 16 per-lane values over a 64-lane wave: each exchange
+// step halves the values a lane holds while summing its partner's half, so
+// the whole reduction takes 8+4+2+1+1+1 = 17 shuffles instead of 16 x 6.
+// Afterwards lane l with (l & 3) == 0 holds the total of slot l >> 2 in v[0].
+__device__ __forceinline__ void wave_reduce16(float (&v)[16], int lane)
 {
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    return x;
+    for (int i = 0; i < 8; ++i) {
+        const bool up = (lane & 32) != 0;
+        const float keep = up ? v[8 + i] : v[i], send = up ? v[i] : v[8 + i];
+        v[i] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool up = (lane & 16) != 0;
+        const float keep = up ? v[4 + i] : v[i], send = up ? v[i] : v[4 + i];
+        v[i] = keep + __shfl_xor(send, 16, 64);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const bool up = (lane & 8) != 0;
+        const float keep = up ? v[2 + i] : v[i], send = up ? v[i] : v[2 + i];
+        v[i] = keep + __shfl_xor(send, 8, 64);
+    }
+    {
+        const bool up = (lane & 4) != 0;
+        const float keep = up ? v[1] : v[0], send = up ? v[0] : v[1];
+        v[0] = keep + __shfl_xor(send, 4, 64);
+    }
+    v[0] += __shfl_xor(v[0], 2, 64);
+    v[0] += __shfl_xor(v[0], 1, 64);
 }
 
 constexpr int kG = 12;  // floats per splat in the screen-space gradient
@@ -207,7 +233,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
     __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
     __shared__ float2 s_u[NB][BATCH];  // c1, c2
     __shared__ uint32_t s_id[BATCH];
-    __shared__ double s_g[BATCH][kG];
+    __shared__ float s_g[BATCH][kG];
     __shared__ uint32_t s_max;
     const uint32_t tile = blockIdx.x;
     const int vi = view_of_tile(views, nv, tile);
@@ -261,7 +287,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                 s_u[bk][j] = make_float2(c1, c2);
             }
 #pragma unroll
-            for (int q = 0; q < kG; ++q) s_g[j][q] = 0.0;
+            for (int q = 0; q < kG; ++q) s_g[j][q] = 0.0f;
         }
         __syncthreads();
         for (int j = cnt - 1; j >= 0; --j) {
@@ -278,13 +304,13 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                 nc += contrib;
             }
             if (__ballot(contrib) == 0ull) continue;
-            float v[11];
+            float v[16];
 #pragma unroll
-            for (int q = 0; q < 11; ++q) v[q] = 0.0f;
+            for (int q = 0; q < 16; ++q) v[q] = 0.0f;
             if (contrib) {
                 const float4 Cc = s_c[j];
                 const float a = e.alpha;
-                T = T / (1.0f - a);
+                T = __fdividef(T, 1.0f - a);
                 const float dal = T * ((Cc.x - R0) * g0 + (Cc.y - R1) * g1 + (Cc.z - R2) * g2);
                 const float aT = a * T;
                 v[7] = aT * g0;
@@ -323,17 +349,15 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                 v[3] = -2.0f * dq * gx * gy;
                 v[4] = -dq * gy * gy;
             }
-#pragma unroll
-            for (int q = 0; q < 11; ++q) {
-                const float sm = wave_sum(v[q]);
-                if (lane == 0 && sm != 0.0f) atomicAdd(&s_g[j][q], (double)sm);
-            }
+            wave_reduce16(v, lane);
+            const int slot = lane >> 2;
+            if ((lane & 3) == 0 && slot < 11 && v[0] != 0.0f) atomicAdd(&s_g[j][slot], v[0]);
         }
         __syncthreads();
         for (int idx = threadIdx.x; idx < cnt * 11; idx += NT) {
             const int j = idx / 11, q = idx % 11;
-            const double sm = s_g[j][q];
-            if (sm != 0.0) unsafeAtomicAdd(&sgrad[(size_t)s_id[j] * kG + q], sm);
+            const float sm = s_g[j][q];
+            if (sm != 0.0f) unsafeAtomicAdd(&sgrad[(size_t)s_id[j] * kG + q], (double)sm);
         }
         __syncthreads();
         hi = lo;

@@ -10,6 +10,10 @@ namespace {
 
 constexpr int kT = 256;
 constexpr double kAlphaMinD = 1.0 / 255.0;
+// per cut entry, gradient w.r.t. the interpolated attributes: mean 0..2,
+// scale 3..5, raw quaternion 6..9, node opacity 10, parent opacity 11,
+// colour cotangent 12..14, SH basis 15..30, live flag 31
+constexpr int kPG = 32;
 
 __device__ __forceinline__ int view_of(const uint32_t *cut_base, int nv, uint32_t k)
 {
@@ -22,7 +26,7 @@ __device__ __forceinline__ int view_of(const uint32_t *cut_base, int nv, uint32_
     return lo;
 }
 
-__global__ __launch_bounds__(kT) void k_preprocess(DevHier h, const DevView *__restrict__ views, int nv,
+__global__ __launch_bounds__(kT, 3) void k_preprocess(DevHier h, const DevView *__restrict__ views, int nv,
                                                    const uint32_t *__restrict__ cut_base,
                                                    const int32_t *__restrict__ cut_ids,
                                                    const double *__restrict__ cut_t,
@@ -30,7 +34,7 @@ __global__ __launch_bounds__(kT) void k_preprocess(DevHier h, const DevView *__r
                                                    SplatRec *__restrict__ recs, double4 *__restrict__ axes,
                                                    uint32_t *__restrict__ depth_key,
                                                    uint2 *__restrict__ rect, uint32_t *__restrict__ ntiles,
-                                                   uint64_t *__restrict__ vis_mask,
+                                                   float *__restrict__ cjac, uint64_t *__restrict__ vis_mask,
                                                    uint32_t *__restrict__ vis_block_counts, int tile_w, int tile_h)
 {
     __shared__ uint32_t s_cnt;
@@ -93,6 +97,14 @@ __global__ __launch_bounds__(kT) void k_preprocess(DevHier h, const DevView *__r
                     r.node = P.node;
                     recs[k] = r;
                     depth_key[k] = __float_as_uint((float)P.pc[2]);
+                    float *cj = cjac + (size_t)k * 12;
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) {
+                        cj[3 * ch] = (float)P.dcol[ch][0];
+                        cj[3 * ch + 1] = (float)P.dcol[ch][1];
+                        cj[3 * ch + 2] = (float)P.dcol[ch][2];
+                        cj[9 + ch] = (float)P.dpn[ch];
+                    }
                 }
             }
         }
@@ -184,25 +196,26 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
 }
 
 // ------------------------------------------------------------------ backward
-__device__ __forceinline__ void add(float *p, double v)
+__device__ __forceinline__ void add(float *p, float v)
 {
-    if (v != 0.0) unsafeAtomicAdd(p, (float)v);
+    if (v != 0.0f) unsafeAtomicAdd(p, v);
 }
 
-__global__ __launch_bounds__(kT) void k_preprocess_bwd(DevHier h, const DevView *__restrict__ views, int nv,
+__global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevView *__restrict__ views, int nv,
                                                        const uint32_t *__restrict__ cut_base,
                                                        const int32_t *__restrict__ cut_ids,
                                                        const double *__restrict__ cut_t,
                                                        const uint32_t *__restrict__ cut_total, uint32_t cap,
                                                        const uint32_t *__restrict__ ntiles,
-                                                       const double *__restrict__ sgrad, float *__restrict__ g_mean,
-                                                       float *__restrict__ g_scale, float *__restrict__ g_rot,
-                                                       float *__restrict__ g_op, float *__restrict__ g_sh,
+                                                       const SplatRec *__restrict__ recs,
+                                                       const float *__restrict__ cjac,
+                                                       const double *__restrict__ sgrad, float *__restrict__ pg,
                                                        float *__restrict__ g_dt)
 {
     const uint32_t total = min(*cut_total, cap);
     const uint32_t k = blockIdx.x * kT + threadIdx.x;
     if (k >= total) return;
+    float *out = pg + (size_t)k * kPG;
     if (ntiles[k] == 0) {
         if (g_dt) g_dt[k] = 0.0f;
         return;
@@ -214,40 +227,43 @@ __global__ __launch_bounds__(kT) void k_preprocess_bwd(DevHier h, const DevView 
     const int vi = view_of(cut_base, nv, k);
     const DevView &V = views[vi];
     Proj P;
-    project_splat(h, V, (uint32_t)cut_ids[k], cut_t[k], P, true);
-    if (!P.ok) return;
+    project_splat(h, V, (uint32_t)cut_ids[k], cut_t[k], P, false);
+    if (!P.ok) {
+        out[kPG - 1] = 0.0f;
+        if (g_dt) g_dt[k] = 0.0f;
+        return;
+    }
     const int64_t n = h.n;
     const uint32_t node = P.node, par = P.par;
     const bool node_leaf = (h.pinfo[node] & kLeafBit) != 0;
     const bool use_par = P.has_par && P.t > 0.0;
     const double t = P.t, w0 = 1.0 - t;
 
-    // colour: rgb = max(0, raw)
+    // colour: rgb = max(0, raw); the forward kept rgb, d raw / d dir and
+    // (SH_p - SH_n) . Y per channel
+    const SplatRec rec = recs[k];
+    const float *cj = cjac + (size_t)k * 12;
     double gr[3];
+    gr[0] = rec.r > 0.0f ? drgb[0] : 0.0;
+    gr[1] = rec.g > 0.0f ? drgb[1] : 0.0;
+    gr[2] = rec.b > 0.0f ? drgb[2] : 0.0;
+    double ddir[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gr[c] = P.raw[c] > 0.0 ? drgb[c] : 0.0;
-    double Y[16], Bw[16];
-    sh_eval(P.dir[0], P.dir[1], P.dir[2], Y);
-#pragma unroll 2
-    for (int kk = 0; kk < 16; ++kk) {
-        Bw[kk] = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int row = 3 * kk + c;
-            const double cn = h.sh[row * n + node];
-            const double cp = use_par ? (double)h.sh[row * n + par] : cn;
-            const double sht = w0 * cn + t * cp;
-            const double dsh = gr[c] * Y[kk];
-            Bw[kk] += gr[c] * sht;
-            if (!node_leaf) add(&g_sh[row * n + node], w0 * dsh);
-            if (use_par) {
-                add(&g_sh[row * n + par], t * dsh);
-                dt += dsh * (cp - cn);
-            }
-        }
+    for (int c = 0; c < 3; ++c) {
+        ddir[0] += gr[c] * (double)cj[3 * c];
+        ddir[1] += gr[c] * (double)cj[3 * c + 1];
+        ddir[2] += gr[c] * (double)cj[3 * c + 2];
+        if (use_par) dt += gr[c] * (double)cj[9 + c];
     }
-    double ddir[3];
-    sh_grad_dot(P.dir[0], P.dir[1], P.dir[2], Bw, ddir);
+    {
+        double Y[16];
+        sh_eval(P.dir[0], P.dir[1], P.dir[2], Y);
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) out[15 + kk] = (float)Y[kk];
+    }
+    out[12] = (float)gr[0];
+    out[13] = (float)gr[1];
+    out[14] = (float)gr[2];
     double dmu[3];
     {
         const double dd = P.dir[0] * ddir[0] + P.dir[1] * ddir[1] + P.dir[2] * ddir[2];
@@ -346,32 +362,104 @@ __global__ __launch_bounds__(kT) void k_preprocess_bwd(DevHier h, const DevView 
 #pragma unroll
     for (int m = 0; m < 4; ++m) dqr[m] = (dq[m] - P.q[m] * qd) / P.qlen;
 
-    // interpolation: node (1 - t), parent t; leaves are frozen
+    // gradient with respect to the interpolated attributes; the scatter
+    // kernel weights it by (1 - t) for the node and t for the parent
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        if (!node_leaf) {
-            add(&g_mean[m * n + node], w0 * dmu[m]);
-            add(&g_scale[m * n + node], w0 * ds[m]);
-        }
+        out[m] = (float)dmu[m];
+        out[3 + m] = (float)ds[m];
         if (use_par) {
-            add(&g_mean[m * n + par], t * dmu[m]);
-            add(&g_scale[m * n + par], t * ds[m]);
             dt += dmu[m] * ((double)h.mean[m * n + par] - (double)h.mean[m * n + node]);
             dt += ds[m] * ((double)h.scale[m * n + par] - (double)h.scale[m * n + node]);
         }
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        if (!node_leaf) add(&g_rot[m * n + node], w0 * dqr[m]);
-        if (use_par) {
-            add(&g_rot[m * n + par], t * dqr[m]);
-            dt += dqr[m] * ((double)h.rot[m * n + par] - (double)h.rot[m * n + node]);
-        }
+        out[6 + m] = (float)dqr[m];
+        if (use_par) dt += dqr[m] * ((double)h.rot[m * n + par] - (double)h.rot[m * n + node]);
     }
     // opacity through |o|
-    if (!node_leaf) add(&g_op[node], (P.on_raw > 0.0 ? 1.0 : (P.on_raw < 0.0 ? -1.0 : 0.0)) * don);
-    if (use_par) add(&g_op[par], (P.op_raw > 0.0 ? 1.0 : (P.op_raw < 0.0 ? -1.0 : 0.0)) * dop);
+    out[10] = (float)((P.on_raw > 0.0 ? 1.0 : (P.on_raw < 0.0 ? -1.0 : 0.0)) * don);
+    out[11] = (float)((P.op_raw > 0.0 ? 1.0 : (P.op_raw < 0.0 ? -1.0 : 0.0)) * dop);
+    out[kPG - 1] = 1.0f;
     if (g_dt) g_dt[k] = use_par ? (float)dt : 0.0f;
+}
+
+// Adds each cut entry's attribute gradient to its node, weighted 1 - t
+// (leaves are frozen), and to its parent, weighted t.  Siblings sit next to
+// each other in a view's cut (node ids ascending, children contiguous), so
+// the first entry of every run of equal parents sums the run and issues one
+// set of atomics for the parent.
+__global__ __launch_bounds__(kT) void k_grad_scatter(DevHier h, const int32_t *__restrict__ cut_ids,
+                                                     const double *__restrict__ cut_t,
+                                                     const uint32_t *__restrict__ cut_total, uint32_t cap,
+                                                     const float *__restrict__ pg, float *__restrict__ g_mean,
+                                                     float *__restrict__ g_scale, float *__restrict__ g_rot,
+                                                     float *__restrict__ g_op, float *__restrict__ g_sh)
+{
+    const uint32_t total = min(*cut_total, cap);
+    const uint32_t k = blockIdx.x * kT + threadIdx.x;
+    if (k >= total) return;
+    const int64_t n = h.n;
+    const uint32_t node = (uint32_t)cut_ids[k];
+    const uint32_t pi = h.pinfo[node];
+    const uint32_t par = pi & ~kLeafBit;
+    const float *g = pg + (size_t)k * kPG;
+    const bool live = g[kPG - 1] != 0.0f;
+    const float t = (float)cut_t[k];
+    if (live && !(pi & kLeafBit)) {
+        const float w0 = 1.0f - t;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            add(&g_mean[m * n + node], w0 * g[m]);
+            add(&g_scale[m * n + node], w0 * g[3 + m]);
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) add(&g_rot[m * n + node], w0 * g[6 + m]);
+        add(&g_op[node], g[10]);  // opacity enters alpha directly, not through the lerp
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) add(&g_sh[(3 * kk + c) * n + node], w0 * g[12 + c] * g[15 + kk]);
+    }
+    if (par == kRootParent) return;
+    if (k > 0 && (h.pinfo[cut_ids[k - 1]] & ~kLeafBit) == par) return;  // not the first of its run
+    float am[3] = {0, 0, 0}, as[3] = {0, 0, 0}, aq[4] = {0, 0, 0, 0}, ao = 0.0f;
+    float ash[48];
+#pragma unroll
+    for (int q = 0; q < 48; ++q) ash[q] = 0.0f;
+    bool any = false;
+    for (uint32_t j = k; j < total; ++j) {
+        const uint32_t nj = (uint32_t)cut_ids[j];
+        if ((h.pinfo[nj] & ~kLeafBit) != par) break;
+        const float *gj = pg + (size_t)j * kPG;
+        const float tj = (float)cut_t[j];
+        if (!(tj > 0.0f) || gj[kPG - 1] == 0.0f) continue;
+        any = true;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            am[m] += tj * gj[m];
+            as[m] += tj * gj[3 + m];
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) aq[m] += tj * gj[6 + m];
+        ao += gj[11];  // likewise the parent's opacity (through alpha')
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ash[3 * kk + c] += tj * gj[12 + c] * gj[15 + kk];
+    }
+    if (!any) return;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        add(&g_mean[m * n + par], am[m]);
+        add(&g_scale[m * n + par], as[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) add(&g_rot[m * n + par], aq[m]);
+    add(&g_op[par], ao);
+#pragma unroll
+    for (int q = 0; q < 48; ++q) add(&g_sh[q * n + par], ash[q]);
 }
 
 }  // namespace
@@ -379,12 +467,13 @@ __global__ __launch_bounds__(kT) void k_preprocess_bwd(DevHier h, const DevView 
 void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                        const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
                        SplatRec *recs, double4 *axes, uint32_t *depth_key, uint2 *rect, uint32_t *ntiles,
-                       uint64_t *vis_mask, uint32_t *vis_block_counts, int tile_w, int tile_h, hipStream_t st)
+                       float *cjac, uint64_t *vis_mask, uint32_t *vis_block_counts, int tile_w, int tile_h,
+                       hipStream_t st)
 {
     const uint32_t blocks = (cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(kT), 0, st, h, views, nv, cut_base, cut_ids, cut_t, cut_total,
-                       cap, recs, axes, depth_key, rect, ntiles, vis_mask, vis_block_counts, tile_w, tile_h);
+                       cap, recs, axes, depth_key, rect, ntiles, cjac, vis_mask, vis_block_counts, tile_w, tile_h);
 }
 
 void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
@@ -425,13 +514,16 @@ void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st)
 
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
-                                const uint32_t *ntiles, const double *sgrad, float *g_mean, float *g_scale,
-                                float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st)
+                                const uint32_t *ntiles, const SplatRec *recs, const float *cjac, const double *sgrad,
+                                float *pg, float *g_mean, float *g_scale, float *g_rot, float *g_opacity, float *g_sh,
+                                float *g_dt, hipStream_t st)
 {
     const uint32_t blocks = (cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(kT), 0, st, h, views, nv, cut_base, cut_ids, cut_t,
-                       cut_total, cap, ntiles, sgrad, g_mean, g_scale, g_rot, g_opacity, g_sh, g_dt);
+                       cut_total, cap, ntiles, recs, cjac, sgrad, pg, g_dt);
+    hipLaunchKernelGGL(k_grad_scatter, dim3(blocks), dim3(kT), 0, st, h, cut_ids, cut_t, cut_total, cap, pg, g_mean,
+                       g_scale, g_rot, g_opacity, g_sh);
 }
 
 }  // namespace hgs

@@ -60,6 +60,64 @@ __device__ __forceinline__ void sh_grad_dot(double x, double y, double z, const 
            c14 * (xx - yy) * B[14];
 }
 
+// Basis function k (compile-time after unrolling) and its polynomial gradient.
+__device__ __forceinline__ void sh_term(int k, double x, double y, double z, double &Y, double g[3])
+{
+    const double xx = x * x, yy = y * y, zz = z * z;
+    g[0] = g[1] = g[2] = 0.0;
+    switch (k) {
+    case 0: Y = 0.28209479177387814; break;
+    case 1: Y = 0.4886025119029199 * y; g[1] = 0.4886025119029199; break;
+    case 2: Y = 0.4886025119029199 * z; g[2] = 0.4886025119029199; break;
+    case 3: Y = 0.4886025119029199 * x; g[0] = 0.4886025119029199; break;
+    case 4: Y = 1.0925484305920792 * x * y; g[0] = 1.0925484305920792 * y; g[1] = 1.0925484305920792 * x; break;
+    case 5: Y = 1.0925484305920792 * y * z; g[1] = 1.0925484305920792 * z; g[2] = 1.0925484305920792 * y; break;
+    case 6: Y = 0.31539156525252005 * (3.0 * zz - 1.0); g[2] = 0.31539156525252005 * 6.0 * z; break;
+    case 7: Y = 1.0925484305920792 * x * z; g[0] = 1.0925484305920792 * z; g[2] = 1.0925484305920792 * x; break;
+    case 8:
+        Y = 0.5462742152960396 * (xx - yy);
+        g[0] = 0.5462742152960396 * 2.0 * x;
+        g[1] = -0.5462742152960396 * 2.0 * y;
+        break;
+    case 9:
+        Y = 0.5900435899266435 * y * (3.0 * xx - yy);
+        g[0] = 0.5900435899266435 * 6.0 * x * y;
+        g[1] = 0.5900435899266435 * (3.0 * xx - 3.0 * yy);
+        break;
+    case 10:
+        Y = 2.890611442640554 * x * y * z;
+        g[0] = 2.890611442640554 * y * z;
+        g[1] = 2.890611442640554 * x * z;
+        g[2] = 2.890611442640554 * x * y;
+        break;
+    case 11:
+        Y = 0.4570457994644658 * y * (5.0 * zz - 1.0);
+        g[1] = 0.4570457994644658 * (5.0 * zz - 1.0);
+        g[2] = 0.4570457994644658 * 10.0 * y * z;
+        break;
+    case 12:
+        Y = 0.3731763325901154 * z * (5.0 * zz - 3.0);
+        g[2] = 0.3731763325901154 * (15.0 * zz - 3.0);
+        break;
+    case 13:
+        Y = 0.4570457994644658 * x * (5.0 * zz - 1.0);
+        g[0] = 0.4570457994644658 * (5.0 * zz - 1.0);
+        g[2] = 0.4570457994644658 * 10.0 * x * z;
+        break;
+    case 14:
+        Y = 1.445305721320277 * z * (xx - yy);
+        g[0] = 1.445305721320277 * 2.0 * x * z;
+        g[1] = -1.445305721320277 * 2.0 * y * z;
+        g[2] = 1.445305721320277 * (xx - yy);
+        break;
+    default:
+        Y = 0.5900435899266435 * x * (xx - 3.0 * yy);
+        g[0] = 0.5900435899266435 * (3.0 * xx - 3.0 * yy);
+        g[1] = -0.5900435899266435 * 6.0 * x * y;
+        break;
+    }
+}
+
 __device__ __forceinline__ void quat_rot(const double q[4], double R[9])
 {
     const double w = q[0], x = q[1], y = q[2], z = q[3];
@@ -89,6 +147,8 @@ struct Proj {
     double u, v;
     double dir[3], rlen;
     double raw[3];
+    double dcol[3][3];  // d raw colour / d dir (polynomial gradient, before normalisation)
+    double dpn[3];      // (SH_p - SH_n) . Y(dir), per channel
     bool front, ok;
 };
 
@@ -188,17 +248,28 @@ __device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V
 #pragma unroll
     for (int k = 0; k < 3; ++k) P.dir[k] = P.mu_rel[k] / P.rlen;
     if (with_colour) {
-        double Y[16];
-        sh_eval(P.dir[0], P.dir[1], P.dir[2], Y);
         double acc[3] = {0.5, 0.5, 0.5};
-        // SH~ row 3k + c; interpolate while accumulating
-#pragma unroll 4
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            P.dpn[ch] = 0.0;
+            P.dcol[ch][0] = P.dcol[ch][1] = P.dcol[ch][2] = 0.0;
+        }
+        // SH~ row 3k + c; interpolate while accumulating colour, its gradient
+        // in the direction, and the parent - node difference
+#pragma unroll 1
         for (int k = 0; k < 16; ++k) {
+            double Yk, gk[3];
+            sh_term(k, P.dir[0], P.dir[1], P.dir[2], Yk, gk);
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 const double cn = h.sh[(3 * k + ch) * n + node];
                 const double cp = use_par ? (double)h.sh[(3 * k + ch) * n + src] : cn;
-                acc[ch] += (w0 * cn + t * cp) * Y[k];
+                const double sht = w0 * cn + t * cp;
+                acc[ch] += sht * Yk;
+                P.dpn[ch] += (cp - cn) * Yk;
+                P.dcol[ch][0] += sht * gk[0];
+                P.dcol[ch][1] += sht * gk[1];
+                P.dcol[ch][2] += sht * gk[2];
             }
         }
         P.raw[0] = acc[0];
