@@ -84,6 +84,9 @@ struct hgs_ctx {
     uint32_t *k2 = nullptr, *v2 = nullptr;
     uint32_t *hist = nullptr, *hist_scan = nullptr, *partial = nullptr, *scan_total = nullptr;
     uint2 *ranges = nullptr;
+    uint32_t *tile_keys = nullptr, *tile_order = nullptr, *tile_k2 = nullptr, *tile_v2 = nullptr;
+    uint32_t *tile_n = nullptr;
+    const uint32_t *tile_sorted = nullptr;  // the longest-first order (one of tile_order / tile_v2)
     float *T_final = nullptr;
     uint32_t *n_last = nullptr, *n_blend = nullptr;
     double *sgrad = nullptr;
@@ -294,6 +297,11 @@ hgs_status ensure_fixed(hgs_ctx *ctx, int nv, uint32_t n_tiles, size_t n_pix)
     }
     if (n_tiles > ctx->tile_cap) {
         if ((s = realloc_buf(ctx, ctx->ranges, n_tiles))) return s;
+        if ((s = realloc_buf(ctx, ctx->tile_keys, n_tiles))) return s;
+        if ((s = realloc_buf(ctx, ctx->tile_order, n_tiles))) return s;
+        if ((s = realloc_buf(ctx, ctx->tile_k2, n_tiles))) return s;
+        if ((s = realloc_buf(ctx, ctx->tile_v2, n_tiles))) return s;
+        if (!ctx->tile_n && (s = realloc_buf(ctx, ctx->tile_n, 4))) return s;
         ctx->tile_cap = n_tiles;
         ctx->layout_gen++;
     }
@@ -361,7 +369,7 @@ int bits_for(uint32_t n)
 void enqueue_blend(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st)
 {
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
-    launch_blend(ctx->views_dev, nv, n_tiles, ctx->ranges, vals, ctx->recs, ctx->axes, ctx->T_final, ctx->n_last,
+    launch_blend(ctx->views_dev, nv, n_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs, ctx->axes, ctx->T_final, ctx->n_last,
                  ctx->n_blend, ctx->ctr, ctx->tile_w, ctx->tile_h, ctx->batch, st);
 }
 
@@ -406,6 +414,13 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
     launch_fill_u32((uint32_t *)ctx->ranges, 0u, (size_t)n_tiles * 2, st);
     launch_ranges(keys, &ctx->ctr->pair_total, ctx->pair_cap, ctx->ranges, st);
+    // longest tile lists first (one stable 8-bit pass over log-scaled lengths)
+    launch_tile_keys(ctx->ranges, n_tiles, ctx->tile_keys, ctx->tile_order, ctx->tile_n, st);
+    {
+        SortScratch ts{ctx->tile_k2, ctx->tile_v2, ctx->hist, ctx->hist_scan, ctx->partial, ctx->scan_total};
+        const bool in_scratch = launch_radix_sort(ctx->tile_keys, ctx->tile_order, n_tiles, ctx->tile_n, 8, ts, st);
+        ctx->tile_sorted = in_scratch ? ctx->tile_v2 : ctx->tile_order;
+    }
     (void)vals;
     mark(6);
     if (with_blend) {
@@ -787,7 +802,8 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_gr
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
     {
         KernelTimer kt(ctx, 1, st);
-        launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->ranges, vals, ctx->recs, ctx->axes, ctx->T_final,
+        launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs,
+                              ctx->axes, ctx->T_final,
                               ctx->n_last, ctx->sgrad, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch, st);
     }
     const DevHier h = dev_hier(ctx);
@@ -853,6 +869,7 @@ hgs_status hgs_get_buffer(hgs_ctx *ctx, int32_t which, const void **dev_ptr, int
     case 4: *dev_ptr = ctx->n_blend; *count = (int64_t)ctx->last_pix; break;
     case 5: *dev_ptr = ctx->sgrad; *count = (int64_t)ctx->last_cut * 12; break;
     case 6: *dev_ptr = ctx->cut_base; *count = ctx->last_nv + 1; break;
+    case 7: *dev_ptr = ctx->ranges; *count = (int64_t)ctx->last_tiles * 2; break;
     default: return fail(ctx, HGS_ERR_INVALID_ARG, "unknown buffer");
     }
     return HGS_OK;

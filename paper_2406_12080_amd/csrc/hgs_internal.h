@@ -125,15 +125,20 @@ void launch_duplicate(const uint2 *rect, const DevView *views, int nv, const uin
 void launch_ranges(const uint32_t *pair_keys, const uint32_t *pair_total, uint32_t pair_cap, uint2 *ranges,
                    hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
+// tiles ordered by descending list length (longest first) for the blend grid
+void launch_tile_keys(const uint2 *ranges, uint32_t n_tiles, uint32_t *keys, uint32_t *order, uint32_t *n_out,
+                      hipStream_t st);
 
 // blend (tile_w x tile_h pixels per workgroup, `batch` records staged per step)
 bool blend_supported(int tw, int th, int batch);
-void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges, const uint32_t *pair_vals,
+void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *tile_order, const uint2 *ranges,
+                  const uint32_t *pair_vals,
                   const SplatRec *recs, const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend,
                   Counters *ctr, int tw, int th, int batch, hipStream_t st);
 
 // backward
-void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges,
+void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *tile_order,
+                           const uint2 *ranges,
                            const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                            const uint32_t *n_last, double *sgrad, Counters *ctr, int tw, int th, int batch,
                            hipStream_t st);

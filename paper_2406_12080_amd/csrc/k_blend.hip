@@ -62,7 +62,7 @@ __device__ __forceinline__ void eval_alpha(const float4 &W, const float4 &O, flo
     e.ap = 0.0f;
     e.apr = 0.0f;
     e.cp = false;
-    if (O.z > 0.0f) {
+    if (__builtin_amdgcn_readfirstlane(__float_as_int(O.z)) > 0) {  // same splat on every lane
         const float ap = O.y * e.G;
         e.cp = ap > kAlphaMax;
         e.ap = e.cp ? kAlphaMax : ap;
@@ -82,8 +82,29 @@ __device__ __forceinline__ int view_of_tile(const DevView *views, int nv, uint32
     return lo;
 }
 
+// Staged copy of one splat for one tile.
+struct Staged {
+    float4 w, o, c;
+    float2 u[8];
+};
+
+template <int NB, int SX>
+__device__ __forceinline__ void stage_one(const SplatRec &r, const double4 &W64, int ox, int oy, Staged &st)
+{
+    st.w = make_float4(r.w1x, r.w1y, r.w2x, r.w2y);
+    st.o = make_float4(r.An, r.Ap, r.t, r.invK);
+    st.c = make_float4(r.r, r.g, r.b, 0.0f);
+#pragma unroll
+    for (int bk = 0; bk < NB; ++bk) {
+        float c1, c2, d0, d1;
+        block_offsets(r, W64, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
+        st.u[bk] = make_float2(c1, c2);
+    }
+}
+
 template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ views, int nv,
+                                                  const uint32_t *__restrict__ tile_order,
                                                   const uint2 *__restrict__ ranges,
                                                   const uint32_t *__restrict__ pair_vals,
                                                   const SplatRec *__restrict__ recs,
@@ -94,9 +115,11 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
     constexpr int NT = TW * TH;
     constexpr int SX = TW / 8;
     constexpr int NB = (TW / 8) * (TH / 8);
+    constexpr int PER = BATCH / NT;  // records staged per thread and batch
+    static_assert(BATCH % NT == 0 && NB <= 8, "tile/batch combination");
     __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
     __shared__ float2 s_u[NB][BATCH];
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = tile_order[blockIdx.x];  // longest lists first
     const int vi = view_of_tile(views, nv, tile);
     const DevView &V = views[vi];
     const uint32_t lt = tile - V.tile_base;
@@ -111,48 +134,71 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     uint32_t last = 0, nb = 0, ne = 0, net = 0;
     bool done = !inside;
-    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
-        if (__syncthreads_count(!done) == 0) break;
-        for (int j = threadIdx.x; j < BATCH; j += NT) {
-            const uint32_t idx = b0 + j;
+
+    // records of the next batch, loaded while the current one is composited
+    SplatRec nxt[PER];
+    double4 nxw[PER];
+    auto fetch = [&](uint32_t b0) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const uint32_t idx = b0 + p * NT + threadIdx.x;
             if (idx < rg.y) {
                 const uint32_t sidx = pair_vals[idx];
-                const SplatRec r = recs[sidx];
-                const double4 W64 = axes[sidx];
-                s_w[j] = make_float4(r.w1x, r.w1y, r.w2x, r.w2y);
-                s_o[j] = make_float4(r.An, r.Ap, r.t, r.invK);
-                s_c[j] = make_float4(r.r, r.g, r.b, 0.0f);
+                nxt[p] = recs[sidx];
+                nxw[p] = axes[sidx];
+            }
+        }
+    };
+    if (rg.x < rg.y) fetch(rg.x);
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
+        if (__syncthreads_count(!done) == 0) break;
 #pragma unroll
-                for (int bk = 0; bk < NB; ++bk) {
-                    float c1, c2, d0, d1;
-                    block_offsets(r, W64, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
-                    s_u[bk][j] = make_float2(c1, c2);
-                }
+        for (int p = 0; p < PER; ++p) {
+            const int j = p * NT + threadIdx.x;
+            if (b0 + j < rg.y) {
+                Staged st;
+                stage_one<NB, SX>(nxt[p], nxw[p], ox, oy, st);
+                s_w[j] = st.w;
+                s_o[j] = st.o;
+                s_c[j] = st.c;
+#pragma unroll
+                for (int bk = 0; bk < NB; ++bk) s_u[bk][j] = st.u[bk];
             }
         }
         __syncthreads();
+        if (b0 + BATCH < rg.y) fetch(b0 + BATCH);
         if (!done) {
             const int cnt = (int)min((uint32_t)BATCH, rg.y - b0);
+            float4 Wn = s_w[0], On = s_o[0], Cn = s_c[0];
+            float2 Un = s_u[w][0];
             for (int j = 0; j < cnt; ++j) {
-                const float4 Wv = s_w[j], Ov = s_o[j];
-                AlphaEval e;
-                eval_alpha(Wv, Ov, s_u[w][j], lx, ly, e);
-                ++ne;
-                net += Ov.z > 0.0f;
-                if (e.alpha < kAlphaMin) continue;
-                const float Tn = T * (1.0f - e.alpha);
-                if (Tn < kTMin) {
-                    done = true;
-                    break;
+                const float4 Wv = Wn, Ov = On, Cc = Cn;
+                const float2 Uv = Un;
+                if (j + 1 < cnt) {
+                    Wn = s_w[j + 1];
+                    On = s_o[j + 1];
+                    Cn = s_c[j + 1];
+                    Un = s_u[w][j + 1];
                 }
-                const float4 Cc = s_c[j];
-                const float wgt = e.alpha * T;
+                AlphaEval e;
+                eval_alpha(Wv, Ov, Uv, lx, ly, e);
+                // branch-free per-lane update
+                const bool live = !done;
+                const bool ok = live && e.alpha >= kAlphaMin;
+                const float Tn = T * (1.0f - e.alpha);
+                const bool stop = ok && Tn < kTMin;
+                const bool take = ok && !stop;
+                const float wgt = take ? e.alpha * T : 0.0f;
                 C0 += Cc.x * wgt;
                 C1 += Cc.y * wgt;
                 C2 += Cc.z * wgt;
-                T = Tn;
-                last = b0 - rg.x + (uint32_t)j + 1u;
-                ++nb;
+                T = take ? Tn : T;
+                last = take ? b0 - rg.x + (uint32_t)j + 1u : last;
+                nb += take;
+                ne += live;
+                net += live && Ov.z > 0.0f;
+                done = done || stop;
+                if (__ballot(!done) == 0ull) break;
             }
         }
     }
@@ -218,6 +264,7 @@ constexpr int kG = 12;  // floats per splat in the screen-space gradient
 
 template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict__ views, int nv,
+                                                      const uint32_t *__restrict__ tile_order,
                                                       const uint2 *__restrict__ ranges,
                                                       const uint32_t *__restrict__ pair_vals,
                                                       const SplatRec *__restrict__ recs,
@@ -235,7 +282,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
     __shared__ uint32_t s_id[BATCH];
     __shared__ float s_g[BATCH][kG];
     __shared__ uint32_t s_max;
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = tile_order[blockIdx.x];  // longest lists first
     const int vi = view_of_tile(views, nv, tile);
     const DevView &V = views[vi];
     const uint32_t lt = tile - V.tile_base;
@@ -377,22 +424,22 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
 }
 
 template <int TW, int TH, int BATCH>
-void launch_blend_t(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges, const uint32_t *pair_vals,
-                    const SplatRec *recs, const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend,
-                    Counters *ctr, hipStream_t st)
+void launch_blend_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
+                    const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, float *T_final,
+                    uint32_t *n_last, uint32_t *n_blend, Counters *ctr, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_blend<TW, TH, BATCH>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, ranges, pair_vals,
-                       recs, axes, T_final, n_last, n_blend, ctr);
+    hipLaunchKernelGGL((k_blend<TW, TH, BATCH>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order, ranges,
+                       pair_vals, recs, axes, T_final, n_last, n_blend, ctr);
 }
 
 template <int TW, int TH, int BATCH>
-void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges,
+void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                         const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                         const uint32_t *n_last, double *sgrad, Counters *ctr, hipStream_t st)
 {
     // the backward stages at most 256 splats per step (its LDS holds FP64 partial sums)
     constexpr int B = BATCH < 256 ? BATCH : 256;
-    hipLaunchKernelGGL((k_blend_bwd<TW, TH, B>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, ranges,
+    hipLaunchKernelGGL((k_blend_bwd<TW, TH, B>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order, ranges,
                        pair_vals, recs, axes, T_final, n_last, sgrad, ctr);
 }
 
@@ -412,22 +459,22 @@ bool blend_supported(int tw, int th, int batch)
     return false;
 }
 
-void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges, const uint32_t *pair_vals,
-                  const SplatRec *recs, const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend,
-                  Counters *ctr, int tw, int th, int batch, hipStream_t st)
+void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
+                  const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, float *T_final,
+                  uint32_t *n_last, uint32_t *n_blend, Counters *ctr, int tw, int th, int batch, hipStream_t st)
 {
     if (batch == 0) batch = tw * th;
     if (!n_tiles) return;
 #define X(a, b, c)                                                                                           \
     if (tw == a && th == b && batch == c)                                                                    \
-        return launch_blend_t<a, b, c>(views, nv, n_tiles, ranges, pair_vals, recs, axes, T_final, n_last, \
+        return launch_blend_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last, \
                                        n_blend, ctr, st);
     HGS_BLEND_CASES(X)
 #undef X
 }
 
-void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint2 *ranges,
-                           const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
+void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order,
+                           const uint2 *ranges, const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                            const uint32_t *n_last, double *sgrad, Counters *ctr, int tw, int th, int batch,
                            hipStream_t st)
 {
@@ -435,8 +482,8 @@ void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const
     if (!n_tiles) return;
 #define X(a, b, c)                                                                                                 \
     if (tw == a && th == b && batch == c)                                                                          \
-        return launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, ranges, pair_vals, recs, axes, T_final, n_last, \
-                                           sgrad, ctr, st);
+        return launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, \
+                                           n_last, sgrad, ctr, st);
     HGS_BLEND_CASES(X)
 #undef X
 }

@@ -189,6 +189,24 @@ __global__ __launch_bounds__(kT) void k_ranges(const uint32_t *__restrict__ keys
     if (i == n - 1 || keys[i + 1] != t) ranges[t].y = i + 1;
 }
 
+// Scheduling key of every tile: 255 minus 8 log2(list length + 1), so that
+// a stable ascending sort puts the longest lists first.
+__global__ __launch_bounds__(kT) void k_tile_keys(const uint2 *__restrict__ ranges, uint32_t n_tiles,
+                                                  uint32_t *__restrict__ keys, uint32_t *__restrict__ order,
+                                                  uint32_t *__restrict__ n_out)
+{
+    const uint32_t i = blockIdx.x * kT + threadIdx.x;
+    if (i == 0) *n_out = n_tiles;
+    if (i >= n_tiles) return;
+    const uint2 r = ranges[i];
+    const uint32_t len = r.y - r.x + 1u;
+    const uint32_t lg = 31u - (uint32_t)__clz(len);                   // floor(log2)
+    const uint32_t frac = lg >= 3 ? (len >> (lg - 3)) & 7u : (len << (3 - lg)) & 7u;
+    const uint32_t k = min(255u, lg * 8u + frac);
+    keys[i] = 255u - k;
+    order[i] = i;
+}
+
 __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -503,6 +521,14 @@ void launch_ranges(const uint32_t *pair_keys, const uint32_t *pair_total, uint32
     const uint32_t blocks = (pair_cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(kT), 0, st, pair_keys, pair_total, pair_cap, ranges);
+}
+
+void launch_tile_keys(const uint2 *ranges, uint32_t n_tiles, uint32_t *keys, uint32_t *order, uint32_t *n_out,
+                      hipStream_t st)
+{
+    if (!n_tiles) return;
+    hipLaunchKernelGGL(k_tile_keys, dim3((n_tiles + kT - 1) / kT), dim3(kT), 0, st, ranges, n_tiles, keys, order,
+                       n_out);
 }
 
 void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st)
