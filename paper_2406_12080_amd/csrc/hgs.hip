@@ -86,6 +86,8 @@ struct hgs_ctx {
     uint2 *ranges = nullptr;
     uint32_t *tile_keys = nullptr, *tile_order = nullptr, *tile_k2 = nullptr, *tile_v2 = nullptr;
     uint32_t *tile_n = nullptr;
+    uint4 *wstats = nullptr;  // per-wave work counts of the blend kernels
+    size_t wstats_cap = 0;
     const uint32_t *tile_sorted = nullptr;  // the longest-first order (one of tile_order / tile_v2)
     float *T_final = nullptr;
     uint32_t *n_last = nullptr, *n_blend = nullptr;
@@ -305,6 +307,12 @@ hgs_status ensure_fixed(hgs_ctx *ctx, int nv, uint32_t n_tiles, size_t n_pix)
         ctx->tile_cap = n_tiles;
         ctx->layout_gen++;
     }
+    const size_t n_waves = (size_t)n_tiles * (size_t)(ctx->tile_w * ctx->tile_h / 64);
+    if (n_waves > ctx->wstats_cap) {
+        if ((s = realloc_buf(ctx, ctx->wstats, n_waves))) return s;
+        ctx->wstats_cap = n_waves;
+        ctx->layout_gen++;
+    }
     if (n_pix > ctx->pix_cap) {
         if ((s = realloc_buf(ctx, ctx->T_final, n_pix))) return s;
         if ((s = realloc_buf(ctx, ctx->n_last, n_pix))) return s;
@@ -370,7 +378,7 @@ void enqueue_blend(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st)
 {
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
     launch_blend(ctx->views_dev, nv, n_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs, ctx->axes, ctx->T_final, ctx->n_last,
-                 ctx->n_blend, ctx->ctr, ctx->tile_w, ctx->tile_h, ctx->batch, st);
+                 ctx->n_blend, ctx->wstats, ctx->ctr, ctx->tile_w, ctx->tile_h, ctx->batch, st);
 }
 
 void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hipEvent_t *ev, bool with_blend)
@@ -804,7 +812,7 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_gr
         KernelTimer kt(ctx, 1, st);
         launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs,
                               ctx->axes, ctx->T_final,
-                              ctx->n_last, ctx->sgrad, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch, st);
+                              ctx->n_last, ctx->sgrad, ctx->wstats, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch, st);
     }
     const DevHier h = dev_hier(ctx);
     {

@@ -134,14 +134,14 @@ bool blend_supported(int tw, int th, int batch);
 void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *tile_order, const uint2 *ranges,
                   const uint32_t *pair_vals,
                   const SplatRec *recs, const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend,
-                  Counters *ctr, int tw, int th, int batch, hipStream_t st);
+                  uint4 *wstats, Counters *ctr, int tw, int th, int batch, hipStream_t st);
 
 // backward
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *tile_order,
                            const uint2 *ranges,
                            const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
-                           const uint32_t *n_last, double *sgrad, Counters *ctr, int tw, int th, int batch,
-                           hipStream_t st);
+                           const uint32_t *n_last, double *sgrad, uint4 *wstats, Counters *ctr, int tw, int th,
+                           int batch, hipStream_t st);
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
                                 const uint32_t *ntiles, const SplatRec *recs, const float *cjac, const double *sgrad,

@@ -46,9 +46,9 @@ __device__ __forceinline__ void block_offsets(const SplatRec &r, const double4 &
 
 // Identical instruction sequence in forward and backward (explicit FMAs, no
 // other contraction), so that the backward reproduces the forward's
-// decisions bit for bit.
+// decisions bit for bit.  `interp` (t > 0) is the same for every lane.
 __device__ __forceinline__ void eval_alpha(const float4 &W, const float4 &O, float2 c, float lx, float ly,
-                                           AlphaEval &e)
+                                           bool interp, AlphaEval &e)
 {
 #pragma clang fp contract(off)
     e.u1 = fmaf(ly, W.y, fmaf(lx, W.x, c.x));
@@ -57,15 +57,15 @@ __device__ __forceinline__ void eval_alpha(const float4 &W, const float4 &O, flo
     e.G = __builtin_amdgcn_exp2f(-s);
     const float an = O.x * e.G;
     e.cn = an > kAlphaMax;
-    e.an = e.cn ? kAlphaMax : an;
+    e.an = fminf(an, kAlphaMax);
     e.alpha = e.an;
     e.ap = 0.0f;
     e.apr = 0.0f;
     e.cp = false;
-    if (__builtin_amdgcn_readfirstlane(__float_as_int(O.z)) > 0) {  // same splat on every lane
+    if (interp) {
         const float ap = O.y * e.G;
         e.cp = ap > kAlphaMax;
-        e.ap = e.cp ? kAlphaMax : ap;
+        e.ap = fminf(ap, kAlphaMax);
         e.apr = 1.0f - __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(1.0f - e.ap) * O.w);
         e.alpha = (1.0f - O.z) * e.an + O.z * e.apr;
     }
@@ -102,6 +102,30 @@ __device__ __forceinline__ void stage_one(const SplatRec &r, const double4 &W64,
     }
 }
 
+// Per-wave work counts, summed by k_stats_reduce into three consecutive
+// counters: forward (evaluated, blended, evaluated with t > 0), backward
+// (evaluated, evaluated with t > 0, contributing).
+// Written with plain stores, one record per wave, and summed by
+// k_stats_reduce: no contended atomics on the hot path.
+__device__ __forceinline__ void store_wave_stats(uint4 *wstats, size_t slot, uint32_t a, uint32_t b, uint32_t c,
+                                                 int lane)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        a += (uint32_t)__shfl_xor((int)a, d, 64);
+        b += (uint32_t)__shfl_xor((int)b, d, 64);
+        c += (uint32_t)__shfl_xor((int)c, d, 64);
+    }
+    if (lane == 0) wstats[slot] = make_uint4(a, b, c, 0u);
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ views, int nv,
                                                   const uint32_t *__restrict__ tile_order,
@@ -110,15 +134,17 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
                                                   const SplatRec *__restrict__ recs,
                                                   const double4 *__restrict__ axes, float *__restrict__ T_final,
                                                   uint32_t *__restrict__ n_last, uint32_t *__restrict__ n_blend,
-                                                  Counters *__restrict__ ctr)
+                                                  uint4 *__restrict__ wstats)
 {
     constexpr int NT = TW * TH;
+    constexpr int NW = NT / 64;
     constexpr int SX = TW / 8;
     constexpr int NB = (TW / 8) * (TH / 8);
     constexpr int PER = BATCH / NT;  // records staged per thread and batch
-    static_assert(BATCH % NT == 0 && NB <= 8, "tile/batch combination");
+    static_assert(BATCH % NT == 0 && BATCH % 64 == 0 && NB <= 8, "tile/batch combination");
     __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
     __shared__ float2 s_u[NB][BATCH];
+    __shared__ uint64_t s_tm[BATCH / 64];  // bit j of word k: entry 64 k + j is interpolated (t > 0)
     const uint32_t tile = tile_order[blockIdx.x];  // longest lists first
     const int vi = view_of_tile(views, nv, tile);
     const DevView &V = views[vi];
@@ -131,9 +157,12 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
     const float lx = (float)(lane & 7), ly = (float)(lane >> 3);
     const uint2 rg = ranges[tile];
 
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    uint32_t last = 0, nb = 0, ne = 0, net = 0;
-    bool done = !inside;
+    // T < 0 marks a finished pixel (or one outside the image); |T| is its
+    // transmittance.  A pixel stops at the splat whose blend would take T
+    // below kTMin; that splat was evaluated but not blended.
+    float T = inside ? 1.0f : -1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    uint32_t last = 0, nb = 0, stop_n = 0, stop_t = 0;
+    uint32_t walked_t = 0;  // interpolated splats walked so far (same on every lane)
 
     // records of the next batch, loaded while the current one is composited
     SplatRec nxt[PER];
@@ -151,55 +180,58 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
     };
     if (rg.x < rg.y) fetch(rg.x);
     for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
-        if (__syncthreads_count(!done) == 0) break;
+        if (__syncthreads_count(T > 0.0f) == 0) break;
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int j = p * NT + threadIdx.x;
-            if (b0 + j < rg.y) {
-                Staged st;
+            const bool real = b0 + j < rg.y;
+            Staged st;
+            if (real) {
                 stage_one<NB, SX>(nxt[p], nxw[p], ox, oy, st);
-                s_w[j] = st.w;
-                s_o[j] = st.o;
-                s_c[j] = st.c;
+            } else {  // padding: alpha = 0 everywhere
+                st.w = st.o = st.c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
-                for (int bk = 0; bk < NB; ++bk) s_u[bk][j] = st.u[bk];
+                for (int bk = 0; bk < NB; ++bk) st.u[bk] = make_float2(0.0f, 0.0f);
             }
+            s_w[j] = st.w;
+            s_o[j] = st.o;
+            s_c[j] = st.c;
+#pragma unroll
+            for (int bk = 0; bk < NB; ++bk) s_u[bk][j] = st.u[bk];
+            const uint64_t m = __ballot(real && st.o.z > 0.0f);
+            if (lane == 0) s_tm[j >> 6] = m;
         }
         __syncthreads();
         if (b0 + BATCH < rg.y) fetch(b0 + BATCH);
-        if (!done) {
-            const int cnt = (int)min((uint32_t)BATCH, rg.y - b0);
-            float4 Wn = s_w[0], On = s_o[0], Cn = s_c[0];
-            float2 Un = s_u[w][0];
-            for (int j = 0; j < cnt; ++j) {
-                const float4 Wv = Wn, Ov = On, Cc = Cn;
-                const float2 Uv = Un;
-                if (j + 1 < cnt) {
-                    Wn = s_w[j + 1];
-                    On = s_o[j + 1];
-                    Cn = s_c[j + 1];
-                    Un = s_u[w][j + 1];
-                }
+        if (__ballot(T > 0.0f) == 0ull) continue;
+        const int cnt4 = ((int)min((uint32_t)BATCH, rg.y - b0) + 3) & ~3;
+        const uint32_t jb = b0 - rg.x + 1u;  // 1-based list position of entry 0
+        uint64_t tm = 0;
+        for (int j0 = 0; j0 < cnt4; j0 += 4) {
+            if ((j0 & 63) == 0) tm = uniform_u64(s_tm[j0 >> 6]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u;
+                const uint32_t bit = (uint32_t)(tm >> (j & 63)) & 1u;
+                walked_t += bit;
                 AlphaEval e;
-                eval_alpha(Wv, Ov, Uv, lx, ly, e);
-                // branch-free per-lane update
-                const bool live = !done;
-                const bool ok = live && e.alpha >= kAlphaMin;
-                const float Tn = T * (1.0f - e.alpha);
-                const bool stop = ok && Tn < kTMin;
-                const bool take = ok && !stop;
-                const float wgt = take ? e.alpha * T : 0.0f;
-                C0 += Cc.x * wgt;
-                C1 += Cc.y * wgt;
-                C2 += Cc.z * wgt;
-                T = take ? Tn : T;
-                last = take ? b0 - rg.x + (uint32_t)j + 1u : last;
-                nb += take;
-                ne += live;
-                net += live && Ov.z > 0.0f;
-                done = done || stop;
-                if (__ballot(!done) == 0ull) break;
+                eval_alpha(s_w[j], s_o[j], s_u[w][j], lx, ly, bit != 0u, e);
+                if (T > 0.0f && e.alpha >= kAlphaMin) {
+                    const float Tn = T * (1.0f - e.alpha);
+                    const bool stop = Tn < kTMin;
+                    const float4 Cc = s_c[j];
+                    const float wgt = stop ? 0.0f : e.alpha * T;
+                    C0 += Cc.x * wgt;
+                    C1 += Cc.y * wgt;
+                    C2 += Cc.z * wgt;
+                    nb += stop ? 0u : 1u;
+                    last = stop ? last : jb + (uint32_t)j;
+                    stop_n = stop ? jb + (uint32_t)j : stop_n;
+                    stop_t = stop ? walked_t : stop_t;
+                    T = stop ? -T : Tn;
+                }
             }
+            if (__ballot(T > 0.0f) == 0ull) break;
         }
     }
     if (inside) {
@@ -209,22 +241,14 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
         o[1] = C1;
         o[2] = C2;
         const size_t g = (size_t)V.pix_base + p;
-        T_final[g] = T;
+        T_final[g] = fabsf(T);
         n_last[g] = last;
         n_blend[g] = nb;
     }
-    unsigned long long e64 = ne, b64 = nb, t64 = net;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        e64 += __shfl_xor(e64, d, 64);
-        b64 += __shfl_xor(b64, d, 64);
-        t64 += __shfl_xor(t64, d, 64);
-    }
-    if (lane == 0) {
-        atomicAdd(&ctr->evaluated, e64);
-        atomicAdd(&ctr->blended, b64);
-        atomicAdd(&ctr->evaluated_t, t64);
-    }
+    // a pixel that never stopped evaluated the whole list
+    const bool stopped = T < 0.0f;
+    store_wave_stats(wstats, (size_t)blockIdx.x * NW + w, stopped ? stop_n : rg.y - rg.x, nb,
+                     stopped ? stop_t : walked_t, lane);
 }
 
 // Reduce-scatter of 16 per-lane values over a 64-lane wave: each exchange
@@ -271,7 +295,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                                                       const double4 *__restrict__ axes,
                                                       const float *__restrict__ T_final,
                                                       const uint32_t *__restrict__ n_last,
-                                                      double *__restrict__ sgrad, Counters *__restrict__ ctr)
+                                                      double *__restrict__ sgrad, uint4 *__restrict__ wstats)
 {
     constexpr int NT = TW * TH;
     constexpr int SX = TW / 8;
@@ -344,7 +368,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
             AlphaEval e;
             bool contrib = false;
             if (li < last) {
-                eval_alpha(Wv, Ov, U, lx, ly, e);
+                eval_alpha(Wv, Ov, U, lx, ly, __builtin_amdgcn_readfirstlane(__float_as_int(Ov.z)) > 0, e);
                 contrib = e.alpha >= kAlphaMin;
                 ++ne;
                 net += Ov.z > 0.0f;
@@ -409,38 +433,58 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
         __syncthreads();
         hi = lo;
     }
-    unsigned long long e64 = ne, t64 = net, c64 = nc;
+    store_wave_stats(wstats, (size_t)blockIdx.x * (NT / 64) + w, ne, net, nc, lane);
+}
+
+__global__ __launch_bounds__(256) void k_stats_reduce(const uint4 *__restrict__ s, uint32_t n,
+                                                      unsigned long long *__restrict__ out)
+{
+    __shared__ unsigned long long s_p[4][3];
+    unsigned long long a = 0, b = 0, c = 0;
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+        const uint4 v = s[i];
+        a += v.x;
+        b += v.y;
+        c += v.z;
+    }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
-        e64 += __shfl_xor(e64, d, 64);
-        t64 += __shfl_xor(t64, d, 64);
-        c64 += __shfl_xor(c64, d, 64);
+        a += __shfl_xor(a, d, 64);
+        b += __shfl_xor(b, d, 64);
+        c += __shfl_xor(c, d, 64);
     }
-    if (lane == 0) {
-        atomicAdd(&ctr->bwd_evaluated, e64);
-        atomicAdd(&ctr->bwd_evaluated_t, t64);
-        atomicAdd(&ctr->bwd_contrib, c64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_p[w][0] = a;
+        s_p[w][1] = b;
+        s_p[w][2] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const unsigned long long t = s_p[0][threadIdx.x] + s_p[1][threadIdx.x] + s_p[2][threadIdx.x] +
+                                     s_p[3][threadIdx.x];
+        if (t) atomicAdd(&out[threadIdx.x], t);
     }
 }
 
 template <int TW, int TH, int BATCH>
 void launch_blend_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                     const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, float *T_final,
-                    uint32_t *n_last, uint32_t *n_blend, Counters *ctr, hipStream_t st)
+                    uint32_t *n_last, uint32_t *n_blend, uint4 *wstats, hipStream_t st)
 {
     hipLaunchKernelGGL((k_blend<TW, TH, BATCH>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order, ranges,
-                       pair_vals, recs, axes, T_final, n_last, n_blend, ctr);
+                       pair_vals, recs, axes, T_final, n_last, n_blend, wstats);
 }
 
 template <int TW, int TH, int BATCH>
 void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                         const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
-                        const uint32_t *n_last, double *sgrad, Counters *ctr, hipStream_t st)
+                        const uint32_t *n_last, double *sgrad, uint4 *wstats, hipStream_t st)
 {
     // the backward stages at most 256 splats per step (its LDS holds FP64 partial sums)
     constexpr int B = BATCH < 256 ? BATCH : 256;
     hipLaunchKernelGGL((k_blend_bwd<TW, TH, B>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order, ranges,
-                       pair_vals, recs, axes, T_final, n_last, sgrad, ctr);
+                       pair_vals, recs, axes, T_final, n_last, sgrad, wstats);
 }
 
 }  // namespace
@@ -459,31 +503,47 @@ bool blend_supported(int tw, int th, int batch)
     return false;
 }
 
-void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
-                  const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, float *T_final,
-                  uint32_t *n_last, uint32_t *n_blend, Counters *ctr, int tw, int th, int batch, hipStream_t st)
+static void launch_blend_cfg(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order,
+                             const uint2 *ranges, const uint32_t *pair_vals, const SplatRec *recs,
+                             const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend, uint4 *wstats,
+                             int tw, int th, int batch, hipStream_t st)
 {
-    if (batch == 0) batch = tw * th;
-    if (!n_tiles) return;
 #define X(a, b, c)                                                                                           \
     if (tw == a && th == b && batch == c)                                                                    \
         return launch_blend_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last, \
-                                       n_blend, ctr, st);
+                                       n_blend, wstats, st);
     HGS_BLEND_CASES(X)
 #undef X
 }
 
+void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
+                  const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, float *T_final,
+                  uint32_t *n_last, uint32_t *n_blend, uint4 *wstats, Counters *ctr, int tw, int th, int batch,
+                  hipStream_t st)
+{
+    if (batch == 0) batch = tw * th;
+    if (!n_tiles) return;
+    const uint32_t nst = n_tiles * (uint32_t)(tw * th / 64);
+    launch_blend_cfg(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last, n_blend, wstats, tw,
+                     th, batch, st);
+    hipLaunchKernelGGL(k_stats_reduce, dim3(256), dim3(256), 0, st, wstats, nst, &ctr->evaluated);
+}
+
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order,
                            const uint2 *ranges, const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
-                           const uint32_t *n_last, double *sgrad, Counters *ctr, int tw, int th, int batch,
-                           hipStream_t st)
+                           const uint32_t *n_last, double *sgrad, uint4 *wstats, Counters *ctr, int tw, int th,
+                           int batch, hipStream_t st)
 {
     if (batch == 0) batch = tw * th;
     if (!n_tiles) return;
 #define X(a, b, c)                                                                                                 \
-    if (tw == a && th == b && batch == c)                                                                          \
-        return launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, \
-                                           n_last, sgrad, ctr, st);
+    if (tw == a && th == b && batch == c) {                                                                        \
+        launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last,    \
+                                    sgrad, wstats, st);                                                            \
+        hipLaunchKernelGGL(k_stats_reduce, dim3(256), dim3(256), 0, st, wstats,                                    \
+                           n_tiles * (uint32_t)(tw * th / 64), &ctr->bwd_evaluated);                               \
+        return;                                                                                                    \
+    }
     HGS_BLEND_CASES(X)
 #undef X
 }

@@ -92,6 +92,11 @@ def _render_and_check(r, h, v):
     clean = o["nalt"] == 0
     assert np.array_equal(nb[clean], o["nblend"][clean])
     assert st["cut"] == len(O.cut(h, v)[0])
+    # work counters: blended pairs are the per-pixel counts summed; every
+    # blended pair, and every pair up to the last blended one, was evaluated
+    nl = r.buffer(hgs.BUF_N_LAST, torch.int32).cpu().numpy()
+    assert st["blended"] == int(nb.astype(np.int64).sum())
+    assert st["evaluated"] >= int(nl.astype(np.int64).sum()) >= st["blended"]
     return res
 
 
@@ -174,6 +179,10 @@ def _grad_case(hgs, h, v, seed=0):
     dt = torch.zeros(len(oids), device="cuda")
     r.backward([w], grads, dt)
     _sync()
+    c = r.counters()
+    # the backward re-evaluates exactly the pairs the forward blended
+    assert c["bwd_contrib"] == st["blended"] == c["blended"], (c, st)
+    assert c["bwd_evaluated"] >= c["bwd_contrib"] and c["bwd_evaluated"] >= c["bwd_evaluated_t"]
     ob = O.backward(h, v, oids, ot, w.cpu().numpy().astype(np.float64))
     leaf = h.child_count == 0
     gpu = {k: grads[k].cpu().numpy() for k in grads}
