@@ -51,7 +51,9 @@ struct hgs_ctx {
     int64_t n = 0, n_leaves = 0;
     uint32_t *pinfo = nullptr;
     float *box = nullptr;
-    int32_t *child_count = nullptr;
+    int32_t *child_count = nullptr, *child_begin = nullptr;
+    int32_t *interior = nullptr;  // ids of the interior nodes, ascending
+    int64_t n_interior = 0;
     float *own[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float *bound[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     bool use_bound = false;
@@ -70,6 +72,7 @@ struct hgs_ctx {
     size_t pix_cap = 0, tile_cap = 0;
     int nblocks_cap = 0, nv_cap = 0;
     uint64_t *masks = nullptr;
+    uint32_t *word_off = nullptr;  // per view and mask word: cut position of its first selected node
     uint32_t *blk_counts = nullptr, *blk_offsets = nullptr, *cut_base = nullptr;
     int32_t *cut_ids = nullptr;
     double *cut_t = nullptr;
@@ -225,6 +228,7 @@ DevHier dev_hier(const hgs_ctx *c)
     h.pinfo = c->pinfo;
     h.box = c->box;
     h.child_count = c->child_count;
+    h.child_begin = c->child_begin;
     float *const *P = c->use_bound ? c->bound : c->own;
     h.mean = P[0];
     h.scale = P[1];
@@ -290,6 +294,7 @@ hgs_status ensure_fixed(hgs_ctx *ctx, int nv, uint32_t n_tiles, size_t n_pix)
         const int nvc = std::max(nv, ctx->nv_cap), nbc = std::max(nb, ctx->nblocks_cap);
         const size_t words = (size_t)((ctx->n + 63) / 64);
         if ((s = realloc_buf(ctx, ctx->masks, words * nvc + 1))) return s;
+        if ((s = realloc_buf(ctx, ctx->word_off, words * nvc + 1))) return s;
         if ((s = realloc_buf(ctx, ctx->blk_counts, (size_t)nbc * nvc))) return s;
         if ((s = realloc_buf(ctx, ctx->blk_offsets, (size_t)nbc * nvc))) return s;
         if ((s = realloc_buf(ctx, ctx->cut_base, (size_t)nvc + 1))) return s;
@@ -393,7 +398,8 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     launch_cut_flags(h, ctx->views_dev, nv, ctx->masks, ctx->blk_counts, nb, st);
     launch_scan(ctx->blk_counts, nullptr, (uint32_t)(nb * nv), nullptr, ctx->blk_offsets, &ctx->ctr->cut_total,
                 ctx->partial, st);
-    launch_cut_emit(h, ctx->views_dev, nv, ctx->masks, ctx->blk_offsets, nb, ctx->cut_ids, nullptr, ctx->cut_t,
+    launch_cut_emit(h, ctx->views_dev, nv, ctx->masks, ctx->blk_offsets, nb, ctx->word_off, ctx->cut_ids, nullptr,
+                    ctx->cut_t,
                     ctx->cut_cap, st);
     launch_cut_finish(ctx->blk_offsets, ctx->blk_counts, nb, nv, ctx->cut_base, ctx->ctr, st);
     mark(1);
@@ -584,14 +590,24 @@ hgs_status hgs_upload(hgs_ctx *ctx, const hgs_hierarchy_desc *d, int src_on_devi
     dfree(ctx, ctx->pinfo);
     dfree(ctx, ctx->box);
     dfree(ctx, ctx->child_count);
+    dfree(ctx, ctx->child_begin);
+    dfree(ctx, ctx->interior);
     ctx->pinfo = nullptr;
     ctx->box = nullptr;
     ctx->child_count = nullptr;
+    ctx->child_begin = nullptr;
+    ctx->interior = nullptr;
     ctx->use_bound = false;
     hgs_status s;
     if ((s = dalloc(ctx, (void **)&ctx->pinfo, 4 * N))) return s;
     if ((s = dalloc(ctx, (void **)&ctx->box, 24 * N))) return s;
     if ((s = dalloc(ctx, (void **)&ctx->child_count, 4 * N))) return s;
+    if ((s = dalloc(ctx, (void **)&ctx->child_begin, 4 * N))) return s;
+    std::vector<int32_t> interior;
+    interior.reserve((size_t)(N - leaves));
+    for (int64_t i = 0; i < N; ++i)
+        if (cc[i] > 0) interior.push_back((int32_t)i);
+    if ((s = dalloc(ctx, (void **)&ctx->interior, 4 * std::max<size_t>(interior.size(), 1)))) return s;
     const size_t comp[5] = {3, 3, 4, 1, 48};
     const float *src[5] = {d->mean, d->scale, d->rot, d->opacity, d->sh};
     for (int k = 0; k < 5; ++k)
@@ -600,6 +616,12 @@ hgs_status hgs_upload(hgs_ctx *ctx, const hgs_hierarchy_desc *d, int src_on_devi
     HIPC(hipMemcpy(ctx->box, bmin.data(), 12 * N, hipMemcpyHostToDevice));
     HIPC(hipMemcpy(ctx->box + 3 * N, bmax.data(), 12 * N, hipMemcpyHostToDevice));
     HIPC(hipMemcpy(ctx->child_count, cc.data(), 4 * N, hipMemcpyHostToDevice));
+    for (int64_t i = 0; i < N; ++i)
+        if (cc[i] == 0) cb[i] = 0;  // unused for leaves
+    HIPC(hipMemcpy(ctx->child_begin, cb.data(), 4 * N, hipMemcpyHostToDevice));
+    if (!interior.empty())
+        HIPC(hipMemcpy(ctx->interior, interior.data(), 4 * interior.size(), hipMemcpyHostToDevice));
+    ctx->n_interior = (int64_t)interior.size();
     const hipMemcpyKind k2 = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     for (int k = 0; k < 5; ++k) HIPC(hipMemcpy(ctx->own[k], src[k], 4 * comp[k] * N, k2));
     HIPC(hipDeviceSynchronize());
@@ -663,7 +685,7 @@ hgs_status hgs_cut(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *
         return fail(ctx, HGS_ERR_CAPACITY, "cut has " + std::to_string(*out_count) + " nodes, capacity " +
                                                std::to_string(capacity));
     if (*out_count > 0)
-        launch_cut_emit(h, ctx->views_dev, 1, ctx->masks, ctx->blk_offsets, nb, out_ids, out_t, nullptr,
+        launch_cut_emit(h, ctx->views_dev, 1, ctx->masks, ctx->blk_offsets, nb, ctx->word_off, out_ids, out_t, nullptr,
                         (uint32_t)capacity, st);
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(st));
@@ -805,7 +827,7 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_gr
     hipStream_t st = ctx->stream;
     HIPC(hipMemcpyAsync(ctx->views_dev, ctx->views_host, sizeof(DevView) * nv, hipMemcpyHostToDevice, st));
     const uint32_t cut = std::min(ctx->last_cut, ctx->cut_cap);
-    launch_fill_u32((uint32_t *)ctx->sgrad, 0u, (size_t)cut * 24, st);
+    launch_zero_rows(ctx->sgrad, 12, ctx->svals, &ctx->ctr->vis_total, std::min(cut, ctx->cut_cap), st);
     launch_fill_u32((uint32_t *)&ctx->ctr->bwd_evaluated, 0u, 6, st);
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
     {
@@ -819,8 +841,9 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_gr
         KernelTimer kt(ctx, 2, st);
         launch_preprocess_backward(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t,
                                    &ctx->ctr->cut_total, ctx->cut_cap, ctx->ntiles, ctx->recs, ctx->cjac, ctx->sgrad,
-                                   ctx->pgrad, out->mean,
-                                   out->scale, out->rot, out->opacity, out->sh, out->dt, st);
+                                   ctx->pgrad, ctx->masks, (ctx->n + 63) / 64, ctx->word_off, ctx->interior,
+                                   ctx->n_interior, out->mean, out->scale, out->rot, out->opacity, out->sh, out->dt,
+                                   st);
     }
     HIPC(hipGetLastError());
     // host copy of views keeps dL for nothing else

@@ -35,6 +35,7 @@ struct DevHier {
     const uint32_t *pinfo;  // parent index | leaf bit
     const float *box;       // [6][n]: bmin x y z, bmax x y z
     const int32_t *child_count;
+    const int32_t *child_begin;  // first child (children are contiguous); 0 for leaves
     const float *mean, *scale, *rot, *opacity, *sh;
 };
 
@@ -85,9 +86,11 @@ constexpr int kCutItems = 4;
 constexpr int kCutBlock = kCutThreads * kCutItems;  // nodes per block
 void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *masks, uint32_t *block_counts,
                       int nblocks, hipStream_t st);
+// Also writes word_off[v][w]: the cut position of the first selected node of
+// mask word w of view v (words holding a selected node only).
 void launch_cut_emit(const DevHier &h, const DevView *views, int nv, const uint64_t *masks,
-                     const uint32_t *block_offsets, int nblocks, int32_t *out_ids, float *out_t, double *out_t64,
-                     uint32_t cap, hipStream_t st);
+                     const uint32_t *block_offsets, int nblocks, uint32_t *word_off, int32_t *out_ids, float *out_t,
+                     double *out_t64, uint32_t cap, hipStream_t st);
 void launch_cut_finish(const uint32_t *block_offsets, const uint32_t *block_counts, int nblocks, int nv,
                        uint32_t *cut_base, Counters *ctr, hipStream_t st);
 
@@ -142,11 +145,14 @@ void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const
                            const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                            const uint32_t *n_last, double *sgrad, uint4 *wstats, Counters *ctr, int tw, int th,
                            int batch, hipStream_t st);
+void launch_zero_rows(double *rows, int width, const uint32_t *sorted_vals, const uint32_t *vis_total,
+                      uint32_t vis_cap, hipStream_t st);
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
                                 const uint32_t *ntiles, const SplatRec *recs, const float *cjac, const double *sgrad,
-                                float *pg, float *g_mean, float *g_scale, float *g_rot, float *g_opacity, float *g_sh,
-                                float *g_dt, hipStream_t st);
+                                float *pg, const uint64_t *masks, int64_t words, const uint32_t *word_off,
+                                const int32_t *interior, int64_t n_interior, float *g_mean, float *g_scale,
+                                float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st);
 
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ uint64_t lanemask_lt()

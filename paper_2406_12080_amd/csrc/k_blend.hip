@@ -15,8 +15,9 @@
 //   C += c alpha T;  T *= 1 - alpha.
 // The backward walks each tile back to front from the final transmittance
 // and the index of the last contributor of each pixel, recovering the
-// transmittance in front of every splat by division (no per-pixel lists),
-// reduces each splat's gradient over the wave (FP32) and the workgroup, and
+// transmittance in front of every splat by dividing by (1 - alpha) (no
+// per-pixel lists), reduces each splat's gradient over rows of 16 lanes with
+// DPP exchanges and over the rows and waves of the tile in LDS (FP32), and
 // adds it once per tile, in FP64, to the splat's screen-space gradient.
 #include "hgs_internal.h"
 
@@ -251,37 +252,39 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
                      stopped ? stop_t : walked_t, lane);
 }
 
-// Reduce-scatter of 16 per-lane values over a 64-lane wave: each exchange
-// step halves the values a lane holds while summing its partner's half, so
-// the whole reduction takes 8+4+2+1+1+1 = 17 shuffles instead of 16 x 6.
-// Afterwards lane l with (l & 3) == 0 holds the total of slot l >> 2 in v[0].
-__device__ __forceinline__ void wave_reduce16(float (&v)[16], int lane)
+// Lane exchange inside each row of 16 lanes through DPP (no LDS traffic).
+// CTRL is a DPP control word: 0x128 rotates a row by 8 (lane l reads l ^ 8),
+// 0x141 mirrors each half row (l ^ 7), quad permutations 0x4E (l ^ 2) and
+// 0xB1 (l ^ 1).
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+
+// One halving step: a lane keeps half of its H * 2 values and adds the same
+// half from its partner, which keeps the other half.
+template <int H, int CTRL>
+__device__ __forceinline__ void rs_step(float (&v)[16], bool up)
 {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const bool up = (lane & 32) != 0;
-        const float keep = up ? v[8 + i] : v[i], send = up ? v[i] : v[8 + i];
-        v[i] = keep + __shfl_xor(send, 32, 64);
+    for (int i = 0; i < H; ++i) {
+        const float keep = up ? v[H + i] : v[i], send = up ? v[i] : v[H + i];
+        v[i] = keep + dpp_row<CTRL>(send);
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const bool up = (lane & 16) != 0;
-        const float keep = up ? v[4 + i] : v[i], send = up ? v[i] : v[4 + i];
-        v[i] = keep + __shfl_xor(send, 16, 64);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const bool up = (lane & 8) != 0;
-        const float keep = up ? v[2 + i] : v[i], send = up ? v[i] : v[2 + i];
-        v[i] = keep + __shfl_xor(send, 8, 64);
-    }
-    {
-        const bool up = (lane & 4) != 0;
-        const float keep = up ? v[1] : v[0], send = up ? v[0] : v[1];
-        v[0] = keep + __shfl_xor(send, 4, 64);
-    }
-    v[0] += __shfl_xor(v[0], 2, 64);
-    v[0] += __shfl_xor(v[0], 1, 64);
+}
+
+// Reduce-scatter of 16 per-lane values within each row of 16 lanes: 8 + 4 +
+// 2 + 1 exchanges with partners l ^ 8, l ^ 7, l ^ 2, l ^ 1 (each pairs lanes
+// that agree on the bits decided before and differ in the next one: bits 3,
+// 2, 1, 0).  Returns, on lane l, slot (l & 15) summed over the lane's row.
+__device__ __forceinline__ float row_reduce16(float (&v)[16], int lane)
+{
+    rs_step<8, 0x128>(v, (lane & 8) != 0);
+    rs_step<4, 0x141>(v, (lane & 4) != 0);
+    rs_step<2, 0x4E>(v, (lane & 2) != 0);
+    rs_step<1, 0xB1>(v, (lane & 1) != 0);
+    return v[0];
 }
 
 constexpr int kG = 12;  // floats per splat in the screen-space gradient
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
             if (contrib) {
                 const float4 Cc = s_c[j];
                 const float a = e.alpha;
-                T = __fdividef(T, 1.0f - a);
+                T = T * __builtin_amdgcn_rcpf(1.0f - a);
                 const float dal = T * ((Cc.x - R0) * g0 + (Cc.y - R1) * g1 + (Cc.z - R2) * g2);
                 const float aT = a * T;
                 v[7] = aT * g0;
@@ -420,9 +423,9 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                 v[3] = -2.0f * dq * gx * gy;
                 v[4] = -dq * gy * gy;
             }
-            wave_reduce16(v, lane);
-            const int slot = lane >> 2;
-            if ((lane & 3) == 0 && slot < 11 && v[0] != 0.0f) atomicAdd(&s_g[j][slot], v[0]);
+            const float rs = row_reduce16(v, lane);
+            const int slot = lane & 15;  // the four rows meet in LDS
+            if (slot < 11 && rs != 0.0f) atomicAdd(&s_g[j][slot], rs);
         }
         __syncthreads();
         for (int idx = threadIdx.x; idx < cnt * 11; idx += NT) {

@@ -12,8 +12,13 @@
 // 64-lane ballot bitmask per wave, a per-block count, one exclusive scan over
 // (view, block), and an emit pass that writes ids and weights.
 //
-// eps and t are evaluated in FP64 with contraction disabled, from the FP32
-// stored boxes, so that the selection does not depend on FP32 rounding.
+// The selection is defined by eps evaluated in FP64 with contraction
+// disabled, from the FP32 stored boxes, so that it does not depend on FP32
+// rounding; t is evaluated the same way.  The sweep first decides each test
+// in FP32 as (f L)^2 against tau^2 d^2 and falls back to the FP64 evaluation
+// only when the two sides are within a relative kCutMargin, far wider than
+// the FP32 rounding error of either side (about a dozen units in the last
+// place), so both evaluations always agree.
 #include "hgs_internal.h"
 
 namespace hgs {
@@ -37,6 +42,34 @@ __device__ __forceinline__ double granularity(const float b[6], const DevView &V
     if (d == 0.0) return __builtin_inf();
     const double f = V.fx > V.fy ? (double)V.fx : (double)V.fy;
     return (f * L) / d;
+}
+
+constexpr float kCutMargin = 1e-5f;
+
+// 1: eps(box) <= tau for certain; 0: eps > tau for certain; -1: too close to
+// call in FP32.  tau2 = tau^2, f = max(fx, fy).
+__device__ __forceinline__ int meets_tau_f32(const float b[6], const DevView &V, float f, float tau2)
+{
+    float L = 0.0f, d2 = 0.0f;
+    bool inside = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float lo = b[k], hi = b[3 + k];
+        const float ext = hi - lo;
+        if (ext > L) L = ext;
+        const float e = V.eye[k];
+        const float c = e < lo ? lo : (e > hi ? hi : e);
+        const float dd = e - c;
+        inside = inside && dd == 0.0f;
+        d2 = fmaf(dd, dd, d2);
+    }
+    if (inside) return 0;  // eps is infinite inside the box
+    if (!(d2 >= 1e-30f)) return -1;
+    const float fl = f * L;
+    const float lhs = fl * fl, rhs = tau2 * d2;
+    if (lhs < rhs * (1.0f - kCutMargin)) return 1;
+    if (lhs > rhs * (1.0f + kCutMargin)) return 0;
+    return -1;
 }
 
 __device__ __forceinline__ void load_box(const DevHier &h, int64_t i, float b[6])
@@ -74,10 +107,22 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_flags(DevHier h, const DevV
         for (int v = 0; v < nv; ++v) {
             const DevView &V = views[v];
             const double tau = V.tau;
+            const float tau2 = V.tau * V.tau, f = V.fx > V.fy ? V.fx : V.fy;
             bool in = false;
             if (valid) {
-                const bool Fn = leaf || granularity(b, V) <= tau;
-                if (Fn) in = root || !(granularity(pb, V) <= tau);
+                bool Fn = leaf;
+                if (!Fn) {
+                    const int a = meets_tau_f32(b, V, f, tau2);
+                    Fn = a > 0 || (a < 0 && granularity(b, V) <= tau);
+                }
+                if (Fn) {
+                    bool Fp = false;
+                    if (!root) {
+                        const int a = meets_tau_f32(pb, V, f, tau2);
+                        Fp = a > 0 || (a < 0 && granularity(pb, V) <= tau);
+                    }
+                    in = !Fp;
+                }
             }
             const uint64_t m = __ballot(in);
             if (lane == 0 && i0 < n) {
@@ -108,6 +153,7 @@ __device__ __forceinline__ double cut_weight(const DevHier &h, const DevView &V,
 __global__ __launch_bounds__(kCutThreads) void k_cut_emit(DevHier h, const DevView *__restrict__ views,
                                                           const uint64_t *__restrict__ masks,
                                                           const uint32_t *__restrict__ block_offsets, int nblocks,
+                                                          uint32_t *__restrict__ word_off,
                                                           int32_t *__restrict__ out_ids, float *__restrict__ out_t,
                                                           double *__restrict__ out_t64, uint32_t cap)
 {
@@ -138,6 +184,8 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_emit(DevHier h, const DevVi
     }
     __syncthreads();
     const uint32_t off = block_offsets[(int64_t)v * nblocks + blockIdx.x];
+    if (threadIdx.x < W && w0 + threadIdx.x < words)
+        word_off[(int64_t)v * words + w0 + threadIdx.x] = off + s_pre[threadIdx.x];
     const DevView &V = views[v];
 #pragma unroll 1
     for (int it = 0; it < kCutItems; ++it) {
@@ -173,11 +221,11 @@ void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *
 }
 
 void launch_cut_emit(const DevHier &h, const DevView *views, int nv, const uint64_t *masks,
-                     const uint32_t *block_offsets, int nblocks, int32_t *out_ids, float *out_t, double *out_t64,
-                     uint32_t cap, hipStream_t st)
+                     const uint32_t *block_offsets, int nblocks, uint32_t *word_off, int32_t *out_ids, float *out_t,
+                     double *out_t64, uint32_t cap, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cut_emit, dim3(nblocks, nv), dim3(kCutThreads), 0, st, h, views, masks, block_offsets,
-                       nblocks, out_ids, out_t, out_t64, cap);
+                       nblocks, word_off, out_ids, out_t, out_t64, cap);
 }
 
 void launch_cut_finish(const uint32_t *block_offsets, const uint32_t *, int nblocks, int nv, uint32_t *cut_base,

@@ -1,5 +1,6 @@
-// Preprocess (one thread per cut entry, FP64): interpolation, EWA projection,
-// SH colour, footprint, tile rectangle; then visibility compaction, tile
+// Preprocess (one thread per cut entry): interpolation and EWA projection in
+// FP64, footprint and tile rectangle, then SH colour (FP32) of the visible
+// splats only; then visibility compaction, tile
 // counts, pair emission and per-tile ranges.  Also the preprocess backward.
 #include "hgs_internal.h"
 #include "project.h"
@@ -26,7 +27,7 @@ __device__ __forceinline__ int view_of(const uint32_t *cut_base, int nv, uint32_
     return lo;
 }
 
-__global__ __launch_bounds__(kT, 3) void k_preprocess(DevHier h, const DevView *__restrict__ views, int nv,
+__global__ __launch_bounds__(kT, 4) void k_preprocess(DevHier h, const DevView *__restrict__ views, int nv,
                                                    const uint32_t *__restrict__ cut_base,
                                                    const int32_t *__restrict__ cut_ids,
                                                    const double *__restrict__ cut_t,
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess(DevHier h, const DevView *
         const int vi = view_of(cut_base, nv, k);
         const DevView &V = views[vi];
         Proj P;
-        project_splat(h, V, (uint32_t)cut_ids[k], cut_t[k], P, true);
+        project_splat(h, V, (uint32_t)cut_ids[k], cut_t[k], P);
         if (P.ok) {
             // footprint: alpha <= min(0.99, A G) with A = kappa((1-t)o_n + t o_p);
             // alpha_min can only be reached inside d^T Sigma2'^-1 d <= 2 ln(A/alpha_min)
@@ -91,19 +92,21 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess(DevHier h, const DevView *
                     r.Ap = (float)(P.kappa * P.o_p);
                     r.t = (float)P.t;
                     r.invK = (float)(1.0 / (double)P.K);
-                    r.r = (float)fmax(P.raw[0], 0.0);
-                    r.g = (float)fmax(P.raw[1], 0.0);
-                    r.b = (float)fmax(P.raw[2], 0.0);
+                    float raw[3], dcol[3][3], dpn[3];
+                    splat_colour(h, P, raw, dcol, dpn);  // visible splats only
+                    r.r = fmaxf(raw[0], 0.0f);
+                    r.g = fmaxf(raw[1], 0.0f);
+                    r.b = fmaxf(raw[2], 0.0f);
                     r.node = P.node;
                     recs[k] = r;
                     depth_key[k] = __float_as_uint((float)P.pc[2]);
                     float *cj = cjac + (size_t)k * 12;
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) {
-                        cj[3 * ch] = (float)P.dcol[ch][0];
-                        cj[3 * ch + 1] = (float)P.dcol[ch][1];
-                        cj[3 * ch + 2] = (float)P.dcol[ch][2];
-                        cj[9 + ch] = (float)P.dpn[ch];
+                        cj[3 * ch] = dcol[ch][0];
+                        cj[3 * ch + 1] = dcol[ch][1];
+                        cj[3 * ch + 2] = dcol[ch][2];
+                        cj[9 + ch] = dpn[ch];
                     }
                 }
             }
@@ -150,6 +153,11 @@ __global__ __launch_bounds__(kT) void k_compact_visible(const uint64_t *__restri
     }
 }
 
+// Emits the (tile, splat) pairs of the visible splats in depth order.  A
+// block takes kT consecutive splats and its threads write their pairs
+// cooperatively (thread o writes the block's pairs o, o + kT, ..., finding
+// the splat by binary search over the block's offsets in LDS), so one splat
+// covering thousands of tiles does not serialise on one thread.
 __global__ __launch_bounds__(kT) void k_duplicate(const uint2 *__restrict__ rect, const DevView *__restrict__ views,
                                                   int nv, const uint32_t *__restrict__ cut_base,
                                                   const uint32_t *__restrict__ sorted_vals,
@@ -159,23 +167,62 @@ __global__ __launch_bounds__(kT) void k_duplicate(const uint2 *__restrict__ rect
                                                   uint32_t *__restrict__ pair_keys, uint32_t *__restrict__ pair_vals,
                                                   Counters *__restrict__ ctr)
 {
+    __shared__ uint32_t s_off[kT + 1];  // block-local exclusive offsets, s_off[kT] = block total
+    __shared__ uint32_t s_val[kT], s_x0[kT], s_w[kT], s_y0[kT], s_base[kT], s_txn[kT];
     const uint32_t nvis = min(*vis_total, vis_cap);
-    const uint32_t i = blockIdx.x * kT + threadIdx.x;
-    if (i == 0 && *pair_total > pair_cap) atomicOr(&ctr->overflow, 4u);
-    if (i >= nvis) return;
-    const uint32_t s = sorted_vals[i];
-    const uint2 r = rect[s];
-    const int v = view_of(cut_base, nv, s);
-    const uint32_t base = views[v].tile_base, tx_n = (uint32_t)views[v].tiles_x;
-    const uint32_t tx0 = r.x & 0xFFFFu, tx1 = r.x >> 16, ty0 = r.y & 0xFFFFu, ty1 = r.y >> 16;
-    uint32_t o = offsets[i];
-    for (uint32_t ty = ty0; ty <= ty1; ++ty)
-        for (uint32_t tx = tx0; tx <= tx1; ++tx, ++o) {
-            if (o < pair_cap) {
-                pair_keys[o] = base + ty * tx_n + tx;
-                pair_vals[o] = s;
-            }
+    const uint32_t i0 = blockIdx.x * kT;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && *pair_total > pair_cap) atomicOr(&ctr->overflow, 4u);
+    if (i0 >= nvis) return;
+    const uint32_t i = i0 + threadIdx.x;
+    const uint32_t first = offsets[i0];
+    uint32_t cnt = 0;
+    if (i < nvis) {
+        const uint32_t s = sorted_vals[i];
+        const uint2 r = rect[s];
+        const int v = view_of(cut_base, nv, s);
+        const uint32_t tx0 = r.x & 0xFFFFu, tx1 = r.x >> 16, ty0 = r.y & 0xFFFFu, ty1 = r.y >> 16;
+        s_val[threadIdx.x] = s;
+        s_x0[threadIdx.x] = tx0;
+        s_w[threadIdx.x] = tx1 - tx0 + 1u;
+        s_y0[threadIdx.x] = ty0;
+        s_base[threadIdx.x] = views[v].tile_base;
+        s_txn[threadIdx.x] = (uint32_t)views[v].tiles_x;
+        s_off[threadIdx.x] = offsets[i] - first;
+        cnt = (tx1 - tx0 + 1u) * (ty1 - ty0 + 1u);
+    }
+    const uint32_t last = min(nvis - i0, (uint32_t)kT) - 1u;  // last valid slot
+    if (threadIdx.x == last) s_off[kT] = offsets[i] - first + cnt;
+    __syncthreads();
+    const uint32_t total = s_off[kT];
+    for (uint32_t o = threadIdx.x; o < total; o += kT) {
+        // slot j: the last one with s_off[j] <= o
+        uint32_t lo = 0, hi = last;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1u) >> 1;
+            if (s_off[mid] <= o) lo = mid;
+            else hi = mid - 1u;
         }
+        const uint32_t q = o - s_off[lo], w = s_w[lo];
+        const uint32_t ty = s_y0[lo] + q / w, tx = s_x0[lo] + q % w;
+        const uint32_t g = first + o;
+        if (g < pair_cap) {
+            pair_keys[g] = s_base[lo] + ty * s_txn[lo] + tx;
+            pair_vals[g] = s_val[lo];
+        }
+    }
+}
+
+// Zeroes the FP64 screen-gradient rows of the visible splats (the only rows
+// the blend backward adds to and the preprocess backward reads).
+__global__ __launch_bounds__(kT) void k_zero_rows(double *__restrict__ rows, int width,
+                                                  const uint32_t *__restrict__ sorted_vals,
+                                                  const uint32_t *__restrict__ vis_total, uint32_t vis_cap)
+{
+    const uint32_t nvis = min(*vis_total, vis_cap);
+    const uint64_t e = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    const uint64_t i = e / (uint32_t)width;
+    if (i >= nvis) return;
+    rows[(size_t)sorted_vals[i] * width + (e - i * width)] = 0.0;
 }
 
 __global__ __launch_bounds__(kT) void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ total,
@@ -214,11 +261,6 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
 }
 
 // ------------------------------------------------------------------ backward
-__device__ __forceinline__ void add(float *p, float v)
-{
-    if (v != 0.0f) unsafeAtomicAdd(p, v);
-}
-
 __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevView *__restrict__ views, int nv,
                                                        const uint32_t *__restrict__ cut_base,
                                                        const int32_t *__restrict__ cut_ids,
@@ -245,7 +287,7 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
     const int vi = view_of(cut_base, nv, k);
     const DevView &V = views[vi];
     Proj P;
-    project_splat(h, V, (uint32_t)cut_ids[k], cut_t[k], P, false);
+    project_splat(h, V, (uint32_t)cut_ids[k], cut_t[k], P);
     if (!P.ok) {
         out[kPG - 1] = 0.0f;
         if (g_dt) g_dt[k] = 0.0f;
@@ -274,10 +316,10 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
         if (use_par) dt += gr[c] * (double)cj[9 + c];
     }
     {
-        double Y[16];
-        sh_eval(P.dir[0], P.dir[1], P.dir[2], Y);
+        float Y[16];  // stored in FP32, evaluated in FP32
+        sh_eval_f((float)P.dir[0], (float)P.dir[1], (float)P.dir[2], Y);
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) out[15 + kk] = (float)Y[kk];
+        for (int kk = 0; kk < 16; ++kk) out[15 + kk] = Y[kk];
     }
     out[12] = (float)gr[0];
     out[13] = (float)gr[1];
@@ -403,81 +445,91 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
     if (g_dt) g_dt[k] = use_par ? (float)dt : 0.0f;
 }
 
-// Adds each cut entry's attribute gradient to its node, weighted 1 - t
-// (leaves are frozen), and to its parent, weighted t.  Siblings sit next to
-// each other in a view's cut (node ids ascending, children contiguous), so
-// the first entry of every run of equal parents sums the run and issues one
-// set of atomics for the parent.
-__global__ __launch_bounds__(kT) void k_grad_scatter(DevHier h, const int32_t *__restrict__ cut_ids,
-                                                     const double *__restrict__ cut_t,
-                                                     const uint32_t *__restrict__ cut_total, uint32_t cap,
-                                                     const float *__restrict__ pg, float *__restrict__ g_mean,
-                                                     float *__restrict__ g_scale, float *__restrict__ g_rot,
-                                                     float *__restrict__ g_op, float *__restrict__ g_sh)
+// Gathers each interior node's parameter gradient from the cut entries of
+// every view: its own entry weighted 1 - t, and the entry of each child in
+// the cut with t > 0 weighted by that child's t (leaves are frozen; both
+// opacity terms enter alpha directly, unweighted).  One thread per interior
+// node, views and children in a fixed order: no atomics, and the result is
+// reproducible bit for bit.  The cut position of node j in view v follows
+// from the cut's bit masks: word_off[v][j / 64] plus the selected nodes
+// below j in its word.
+__global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uint64_t *__restrict__ masks,
+                                                    int64_t words, const uint32_t *__restrict__ word_off,
+                                                    const uint32_t *__restrict__ cut_total, uint32_t cap,
+                                                    const double *__restrict__ cut_t,
+                                                    const uint32_t *__restrict__ ntiles, const float *__restrict__ pg,
+                                                    const int32_t *__restrict__ interior, int64_t n_interior,
+                                                    float *__restrict__ g_mean, float *__restrict__ g_scale,
+                                                    float *__restrict__ g_rot, float *__restrict__ g_op,
+                                                    float *__restrict__ g_sh)
 {
-    const uint32_t total = min(*cut_total, cap);
-    const uint32_t k = blockIdx.x * kT + threadIdx.x;
-    if (k >= total) return;
+    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (q >= n_interior) return;
     const int64_t n = h.n;
-    const uint32_t node = (uint32_t)cut_ids[k];
-    const uint32_t pi = h.pinfo[node];
-    const uint32_t par = pi & ~kLeafBit;
-    const float *g = pg + (size_t)k * kPG;
-    const bool live = g[kPG - 1] != 0.0f;
-    const float t = (float)cut_t[k];
-    if (live && !(pi & kLeafBit)) {
-        const float w0 = 1.0f - t;
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            add(&g_mean[m * n + node], w0 * g[m]);
-            add(&g_scale[m * n + node], w0 * g[3 + m]);
-        }
-#pragma unroll
-        for (int m = 0; m < 4; ++m) add(&g_rot[m * n + node], w0 * g[6 + m]);
-        add(&g_op[node], g[10]);  // opacity enters alpha directly, not through the lerp
-#pragma unroll 4
-        for (int kk = 0; kk < 16; ++kk)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) add(&g_sh[(3 * kk + c) * n + node], w0 * g[12 + c] * g[15 + kk]);
-    }
-    if (par == kRootParent) return;
-    if (k > 0 && (h.pinfo[cut_ids[k - 1]] & ~kLeafBit) == par) return;  // not the first of its run
-    float am[3] = {0, 0, 0}, as[3] = {0, 0, 0}, aq[4] = {0, 0, 0, 0}, ao = 0.0f;
+    const uint32_t total = min(*cut_total, cap);
+    const int64_t i = interior[q];
+    const int64_t c0 = h.child_begin[i];
+    const int nc = h.child_count[i];
+    float a[11];   // mean 3, scale 3, rotation 4, opacity
     float ash[48];
 #pragma unroll
-    for (int q = 0; q < 48; ++q) ash[q] = 0.0f;
+    for (int m = 0; m < 11; ++m) a[m] = 0.0f;
+#pragma unroll
+    for (int m = 0; m < 48; ++m) ash[m] = 0.0f;
     bool any = false;
-    for (uint32_t j = k; j < total; ++j) {
-        const uint32_t nj = (uint32_t)cut_ids[j];
-        if ((h.pinfo[nj] & ~kLeafBit) != par) break;
-        const float *gj = pg + (size_t)j * kPG;
-        const float tj = (float)cut_t[j];
-        if (!(tj > 0.0f) || gj[kPG - 1] == 0.0f) continue;
-        any = true;
+    // cut position of node j in view v, or ~0u when j is not in that view's cut
+    auto position = [&](int v, int64_t j) -> uint32_t {
+        const int64_t wi = (int64_t)v * words + (j >> 6);
+        const uint64_t m = masks[wi];
+        const int b = (int)(j & 63);
+        if (!((m >> b) & 1ull)) return ~0u;
+        return word_off[wi] + (uint32_t)__popcll(m & ((1ull << b) - 1ull));
+    };
+    // adds w x the attribute gradient of entry pos; `op` selects the node
+    // (10) or parent (11) opacity term
+    auto take = [&](uint32_t pos, float w, int op) {
+        const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pos * kPG);
+        const float4 r7 = g4[7];
+        if (r7.w == 0.0f) return;  // no live splat
+        const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4], r5 = g4[5], r6 = g4[6];
+        const float g[31] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z,
+                             r2.w, r3.x, r3.y, r3.z, r3.w, r4.x, r4.y, r4.z, r4.w, r5.x, r5.y,
+                             r5.z, r5.w, r6.x, r6.y, r6.z, r6.w, r7.x, r7.y, r7.z};
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            am[m] += tj * gj[m];
-            as[m] += tj * gj[3 + m];
+        for (int m = 0; m < 10; ++m) a[m] += w * g[m];
+        a[10] += op == 10 ? g[10] : g[11];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float wc = w * g[12 + c];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) ash[3 * k + c] += wc * g[15 + k];
         }
-#pragma unroll
-        for (int m = 0; m < 4; ++m) aq[m] += tj * gj[6 + m];
-        ao += gj[11];  // likewise the parent's opacity (through alpha')
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) ash[3 * kk + c] += tj * gj[12 + c] * gj[15 + kk];
+        any = true;
+    };
+#pragma unroll 1
+    for (int v = 0; v < nv; ++v) {
+        uint32_t pos = position(v, i);
+        if (pos < total && ntiles[pos] != 0) take(pos, 1.0f - (float)cut_t[pos], 10);
+#pragma unroll 1
+        for (int c = 0; c < nc; ++c) {
+            pos = position(v, c0 + c);
+            if (pos < total && ntiles[pos] != 0) {
+                const float t = (float)cut_t[pos];
+                if (t > 0.0f) take(pos, t, 11);
+            }
+        }
     }
     if (!any) return;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        add(&g_mean[m * n + par], am[m]);
-        add(&g_scale[m * n + par], as[m]);
+        g_mean[m * n + i] += a[m];
+        g_scale[m * n + i] += a[3 + m];
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) add(&g_rot[m * n + par], aq[m]);
-    add(&g_op[par], ao);
+    for (int m = 0; m < 4; ++m) g_rot[m * n + i] += a[6 + m];
+    g_op[i] += a[10];
 #pragma unroll
-    for (int q = 0; q < 48; ++q) add(&g_sh[q * n + par], ash[q]);
+    for (int m = 0; m < 48; ++m) g_sh[m * n + i] += ash[m];
 }
 
 }  // namespace
@@ -502,6 +554,15 @@ void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_
     if (!blocks) return;
     hipLaunchKernelGGL(k_compact_visible, dim3(blocks), dim3(kT), 0, st, vis_mask, vis_block_offsets, cut_total, cap,
                        depth_key, keys, vals);
+}
+
+void launch_zero_rows(double *rows, int width, const uint32_t *sorted_vals, const uint32_t *vis_total,
+                      uint32_t vis_cap, hipStream_t st)
+{
+    const uint64_t blocks = ((uint64_t)vis_cap * width + kT - 1) / kT;
+    if (!blocks) return;
+    hipLaunchKernelGGL(k_zero_rows, dim3((uint32_t)blocks), dim3(kT), 0, st, rows, width, sorted_vals, vis_total,
+                       vis_cap);
 }
 
 void launch_duplicate(const uint2 *rect, const DevView *views, int nv, const uint32_t *cut_base,
@@ -541,15 +602,19 @@ void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st)
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
                                 const uint32_t *ntiles, const SplatRec *recs, const float *cjac, const double *sgrad,
-                                float *pg, float *g_mean, float *g_scale, float *g_rot, float *g_opacity, float *g_sh,
-                                float *g_dt, hipStream_t st)
+                                float *pg, const uint64_t *masks, int64_t words, const uint32_t *word_off,
+                                const int32_t *interior, int64_t n_interior, float *g_mean, float *g_scale,
+                                float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st)
 {
     const uint32_t blocks = (cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(kT), 0, st, h, views, nv, cut_base, cut_ids, cut_t,
                        cut_total, cap, ntiles, recs, cjac, sgrad, pg, g_dt);
-    hipLaunchKernelGGL(k_grad_scatter, dim3(blocks), dim3(kT), 0, st, h, cut_ids, cut_t, cut_total, cap, pg, g_mean,
-                       g_scale, g_rot, g_opacity, g_sh);
+    const int64_t gblocks = (n_interior + kT - 1) / kT;
+    if (gblocks)
+        hipLaunchKernelGGL(k_grad_gather, dim3((uint32_t)gblocks), dim3(kT), 0, st, h, nv, masks, words, word_off,
+                           cut_total, cap, cut_t, ntiles, pg, interior, n_interior, g_mean, g_scale, g_rot,
+                           g_opacity, g_sh);
 }
 
 }  // namespace hgs

@@ -60,62 +60,43 @@ __device__ __forceinline__ void sh_grad_dot(double x, double y, double z, const 
            c14 * (xx - yy) * B[14];
 }
 
-// Basis function k (compile-time after unrolling) and its polynomial gradient.
-__device__ __forceinline__ void sh_term(int k, double x, double y, double z, double &Y, double g[3])
+// FP32 versions for the forward colour (stored in FP32 afterwards).
+__device__ __forceinline__ void sh_eval_f(float x, float y, float z, float Y[16])
 {
-    const double xx = x * x, yy = y * y, zz = z * z;
-    g[0] = g[1] = g[2] = 0.0;
-    switch (k) {
-    case 0: Y = 0.28209479177387814; break;
-    case 1: Y = 0.4886025119029199 * y; g[1] = 0.4886025119029199; break;
-    case 2: Y = 0.4886025119029199 * z; g[2] = 0.4886025119029199; break;
-    case 3: Y = 0.4886025119029199 * x; g[0] = 0.4886025119029199; break;
-    case 4: Y = 1.0925484305920792 * x * y; g[0] = 1.0925484305920792 * y; g[1] = 1.0925484305920792 * x; break;
-    case 5: Y = 1.0925484305920792 * y * z; g[1] = 1.0925484305920792 * z; g[2] = 1.0925484305920792 * y; break;
-    case 6: Y = 0.31539156525252005 * (3.0 * zz - 1.0); g[2] = 0.31539156525252005 * 6.0 * z; break;
-    case 7: Y = 1.0925484305920792 * x * z; g[0] = 1.0925484305920792 * z; g[2] = 1.0925484305920792 * x; break;
-    case 8:
-        Y = 0.5462742152960396 * (xx - yy);
-        g[0] = 0.5462742152960396 * 2.0 * x;
-        g[1] = -0.5462742152960396 * 2.0 * y;
-        break;
-    case 9:
-        Y = 0.5900435899266435 * y * (3.0 * xx - yy);
-        g[0] = 0.5900435899266435 * 6.0 * x * y;
-        g[1] = 0.5900435899266435 * (3.0 * xx - 3.0 * yy);
-        break;
-    case 10:
-        Y = 2.890611442640554 * x * y * z;
-        g[0] = 2.890611442640554 * y * z;
-        g[1] = 2.890611442640554 * x * z;
-        g[2] = 2.890611442640554 * x * y;
-        break;
-    case 11:
-        Y = 0.4570457994644658 * y * (5.0 * zz - 1.0);
-        g[1] = 0.4570457994644658 * (5.0 * zz - 1.0);
-        g[2] = 0.4570457994644658 * 10.0 * y * z;
-        break;
-    case 12:
-        Y = 0.3731763325901154 * z * (5.0 * zz - 3.0);
-        g[2] = 0.3731763325901154 * (15.0 * zz - 3.0);
-        break;
-    case 13:
-        Y = 0.4570457994644658 * x * (5.0 * zz - 1.0);
-        g[0] = 0.4570457994644658 * (5.0 * zz - 1.0);
-        g[2] = 0.4570457994644658 * 10.0 * x * z;
-        break;
-    case 14:
-        Y = 1.445305721320277 * z * (xx - yy);
-        g[0] = 1.445305721320277 * 2.0 * x * z;
-        g[1] = -1.445305721320277 * 2.0 * y * z;
-        g[2] = 1.445305721320277 * (xx - yy);
-        break;
-    default:
-        Y = 0.5900435899266435 * x * (xx - 3.0 * yy);
-        g[0] = 0.5900435899266435 * (3.0 * xx - 3.0 * yy);
-        g[1] = -0.5900435899266435 * 6.0 * x * y;
-        break;
-    }
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = 0.28209479177387814f;
+    Y[1] = 0.4886025119029199f * y;
+    Y[2] = 0.4886025119029199f * z;
+    Y[3] = 0.4886025119029199f * x;
+    Y[4] = 1.0925484305920792f * x * y;
+    Y[5] = 1.0925484305920792f * y * z;
+    Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
+    Y[7] = 1.0925484305920792f * x * z;
+    Y[8] = 0.5462742152960396f * (xx - yy);
+    Y[9] = 0.5900435899266435f * y * (3.0f * xx - yy);
+    Y[10] = 2.890611442640554f * x * y * z;
+    Y[11] = 0.4570457994644658f * y * (5.0f * zz - 1.0f);
+    Y[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
+    Y[13] = 0.4570457994644658f * x * (5.0f * zz - 1.0f);
+    Y[14] = 1.445305721320277f * z * (xx - yy);
+    Y[15] = 0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+__device__ __forceinline__ void sh_grad_dot_f(float x, float y, float z, const float B[16], float g[3])
+{
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float c1 = 0.4886025119029199f, c2 = 1.0925484305920792f, c20 = 0.31539156525252005f;
+    const float c22 = 0.5462742152960396f, c9 = 0.5900435899266435f, c10 = 2.890611442640554f;
+    const float c11 = 0.4570457994644658f, c12 = 0.3731763325901154f, c14 = 1.445305721320277f;
+    g[0] = c1 * B[3] + c2 * (y * B[4] + z * B[7]) + c22 * 2.0f * x * B[8] + c9 * 6.0f * x * y * B[9] +
+           c10 * y * z * B[10] + c11 * (5.0f * zz - 1.0f) * B[13] + c14 * 2.0f * x * z * B[14] +
+           c9 * (3.0f * xx - 3.0f * yy) * B[15];
+    g[1] = c1 * B[1] + c2 * (x * B[4] + z * B[5]) - c22 * 2.0f * y * B[8] + c9 * (3.0f * xx - 3.0f * yy) * B[9] +
+           c10 * x * z * B[10] + c11 * (5.0f * zz - 1.0f) * B[11] - c14 * 2.0f * y * z * B[14] -
+           c9 * 6.0f * x * y * B[15];
+    g[2] = c1 * B[2] + c2 * (y * B[5] + x * B[7]) + c20 * 6.0f * z * B[6] + c10 * x * y * B[10] +
+           c11 * 10.0f * y * z * B[11] + c12 * (15.0f * zz - 3.0f) * B[12] + c11 * 10.0f * x * z * B[13] +
+           c14 * (xx - yy) * B[14];
 }
 
 __device__ __forceinline__ void quat_rot(const double q[4], double R[9])
@@ -146,16 +127,14 @@ struct Proj {
     double D, Dd, kappa, conic[3];
     double u, v;
     double dir[3], rlen;
-    double raw[3];
-    double dcol[3][3];  // d raw colour / d dir (polynomial gradient, before normalisation)
-    double dpn[3];      // (SH_p - SH_n) . Y(dir), per channel
+    bool use_par;
     bool front, ok;
 };
 
-// Gathers node and parent, interpolates, projects; computes the colour only
-// when with_colour (the backward recomputes it on the fly).
+// Gathers node and parent, interpolates and projects (geometry only; the
+// colour is splat_colour's).
 __device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V, uint32_t node, double t_in,
-                                              Proj &P, bool with_colour)
+                                              Proj &P)
 {
     const int64_t n = h.n;
     P.node = node;
@@ -164,6 +143,7 @@ __device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V
     P.has_par = par != kRootParent;
     P.t = P.has_par ? t_in : 0.0;
     const bool use_par = P.has_par && P.t > 0.0;
+    P.use_par = use_par;
     P.par = P.has_par ? par : node;
     P.K = P.has_par ? h.child_count[par] : 1;
     const uint32_t src = use_par ? par : node;
@@ -247,36 +227,38 @@ __device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V
     P.rlen = sqrt(P.mu_rel[0] * P.mu_rel[0] + P.mu_rel[1] * P.mu_rel[1] + P.mu_rel[2] * P.mu_rel[2]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) P.dir[k] = P.mu_rel[k] / P.rlen;
-    if (with_colour) {
-        double acc[3] = {0.5, 0.5, 0.5};
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            P.dpn[ch] = 0.0;
-            P.dcol[ch][0] = P.dcol[ch][1] = P.dcol[ch][2] = 0.0;
-        }
-        // SH~ row 3k + c; interpolate while accumulating colour, its gradient
-        // in the direction, and the parent - node difference
-#pragma unroll 1
-        for (int k = 0; k < 16; ++k) {
-            double Yk, gk[3];
-            sh_term(k, P.dir[0], P.dir[1], P.dir[2], Yk, gk);
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const double cn = h.sh[(3 * k + ch) * n + node];
-                const double cp = use_par ? (double)h.sh[(3 * k + ch) * n + src] : cn;
-                const double sht = w0 * cn + t * cp;
-                acc[ch] += sht * Yk;
-                P.dpn[ch] += (cp - cn) * Yk;
-                P.dcol[ch][0] += sht * gk[0];
-                P.dcol[ch][1] += sht * gk[1];
-                P.dcol[ch][2] += sht * gk[2];
-            }
-        }
-        P.raw[0] = acc[0];
-        P.raw[1] = acc[1];
-        P.raw[2] = acc[2];
-    }
     P.ok = true;
+}
+
+// Colour of the interpolated SH (FP32): per channel raw = SH~ . Y(dir) + 1/2,
+// dcol = sum_k SH~_k grad Y_k(dir) (the polynomial gradient, before the
+// normalisation of dir) and dpn = (SH_p - SH_n) . Y(dir), the derivative of
+// raw in t.
+__device__ __forceinline__ void splat_colour(const DevHier &h, const Proj &P, float raw[3], float dcol[3][3],
+                                             float dpn[3])
+{
+    const int64_t n = h.n;
+    const float x = (float)P.dir[0], y = (float)P.dir[1], z = (float)P.dir[2];
+    const float t = (float)P.t, w0 = 1.0f - t;
+    const uint32_t node = P.node, src = P.use_par ? P.par : P.node;
+    float Y[16];
+    sh_eval_f(x, y, z, Y);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float c[16];
+        float acc = 0.5f, dp = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const float cn = h.sh[(3 * k + ch) * n + node];
+            const float cp = P.use_par ? h.sh[(3 * k + ch) * n + src] : cn;
+            c[k] = w0 * cn + t * cp;
+            acc += c[k] * Y[k];
+            dp += (cp - cn) * Y[k];
+        }
+        raw[ch] = acc;
+        dpn[ch] = dp;
+        sh_grad_dot_f(x, y, z, c, dcol[ch]);
+    }
 }
 
 }  // namespace hgs

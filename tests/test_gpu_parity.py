@@ -77,6 +77,25 @@ def test_cut_bitexact_c2s(r_c2s, c2s, tau):
     assert np.abs(t.cpu().numpy() - ot).max(initial=0) <= 1e-6
 
 
+@pytest.mark.parametrize("rel", [3e-7, -3e-7, 4e-6])
+def test_cut_bitexact_inside_fp32_band(r_c2s, c2s, rel):
+    # tau within the FP32 prefilter's undecided band around some interior
+    # node's granularity: that node's test goes through the FP64 evaluation
+    v = synth.make_views(2, tau=6.0)[0]
+    H = O.Hier(c2s)
+    eps = O.granularity(H, v)
+    inner = (H.child_count > 0) & np.isfinite(eps) & (eps > 0)
+    idx = np.nonzero(inner)[0]
+    pick = idx[np.argmin(np.abs(eps[idx] - 6.0))]
+    tau = float(np.float32(eps[pick] * (1.0 + rel)))
+    assert abs(tau / eps[pick] - 1.0) < 1e-5
+    v = v.replace(tau=tau)
+    ids, t = r_c2s.cut(v)
+    oids, ot = O.cut(c2s, v)
+    assert np.array_equal(ids.cpu().numpy(), oids)
+    assert np.abs(t.cpu().numpy() - ot).max(initial=0) <= 1e-6
+
+
 # ---------------------------------------------------------------- render
 def _render_and_check(r, h, v):
     from paper_2406_12080_amd import hgs
