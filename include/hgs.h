@@ -192,10 +192,13 @@ hgs_status hgs_counters(hgs_ctx *ctx, int64_t *out, int32_t n);
  * 2 final transmittance per pixel (float, views concatenated, row-major),
  * 3 contributors processed per pixel (uint32: index within its tile's list
  * after the last blended splat, + 1; 0 if none), 4 blended splats per pixel
- * (uint32), 5 screen-space gradients of the last backward (double[cut][12]:
- * du, dv, dL/d(a, b, c) of the 2D covariance through the conic, dA_n, dA_p,
- * drgb(3), dt_alpha, unused), 6 cut offsets
- * per view (uint32[n_views + 1]).  *count receives the element count. */
+ * (uint32), 5 screen-space gradients of the last backward (double[visible]
+ * [12], one row per visible splat: du, dv, dL/d(a, b, c) of the 2D
+ * covariance through the conic, dA_n, dA_p, drgb(3), dt_alpha, unused), 6 cut
+ * offsets per view (uint32[n_views + 1]), 7 per-tile ranges of the sorted
+ * (tile, splat) pairs (uint32[tiles][2], tiles of all views), 8 row of buffer
+ * 5 for each cut entry (uint32[cut], defined for visible entries).  *count
+ * receives the element count. */
 hgs_status hgs_get_buffer(hgs_ctx *ctx, int32_t which, const void **dev_ptr, int64_t *count);
 
 #ifdef __cplusplus

@@ -84,6 +84,7 @@ struct hgs_ctx {
     uint32_t *vis_counts = nullptr, *vis_offsets = nullptr;
     uint32_t *skeys = nullptr, *svals = nullptr, *pair_offsets = nullptr;
     uint32_t *pkeys = nullptr, *pvals = nullptr;
+    uint32_t *dup_first = nullptr;  // first splat of every pair-emission block
     uint32_t *k2 = nullptr, *v2 = nullptr;
     uint32_t *hist = nullptr, *hist_scan = nullptr, *partial = nullptr, *scan_total = nullptr;
     uint2 *ranges = nullptr;
@@ -94,7 +95,8 @@ struct hgs_ctx {
     const uint32_t *tile_sorted = nullptr;  // the longest-first order (one of tile_order / tile_v2)
     float *T_final = nullptr;
     uint32_t *n_last = nullptr, *n_blend = nullptr;
-    double *sgrad = nullptr;
+    double *sgrad = nullptr;     // [visible rank][12] screen-space gradients
+    uint32_t *vis_rank = nullptr;  // per cut entry: its visible rank (visible entries only)
     float *pgrad = nullptr;  // per cut entry, 32 floats
     float *cjac = nullptr;   // per cut entry, 12 floats: d colour / d dir, parent - node colour
 
@@ -103,7 +105,7 @@ struct hgs_ctx {
     uint64_t render_param_gen = 0;
     int last_nv = 0;
     uint32_t last_tiles = 0;
-    uint32_t last_cut = 0;
+    uint32_t last_cut = 0, last_visible = 0;
     size_t last_pix = 0;
     bool pairs_in_scratch = false;
     bool g_pairs_in_scratch = false;
@@ -346,6 +348,7 @@ hgs_status ensure_cut_cap(hgs_ctx *ctx, uint32_t cap)
     if ((s = realloc_buf(ctx, ctx->svals, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->pair_offsets, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->sgrad, (size_t)cap * 12))) return s;
+    if ((s = realloc_buf(ctx, ctx->vis_rank, (size_t)cap))) return s;
     if ((s = realloc_buf(ctx, ctx->pgrad, (size_t)cap * 32))) return s;
     if ((s = realloc_buf(ctx, ctx->cjac, (size_t)cap * 12))) return s;
     ctx->cut_cap = cap;
@@ -362,6 +365,7 @@ hgs_status ensure_pair_cap(hgs_ctx *ctx, uint32_t cap)
     hgs_status s;
     if ((s = realloc_buf(ctx, ctx->pkeys, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->pvals, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->dup_first, (size_t)duplicate_blocks(cap) + 1))) return s;
     ctx->pair_cap = cap;
     const size_t scratch = std::max<size_t>(ctx->cut_cap, ctx->pair_cap);
     if ((s = realloc_buf(ctx, ctx->k2, scratch))) return s;
@@ -411,13 +415,13 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     const uint32_t vblocks = (ctx->cut_cap + 255) / 256;
     launch_scan(ctx->vis_counts, nullptr, vblocks, nullptr, ctx->vis_offsets, &ctx->ctr->vis_total, ctx->partial, st);
     launch_compact_visible(ctx->vis_mask, ctx->vis_offsets, &ctx->ctr->cut_total, ctx->cut_cap, ctx->depth_key,
-                           ctx->skeys, ctx->svals, st);
+                           ctx->skeys, ctx->svals, ctx->vis_rank, st);
     SortScratch sc{ctx->k2, ctx->v2, ctx->hist, ctx->hist_scan, ctx->partial, ctx->scan_total};
     launch_radix_sort(ctx->skeys, ctx->svals, ctx->cut_cap, &ctx->ctr->vis_total, 32, sc, st);  // 4 passes: in place
     mark(3);
     launch_scan(ctx->ntiles, ctx->svals, ctx->cut_cap, &ctx->ctr->vis_total, ctx->pair_offsets, &ctx->ctr->pair_total,
                 ctx->partial, st);
-    launch_duplicate(ctx->rect, ctx->views_dev, nv, ctx->cut_base, ctx->svals, ctx->pair_offsets,
+    launch_duplicate(ctx->rect, ctx->views_dev, nv, ctx->cut_base, ctx->svals, ctx->pair_offsets, ctx->dup_first,
                      &ctx->ctr->vis_total, ctx->cut_cap, &ctx->ctr->pair_total, ctx->pair_cap, ctx->pkeys,
                      ctx->pvals, ctx->ctr, st);
     mark(4);
@@ -786,6 +790,7 @@ hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, floa
         ctx->last_nv = n_views;
         ctx->last_tiles = n_tiles;
         ctx->last_cut = c.cut_total;
+        ctx->last_visible = c.vis_total;
         ctx->last_pix = n_pix;
         ctx->r_tw = ctx->tile_w;
         ctx->r_th = ctx->tile_h;
@@ -827,20 +832,20 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_gr
     hipStream_t st = ctx->stream;
     HIPC(hipMemcpyAsync(ctx->views_dev, ctx->views_host, sizeof(DevView) * nv, hipMemcpyHostToDevice, st));
     const uint32_t cut = std::min(ctx->last_cut, ctx->cut_cap);
-    launch_zero_rows(ctx->sgrad, 12, ctx->svals, &ctx->ctr->vis_total, std::min(cut, ctx->cut_cap), st);
+    launch_zero_rows(ctx->sgrad, 12, &ctx->ctr->vis_total, std::min(cut, ctx->cut_cap), st);
     launch_fill_u32((uint32_t *)&ctx->ctr->bwd_evaluated, 0u, 6, st);
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
     {
         KernelTimer kt(ctx, 1, st);
         launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs,
                               ctx->axes, ctx->T_final,
-                              ctx->n_last, ctx->sgrad, ctx->wstats, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch, st);
+                              ctx->n_last, ctx->vis_rank, ctx->sgrad, ctx->wstats, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch, st);
     }
     const DevHier h = dev_hier(ctx);
     {
         KernelTimer kt(ctx, 2, st);
         launch_preprocess_backward(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t,
-                                   &ctx->ctr->cut_total, ctx->cut_cap, ctx->ntiles, ctx->recs, ctx->cjac, ctx->sgrad,
+                                   &ctx->ctr->cut_total, ctx->cut_cap, ctx->ntiles, ctx->recs, ctx->cjac, ctx->vis_rank, ctx->sgrad,
                                    ctx->pgrad, ctx->masks, (ctx->n + 63) / 64, ctx->word_off, ctx->interior,
                                    ctx->n_interior, out->mean, out->scale, out->rot, out->opacity, out->sh, out->dt,
                                    st);
@@ -898,7 +903,8 @@ hgs_status hgs_get_buffer(hgs_ctx *ctx, int32_t which, const void **dev_ptr, int
     case 2: *dev_ptr = ctx->T_final; *count = (int64_t)ctx->last_pix; break;
     case 3: *dev_ptr = ctx->n_last; *count = (int64_t)ctx->last_pix; break;
     case 4: *dev_ptr = ctx->n_blend; *count = (int64_t)ctx->last_pix; break;
-    case 5: *dev_ptr = ctx->sgrad; *count = (int64_t)ctx->last_cut * 12; break;
+    case 5: *dev_ptr = ctx->sgrad; *count = (int64_t)ctx->last_visible * 12; break;
+    case 8: *dev_ptr = ctx->vis_rank; *count = (int64_t)ctx->last_cut; break;
     case 6: *dev_ptr = ctx->cut_base; *count = ctx->last_nv + 1; break;
     case 7: *dev_ptr = ctx->ranges; *count = (int64_t)ctx->last_tiles * 2; break;
     default: return fail(ctx, HGS_ERR_INVALID_ARG, "unknown buffer");

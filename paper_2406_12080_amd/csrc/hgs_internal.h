@@ -118,13 +118,17 @@ void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uin
                        SplatRec *recs, double4 *axes, uint32_t *depth_key, uint2 *rect, uint32_t *ntiles,
                        float *cjac, uint64_t *vis_mask, uint32_t *vis_block_counts, int tile_w, int tile_h,
                        hipStream_t st);
+// Also writes vis_rank[k] = compaction position of visible cut entry k (the
+// row of its screen-space gradient).
 void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
                             uint32_t cap, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals,
-                            hipStream_t st);
+                            uint32_t *vis_rank, hipStream_t st);
+// block_first: duplicate_blocks(pair_cap) + 1 entries of workspace.
 void launch_duplicate(const uint2 *rect, const DevView *views, int nv, const uint32_t *cut_base,
-                      const uint32_t *sorted_vals, const uint32_t *pair_offsets, const uint32_t *vis_total,
-                      uint32_t vis_cap, const uint32_t *pair_total, uint32_t pair_cap, uint32_t *pair_keys,
-                      uint32_t *pair_vals, Counters *ctr, hipStream_t st);
+                      const uint32_t *sorted_vals, const uint32_t *pair_offsets, uint32_t *block_first,
+                      const uint32_t *vis_total, uint32_t vis_cap, const uint32_t *pair_total, uint32_t pair_cap,
+                      uint32_t *pair_keys, uint32_t *pair_vals, Counters *ctr, hipStream_t st);
+uint32_t duplicate_blocks(uint32_t pair_cap);
 void launch_ranges(const uint32_t *pair_keys, const uint32_t *pair_total, uint32_t pair_cap, uint2 *ranges,
                    hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
@@ -143,18 +147,27 @@ void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *tile_order,
                            const uint2 *ranges,
                            const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
-                           const uint32_t *n_last, double *sgrad, uint4 *wstats, Counters *ctr, int tw, int th,
-                           int batch, hipStream_t st);
-void launch_zero_rows(double *rows, int width, const uint32_t *sorted_vals, const uint32_t *vis_total,
-                      uint32_t vis_cap, hipStream_t st);
+                           const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
+                           Counters *ctr, int tw, int th, int batch, hipStream_t st);
+void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32_t vis_cap, hipStream_t st);
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
-                                const uint32_t *ntiles, const SplatRec *recs, const float *cjac, const double *sgrad,
-                                float *pg, const uint64_t *masks, int64_t words, const uint32_t *word_off,
+                                const uint32_t *ntiles, const SplatRec *recs, const float *cjac,
+                                const uint32_t *vis_rank, const double *sgrad, float *pg, const uint64_t *masks, int64_t words, const uint32_t *word_off,
                                 const int32_t *interior, int64_t n_interior, float *g_mean, float *g_scale,
                                 float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st);
 
 // ------------------------------------------------------------ wave helpers
+// Lane exchange through DPP (no LDS traffic); CTRL is a DPP control word:
+// 0x128 rotates each row of 16 lanes by 8 (lane l reads l ^ 8), 0x141
+// mirrors each half row (l ^ 7), quad permutations 0x4E (l ^ 2) and 0xB1
+// (l ^ 1).
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
     const uint32_t lane = __lane_id();

@@ -252,16 +252,6 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
                      stopped ? stop_t : walked_t, lane);
 }
 
-// Lane exchange inside each row of 16 lanes through DPP (no LDS traffic).
-// CTRL is a DPP control word: 0x128 rotates a row by 8 (lane l reads l ^ 8),
-// 0x141 mirrors each half row (l ^ 7), quad permutations 0x4E (l ^ 2) and
-// 0xB1 (l ^ 1).
-template <int CTRL>
-__device__ __forceinline__ float dpp_row(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
-}
-
 // One halving step: a lane keeps half of its H * 2 values and adds the same
 // half from its partner, which keeps the other half.
 template <int H, int CTRL>
@@ -270,7 +260,7 @@ __device__ __forceinline__ void rs_step(float (&v)[16], bool up)
 #pragma unroll
     for (int i = 0; i < H; ++i) {
         const float keep = up ? v[H + i] : v[i], send = up ? v[i] : v[H + i];
-        v[i] = keep + dpp_row<CTRL>(send);
+        v[i] = keep + dpp_move<CTRL>(send);
     }
 }
 
@@ -298,6 +288,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                                                       const double4 *__restrict__ axes,
                                                       const float *__restrict__ T_final,
                                                       const uint32_t *__restrict__ n_last,
+                                                      const uint32_t *__restrict__ vis_rank,
                                                       double *__restrict__ sgrad, uint4 *__restrict__ wstats)
 {
     constexpr int NT = TW * TH;
@@ -350,7 +341,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
             const uint32_t sidx = pair_vals[lo + j];
             const SplatRec r = recs[sidx];
             const double4 W64 = axes[sidx];
-            s_id[j] = sidx;
+            s_id[j] = vis_rank[sidx];  // gradient row
             s_w[j] = make_float4(r.w1x, r.w1y, r.w2x, r.w2y);
             s_o[j] = make_float4(r.An, r.Ap, r.t, r.invK);
             s_c[j] = make_float4(r.r, r.g, r.b, 0.0f);
@@ -482,12 +473,13 @@ void launch_blend_t(const DevView *views, int nv, uint32_t n_tiles, const uint32
 template <int TW, int TH, int BATCH>
 void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                         const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
-                        const uint32_t *n_last, double *sgrad, uint4 *wstats, hipStream_t st)
+                        const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
+                        hipStream_t st)
 {
     // the backward stages at most 256 splats per step (its LDS holds FP64 partial sums)
     constexpr int B = BATCH < 256 ? BATCH : 256;
     hipLaunchKernelGGL((k_blend_bwd<TW, TH, B>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order, ranges,
-                       pair_vals, recs, axes, T_final, n_last, sgrad, wstats);
+                       pair_vals, recs, axes, T_final, n_last, vis_rank, sgrad, wstats);
 }
 
 }  // namespace
@@ -534,15 +526,15 @@ void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t
 
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order,
                            const uint2 *ranges, const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
-                           const uint32_t *n_last, double *sgrad, uint4 *wstats, Counters *ctr, int tw, int th,
-                           int batch, hipStream_t st)
+                           const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
+                           Counters *ctr, int tw, int th, int batch, hipStream_t st)
 {
     if (batch == 0) batch = tw * th;
     if (!n_tiles) return;
 #define X(a, b, c)                                                                                                 \
     if (tw == a && th == b && batch == c) {                                                                        \
         launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last,    \
-                                    sgrad, wstats, st);                                                            \
+                                    vis_rank, sgrad, wstats, st);                                                  \
         hipLaunchKernelGGL(k_stats_reduce, dim3(256), dim3(256), 0, st, wstats,                                    \
                            n_tiles * (uint32_t)(tw * th / 64), &ctr->bwd_evaluated);                               \
         return;                                                                                                    \

@@ -2,6 +2,8 @@
 // FP64, footprint and tile rectangle, then SH colour (FP32) of the visible
 // splats only; then visibility compaction, tile
 // counts, pair emission and per-tile ranges.  Also the preprocess backward.
+#include <algorithm>
+
 #include "hgs_internal.h"
 #include "project.h"
 
@@ -127,7 +129,8 @@ __global__ __launch_bounds__(kT) void k_compact_visible(const uint64_t *__restri
                                                         const uint32_t *__restrict__ offsets,
                                                         const uint32_t *__restrict__ cut_total, uint32_t cap,
                                                         const uint32_t *__restrict__ depth_key,
-                                                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+                                                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                        uint32_t *__restrict__ vis_rank)
 {
     const uint32_t total = min(*cut_total, cap);
     const uint32_t k = blockIdx.x * kT + threadIdx.x;
@@ -150,79 +153,92 @@ __global__ __launch_bounds__(kT) void k_compact_visible(const uint64_t *__restri
         const uint32_t pos = offsets[blockIdx.x] + s_pre[w] + (uint32_t)__popcll(m & ((1ull << bit) - 1ull));
         keys[pos] = depth_key[k];
         vals[pos] = k;
+        vis_rank[k] = pos;
     }
 }
 
-// Emits the (tile, splat) pairs of the visible splats in depth order.  A
-// block takes kT consecutive splats and its threads write their pairs
-// cooperatively (thread o writes the block's pairs o, o + kT, ..., finding
-// the splat by binary search over the block's offsets in LDS), so one splat
-// covering thousands of tiles does not serialise on one thread.
+// Pair emission, balanced by pairs: block b writes pairs [b P, (b + 1) P)
+// of the depth-ordered list, whatever the footprints of the splats they come
+// from (the nearest splats of every view sort first and may cover thousands
+// of tiles each).  k_dup_starts records the splat holding each block's first
+// pair; k_duplicate stages the block's slice of the pair offsets in LDS and
+// finds every pair's splat by binary search there.
+constexpr uint32_t kDupPairs = 2048;
+
+__global__ __launch_bounds__(kT) void k_dup_starts(const uint32_t *__restrict__ offsets,
+                                                   const uint32_t *__restrict__ vis_total, uint32_t vis_cap,
+                                                   const uint32_t *__restrict__ pair_total, uint32_t pair_cap,
+                                                   uint32_t *__restrict__ block_first)
+{
+    const uint32_t nvis = min(*vis_total, vis_cap);
+    const uint32_t npairs = min(*pair_total, pair_cap);
+    const uint32_t j = blockIdx.x * kT + threadIdx.x;
+    if (j >= nvis) return;
+    const uint32_t o = offsets[j];
+    const uint32_t e = j + 1 < nvis ? offsets[j + 1] : *pair_total;  // end of splat j's pairs
+    for (uint32_t b = (o + kDupPairs - 1) / kDupPairs; b * kDupPairs < min(e, npairs); ++b) block_first[b] = j;
+}
+
 __global__ __launch_bounds__(kT) void k_duplicate(const uint2 *__restrict__ rect, const DevView *__restrict__ views,
                                                   int nv, const uint32_t *__restrict__ cut_base,
                                                   const uint32_t *__restrict__ sorted_vals,
                                                   const uint32_t *__restrict__ offsets,
+                                                  const uint32_t *__restrict__ block_first,
                                                   const uint32_t *__restrict__ vis_total, uint32_t vis_cap,
                                                   const uint32_t *__restrict__ pair_total, uint32_t pair_cap,
                                                   uint32_t *__restrict__ pair_keys, uint32_t *__restrict__ pair_vals,
                                                   Counters *__restrict__ ctr)
 {
-    __shared__ uint32_t s_off[kT + 1];  // block-local exclusive offsets, s_off[kT] = block total
-    __shared__ uint32_t s_val[kT], s_x0[kT], s_w[kT], s_y0[kT], s_base[kT], s_txn[kT];
-    const uint32_t nvis = min(*vis_total, vis_cap);
-    const uint32_t i0 = blockIdx.x * kT;
+    __shared__ uint32_t s_off[kDupPairs + 1];
+    __shared__ uint32_t s_cb[kMaxViews + 1];
     if (blockIdx.x == 0 && threadIdx.x == 0 && *pair_total > pair_cap) atomicOr(&ctr->overflow, 4u);
-    if (i0 >= nvis) return;
-    const uint32_t i = i0 + threadIdx.x;
-    const uint32_t first = offsets[i0];
-    uint32_t cnt = 0;
-    if (i < nvis) {
-        const uint32_t s = sorted_vals[i];
-        const uint2 r = rect[s];
-        const int v = view_of(cut_base, nv, s);
-        const uint32_t tx0 = r.x & 0xFFFFu, tx1 = r.x >> 16, ty0 = r.y & 0xFFFFu, ty1 = r.y >> 16;
-        s_val[threadIdx.x] = s;
-        s_x0[threadIdx.x] = tx0;
-        s_w[threadIdx.x] = tx1 - tx0 + 1u;
-        s_y0[threadIdx.x] = ty0;
-        s_base[threadIdx.x] = views[v].tile_base;
-        s_txn[threadIdx.x] = (uint32_t)views[v].tiles_x;
-        s_off[threadIdx.x] = offsets[i] - first;
-        cnt = (tx1 - tx0 + 1u) * (ty1 - ty0 + 1u);
-    }
-    const uint32_t last = min(nvis - i0, (uint32_t)kT) - 1u;  // last valid slot
-    if (threadIdx.x == last) s_off[kT] = offsets[i] - first + cnt;
+    const uint32_t nvis = min(*vis_total, vis_cap);
+    const uint32_t npairs = min(*pair_total, pair_cap);
+    const uint32_t o0 = blockIdx.x * kDupPairs;
+    if (o0 >= npairs || nvis == 0) return;
+    const uint32_t o1 = min(o0 + kDupPairs, npairs);
+    const uint32_t j0 = block_first[blockIdx.x];
+    // last splat that can hold one of the block's pairs: the one holding pair
+    // o1 (or the last splat); never more than kDupPairs past j0, since every
+    // splat has at least one pair (this also bounds the LDS slice when the
+    // pair count exceeded the capacity)
+    uint32_t j1 = o1 < npairs ? block_first[blockIdx.x + 1] : nvis - 1;
+    j1 = min(j1, j0 + kDupPairs);
+    const uint32_t cnt = j1 - j0 + 1;
+    for (uint32_t k = threadIdx.x; k < cnt; k += kT) s_off[k] = offsets[j0 + k];
+    for (int k = threadIdx.x; k <= nv; k += kT) s_cb[k] = cut_base[k];
     __syncthreads();
-    const uint32_t total = s_off[kT];
-    for (uint32_t o = threadIdx.x; o < total; o += kT) {
-        // slot j: the last one with s_off[j] <= o
-        uint32_t lo = 0, hi = last;
+    for (uint32_t o = o0 + threadIdx.x; o < o1; o += kT) {
+        uint32_t lo = 0, hi = cnt - 1;  // the last slot with s_off <= o
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1u) >> 1;
             if (s_off[mid] <= o) lo = mid;
             else hi = mid - 1u;
         }
-        const uint32_t q = o - s_off[lo], w = s_w[lo];
-        const uint32_t ty = s_y0[lo] + q / w, tx = s_x0[lo] + q % w;
-        const uint32_t g = first + o;
-        if (g < pair_cap) {
-            pair_keys[g] = s_base[lo] + ty * s_txn[lo] + tx;
-            pair_vals[g] = s_val[lo];
+        const uint32_t s = sorted_vals[j0 + lo];
+        int vlo = 0, vhi = nv - 1;  // view of cut entry s
+        while (vlo < vhi) {
+            const int mid = (vlo + vhi + 1) >> 1;
+            if (s_cb[mid] <= s) vlo = mid;
+            else vhi = mid - 1;
         }
+        const DevView &V = views[vlo];
+        const uint2 r = rect[s];
+        const uint32_t tx0 = r.x & 0xFFFFu, tx1 = r.x >> 16, ty0 = r.y & 0xFFFFu;
+        const uint32_t w = tx1 - tx0 + 1u, q = o - s_off[lo];
+        const uint32_t ty = ty0 + q / w, tx = tx0 + q % w;
+        pair_keys[o] = V.tile_base + ty * (uint32_t)V.tiles_x + tx;
+        pair_vals[o] = s;
     }
 }
 
-// Zeroes the FP64 screen-gradient rows of the visible splats (the only rows
-// the blend backward adds to and the preprocess backward reads).
+// Zeroes the first (visible count) x width doubles of `rows` (the screen
+// gradients, one row per visible splat by visible rank).
 __global__ __launch_bounds__(kT) void k_zero_rows(double *__restrict__ rows, int width,
-                                                  const uint32_t *__restrict__ sorted_vals,
                                                   const uint32_t *__restrict__ vis_total, uint32_t vis_cap)
 {
-    const uint32_t nvis = min(*vis_total, vis_cap);
-    const uint64_t e = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    const uint64_t i = e / (uint32_t)width;
-    if (i >= nvis) return;
-    rows[(size_t)sorted_vals[i] * width + (e - i * width)] = 0.0;
+    const size_t n = (size_t)min(*vis_total, vis_cap) * (size_t)width;
+    for (size_t e = (size_t)blockIdx.x * kT + threadIdx.x; e < n; e += (size_t)gridDim.x * kT) rows[e] = 0.0;
 }
 
 __global__ __launch_bounds__(kT) void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ total,
@@ -269,6 +285,7 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
                                                        const uint32_t *__restrict__ ntiles,
                                                        const SplatRec *__restrict__ recs,
                                                        const float *__restrict__ cjac,
+                                                       const uint32_t *__restrict__ vis_rank,
                                                        const double *__restrict__ sgrad, float *__restrict__ pg,
                                                        float *__restrict__ g_dt)
 {
@@ -280,7 +297,7 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
         if (g_dt) g_dt[k] = 0.0f;
         return;
     }
-    const double *sg = sgrad + (size_t)k * 12;
+    const double *sg = sgrad + (size_t)vis_rank[k] * 12;
     const double du = sg[0], dv = sg[1], dAn = sg[5], dAp = sg[6];
     const double drgb[3] = {sg[7], sg[8], sg[9]};
     double dt = sg[10];
@@ -448,11 +465,12 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
 // Gathers each interior node's parameter gradient from the cut entries of
 // every view: its own entry weighted 1 - t, and the entry of each child in
 // the cut with t > 0 weighted by that child's t (leaves are frozen; both
-// opacity terms enter alpha directly, unweighted).  One thread per interior
-// node, views and children in a fixed order: no atomics, and the result is
-// reproducible bit for bit.  The cut position of node j in view v follows
-// from the cut's bit masks: word_off[v][j / 64] plus the selected nodes
-// below j in its word.
+// opacity terms enter alpha directly, unweighted).  Four lanes per interior
+// node, lane g of the quad taking views g, g + 4, ...; the quad's partial
+// sums meet through DPP exchanges.  No atomics, and the summation order is
+// fixed, so the result is reproducible bit for bit.  The cut position of
+// node j in view v follows from the cut's bit masks: word_off[v][j / 64]
+// plus the selected nodes below j in its word.
 __global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uint64_t *__restrict__ masks,
                                                     int64_t words, const uint32_t *__restrict__ word_off,
                                                     const uint32_t *__restrict__ cut_total, uint32_t cap,
@@ -463,63 +481,79 @@ __global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uin
                                                     float *__restrict__ g_rot, float *__restrict__ g_op,
                                                     float *__restrict__ g_sh)
 {
-    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (q >= n_interior) return;
+    const int64_t q = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 2;
+    const int sub = threadIdx.x & 3;
+    const bool valid = q < n_interior;  // every lane of a quad stays for the exchange
     const int64_t n = h.n;
     const uint32_t total = min(*cut_total, cap);
-    const int64_t i = interior[q];
-    const int64_t c0 = h.child_begin[i];
-    const int nc = h.child_count[i];
-    float a[11];   // mean 3, scale 3, rotation 4, opacity
+    float a[11];  // mean 3, scale 3, rotation 4, opacity
     float ash[48];
 #pragma unroll
     for (int m = 0; m < 11; ++m) a[m] = 0.0f;
 #pragma unroll
     for (int m = 0; m < 48; ++m) ash[m] = 0.0f;
     bool any = false;
-    // cut position of node j in view v, or ~0u when j is not in that view's cut
-    auto position = [&](int v, int64_t j) -> uint32_t {
-        const int64_t wi = (int64_t)v * words + (j >> 6);
-        const uint64_t m = masks[wi];
-        const int b = (int)(j & 63);
-        if (!((m >> b) & 1ull)) return ~0u;
-        return word_off[wi] + (uint32_t)__popcll(m & ((1ull << b) - 1ull));
-    };
-    // adds w x the attribute gradient of entry pos; `op` selects the node
-    // (10) or parent (11) opacity term
-    auto take = [&](uint32_t pos, float w, int op) {
-        const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pos * kPG);
-        const float4 r7 = g4[7];
-        if (r7.w == 0.0f) return;  // no live splat
-        const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4], r5 = g4[5], r6 = g4[6];
-        const float g[31] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z,
-                             r2.w, r3.x, r3.y, r3.z, r3.w, r4.x, r4.y, r4.z, r4.w, r5.x, r5.y,
-                             r5.z, r5.w, r6.x, r6.y, r6.z, r6.w, r7.x, r7.y, r7.z};
+    int64_t i = 0;
+    if (valid) {
+        i = interior[q];
+        const int64_t c0 = h.child_begin[i];
+        const int nc = h.child_count[i];
+        // cut position of node j in view v, or ~0u when j is not in that view's cut
+        auto position = [&](int v, int64_t j) -> uint32_t {
+            const int64_t wi = (int64_t)v * words + (j >> 6);
+            const uint64_t m = masks[wi];
+            const int b = (int)(j & 63);
+            if (!((m >> b) & 1ull)) return ~0u;
+            return word_off[wi] + (uint32_t)__popcll(m & ((1ull << b) - 1ull));
+        };
+        // adds w x the attribute gradient of entry pos; `op` selects the node
+        // (10) or parent (11) opacity term
+        auto take = [&](uint32_t pos, float w, int op) {
+            const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pos * kPG);
+            const float4 r7 = g4[7];
+            if (r7.w == 0.0f) return;  // no live splat
+            const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4], r5 = g4[5], r6 = g4[6];
+            const float g[31] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z,
+                                 r2.w, r3.x, r3.y, r3.z, r3.w, r4.x, r4.y, r4.z, r4.w, r5.x, r5.y,
+                                 r5.z, r5.w, r6.x, r6.y, r6.z, r6.w, r7.x, r7.y, r7.z};
 #pragma unroll
-        for (int m = 0; m < 10; ++m) a[m] += w * g[m];
-        a[10] += op == 10 ? g[10] : g[11];
+            for (int m = 0; m < 10; ++m) a[m] += w * g[m];
+            a[10] += op == 10 ? g[10] : g[11];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float wc = w * g[12 + c];
+            for (int c = 0; c < 3; ++c) {
+                const float wc = w * g[12 + c];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) ash[3 * k + c] += wc * g[15 + k];
-        }
-        any = true;
-    };
+                for (int k = 0; k < 16; ++k) ash[3 * k + c] += wc * g[15 + k];
+            }
+            any = true;
+        };
 #pragma unroll 1
-    for (int v = 0; v < nv; ++v) {
-        uint32_t pos = position(v, i);
-        if (pos < total && ntiles[pos] != 0) take(pos, 1.0f - (float)cut_t[pos], 10);
+        for (int v = sub; v < nv; v += 4) {
+            uint32_t pos = position(v, i);
+            if (pos < total && ntiles[pos] != 0) take(pos, 1.0f - (float)cut_t[pos], 10);
 #pragma unroll 1
-        for (int c = 0; c < nc; ++c) {
-            pos = position(v, c0 + c);
-            if (pos < total && ntiles[pos] != 0) {
-                const float t = (float)cut_t[pos];
-                if (t > 0.0f) take(pos, t, 11);
+            for (int c = 0; c < nc; ++c) {
+                pos = position(v, c0 + c);
+                if (pos < total && ntiles[pos] != 0) {
+                    const float t = (float)cut_t[pos];
+                    if (t > 0.0f) take(pos, t, 11);
+                }
             }
         }
     }
-    if (!any) return;
+    const uint64_t anym = __ballot(any);
+    if (!((anym >> (__lane_id() & ~3u)) & 0xFull)) return;  // nothing in this quad
+#pragma unroll
+    for (int m = 0; m < 11; ++m) {
+        a[m] += dpp_move<0xB1>(a[m]);
+        a[m] += dpp_move<0x4E>(a[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < 48; ++m) {
+        ash[m] += dpp_move<0xB1>(ash[m]);
+        ash[m] += dpp_move<0x4E>(ash[m]);
+    }
+    if (!valid || sub != 0) return;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         g_mean[m * n + i] += a[m];
@@ -548,32 +582,39 @@ void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uin
 
 void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
                             uint32_t cap, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals,
-                            hipStream_t st)
+                            uint32_t *vis_rank, hipStream_t st)
 {
     const uint32_t blocks = (cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_compact_visible, dim3(blocks), dim3(kT), 0, st, vis_mask, vis_block_offsets, cut_total, cap,
-                       depth_key, keys, vals);
+                       depth_key, keys, vals, vis_rank);
 }
 
-void launch_zero_rows(double *rows, int width, const uint32_t *sorted_vals, const uint32_t *vis_total,
-                      uint32_t vis_cap, hipStream_t st)
+void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32_t vis_cap, hipStream_t st)
 {
-    const uint64_t blocks = ((uint64_t)vis_cap * width + kT - 1) / kT;
+    const uint64_t need = ((uint64_t)vis_cap * width + kT - 1) / kT;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(need, 8192);
     if (!blocks) return;
-    hipLaunchKernelGGL(k_zero_rows, dim3((uint32_t)blocks), dim3(kT), 0, st, rows, width, sorted_vals, vis_total,
-                       vis_cap);
+    hipLaunchKernelGGL(k_zero_rows, dim3(blocks), dim3(kT), 0, st, rows, width, vis_total, vis_cap);
 }
 
 void launch_duplicate(const uint2 *rect, const DevView *views, int nv, const uint32_t *cut_base,
-                      const uint32_t *sorted_vals, const uint32_t *pair_offsets, const uint32_t *vis_total,
-                      uint32_t vis_cap, const uint32_t *pair_total, uint32_t pair_cap, uint32_t *pair_keys,
-                      uint32_t *pair_vals, Counters *ctr, hipStream_t st)
+                      const uint32_t *sorted_vals, const uint32_t *pair_offsets, uint32_t *block_first,
+                      const uint32_t *vis_total, uint32_t vis_cap, const uint32_t *pair_total, uint32_t pair_cap,
+                      uint32_t *pair_keys, uint32_t *pair_vals, Counters *ctr, hipStream_t st)
 {
-    const uint32_t blocks = (vis_cap + kT - 1) / kT;
-    if (!blocks) return;
-    hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(kT), 0, st, rect, views, nv, cut_base, sorted_vals,
-                       pair_offsets, vis_total, vis_cap, pair_total, pair_cap, pair_keys, pair_vals, ctr);
+    const uint32_t sblocks = (vis_cap + kT - 1) / kT;
+    const uint32_t dblocks = (pair_cap + kDupPairs - 1) / kDupPairs;
+    if (!sblocks || !dblocks) return;
+    hipLaunchKernelGGL(k_dup_starts, dim3(sblocks), dim3(kT), 0, st, pair_offsets, vis_total, vis_cap, pair_total,
+                       pair_cap, block_first);
+    hipLaunchKernelGGL(k_duplicate, dim3(dblocks), dim3(kT), 0, st, rect, views, nv, cut_base, sorted_vals,
+                       pair_offsets, block_first, vis_total, vis_cap, pair_total, pair_cap, pair_keys, pair_vals, ctr);
+}
+
+uint32_t duplicate_blocks(uint32_t pair_cap)
+{
+    return (pair_cap + kDupPairs - 1) / kDupPairs;
 }
 
 void launch_ranges(const uint32_t *pair_keys, const uint32_t *pair_total, uint32_t pair_cap, uint2 *ranges,
@@ -601,16 +642,16 @@ void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st)
 
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
-                                const uint32_t *ntiles, const SplatRec *recs, const float *cjac, const double *sgrad,
-                                float *pg, const uint64_t *masks, int64_t words, const uint32_t *word_off,
+                                const uint32_t *ntiles, const SplatRec *recs, const float *cjac,
+                                const uint32_t *vis_rank, const double *sgrad, float *pg, const uint64_t *masks, int64_t words, const uint32_t *word_off,
                                 const int32_t *interior, int64_t n_interior, float *g_mean, float *g_scale,
                                 float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st)
 {
     const uint32_t blocks = (cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(kT), 0, st, h, views, nv, cut_base, cut_ids, cut_t,
-                       cut_total, cap, ntiles, recs, cjac, sgrad, pg, g_dt);
-    const int64_t gblocks = (n_interior + kT - 1) / kT;
+                       cut_total, cap, ntiles, recs, cjac, vis_rank, sgrad, pg, g_dt);
+    const int64_t gblocks = (4 * n_interior + kT - 1) / kT;
     if (gblocks)
         hipLaunchKernelGGL(k_grad_gather, dim3((uint32_t)gblocks), dim3(kT), 0, st, h, nv, masks, words, word_off,
                            cut_total, cap, cut_t, ntiles, pg, interior, n_interior, g_mean, g_scale, g_rot,

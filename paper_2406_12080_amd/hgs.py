@@ -25,7 +25,8 @@ COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t
                  "bwd_evaluated_t", "bwd_contrib")
 K_BLEND, K_BLEND_BWD, K_PREPROCESS_BWD = range(3)
 
-BUF_CUT_IDS, BUF_CUT_T, BUF_T_FINAL, BUF_N_LAST, BUF_N_BLEND, BUF_SGRAD, BUF_CUT_BASE, BUF_RANGES = range(8)
+(BUF_CUT_IDS, BUF_CUT_T, BUF_T_FINAL, BUF_N_LAST, BUF_N_BLEND, BUF_SGRAD, BUF_CUT_BASE, BUF_RANGES,
+ BUF_VIS_RANK) = range(9)
 
 
 class HgsError(RuntimeError):
