@@ -465,12 +465,13 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
 // Gathers each interior node's parameter gradient from the cut entries of
 // every view: its own entry weighted 1 - t, and the entry of each child in
 // the cut with t > 0 weighted by that child's t (leaves are frozen; both
-// opacity terms enter alpha directly, unweighted).  Four lanes per interior
-// node, lane g of the quad taking views g, g + 4, ...; the quad's partial
-// sums meet through DPP exchanges.  No atomics, and the summation order is
-// fixed, so the result is reproducible bit for bit.  The cut position of
-// node j in view v follows from the cut's bit masks: word_off[v][j / 64]
-// plus the selected nodes below j in its word.
+// opacity terms enter alpha directly, unweighted).  One thread per interior
+// node, views and entries in a fixed order: no atomics, and the result is
+// reproducible bit for bit.  Positions come from the cut's bit masks: node j
+// of view v sits at word_off[v][j / 64] plus the selected nodes below j in
+// its word.  The children of a node are contiguous ids, and those in the
+// cut are consecutive cut entries, so one or two mask words give all of
+// them at once.
 __global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uint64_t *__restrict__ masks,
                                                     int64_t words, const uint32_t *__restrict__ word_off,
                                                     const uint32_t *__restrict__ cut_total, uint32_t cap,
@@ -481,11 +482,12 @@ __global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uin
                                                     float *__restrict__ g_rot, float *__restrict__ g_op,
                                                     float *__restrict__ g_sh)
 {
-    const int64_t q = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 2;
-    const int sub = threadIdx.x & 3;
-    const bool valid = q < n_interior;  // every lane of a quad stays for the exchange
+    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (q >= n_interior) return;
     const int64_t n = h.n;
     const uint32_t total = min(*cut_total, cap);
+    const int64_t i = interior[q];
+    const int64_t c0 = h.child_begin[i], c1 = c0 + h.child_count[i];  // children [c0, c1)
     float a[11];  // mean 3, scale 3, rotation 4, opacity
     float ash[48];
 #pragma unroll
@@ -493,67 +495,57 @@ __global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uin
 #pragma unroll
     for (int m = 0; m < 48; ++m) ash[m] = 0.0f;
     bool any = false;
-    int64_t i = 0;
-    if (valid) {
-        i = interior[q];
-        const int64_t c0 = h.child_begin[i];
-        const int nc = h.child_count[i];
-        // cut position of node j in view v, or ~0u when j is not in that view's cut
-        auto position = [&](int v, int64_t j) -> uint32_t {
-            const int64_t wi = (int64_t)v * words + (j >> 6);
-            const uint64_t m = masks[wi];
-            const int b = (int)(j & 63);
-            if (!((m >> b) & 1ull)) return ~0u;
-            return word_off[wi] + (uint32_t)__popcll(m & ((1ull << b) - 1ull));
-        };
-        // adds w x the attribute gradient of entry pos; `op` selects the node
-        // (10) or parent (11) opacity term
-        auto take = [&](uint32_t pos, float w, int op) {
-            const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pos * kPG);
-            const float4 r7 = g4[7];
-            if (r7.w == 0.0f) return;  // no live splat
-            const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4], r5 = g4[5], r6 = g4[6];
-            const float g[31] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z,
-                                 r2.w, r3.x, r3.y, r3.z, r3.w, r4.x, r4.y, r4.z, r4.w, r5.x, r5.y,
-                                 r5.z, r5.w, r6.x, r6.y, r6.z, r6.w, r7.x, r7.y, r7.z};
+    // adds w x the attribute gradient of entry pos; `op` selects the node
+    // (10) or parent (11) opacity term
+    auto take = [&](uint32_t pos, float w, int op) {
+        const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pos * kPG);
+        const float4 r7 = g4[7];
+        if (r7.w == 0.0f) return;  // no live splat
+        const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4], r5 = g4[5], r6 = g4[6];
+        const float g[31] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z,
+                             r2.w, r3.x, r3.y, r3.z, r3.w, r4.x, r4.y, r4.z, r4.w, r5.x, r5.y,
+                             r5.z, r5.w, r6.x, r6.y, r6.z, r6.w, r7.x, r7.y, r7.z};
 #pragma unroll
-            for (int m = 0; m < 10; ++m) a[m] += w * g[m];
-            a[10] += op == 10 ? g[10] : g[11];
+        for (int m = 0; m < 10; ++m) a[m] += w * g[m];
+        a[10] += op == 10 ? g[10] : g[11];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float wc = w * g[12 + c];
+        for (int c = 0; c < 3; ++c) {
+            const float wc = w * g[12 + c];
 #pragma unroll
-                for (int k = 0; k < 16; ++k) ash[3 * k + c] += wc * g[15 + k];
-            }
-            any = true;
-        };
+            for (int k = 0; k < 16; ++k) ash[3 * k + c] += wc * g[15 + k];
+        }
+        any = true;
+    };
+    const int64_t wi = i >> 6, wa = c0 >> 6, wb = (c1 - 1) >> 6;
+    const uint64_t below_i = (1ull << (i & 63)) - 1ull;
 #pragma unroll 1
-        for (int v = sub; v < nv; v += 4) {
-            uint32_t pos = position(v, i);
+    for (int v = 0; v < nv; ++v) {
+        const uint64_t *mv = masks + (int64_t)v * words;
+        const uint32_t *ov = word_off + (int64_t)v * words;
+        // own entry
+        const uint64_t mo = mv[wi];
+        // children: the selected ones among [c0, c1), first position p0
+        uint32_t p0 = ~0u, nsel = 0;
+        for (int64_t w = wa; w <= wb; ++w) {
+            uint64_t m = mv[w];
+            const int lo = w == wa ? (int)(c0 & 63) : 0, hi = w == wb ? (int)((c1 - 1) & 63) : 63;
+            m &= (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull)) & ~((1ull << lo) - 1ull);
+            if (!m) continue;
+            if (p0 == ~0u) p0 = ov[w] + (uint32_t)__popcll(mv[w] & ((1ull << (__ffsll((long long)m) - 1)) - 1ull));
+            nsel += (uint32_t)__popcll(m);
+        }
+        if ((mo >> (i & 63)) & 1ull) {
+            const uint32_t pos = ov[wi] + (uint32_t)__popcll(mo & below_i);
             if (pos < total && ntiles[pos] != 0) take(pos, 1.0f - (float)cut_t[pos], 10);
-#pragma unroll 1
-            for (int c = 0; c < nc; ++c) {
-                pos = position(v, c0 + c);
-                if (pos < total && ntiles[pos] != 0) {
-                    const float t = (float)cut_t[pos];
-                    if (t > 0.0f) take(pos, t, 11);
-                }
-            }
+        }
+        for (uint32_t k = 0; k < nsel; ++k) {
+            const uint32_t pos = p0 + k;
+            if (pos >= total || ntiles[pos] == 0) continue;
+            const float t = (float)cut_t[pos];
+            if (t > 0.0f) take(pos, t, 11);
         }
     }
-    const uint64_t anym = __ballot(any);
-    if (!((anym >> (__lane_id() & ~3u)) & 0xFull)) return;  // nothing in this quad
-#pragma unroll
-    for (int m = 0; m < 11; ++m) {
-        a[m] += dpp_move<0xB1>(a[m]);
-        a[m] += dpp_move<0x4E>(a[m]);
-    }
-#pragma unroll
-    for (int m = 0; m < 48; ++m) {
-        ash[m] += dpp_move<0xB1>(ash[m]);
-        ash[m] += dpp_move<0x4E>(ash[m]);
-    }
-    if (!valid || sub != 0) return;
+    if (!any) return;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         g_mean[m * n + i] += a[m];
@@ -643,15 +635,16 @@ void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st)
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
                                 const uint32_t *ntiles, const SplatRec *recs, const float *cjac,
-                                const uint32_t *vis_rank, const double *sgrad, float *pg, const uint64_t *masks, int64_t words, const uint32_t *word_off,
-                                const int32_t *interior, int64_t n_interior, float *g_mean, float *g_scale,
-                                float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st)
+                                const uint32_t *vis_rank, const double *sgrad, float *pg, const uint64_t *masks,
+                                int64_t words, const uint32_t *word_off, const int32_t *interior, int64_t n_interior,
+                                float *g_mean, float *g_scale, float *g_rot, float *g_opacity, float *g_sh,
+                                float *g_dt, hipStream_t st)
 {
     const uint32_t blocks = (cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(kT), 0, st, h, views, nv, cut_base, cut_ids, cut_t,
                        cut_total, cap, ntiles, recs, cjac, vis_rank, sgrad, pg, g_dt);
-    const int64_t gblocks = (4 * n_interior + kT - 1) / kT;
+    const int64_t gblocks = (n_interior + kT - 1) / kT;
     if (gblocks)
         hipLaunchKernelGGL(k_grad_gather, dim3((uint32_t)gblocks), dim3(kT), 0, st, h, nv, masks, words, word_off,
                            cut_total, cap, cut_t, ntiles, pg, interior, n_interior, g_mean, g_scale, g_rot,
