@@ -103,23 +103,10 @@ __device__ __forceinline__ void stage_one(const SplatRec &r, const double4 &W64,
     }
 }
 
-// Per-wave work counts, summed by k_stats_reduce into three consecutive
-// counters: forward (evaluated, blended, evaluated with t > 0), backward
-// (evaluated, evaluated with t > 0, contributing).
-// Written with plain stores, one record per wave, and summed by
-// k_stats_reduce: no contended atomics on the hot path.
-__device__ __forceinline__ void store_wave_stats(uint4 *wstats, size_t slot, uint32_t a, uint32_t b, uint32_t c,
-                                                 int lane)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        a += (uint32_t)__shfl_xor((int)a, d, 64);
-        b += (uint32_t)__shfl_xor((int)b, d, 64);
-        c += (uint32_t)__shfl_xor((int)c, d, 64);
-    }
-    if (lane == 0) wstats[slot] = make_uint4(a, b, c, 0u);
-}
-
+// Per-wave work counts (uint4 per wave, plain stores) are summed by
+// k_stats_reduce into three consecutive counters: forward (evaluated,
+// blended, evaluated with t > 0), backward (evaluated, evaluated with t > 0,
+// contributing).  No contended atomics on the hot path.
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
 {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -162,8 +149,8 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
     // transmittance.  A pixel stops at the splat whose blend would take T
     // below kTMin; that splat was evaluated but not blended.
     float T = inside ? 1.0f : -1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    uint32_t last = 0, nb = 0, stop_n = 0, stop_t = 0;
-    uint32_t walked_t = 0;  // interpolated splats walked so far (same on every lane)
+    uint32_t last = 0, nb = 0;
+    uint32_t n_eval = 0, n_eval_t = 0;  // wave totals (scalar): evaluated pairs, of them interpolated
 
     // records of the next batch, loaded while the current one is composited
     SplatRec nxt[PER];
@@ -205,7 +192,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
         __syncthreads();
         if (b0 + BATCH < rg.y) fetch(b0 + BATCH);
         if (__ballot(T > 0.0f) == 0ull) continue;
-        const int cnt4 = ((int)min((uint32_t)BATCH, rg.y - b0) + 3) & ~3;
+        const int cnt = (int)min((uint32_t)BATCH, rg.y - b0), cnt4 = (cnt + 3) & ~3;
         const uint32_t jb = b0 - rg.x + 1u;  // 1-based list position of entry 0
         uint64_t tm = 0;
         for (int j0 = 0; j0 < cnt4; j0 += 4) {
@@ -214,7 +201,10 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
             for (int u = 0; u < 4; ++u) {
                 const int j = j0 + u;
                 const uint32_t bit = (uint32_t)(tm >> (j & 63)) & 1u;
-                walked_t += bit;
+                // work counts from the wave's live mask (scalar unit only)
+                const uint32_t n_live = j < cnt ? (uint32_t)__popcll(__ballot(T > 0.0f)) : 0u;
+                n_eval += n_live;
+                n_eval_t += bit ? n_live : 0u;
                 AlphaEval e;
                 eval_alpha(s_w[j], s_o[j], s_u[w][j], lx, ly, bit != 0u, e);
                 if (T > 0.0f && e.alpha >= kAlphaMin) {
@@ -227,8 +217,6 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
                     C2 += Cc.z * wgt;
                     nb += stop ? 0u : 1u;
                     last = stop ? last : jb + (uint32_t)j;
-                    stop_n = stop ? jb + (uint32_t)j : stop_n;
-                    stop_t = stop ? walked_t : stop_t;
                     T = stop ? -T : Tn;
                 }
             }
@@ -246,38 +234,81 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
         n_last[g] = last;
         n_blend[g] = nb;
     }
-    // a pixel that never stopped evaluated the whole list
-    const bool stopped = T < 0.0f;
-    store_wave_stats(wstats, (size_t)blockIdx.x * NW + w, stopped ? stop_n : rg.y - rg.x, nb,
-                     stopped ? stop_t : walked_t, lane);
-}
-
-// One halving step: a lane keeps half of its H * 2 values and adds the same
-// half from its partner, which keeps the other half.
-template <int H, int CTRL>
-__device__ __forceinline__ void rs_step(float (&v)[16], bool up)
-{
+    uint32_t nb_w = nb;
 #pragma unroll
-    for (int i = 0; i < H; ++i) {
-        const float keep = up ? v[H + i] : v[i], send = up ? v[i] : v[H + i];
-        v[i] = keep + dpp_move<CTRL>(send);
-    }
+    for (int d = 32; d >= 1; d >>= 1) nb_w += (uint32_t)__shfl_xor((int)nb_w, d, 64);
+    if (lane == 0) wstats[(size_t)blockIdx.x * NW + w] = make_uint4(n_eval, nb_w, n_eval_t, 0u);
 }
 
-// Reduce-scatter of 16 per-lane values within each row of 16 lanes: 8 + 4 +
-// 2 + 1 exchanges with partners l ^ 8, l ^ 7, l ^ 2, l ^ 1 (each pairs lanes
-// that agree on the bits decided before and differ in the next one: bits 3,
-// 2, 1, 0).  Returns, on lane l, slot (l & 15) summed over the lane's row.
-__device__ __forceinline__ float row_reduce16(float (&v)[16], int lane)
+// Cross-row halvings with the gfx950 lane swaps: permlane32_swap(x, y) moves
+// the upper half of x and the lower half of y into each other's place, so
+// x + y afterwards holds, on lanes 0-31, x summed over lanes l and l + 32
+// and, on lanes 32-63, y summed likewise (permlane16_swap does the same for
+// odd and even rows of 16): one swap and one add per pair of values.
+__device__ __forceinline__ float swap_add32(float x, float y)
 {
-    rs_step<8, 0x128>(v, (lane & 8) != 0);
-    rs_step<4, 0x141>(v, (lane & 4) != 0);
-    rs_step<2, 0x4E>(v, (lane & 2) != 0);
-    rs_step<1, 0xB1>(v, (lane & 1) != 0);
-    return v[0];
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap_add16(float x, float y)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sum over the 64 lanes of 11 per-lane values v[0..10]: two swap steps
+// (across halves, then across rows), two in-row halvings with DPP (partners
+// l ^ 8, then l ^ 7, each keeping one of two values), and a sum over the
+// quad (l ^ 2, l ^ 1).  Every lane of quad q = l >> 2 ends with the total of
+// value wave_slot(l) (-1: nothing).
+__device__ __forceinline__ float wave_reduce11(const float (&v)[11], int lane)
+{
+    const float S0 = swap_add32(v[0], v[1]), S1 = swap_add32(v[2], v[3]), S2 = swap_add32(v[4], v[5]);
+    const float S3 = swap_add32(v[6], v[7]), S4 = swap_add32(v[8], v[9]), S5 = swap_add32(v[10], 0.0f);
+    // rows 0..3 of Z0: v0 v2 v1 v3; Z1: v4 v6 v5 v7; Z2: v8 v10 v9 -
+    const float Z0 = swap_add16(S0, S1), Z1 = swap_add16(S2, S3), Z2 = swap_add16(S4, S5);
+    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
+    const float R0 = (b3 ? Z1 : Z0) + dpp_move<0x128>(b3 ? Z0 : Z1);
+    const float R1 = (b3 ? 0.0f : Z2) + dpp_move<0x128>(b3 ? Z2 : 0.0f);
+    float F = (b2 ? R1 : R0) + dpp_move<0x141>(b2 ? R0 : R1);
+    F += dpp_move<0x4E>(F);
+    F += dpp_move<0xB1>(F);
+    return F;
+}
+
+__device__ __forceinline__ int wave_slot(int lane)
+{
+    // by row (lane >> 4) and (b2, b3) = bits 2 and 3 of the lane
+    constexpr int8_t kSlot[4][4] = {{0, 4, 8, -1}, {2, 6, 10, -1}, {1, 5, 9, -1}, {3, 7, -1, -1}};
+    return kSlot[lane >> 4][((lane >> 2) & 1) * 2 + ((lane >> 3) & 1)];
 }
 
 constexpr int kG = 12;  // floats per splat in the screen-space gradient
+
+// Per-lane gradient slots of one (pixel, splat) pair, summed over the tile:
+//   0, 1   P1, P2 = h u1, h u2           with h = G dL/dG (G the Gaussian)
+//   2..4   Q11, Q12, Q22 = h u1 u1, h u1 u2, h u2 u2
+//   5, 6   dL/dA_n, dL/dA_p (A = kappa |o|)
+//   7..9   dL/d colour
+//   10     dL/dt through alpha
+// The screen-space gradient follows from the tile sums by the splat's
+// (per-tile constant) axes: with g = conic d = (u1 w1 + u2 w2) / kHalfLog2e
+// and G = exp(-q/2), dL/dmean = sum h g and dL/dSigma2' = -sum (h / 2) g g^T
+// (the covariance gradient through the conic), both linear in P and Q.
+__device__ __forceinline__ void screen_grad(const float4 &W, const float *sg, double out[5])
+{
+    const double k = 1.0 / kHalfLog2e;
+    const double wx = W.x, wy = W.y, wz = W.z, ww = W.w;
+    const double P1 = sg[0], P2 = sg[1], Q11 = sg[2], Q12 = sg[3], Q22 = sg[4];
+    out[0] = k * (wx * P1 + wz * P2);
+    out[1] = k * (wy * P1 + ww * P2);
+    // (a, b, c) = (xx, 2 xy, yy) of sum (h / 2) g g^T, entering dL/dSigma2' with a minus
+    // sign that the chain below takes as -dq = h / 2
+    out[2] = 0.5 * k * k * (wx * wx * Q11 + 2.0 * wx * wz * Q12 + wz * wz * Q22);
+    out[3] = k * k * (wx * wy * Q11 + (wx * ww + wz * wy) * Q12 + wz * ww * Q22);
+    out[4] = 0.5 * k * k * (wy * wy * Q11 + 2.0 * wy * ww * Q12 + ww * ww * Q22);
+}
 
 template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict__ views, int nv,
@@ -292,9 +323,9 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                                                       double *__restrict__ sgrad, uint4 *__restrict__ wstats)
 {
     constexpr int NT = TW * TH;
+    constexpr int NW = NT / 64;
     constexpr int SX = TW / 8;
     constexpr int NB = (TW / 8) * (TH / 8);
-    constexpr float kInvHL2e = (float)(1.0 / kHalfLog2e);
     __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
     __shared__ float2 s_u[NB][BATCH];  // c1, c2
     __shared__ uint32_t s_id[BATCH];
@@ -311,6 +342,8 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
     const bool inside = px < V.W && py < V.H;
     const float lx = (float)(lane & 7), ly = (float)(lane >> 3);
     const uint2 rg = ranges[tile];
+    const int slot = wave_slot(lane);
+    const bool writer = (lane & 3) == 0 && slot >= 0;
 
     float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
     uint32_t last = 0;
@@ -332,7 +365,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
     __syncthreads();
     const uint32_t end = rg.x + s_max;
     float R0 = 0.0f, R1 = 0.0f, R2 = 0.0f;  // colour composited behind the current splat
-    uint32_t ne = 0, net = 0, nc = 0;
+    uint32_t n_eval = 0, n_eval_t = 0, n_con = 0;  // wave totals (scalar)
 
     for (uint32_t hi = end; hi > rg.x;) {
         const uint32_t lo = hi - rg.x > (uint32_t)BATCH ? hi - BATCH : rg.x;
@@ -357,77 +390,76 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
         __syncthreads();
         for (int j = cnt - 1; j >= 0; --j) {
             const uint32_t li = lo - rg.x + (uint32_t)j;
+            const bool in_range = li < last;
+            const uint64_t live = __ballot(in_range);
+            if (live == 0ull) continue;
             const float4 Wv = s_w[j], Ov = s_o[j];
             const float2 U = s_u[w][j];
+            const bool interp = __builtin_amdgcn_readfirstlane(__float_as_int(Ov.z)) > 0;
             AlphaEval e;
-            bool contrib = false;
-            if (li < last) {
-                eval_alpha(Wv, Ov, U, lx, ly, __builtin_amdgcn_readfirstlane(__float_as_int(Ov.z)) > 0, e);
-                contrib = e.alpha >= kAlphaMin;
-                ++ne;
-                net += Ov.z > 0.0f;
-                nc += contrib;
+            eval_alpha(Wv, Ov, U, lx, ly, interp, e);
+            const bool contrib = in_range && e.alpha >= kAlphaMin;
+            const uint64_t cm = __ballot(contrib);
+            n_eval += (uint32_t)__popcll(live);
+            n_eval_t += interp ? (uint32_t)__popcll(live) : 0u;
+            if (cm == 0ull) continue;
+            n_con += (uint32_t)__popcll(cm);
+            // every lane runs the update; a non-contributing lane has a = 0 and
+            // dL/dalpha = 0, which leaves T and R as they are and all slots 0
+            const float4 Cc = s_c[j];
+            const float a = contrib ? e.alpha : 0.0f;
+            T = T * __builtin_amdgcn_rcpf(1.0f - a);
+            const float dal_raw = T * ((Cc.x - R0) * g0 + (Cc.y - R1) * g1 + (Cc.z - R2) * g2);
+            const float dal = contrib ? dal_raw : 0.0f;
+            const float aT = a * T;
+            float v[11];
+            v[7] = aT * g0;
+            v[8] = aT * g1;
+            v[9] = aT * g2;
+            R0 = a * Cc.x + (1.0f - a) * R0;
+            R1 = a * Cc.y + (1.0f - a) * R1;
+            R2 = a * Cc.z + (1.0f - a) * R2;
+            float dan = dal, dap = 0.0f;
+            v[10] = 0.0f;
+            if (interp) {
+                dan = (1.0f - Ov.z) * dal;
+                const float dapr = Ov.z * dal;
+                v[10] = (e.apr - e.an) * dal;
+                dap = dapr * Ov.w * __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(1.0f - e.ap) * (Ov.w - 1.0f));
             }
-            if (__ballot(contrib) == 0ull) continue;
-            float v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = 0.0f;
-            if (contrib) {
-                const float4 Cc = s_c[j];
-                const float a = e.alpha;
-                T = T * __builtin_amdgcn_rcpf(1.0f - a);
-                const float dal = T * ((Cc.x - R0) * g0 + (Cc.y - R1) * g1 + (Cc.z - R2) * g2);
-                const float aT = a * T;
-                v[7] = aT * g0;
-                v[8] = aT * g1;
-                v[9] = aT * g2;
-                R0 = a * Cc.x + (1.0f - a) * R0;
-                R1 = a * Cc.y + (1.0f - a) * R1;
-                R2 = a * Cc.z + (1.0f - a) * R2;
-                float dan = dal, dap = 0.0f;
-                if (Ov.z > 0.0f) {
-                    dan = (1.0f - Ov.z) * dal;
-                    const float dapr = Ov.z * dal;
-                    v[10] = (e.apr - e.an) * dal;
-                    dap = dapr * Ov.w *
-                          __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(1.0f - e.ap) * (Ov.w - 1.0f));
-                }
-                float dG = 0.0f;
-                if (!e.cn) {
-                    v[5] = dan * e.G;
-                    dG += dan * Ov.x;
-                }
-                if (Ov.z > 0.0f && !e.cp) {
-                    v[6] = dap * e.G;
-                    dG += dap * Ov.y;
-                }
-                // G = exp(-q/2), q = d^T conic d, d = pixel - mean.  With g = conic d
-                // = (u1 w1 + u2 w2) / kHalfLog2e:  dq/dmean = -2 g, and through the
-                // conic (the inverse of Sigma2'), dL/dSigma2' = -sum dL/dq g g^T;
-                // accumulated as (a, b, c) = (xx, 2 xy, yy) of that symmetric matrix.
-                const float dq = -0.5f * e.G * dG;
-                const float gx = kInvHL2e * (e.u1 * Wv.x + e.u2 * Wv.z);
-                const float gy = kInvHL2e * (e.u1 * Wv.y + e.u2 * Wv.w);
-                v[0] = -2.0f * dq * gx;
-                v[1] = -2.0f * dq * gy;
-                v[2] = -dq * gx * gx;
-                v[3] = -2.0f * dq * gx * gy;
-                v[4] = -dq * gy * gy;
+            const float dan_c = e.cn ? 0.0f : dan, dap_c = e.cp ? 0.0f : dap;
+            v[5] = dan_c * e.G;
+            v[6] = dap_c * e.G;
+            const float h = e.G * (dan_c * Ov.x + dap_c * Ov.y);  // G dL/dG
+            v[0] = h * e.u1;
+            v[1] = h * e.u2;
+            v[2] = v[0] * e.u1;
+            v[3] = v[0] * e.u2;
+            v[4] = v[1] * e.u2;
+            const float tot = wave_reduce11(v, lane);
+            if (writer && tot != 0.0f) {
+                if constexpr (NW == 1) s_g[j][slot] = tot;
+                else atomicAdd(&s_g[j][slot], tot);
             }
-            const float rs = row_reduce16(v, lane);
-            const int slot = lane & 15;  // the four rows meet in LDS
-            if (slot < 11 && rs != 0.0f) atomicAdd(&s_g[j][slot], rs);
         }
         __syncthreads();
         for (int idx = threadIdx.x; idx < cnt * 11; idx += NT) {
             const int j = idx / 11, q = idx % 11;
-            const float sm = s_g[j][q];
-            if (sm != 0.0f) unsafeAtomicAdd(&sgrad[(size_t)s_id[j] * kG + q], (double)sm);
+            double val;
+            if (q < 5) {
+                const float sg5[5] = {s_g[j][0], s_g[j][1], s_g[j][2], s_g[j][3], s_g[j][4]};
+                double sc[5];
+                screen_grad(s_w[j], sg5, sc);
+                val = sc[q];
+            } else {
+                val = (double)s_g[j][q];
+            }
+            if (val != 0.0) unsafeAtomicAdd(&sgrad[(size_t)s_id[j] * kG + q], val);
         }
         __syncthreads();
         hi = lo;
     }
-    store_wave_stats(wstats, (size_t)blockIdx.x * (NT / 64) + w, ne, net, nc, lane);
+    if (lane == 0) wstats[(size_t)blockIdx.x * NW + w] = make_uint4(n_eval, n_eval_t, n_con, 0u);
 }
 
 __global__ __launch_bounds__(256) void k_stats_reduce(const uint4 *__restrict__ s, uint32_t n,
