@@ -30,15 +30,17 @@
  *     stream) unless a call is documented to synchronise;
  *   - a ctx must not be used from two threads at once.
  *
- * Hierarchy layout (structure of arrays, FP32, component index major):
+ * Hierarchy layout (one array per attribute, FP32, node-major: the
+ * components of a node are contiguous, so the sparse reads of a cut touch
+ * few cache lines):
  *   nodes in BFS order, root = 0, parent[i] < i, the children of a node
  *   contiguous starting at child_begin; child_count == 0 <=> leaf;
- *   bmin/bmax [3][N] axis-aligned box over the node's leaves;
- *   mean [3][N]; scale [3][N] (activated, world units);
- *   rot [4][N] quaternion (w, x, y, z);
+ *   bmin/bmax [N][3] axis-aligned box over the node's leaves;
+ *   mean [N][3]; scale [N][3] (activated, world units);
+ *   rot [N][4] quaternion (w, x, y, z);
  *   opacity [N]: opacity of a leaf, "falloff" (may exceed 1) of an interior
  *   node; the renderer uses |opacity|;
- *   sh [48][N]: row 3*k + c = coefficient of real SH basis function k
+ *   sh [N][48]: entry 3*k + c = coefficient of real SH basis function k
  *   (k = l*l + l + m, degree <= 3) for colour channel c.
  */
 #ifndef HGS_H
@@ -81,8 +83,8 @@ typedef struct {
     int64_t n_nodes;
     int32_t sh_degree;                               /* must be 3 */
     const int32_t *parent, *child_begin, *child_count; /* [N] */
-    const float *bmin, *bmax;                        /* [3][N] */
-    const float *mean, *scale, *rot, *opacity, *sh;  /* [3][N] [3][N] [4][N] [N] [48][N] */
+    const float *bmin, *bmax;                        /* [N][3] */
+    const float *mean, *scale, *rot, *opacity, *sh;  /* [N][3] [N][3] [N][4] [N] [N][48] */
 } hgs_hierarchy_desc;
 
 /* Copy a hierarchy into library-owned device memory.  `src_on_device` = 0:

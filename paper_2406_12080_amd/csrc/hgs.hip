@@ -575,7 +575,7 @@ hgs_status hgs_upload(hgs_ctx *ctx, const hgs_hierarchy_desc *d, int src_on_devi
             kids += cc[i];
         }
         for (int k = 0; k < 3; ++k) {
-            const float lo = bmin[k * N + i], hi = bmax[k * N + i];
+            const float lo = bmin[3 * i + k], hi = bmax[3 * i + k];
             if (!(lo <= hi) || !std::isfinite(lo) || !std::isfinite(hi))
                 return fail(ctx, HGS_ERR_INVALID_ARG, "box of node " + std::to_string(i) + " is invalid");
         }
@@ -617,8 +617,16 @@ hgs_status hgs_upload(hgs_ctx *ctx, const hgs_hierarchy_desc *d, int src_on_devi
     for (int k = 0; k < 5; ++k)
         if ((s = dalloc(ctx, (void **)&ctx->own[k], 4 * comp[k] * N))) return s;
     HIPC(hipMemcpy(ctx->pinfo, pinfo.data(), 4 * N, hipMemcpyHostToDevice));
-    HIPC(hipMemcpy(ctx->box, bmin.data(), 12 * N, hipMemcpyHostToDevice));
-    HIPC(hipMemcpy(ctx->box + 3 * N, bmax.data(), 12 * N, hipMemcpyHostToDevice));
+    {
+        // the cut sweep reads the boxes component-major ([6][N]), one thread per node
+        std::vector<float> box(6 * (size_t)N);
+        for (int64_t i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k) {
+                box[k * N + i] = bmin[3 * i + k];
+                box[(3 + k) * N + i] = bmax[3 * i + k];
+            }
+        HIPC(hipMemcpy(ctx->box, box.data(), 24 * N, hipMemcpyHostToDevice));
+    }
     HIPC(hipMemcpy(ctx->child_count, cc.data(), 4 * N, hipMemcpyHostToDevice));
     for (int64_t i = 0; i < N; ++i)
         if (cc[i] == 0) cb[i] = 0;  // unused for leaves

@@ -36,7 +36,7 @@ struct DevHier {
     const float *box;       // [6][n]: bmin x y z, bmax x y z
     const int32_t *child_count;
     const int32_t *child_begin;  // first child (children are contiguous); 0 for leaves
-    const float *mean, *scale, *rot, *opacity, *sh;
+    const float *mean, *scale, *rot, *opacity, *sh;  // node-major: [N][3] [N][3] [N][4] [N] [N][48]
 };
 
 // Blend record of one splat (64 bytes).  The mean is kept as an integer pixel

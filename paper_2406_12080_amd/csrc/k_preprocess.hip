@@ -293,6 +293,7 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
     const uint32_t k = blockIdx.x * kT + threadIdx.x;
     if (k >= total) return;
     float *out = pg + (size_t)k * kPG;
+    float row[kPG];  // the entry's attribute gradient, stored as eight float4
     if (ntiles[k] == 0) {
         if (g_dt) g_dt[k] = 0.0f;
         return;
@@ -310,7 +311,6 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
         if (g_dt) g_dt[k] = 0.0f;
         return;
     }
-    const int64_t n = h.n;
     const uint32_t node = P.node, par = P.par;
     const bool node_leaf = (h.pinfo[node] & kLeafBit) != 0;
     const bool use_par = P.has_par && P.t > 0.0;
@@ -336,11 +336,11 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
         float Y[16];  // stored in FP32, evaluated in FP32
         sh_eval_f((float)P.dir[0], (float)P.dir[1], (float)P.dir[2], Y);
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) out[15 + kk] = Y[kk];
+        for (int kk = 0; kk < 16; ++kk) row[15 + kk] = Y[kk];
     }
-    out[12] = (float)gr[0];
-    out[13] = (float)gr[1];
-    out[14] = (float)gr[2];
+    row[12] = (float)gr[0];
+    row[13] = (float)gr[1];
+    row[14] = (float)gr[2];
     double dmu[3];
     {
         const double dd = P.dir[0] * ddir[0] + P.dir[1] * ddir[1] + P.dir[2] * ddir[2];
@@ -439,26 +439,37 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
 #pragma unroll
     for (int m = 0; m < 4; ++m) dqr[m] = (dq[m] - P.q[m] * qd) / P.qlen;
 
-    // gradient with respect to the interpolated attributes; the scatter
-    // kernel weights it by (1 - t) for the node and t for the parent
+    // gradient with respect to the interpolated attributes; the gather
+    // weights it by (1 - t) for the node and t for the parent
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        out[m] = (float)dmu[m];
-        out[3 + m] = (float)ds[m];
-        if (use_par) {
-            dt += dmu[m] * ((double)h.mean[m * n + par] - (double)h.mean[m * n + node]);
-            dt += ds[m] * ((double)h.scale[m * n + par] - (double)h.scale[m * n + node]);
-        }
+        row[m] = (float)dmu[m];
+        row[3 + m] = (float)ds[m];
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        out[6 + m] = (float)dqr[m];
-        if (use_par) dt += dqr[m] * ((double)h.rot[m * n + par] - (double)h.rot[m * n + node]);
+    for (int m = 0; m < 4; ++m) row[6 + m] = (float)dqr[m];
+    if (use_par) {
+        const float3 mn = *reinterpret_cast<const float3 *>(h.mean + 3 * (size_t)node);
+        const float3 mp = *reinterpret_cast<const float3 *>(h.mean + 3 * (size_t)par);
+        const float3 sn = *reinterpret_cast<const float3 *>(h.scale + 3 * (size_t)node);
+        const float3 sp = *reinterpret_cast<const float3 *>(h.scale + 3 * (size_t)par);
+        const float4 qn = *reinterpret_cast<const float4 *>(h.rot + 4 * (size_t)node);
+        const float4 qp = *reinterpret_cast<const float4 *>(h.rot + 4 * (size_t)par);
+        dt += dmu[0] * ((double)mp.x - (double)mn.x) + dmu[1] * ((double)mp.y - (double)mn.y) +
+              dmu[2] * ((double)mp.z - (double)mn.z);
+        dt += ds[0] * ((double)sp.x - (double)sn.x) + ds[1] * ((double)sp.y - (double)sn.y) +
+              ds[2] * ((double)sp.z - (double)sn.z);
+        dt += dqr[0] * ((double)qp.x - (double)qn.x) + dqr[1] * ((double)qp.y - (double)qn.y) +
+              dqr[2] * ((double)qp.z - (double)qn.z) + dqr[3] * ((double)qp.w - (double)qn.w);
     }
     // opacity through |o|
-    out[10] = (float)((P.on_raw > 0.0 ? 1.0 : (P.on_raw < 0.0 ? -1.0 : 0.0)) * don);
-    out[11] = (float)((P.op_raw > 0.0 ? 1.0 : (P.op_raw < 0.0 ? -1.0 : 0.0)) * dop);
-    out[kPG - 1] = 1.0f;
+    row[10] = (float)((P.on_raw > 0.0 ? 1.0 : (P.on_raw < 0.0 ? -1.0 : 0.0)) * don);
+    row[11] = (float)((P.op_raw > 0.0 ? 1.0 : (P.op_raw < 0.0 ? -1.0 : 0.0)) * dop);
+    row[kPG - 1] = 1.0f;
+    float4 *out4 = reinterpret_cast<float4 *>(out);
+#pragma unroll
+    for (int q = 0; q < kPG / 4; ++q)
+        out4[q] = make_float4(row[4 * q], row[4 * q + 1], row[4 * q + 2], row[4 * q + 3]);
     if (g_dt) g_dt[k] = use_par ? (float)dt : 0.0f;
 }
 
@@ -484,7 +495,6 @@ __global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uin
 {
     const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (q >= n_interior) return;
-    const int64_t n = h.n;
     const uint32_t total = min(*cut_total, cap);
     const int64_t i = interior[q];
     const int64_t c0 = h.child_begin[i], c1 = c0 + h.child_count[i];  // children [c0, c1)
@@ -546,16 +556,34 @@ __global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uin
         }
     }
     if (!any) return;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        g_mean[m * n + i] += a[m];
-        g_scale[m * n + i] += a[3 + m];
-    }
-#pragma unroll
-    for (int m = 0; m < 4; ++m) g_rot[m * n + i] += a[6 + m];
+    // node-major records: vector read-modify-write
+    float3 *gm = reinterpret_cast<float3 *>(g_mean + 3 * i), *gs = reinterpret_cast<float3 *>(g_scale + 3 * i);
+    float4 *gr = reinterpret_cast<float4 *>(g_rot + 4 * i), *gh = reinterpret_cast<float4 *>(g_sh + 48 * i);
+    float3 m3 = *gm, s3 = *gs;
+    float4 r4 = *gr;
+    m3.x += a[0];
+    m3.y += a[1];
+    m3.z += a[2];
+    s3.x += a[3];
+    s3.y += a[4];
+    s3.z += a[5];
+    r4.x += a[6];
+    r4.y += a[7];
+    r4.z += a[8];
+    r4.w += a[9];
+    *gm = m3;
+    *gs = s3;
+    *gr = r4;
     g_op[i] += a[10];
 #pragma unroll
-    for (int m = 0; m < 48; ++m) g_sh[m * n + i] += ash[m];
+    for (int q = 0; q < 12; ++q) {
+        float4 h4 = gh[q];
+        h4.x += ash[4 * q];
+        h4.y += ash[4 * q + 1];
+        h4.z += ash[4 * q + 2];
+        h4.w += ash[4 * q + 3];
+        gh[q] = h4;
+    }
 }
 
 }  // namespace

@@ -136,7 +136,6 @@ struct Proj {
 __device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V, uint32_t node, double t_in,
                                               Proj &P)
 {
-    const int64_t n = h.n;
     P.node = node;
     const uint32_t pi = h.pinfo[node];
     const uint32_t par = pi & ~kLeafBit;
@@ -146,23 +145,27 @@ __device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V
     P.use_par = use_par;
     P.par = P.has_par ? par : node;
     P.K = P.has_par ? h.child_count[par] : 1;
-    const uint32_t src = use_par ? par : node;
+    const uint32_t src = use_par ? par : node;  // the node itself when t = 0: same values
     const double t = P.t, w0 = 1.0 - t;
+    // node-major records: one vector load per attribute
+    const float3 mn3 = *reinterpret_cast<const float3 *>(h.mean + 3 * (size_t)node);
+    const float3 mp3 = *reinterpret_cast<const float3 *>(h.mean + 3 * (size_t)src);
+    const float3 sn3 = *reinterpret_cast<const float3 *>(h.scale + 3 * (size_t)node);
+    const float3 sp3 = *reinterpret_cast<const float3 *>(h.scale + 3 * (size_t)src);
+    const float4 qn4 = *reinterpret_cast<const float4 *>(h.rot + 4 * (size_t)node);
+    const float4 qp4 = *reinterpret_cast<const float4 *>(h.rot + 4 * (size_t)src);
+    const float mn[3] = {mn3.x, mn3.y, mn3.z}, mp[3] = {mp3.x, mp3.y, mp3.z};
+    const float sn[3] = {sn3.x, sn3.y, sn3.z}, sp[3] = {sp3.x, sp3.y, sp3.z};
+    const float qn[4] = {qn4.x, qn4.y, qn4.z, qn4.w}, qp[4] = {qp4.x, qp4.y, qp4.z, qp4.w};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double mn = h.mean[k * n + node];
-        const double mp = use_par ? (double)h.mean[k * n + src] : mn;
-        P.mu_rel[k] = (mn - (double)V.eye[k]) + t * (mp - mn);
-        const double sn = h.scale[k * n + node];
-        const double sp = use_par ? (double)h.scale[k * n + src] : sn;
-        P.s[k] = w0 * sn + t * sp;
+        P.mu_rel[k] = ((double)mn[k] - (double)V.eye[k]) + t * ((double)mp[k] - (double)mn[k]);
+        P.s[k] = w0 * (double)sn[k] + t * (double)sp[k];
     }
     double ql = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double qn = h.rot[k * n + node];
-        const double qp = use_par ? (double)h.rot[k * n + src] : qn;
-        P.qraw[k] = w0 * qn + t * qp;
+        P.qraw[k] = w0 * (double)qn[k] + t * (double)qp[k];
         ql += P.qraw[k] * P.qraw[k];
     }
     P.qlen = sqrt(ql);
@@ -237,26 +240,34 @@ __device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V
 __device__ __forceinline__ void splat_colour(const DevHier &h, const Proj &P, float raw[3], float dcol[3][3],
                                              float dpn[3])
 {
-    const int64_t n = h.n;
     const float x = (float)P.dir[0], y = (float)P.dir[1], z = (float)P.dir[2];
     const float t = (float)P.t, w0 = 1.0f - t;
-    const uint32_t node = P.node, src = P.use_par ? P.par : P.node;
+    // 48 coefficients per node, 192 B: twelve 16-byte loads per record
+    const float4 *a4 = reinterpret_cast<const float4 *>(h.sh + (size_t)48 * P.node);
+    const float4 *b4 = reinterpret_cast<const float4 *>(h.sh + (size_t)48 * (P.use_par ? P.par : P.node));
     float Y[16];
     sh_eval_f(x, y, z, Y);
+    float sht[48];
+    float acc[3] = {0.5f, 0.5f, 0.5f}, dp[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int q4 = 0; q4 < 12; ++q4) {
+        const float4 cn4 = a4[q4], cp4 = b4[q4];
+        const float cn[4] = {cn4.x, cn4.y, cn4.z, cn4.w}, cp[4] = {cp4.x, cp4.y, cp4.z, cp4.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int q = 4 * q4 + e, k = q / 3, ch = q % 3;  // coefficient 3 k + ch
+            sht[q] = w0 * cn[e] + t * cp[e];
+            acc[ch] += sht[q] * Y[k];
+            dp[ch] += (cp[e] - cn[e]) * Y[k];
+        }
+    }
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         float c[16];
-        float acc = 0.5f, dp = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const float cn = h.sh[(3 * k + ch) * n + node];
-            const float cp = P.use_par ? h.sh[(3 * k + ch) * n + src] : cn;
-            c[k] = w0 * cn + t * cp;
-            acc += c[k] * Y[k];
-            dp += (cp - cn) * Y[k];
-        }
-        raw[ch] = acc;
-        dpn[ch] = dp;
+        for (int k = 0; k < 16; ++k) c[k] = sht[3 * k + ch];
+        raw[ch] = acc[ch];
+        dpn[ch] = dp[ch];
         sh_grad_dot_f(x, y, z, c, dcol[ch]);
     }
 }

@@ -168,9 +168,10 @@ class Renderer:
 
     # -- hierarchy ---------------------------------------------------------
     def upload(self, hier) -> None:
-        """Upload a hierarchy: a ``synth.Hierarchy`` / dict of numpy arrays
-        (host) or of CUDA tensors (device)."""
-        a = hier.arrays() if hasattr(hier, "arrays") else dict(hier)
+        """Upload a hierarchy: a ``synth.Hierarchy``, or a dict of node-major
+        arrays (see ``node_major``) as numpy arrays (host) or CUDA tensors
+        (device)."""
+        a = node_major(hier) if hasattr(hier, "arrays") else dict(hier)
         torch = self.torch
         on_dev = isinstance(a["mean"], torch.Tensor) and a["mean"].is_cuda
         keep = {}
@@ -277,8 +278,21 @@ class Renderer:
         return out[:n.value]
 
 
+NODE_MAJOR_FIELDS = ("bmin", "bmax", "mean", "scale", "rot", "sh")
+
+
+def node_major(hier) -> dict:
+    """The arrays of a ``synth.Hierarchy`` (component-major, [k][N]) in the
+    C ABI's node-major layout ([N][k]: a node's components contiguous)."""
+    a = dict(hier.arrays())
+    for k in NODE_MAJOR_FIELDS:
+        a[k] = np.ascontiguousarray(np.asarray(a[k]).T)
+    return a
+
+
 def params_to_device(hier, device="cuda"):
-    """The five parameter arrays of a hierarchy as contiguous CUDA tensors."""
+    """The five parameter arrays of a hierarchy (a ``synth.Hierarchy`` or a
+    node-major dict) as contiguous CUDA tensors in the node-major layout."""
     import torch
-    a = hier.arrays() if hasattr(hier, "arrays") else hier
+    a = node_major(hier) if hasattr(hier, "arrays") else hier
     return {k: torch.as_tensor(np.ascontiguousarray(a[k], np.float32)).to(device) for k in PARAM_FIELDS}

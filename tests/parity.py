@@ -75,7 +75,8 @@ def check_grads(gpu: dict, og: np.ndarray, leaf_mask, rel=GRAD_REL, exclude=None
         ref = og[a:b].copy()
         ref[:, leaf_mask] = 0.0
         ref = ref[:, keep]
-        g = np.asarray(gpu[name], np.float64).reshape(b - a, -1)[:, keep]
+        # GPU gradients are node-major ([N][k]), the oracle's component-major
+        g = np.asarray(gpu[name], np.float64).reshape(-1, b - a).T[:, keep]
         nrm = np.linalg.norm(ref)
         err = np.linalg.norm(g - ref)
         rms = nrm / np.sqrt(ref.size)

@@ -275,8 +275,7 @@ def test_error_paths(hgs_mod, c1):
     with pytest.raises(H.HgsError) as e:
         r.render([synth.make_views(1)[0]])
     assert e.value.status == H.ERR_STATE
-    bad = c1.arrays()
-    bad = {k: np.array(v) for k, v in bad.items()}
+    bad = {k: np.array(v) for k, v in H.node_major(c1).items()}
     bad["parent"][5] = 7  # parent index not below the child
     with pytest.raises(H.HgsError) as e:
         r.upload(bad)
