@@ -10,7 +10,10 @@
 // by the thread that holds the node (the node's box is read once per batch
 // of views).  Selected nodes are compacted in ascending id order with a
 // 64-lane ballot bitmask per wave, a per-block count, one exclusive scan over
-// (view, block), and an emit pass that writes ids and weights.
+// (view, block), and an emit pass that writes ids and weights.  The
+// predicate F(n) = leaf or eps(n) <= tau is evaluated once per (view, node)
+// into a bit mask; a second sweep combines each node's bit with its
+// parent's (parents of neighbouring nodes are neighbours: cached words).
 //
 // The selection is defined by eps evaluated in FP64 with contraction
 // disabled, from the FP32 stored boxes, so that it does not depend on FP32
@@ -58,7 +61,7 @@ __device__ __forceinline__ int meets_tau_f32(const float b[6], const DevView &V,
         const float ext = hi - lo;
         if (ext > L) L = ext;
         const float e = V.eye[k];
-        const float c = e < lo ? lo : (e > hi ? hi : e);
+        const float c = __builtin_amdgcn_fmed3f(e, lo, hi);  // clamp of e to [lo, hi] (lo <= hi)
         const float dd = e - c;
         inside = inside && dd == 0.0f;
         d2 = fmaf(dd, dd, d2);
@@ -78,7 +81,52 @@ __device__ __forceinline__ void load_box(const DevHier &h, int64_t i, float b[6]
     for (int k = 0; k < 6; ++k) b[k] = h.box[k * h.n + i];
 }
 
-__global__ __launch_bounds__(kCutThreads) void k_cut_flags(DevHier h, const DevView *__restrict__ views, int nv,
+// Pass 1: F(n) = leaf or eps(n) <= tau, one bit per (view, node) in fmask.
+__global__ __launch_bounds__(kCutThreads) void k_cut_meets(DevHier h, const DevView *__restrict__ views, int nv,
+                                                           uint64_t *__restrict__ fmask)
+{
+    const int64_t n = h.n;
+    const int64_t words = (n + 63) >> 6;
+    const int lane = threadIdx.x & 63;
+#pragma unroll 1
+    for (int it = 0; it < kCutItems; ++it) {
+        const int64_t i0 = (int64_t)blockIdx.x * kCutBlock + it * kCutThreads + (threadIdx.x & ~63);
+        const int64_t i = i0 + lane;
+        const bool valid = i < n;
+        if (i0 >= n) break;
+        float b[6] = {0, 0, 0, 0, 0, 0};
+        bool leaf = true;
+        if (valid) {
+            load_box(h, i, b);
+            leaf = (h.pinfo[i] & kLeafBit) != 0;
+        }
+        const bool all_leaves = __ballot(valid && !leaf) == 0ull;
+        // the words of up to 64 views are gathered on lanes (lane u: view
+        // v0 + u) and stored with one instruction
+#pragma unroll 1
+        for (int v0 = 0; v0 < nv; v0 += 64) {
+            uint64_t word = 0;
+            const int nvc = min(64, nv - v0);
+#pragma unroll 1
+            for (int u = 0; u < nvc; ++u) {
+                bool F = true;  // leaves (and the padding past n) always meet tau
+                if (!all_leaves && !leaf) {
+                    const DevView &V = views[v0 + u];
+                    const float tau2 = V.tau * V.tau, f = V.fx > V.fy ? V.fx : V.fy;
+                    const int a = meets_tau_f32(b, V, f, tau2);
+                    F = a > 0 || (a < 0 && granularity(b, V) <= (double)V.tau);
+                }
+                const uint64_t m = __ballot(F);
+                word = lane == u ? m : word;
+            }
+            if (lane < nvc) fmask[(int64_t)(v0 + lane) * words + (i0 >> 6)] = word;
+        }
+    }
+}
+
+// Pass 2: n is in the cut when F(n) holds and F(parent) does not (or n is the
+// root): a test of two bits.  Writes the cut bit masks and per-block counts.
+__global__ __launch_bounds__(kCutThreads) void k_cut_flags(DevHier h, int nv, const uint64_t *__restrict__ fmask,
                                                            uint64_t *__restrict__ masks,
                                                            uint32_t *__restrict__ block_counts, int nblocks)
 {
@@ -93,41 +141,36 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_flags(DevHier h, const DevV
         const int64_t i0 = (int64_t)blockIdx.x * kCutBlock + it * kCutThreads + (threadIdx.x & ~63);
         const int64_t i = i0 + lane;
         const bool valid = i < n;
-        float b[6] = {0, 0, 0, 0, 0, 0}, pb[6] = {0, 0, 0, 0, 0, 0};
-        uint32_t pi = kRootParent;
-        if (valid) {
-            load_box(h, i, b);
-            pi = h.pinfo[i];
-        }
-        const bool leaf = (pi & kLeafBit) != 0;
-        const uint32_t par = pi & ~kLeafBit;
+        uint32_t par = kRootParent;
+        if (valid) par = h.pinfo[i] & ~kLeafBit;
         const bool root = par == kRootParent;
-        if (valid && !root) load_box(h, par, pb);
+        if (i0 >= n) break;
+        constexpr int U = 8;  // views per step: their loads are independent
 #pragma unroll 1
-        for (int v = 0; v < nv; ++v) {
-            const DevView &V = views[v];
-            const double tau = V.tau;
-            const float tau2 = V.tau * V.tau, f = V.fx > V.fy ? V.fx : V.fy;
-            bool in = false;
-            if (valid) {
-                bool Fn = leaf;
-                if (!Fn) {
-                    const int a = meets_tau_f32(b, V, f, tau2);
-                    Fn = a > 0 || (a < 0 && granularity(b, V) <= tau);
+        for (int c0 = 0; c0 < nv; c0 += 64) {  // up to 64 views gathered on lanes
+            const int nvc = min(64, nv - c0);
+            uint64_t word = 0;
+#pragma unroll 1
+            for (int u0 = 0; u0 < nvc; u0 += U) {
+                uint64_t own[U], pw[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int v = c0 + u0 + u;
+                    const uint64_t *fv = fmask + (int64_t)v * words;
+                    own[u] = u0 + u < nvc ? fv[i0 >> 6] : 0ull;  // the wave's own word
+                    pw[u] = u0 + u < nvc && valid && !root ? fv[par >> 6] : 0ull;
                 }
-                if (Fn) {
-                    bool Fp = false;
-                    if (!root) {
-                        const int a = meets_tau_f32(pb, V, f, tau2);
-                        Fp = a > 0 || (a < 0 && granularity(pb, V) <= tau);
-                    }
-                    in = !Fp;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool in =
+                        valid && ((own[u] >> lane) & 1ull) && (root || !((pw[u] >> (par & 63)) & 1ull));
+                    const uint64_t m = __ballot(in);
+                    word = lane == u0 + u ? m : word;
                 }
             }
-            const uint64_t m = __ballot(in);
-            if (lane == 0 && i0 < n) {
-                masks[(int64_t)v * words + (i0 >> 6)] = m;
-                if (m) atomicAdd(&s_cnt[v], (uint32_t)__popcll(m));
+            if (lane < nvc) {
+                masks[(int64_t)(c0 + lane) * words + (i0 >> 6)] = word;
+                if (word) atomicAdd(&s_cnt[c0 + lane], (uint32_t)__popcll(word));
             }
         }
     }
@@ -213,10 +256,11 @@ __global__ void k_cut_finish(const uint32_t *__restrict__ block_offsets, int nbl
     if (v == nv) cut_base[nv] = *total;
 }
 
-void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *masks, uint32_t *block_counts,
-                      int nblocks, hipStream_t st)
+void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *fmask, uint64_t *masks,
+                      uint32_t *block_counts, int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cut_flags, dim3(nblocks), dim3(kCutThreads), 0, st, h, views, nv, masks, block_counts,
+    hipLaunchKernelGGL(k_cut_meets, dim3(nblocks), dim3(kCutThreads), 0, st, h, views, nv, fmask);
+    hipLaunchKernelGGL(k_cut_flags, dim3(nblocks), dim3(kCutThreads), 0, st, h, nv, fmask, masks, block_counts,
                        nblocks);
 }
 
