@@ -156,7 +156,7 @@ def main(argv=None):
     ap.add_argument("--tile", default=None, help="WxHxB, skips the autotuner (e.g. 16x16x256)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-row-stride", type=int, default=16)
+    ap.add_argument("--cpu-row-stride", type=int, default=4)
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
