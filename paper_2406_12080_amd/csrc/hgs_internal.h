@@ -108,7 +108,7 @@ struct SortScratch {
     uint32_t *partial;   // kScanBlocks
     uint32_t *total;     // 1
 };
-constexpr int kSortBlocksMax = 1024;
+constexpr int kSortBlocksMax = 4096;
 // Returns true when the sorted result is in (s.k2, s.v2) (odd pass count).
 bool launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t cap, const uint32_t *n_dev, int bits,
                        const SortScratch &s, hipStream_t st);

@@ -55,12 +55,20 @@ __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *__restrict__ key
     uint32_t b0, b1;
     chunk_of(n, G, b0, b1);
     const uint64_t lt = lanemask_lt();
-    for (uint32_t base = b0; base < b1; base += kT) {
-        const uint32_t i = base + threadIdx.x;
-        const bool valid = i < b1;
-        const uint32_t d = valid ? (keys[i] >> shift) & 0xFFu : 0u;
-        const uint64_t peers = match_digit(d, valid);
-        if (valid && (peers & lt) == 0) atomicAdd(&s_h[d], (uint32_t)__popcll(peers));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (uint32_t base = b0; base < b1; base += kTile) {
+        uint32_t d[kItems];
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {  // all loads of the tile in flight at once
+            const uint32_t i = base + (uint32_t)(w * 64 * kItems + it * 64 + lane);
+            d[it] = i < b1 ? (keys[i] >> shift) & 0xFFu : 0x100u;
+        }
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const bool valid = d[it] < 0x100u;
+            const uint64_t peers = match_digit(d[it] & 0xFFu, valid);
+            if (valid && (peers & lt) == 0) atomicAdd(&s_h[d[it]], (uint32_t)__popcll(peers));
+        }
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * G + blockIdx.x] = s_h[threadIdx.x];
@@ -165,7 +173,10 @@ bool launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t cap, const uint3
 {
     if (cap == 0 || bits <= 0) return false;
     const int passes = (bits + 7) / 8;
-    const int G = (int)std::min<uint32_t>(kSortBlocksMax, std::max<uint32_t>(1u, (cap + 16383u) / 16384u));
+    // blocks of >= 4 tiles each, up to kSortBlocksMax: enough waves in flight
+    // to cover the memory latency of the digit passes
+    const uint32_t want = std::max<uint32_t>(1u, (cap + 4 * kTile - 1) / (4 * kTile));
+    const int G = (int)std::min<uint32_t>(kSortBlocksMax, want);
     uint32_t *ki = keys, *vi = vals, *ko = s.k2, *vo = s.v2;
     for (int p = 0; p < passes; ++p) {
         const int shift = p * 8;
