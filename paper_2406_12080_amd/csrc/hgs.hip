@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,7 @@ struct DBuf {
 };
 
 constexpr int kTimedKernels = 4;  // blend, blend backward, preprocess backward, preprocess
+constexpr int kStageRing = 4;     // pinned staging slots for the view copies
 
 struct RenderKey {
     int nv = -1;
@@ -65,7 +67,13 @@ struct hgs_ctx {
     uint64_t layout_gen = 1;
     std::vector<void *> allocs;
     DevView *views_dev = nullptr;
-    DevView *views_host = nullptr;  // pinned
+    DevView *views_host = nullptr;  // host records of the current views (pageable, changed freely)
+    // pinned staging slots of the asynchronous view copies: a slot is reused
+    // only after the copy that reads it has run (its event)
+    DevView *stage[kStageRing] = {};
+    hipEvent_t stage_ev[kStageRing] = {};
+    bool stage_used[kStageRing] = {};
+    int stage_next = 0;
     Counters *ctr = nullptr;
     Counters *ctr_host = nullptr;   // pinned
     uint32_t cut_cap = 0, pair_cap = 0;
@@ -142,6 +150,22 @@ hgs_status fail(hgs_ctx *c, hgs_status s, const std::string &msg)
         if (e_ != hipSuccess)                                                                          \
             return fail(ctx, HGS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
     } while (0)
+
+// Queues the copy of the first n host view records to views_dev on st.  The
+// DMA reads a pinned staging slot, not views_host: the copy may run long
+// after this returns (behind earlier work on st), and the host records may
+// change meanwhile.  A slot is reused only once its previous copy has run.
+hgs_status push_views(hgs_ctx *ctx, int n, hipStream_t st)
+{
+    const int k = ctx->stage_next;
+    ctx->stage_next = (k + 1) % kStageRing;
+    if (ctx->stage_used[k]) HIPC(hipEventSynchronize(ctx->stage_ev[k]));
+    memcpy(ctx->stage[k], ctx->views_host, sizeof(DevView) * (size_t)n);
+    HIPC(hipMemcpyAsync(ctx->views_dev, ctx->stage[k], sizeof(DevView) * (size_t)n, hipMemcpyHostToDevice, st));
+    HIPC(hipEventRecord(ctx->stage_ev[k], st));
+    ctx->stage_used[k] = true;
+    return HGS_OK;
+}
 
 hgs_status dalloc(hgs_ctx *ctx, void **p, size_t bytes)
 {
@@ -471,10 +495,15 @@ hgs_status hgs_create(hgs_ctx **out, int device, void *hip_stream)
         if (hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess) { s = HGS_ERR_HIP; break; }
         if (hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess) { s = HGS_ERR_HIP; break; }
         if (hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess) { s = HGS_ERR_HIP; break; }
-        if (hipHostMalloc((void **)&ctx->views_host, sizeof(DevView) * kMaxViews, hipHostMallocDefault) != hipSuccess) {
-            s = HGS_ERR_OOM;
-            break;
+        ctx->views_host = new (std::nothrow) DevView[kMaxViews];
+        if (!ctx->views_host) { s = HGS_ERR_OOM; break; }
+        for (int k = 0; k < kStageRing && s == HGS_OK; ++k) {
+            if (hipHostMalloc((void **)&ctx->stage[k], sizeof(DevView) * kMaxViews, hipHostMallocDefault) != hipSuccess)
+                s = HGS_ERR_OOM;
+            else if (hipEventCreateWithFlags(&ctx->stage_ev[k], hipEventDisableTiming) != hipSuccess)
+                s = HGS_ERR_HIP;
         }
+        if (s != HGS_OK) break;
         if (hipHostMalloc((void **)&ctx->ctr_host, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
             s = HGS_ERR_OOM;
             break;
@@ -506,7 +535,11 @@ void hgs_destroy(hgs_ctx *ctx)
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     for (void *p : ctx->allocs) (void)hipFree(p);
     ctx->allocs.clear();
-    if (ctx->views_host) (void)hipHostFree(ctx->views_host);
+    delete[] ctx->views_host;
+    for (int k = 0; k < kStageRing; ++k) {
+        if (ctx->stage[k]) (void)hipHostFree(ctx->stage[k]);
+        if (ctx->stage_ev[k]) (void)hipEventDestroy(ctx->stage_ev[k]);
+    }
     if (ctx->ctr_host) (void)hipHostFree(ctx->ctr_host);
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
@@ -683,7 +716,7 @@ hgs_status hgs_cut(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *
     if ((s = setup_views(ctx, view, 1, nullptr, n_tiles, n_pix))) return s;
     if ((s = ensure_fixed(ctx, 1, 0, 0))) return s;
     hipStream_t st = ctx->stream;
-    HIPC(hipMemcpyAsync(ctx->views_dev, ctx->views_host, sizeof(DevView), hipMemcpyHostToDevice, st));
+    if ((s = push_views(ctx, 1, st))) return s;
     const DevHier h = dev_hier(ctx);
     const int nb = cut_blocks(ctx->n);
     launch_fill_u32((uint32_t *)ctx->ctr, 0u, sizeof(Counters) / 4, st);
@@ -740,7 +773,7 @@ hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, floa
             HIPC(hipEventRecord(ctx->ev_in, ctx->stream));
             HIPC(hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
         }
-        HIPC(hipMemcpyAsync(ctx->views_dev, ctx->views_host, sizeof(DevView) * n_views, hipMemcpyHostToDevice, st));
+        if ((s = push_views(ctx, n_views, st))) return s;
         if (graph) {
             RenderKey key;
             key.nv = n_views;
@@ -839,7 +872,7 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_gr
     }
     HIPC(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
-    HIPC(hipMemcpyAsync(ctx->views_dev, ctx->views_host, sizeof(DevView) * nv, hipMemcpyHostToDevice, st));
+    if (hgs_status s = push_views(ctx, nv, st)) return s;
     const uint32_t cut = std::min(ctx->last_cut, ctx->cut_cap);
     launch_zero_rows(ctx->sgrad, 12, &ctx->ctr->vis_total, std::min(cut, ctx->cut_cap), st);
     launch_fill_u32((uint32_t *)&ctx->ctr->bwd_evaluated, 0u, 6, st);

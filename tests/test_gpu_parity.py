@@ -243,6 +243,35 @@ def test_backward_parity_c2s(hgs_mod, c2s):
     assert nt > 0 and dt_rel <= PR.GRAD_REL
 
 
+def test_backward_queued_behind_busy_stream(r_c2s, c2s):
+    # the backward's view records (with the dL pointers) are copied to the
+    # device asynchronously; queued behind long-running work on the same
+    # stream, the copy runs after the call has returned and must still see
+    # this call's records
+    from paper_2406_12080_amd import hgs as H
+    views = [synth.look_at((0, -40, 1.7), (0, 0, 2.5), (0, 0, 1), 640, 360, 6.0),
+             synth.look_at((30, -30, 1.7), (0, 0, 2.5), (0, 0, 1), 1280, 720, 6.0)]
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    dL = [torch.randn((v.height, v.width, 3), generator=gen).cuda() for v in views]
+    P = H.params_to_device(c2s)
+    out = []
+    for busy in (False, True):
+        r_c2s.render(views)
+        grads = {k: torch.zeros_like(P[k]) for k in H.PARAM_FIELDS}
+        _sync()
+        if busy:
+            big = torch.empty(1 << 28, device="cuda")
+            for _ in range(8):
+                big.fill_(1.0)
+        r_c2s.backward(dL, grads)
+        _sync()
+        out.append({k: g.cpu().numpy().astype(np.float64) for k, g in grads.items()})
+    for k in out[0]:
+        a, b = out[0][k], out[1][k]
+        assert np.linalg.norm(a) > 0
+        assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a), k
+
+
 def test_autograd_l1_matches_oracle(hgs_mod, c1):
     from paper_2406_12080_amd import hgs as H
     from paper_2406_12080_amd.autograd import render
