@@ -329,7 +329,8 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
     __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
     __shared__ float2 s_u[NB][BATCH];  // c1, c2
     __shared__ uint32_t s_id[BATCH];
-    __shared__ float s_g[BATCH][kG];
+    __shared__ __align__(16) float s_g[BATCH][kG];
+    __shared__ double s_d[BATCH * 11];  // the flushed terms, splat-major
     __shared__ uint32_t s_max;
     const uint32_t tile = tile_order[blockIdx.x];  // longest lists first
     const int vi = view_of_tile(views, nv, tile);
@@ -443,17 +444,30 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
             }
         }
         __syncthreads();
+        // flush: one lane per splat turns the tile's partial sums into the
+        // 11 screen-space terms (FP64); then the terms of all splats go out
+        // as consecutive atomics, row by row
+        for (int j = threadIdx.x; j < cnt; j += NT) {
+            const float4 a = *reinterpret_cast<const float4 *>(&s_g[j][0]);
+            const float4 b = *reinterpret_cast<const float4 *>(&s_g[j][4]);
+            const float4 c = *reinterpret_cast<const float4 *>(&s_g[j][8]);
+            const float sg5[5] = {a.x, a.y, a.z, a.w, b.x};
+            double sc[5];
+            screen_grad(s_w[j], sg5, sc);
+            double *d = s_d + j * 11;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) d[q] = sc[q];
+            d[5] = (double)b.y;
+            d[6] = (double)b.z;
+            d[7] = (double)b.w;
+            d[8] = (double)c.x;
+            d[9] = (double)c.y;
+            d[10] = (double)c.z;
+        }
+        __syncthreads();
         for (int idx = threadIdx.x; idx < cnt * 11; idx += NT) {
-            const int j = idx / 11, q = idx % 11;
-            double val;
-            if (q < 5) {
-                const float sg5[5] = {s_g[j][0], s_g[j][1], s_g[j][2], s_g[j][3], s_g[j][4]};
-                double sc[5];
-                screen_grad(s_w[j], sg5, sc);
-                val = sc[q];
-            } else {
-                val = (double)s_g[j][q];
-            }
+            const double val = s_d[idx];
+            const int j = idx / 11, q = idx - 11 * j;
             if (val != 0.0) unsafeAtomicAdd(&sgrad[(size_t)s_id[j] * kG + q], val);
         }
         __syncthreads();
@@ -508,8 +522,11 @@ void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const ui
                         const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
                         hipStream_t st)
 {
-    // the backward stages at most 256 splats per step (its LDS holds FP64 partial sums)
-    constexpr int B = BATCH < 256 ? BATCH : 256;
+    // the backward stages at most 32 splats per wave and step: its LDS holds
+    // the FP32 partial sums and the FP64 flushed terms of every staged
+    // splat, and a smaller footprint keeps more tiles resident per CU
+    constexpr int BMAX = 32 * (TW * TH / 64);
+    constexpr int B = BATCH < BMAX ? BATCH : BMAX;
     hipLaunchKernelGGL((k_blend_bwd<TW, TH, B>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order, ranges,
                        pair_vals, recs, axes, T_final, n_last, vis_rank, sgrad, wstats);
 }
