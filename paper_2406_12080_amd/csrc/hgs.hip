@@ -87,7 +87,8 @@ struct hgs_ctx {
     SplatRec *recs = nullptr;
     double4 *axes = nullptr;
     uint32_t *depth_key = nullptr, *ntiles = nullptr;
-    uint2 *rect = nullptr;
+    uint4 *trec = nullptr;  // per cut entry: tile rectangle and count (visible entries)
+    uint2 *rect = nullptr;  // tile rectangles of the visible splats in depth order
     uint64_t *vis_mask = nullptr;
     uint32_t *vis_counts = nullptr, *vis_offsets = nullptr;
     uint32_t *skeys = nullptr, *svals = nullptr, *pair_offsets = nullptr;
@@ -297,6 +298,16 @@ hgs_status setup_views(hgs_ctx *ctx, const hgs_view *views, int nv, float *const
         d.H = s.height;
         d.z_near = s.z_near;
         d.tau = s.tau;
+        {
+            // eps <= tau  <=>  L^2 <= (tau / f)^2 d^2; the prefilter decides it
+            // in FP32 outside a band of kCutMargin and stays off (NaN) where the
+            // constant is so small or large that FP32 products could leave the
+            // normal range
+            const double f = s.fx > s.fy ? s.fx : s.fy, k = (double)s.tau * (double)s.tau / (f * f);
+            const bool use = s.tau == 0.0f || (k >= 1e-12 && k <= 1e12);
+            d.cut_klo = use ? (float)(k * (1.0 - (double)kCutMargin)) : NAN;
+            d.cut_khi = use ? (float)(k * (1.0 + (double)kCutMargin)) : NAN;
+        }
         d.tiles_x = (s.width + ctx->tile_w - 1) / ctx->tile_w;
         d.tiles_y = (s.height + ctx->tile_h - 1) / ctx->tile_h;
         d.tile_base = n_tiles;
@@ -366,6 +377,7 @@ hgs_status ensure_cut_cap(hgs_ctx *ctx, uint32_t cap)
     if ((s = realloc_buf(ctx, ctx->depth_key, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->ntiles, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->rect, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->trec, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->vis_mask, (size_t)cap / 64 + 8))) return s;
     if ((s = realloc_buf(ctx, ctx->vis_counts, (size_t)cap / 256 + 2))) return s;
     if ((s = realloc_buf(ctx, ctx->vis_offsets, (size_t)cap / 256 + 2))) return s;
@@ -433,7 +445,7 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     launch_cut_finish(ctx->blk_offsets, ctx->blk_counts, nb, nv, ctx->cut_base, ctx->ctr, st);
     mark(1);
     launch_preprocess(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t, &ctx->ctr->cut_total,
-                      ctx->cut_cap, ctx->recs, ctx->axes, ctx->depth_key, ctx->rect, ctx->ntiles, ctx->cjac,
+                      ctx->cut_cap, ctx->recs, ctx->axes, ctx->depth_key, ctx->trec, ctx->ntiles, ctx->cjac,
                       ctx->vis_mask,
                       ctx->vis_counts, ctx->tile_w, ctx->tile_h, st);
     mark(2);
@@ -444,8 +456,9 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     SortScratch sc{ctx->k2, ctx->v2, ctx->hist, ctx->hist_scan, ctx->partial, ctx->scan_total};
     launch_radix_sort(ctx->skeys, ctx->svals, ctx->cut_cap, &ctx->ctr->vis_total, 32, sc, st);  // 4 passes: in place
     mark(3);
-    launch_scan(ctx->ntiles, ctx->svals, ctx->cut_cap, &ctx->ctr->vis_total, ctx->pair_offsets, &ctx->ctr->pair_total,
-                ctx->partial, st);
+    launch_gather_tiles(ctx->trec, ctx->svals, &ctx->ctr->vis_total, ctx->cut_cap, ctx->pair_offsets, ctx->rect, st);
+    launch_scan(ctx->pair_offsets, nullptr, ctx->cut_cap, &ctx->ctr->vis_total, ctx->pair_offsets,
+                &ctx->ctr->pair_total, ctx->partial, st);  // in place
     launch_duplicate(ctx->rect, ctx->views_dev, nv, ctx->cut_base, ctx->svals, ctx->pair_offsets, ctx->dup_first,
                      &ctx->ctr->vis_total, ctx->cut_cap, &ctx->ctr->pair_total, ctx->pair_cap, ctx->pkeys,
                      ctx->pvals, ctx->ctr, st);

@@ -23,12 +23,17 @@ struct DevView {
     float fx, fy, cx, cy;
     int32_t W, H;
     float z_near, tau;
+    float cut_klo, cut_khi;  // tau^2 (1 -+ kCutMargin) / max(fx, fy)^2: the cut's FP32 prefilter (NaN: off)
     int32_t tiles_x, tiles_y;
     uint32_t tile_base;  // first global tile id of this view
     uint32_t pix_base;   // first pixel of this view in per-pixel state arrays
     float *out_rgb;      // [H][W][3]
     const float *dL;     // [H][W][3], backward only
 };
+
+// Relative band around the cut threshold inside which the FP32 prefilter
+// defers to the FP64 evaluation.
+constexpr float kCutMargin = 1e-5f;
 
 struct DevHier {
     int64_t n;
@@ -95,7 +100,8 @@ void launch_cut_emit(const DevHier &h, const DevView *views, int nv, const uint6
 void launch_cut_finish(const uint32_t *block_offsets, const uint32_t *block_counts, int nblocks, int nv,
                        uint32_t *cut_base, Counters *ctr, hipStream_t st);
 
-// exclusive scan of uint32 (optionally in[idx[i]]); writes *total
+// exclusive scan of uint32 (optionally of in[idx[i]], gathered once into
+// out); writes *total
 void launch_scan(const uint32_t *in, const uint32_t *idx, uint32_t n_host, const uint32_t *n_dev, uint32_t *out,
                  uint32_t *total, uint32_t *partial, hipStream_t st);
 constexpr int kScanBlocks = 512;
@@ -116,7 +122,7 @@ bool launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t cap, const uint3
 // preprocess: interpolation, EWA projection, SH colour, footprint, per cut entry
 void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                        const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
-                       SplatRec *recs, double4 *axes, uint32_t *depth_key, uint2 *rect, uint32_t *ntiles,
+                       SplatRec *recs, double4 *axes, uint32_t *depth_key, uint4 *trec, uint32_t *ntiles,
                        float *cjac, uint64_t *vis_mask, uint32_t *vis_block_counts, int tile_w, int tile_h,
                        hipStream_t st);
 // Also writes vis_rank[k] = compaction position of visible cut entry k (the
@@ -124,7 +130,14 @@ void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uin
 void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
                             uint32_t cap, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals,
                             uint32_t *vis_rank, hipStream_t st);
-// block_first: duplicate_blocks(pair_cap) + 1 entries of workspace.
+// Tile records of the visible splats in depth order (one gather through
+// the sorted values): counts[i] = tile count and rect[i] = tile rectangle of
+// the splat at depth slot i, from trec (per cut entry: rect.x, rect.y,
+// tile count, unused; written for visible entries).
+void launch_gather_tiles(const uint4 *trec, const uint32_t *sorted_vals, const uint32_t *vis_total, uint32_t vis_cap,
+                         uint32_t *counts, uint2 *rect, hipStream_t st);
+// block_first: duplicate_blocks(pair_cap) + 1 entries of workspace.  rect:
+// tile rectangles in depth order (launch_gather_tiles).
 void launch_duplicate(const uint2 *rect, const DevView *views, int nv, const uint32_t *cut_base,
                       const uint32_t *sorted_vals, const uint32_t *pair_offsets, uint32_t *block_first,
                       const uint32_t *vis_total, uint32_t vis_cap, const uint32_t *pair_total, uint32_t pair_cap,

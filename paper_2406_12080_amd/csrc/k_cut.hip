@@ -18,9 +18,9 @@
 // The selection is defined by eps evaluated in FP64 with contraction
 // disabled, from the FP32 stored boxes, so that it does not depend on FP32
 // rounding; t is evaluated the same way.  The sweep first decides each test
-// in FP32 as (f L)^2 against tau^2 d^2 and falls back to the FP64 evaluation
-// only when the two sides are within a relative kCutMargin, far wider than
-// the FP32 rounding error of either side (about a dozen units in the last
+// in FP32 as L^2 against (tau / f)^2 d^2 and falls back to the FP64
+// evaluation only when the two sides are within a relative kCutMargin, far
+// wider than the FP32 rounding error of either side (a few units in the last
 // place), so both evaluations always agree.
 #include "hgs_internal.h"
 
@@ -47,32 +47,33 @@ __device__ __forceinline__ double granularity(const float b[6], const DevView &V
     return (f * L) / d;
 }
 
-constexpr float kCutMargin = 1e-5f;
+// The FP32 prefilter of eps(box) <= tau, written L^2 <= k d^2 with the
+// per-view constant k = (tau / f)^2, as lane masks of one wave: `yes` where
+// L^2 < k (1 - kCutMargin) d^2, `no` where L^2 > k (1 + kCutMargin) d^2, and
+// neither inside that band or where a square is too small to be accurate in
+// FP32 (d^2 < 1e-18, which includes the eye inside the box, or a non-zero
+// L^2 < 1e-30).  Either side carries at most a few units in the last place
+// of rounding, far inside the band, so a decision taken here is the FP64
+// one.  Lok: the lanes whose L^2 is usable.
+struct CutTest {
+    uint64_t yes, no;
+};
 
-// 1: eps(box) <= tau for certain; 0: eps > tau for certain; -1: too close to
-// call in FP32.  tau2 = tau^2, f = max(fx, fy).
-__device__ __forceinline__ int meets_tau_f32(const float b[6], const DevView &V, float f, float tau2)
+// (wave-wide float compares straight to lane masks)
+constexpr int kFcmpOgt = 2, kFcmpOge = 3, kFcmpOlt = 4;
+
+__device__ __forceinline__ CutTest meets_tau_f32(const float b[6], float L2, uint64_t Lok, const DevView &V)
 {
-    float L = 0.0f, d2 = 0.0f;
-    bool inside = true;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const float lo = b[k], hi = b[3 + k];
-        const float ext = hi - lo;
-        if (ext > L) L = ext;
-        const float e = V.eye[k];
-        const float c = __builtin_amdgcn_fmed3f(e, lo, hi);  // clamp of e to [lo, hi] (lo <= hi)
-        const float dd = e - c;
-        inside = inside && dd == 0.0f;
-        d2 = fmaf(dd, dd, d2);
-    }
-    if (inside) return 0;  // eps is infinite inside the box
-    if (!(d2 >= 1e-30f)) return -1;
-    const float fl = f * L;
-    const float lhs = fl * fl, rhs = tau2 * d2;
-    if (lhs < rhs * (1.0f - kCutMargin)) return 1;
-    if (lhs > rhs * (1.0f + kCutMargin)) return 0;
-    return -1;
+    const float ex = V.eye[0], ey = V.eye[1], ez = V.eye[2];
+    const float dx = ex - __builtin_amdgcn_fmed3f(ex, b[0], b[3]);  // eye minus its clamp to the box
+    const float dy = ey - __builtin_amdgcn_fmed3f(ey, b[1], b[4]);
+    const float dz = ez - __builtin_amdgcn_fmed3f(ez, b[2], b[5]);
+    const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const uint64_t ok = Lok & __builtin_amdgcn_fcmpf(d2, 1e-18f, kFcmpOge);
+    CutTest r;
+    r.yes = ok & __builtin_amdgcn_fcmpf(L2, V.cut_klo * d2, kFcmpOlt);
+    r.no = ok & __builtin_amdgcn_fcmpf(L2, V.cut_khi * d2, kFcmpOgt);
+    return r;
 }
 
 __device__ __forceinline__ void load_box(const DevHier &h, int64_t i, float b[6])
@@ -100,24 +101,34 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_meets(DevHier h, const DevV
             load_box(h, i, b);
             leaf = (h.pinfo[i] & kLeafBit) != 0;
         }
-        const bool all_leaves = __ballot(valid && !leaf) == 0ull;
+        // leaves (and the padding past n) always meet tau
+        const uint64_t leaves = __ballot(leaf);
+        const bool all_leaves = leaves == ~0ull;
+        float L = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) L = fmaxf(L, b[3 + k] - b[k]);
+        const float L2 = L * L;
+        const uint64_t Lok = __ballot(L2 == 0.0f || L2 >= 1e-30f);
         // the words of up to 64 views are gathered on lanes (lane u: view
         // v0 + u) and stored with one instruction
 #pragma unroll 1
         for (int v0 = 0; v0 < nv; v0 += 64) {
             uint64_t word = 0;
             const int nvc = min(64, nv - v0);
-#pragma unroll 1
+#pragma unroll 2
             for (int u = 0; u < nvc; ++u) {
-                bool F = true;  // leaves (and the padding past n) always meet tau
-                if (!all_leaves && !leaf) {
+                uint64_t F = ~0ull;
+                if (!all_leaves) {
                     const DevView &V = views[v0 + u];
-                    const float tau2 = V.tau * V.tau, f = V.fx > V.fy ? V.fx : V.fy;
-                    const int a = meets_tau_f32(b, V, f, tau2);
-                    F = a > 0 || (a < 0 && granularity(b, V) <= (double)V.tau);
+                    const CutTest c = meets_tau_f32(b, L2, Lok, V);
+                    F = leaves | c.yes;
+                    const uint64_t open = ~(F | c.no);
+                    if (open) {  // rare: decide by the FP64 evaluation that defines the cut
+                        const bool m = ((open >> lane) & 1ull) && granularity(b, V) <= (double)V.tau;
+                        F |= __ballot(m);
+                    }
                 }
-                const uint64_t m = __ballot(F);
-                word = lane == u ? m : word;
+                word = lane == u ? F : word;
             }
             if (lane < nvc) fmask[(int64_t)(v0 + lane) * words + (i0 >> 6)] = word;
         }
@@ -145,6 +156,8 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_flags(DevHier h, int nv, co
         if (valid) par = h.pinfo[i] & ~kLeafBit;
         const bool root = par == kRootParent;
         if (i0 >= n) break;
+        const int64_t wown = i0 >> 6;                           // this wave's word
+        const int64_t wpar = valid && !root ? (int64_t)(par >> 6) : wown;  // the parent's (in bounds)
         constexpr int U = 8;  // views per step: their loads are independent
 #pragma unroll 1
         for (int c0 = 0; c0 < nv; c0 += 64) {  // up to 64 views gathered on lanes
@@ -154,18 +167,17 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_flags(DevHier h, int nv, co
             for (int u0 = 0; u0 < nvc; u0 += U) {
                 uint64_t own[U], pw[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int v = c0 + u0 + u;
-                    const uint64_t *fv = fmask + (int64_t)v * words;
-                    own[u] = u0 + u < nvc ? fv[i0 >> 6] : 0ull;  // the wave's own word
-                    pw[u] = u0 + u < nvc && valid && !root ? fv[par >> 6] : 0ull;
+                for (int u = 0; u < U; ++u) {  // views past the last re-read the last one (in bounds)
+                    const uint64_t *fv = fmask + (int64_t)(c0 + min(u0 + u, nvc - 1)) * words;
+                    own[u] = fv[wown];
+                    pw[u] = fv[wpar];
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const bool in =
                         valid && ((own[u] >> lane) & 1ull) && (root || !((pw[u] >> (par & 63)) & 1ull));
                     const uint64_t m = __ballot(in);
-                    word = lane == u0 + u ? m : word;
+                    if (u0 + u < nvc) word = lane == u0 + u ? m : word;
                 }
             }
             if (lane < nvc) {

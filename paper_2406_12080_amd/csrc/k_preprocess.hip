@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kT, 4) void k_preprocess(DevHier h, const DevView *
                                                    const uint32_t *__restrict__ cut_total, uint32_t cap,
                                                    SplatRec *__restrict__ recs, double4 *__restrict__ axes,
                                                    uint32_t *__restrict__ depth_key,
-                                                   uint2 *__restrict__ rect, uint32_t *__restrict__ ntiles,
+                                                   uint4 *__restrict__ trec, uint32_t *__restrict__ ntiles,
                                                    float *__restrict__ cjac, uint64_t *__restrict__ vis_mask,
                                                    uint32_t *__restrict__ vis_block_counts, int tile_w, int tile_h)
 {
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kT, 4) void k_preprocess(DevHier h, const DevView *
                     const uint32_t tx0 = (uint32_t)x0 / tile_w, tx1 = (uint32_t)x1 / tile_w;
                     const uint32_t ty0 = (uint32_t)y0 / tile_h, ty1 = (uint32_t)y1 / tile_h;
                     nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-                    rect[k] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+                    trec[k] = make_uint4(tx0 | (tx1 << 16), ty0 | (ty1 << 16), nt, 0u);
                     SplatRec r;
                     const double fu = floor(P.u), fv = floor(P.v);
                     r.ax = (int32_t)fu;
@@ -157,13 +157,31 @@ __global__ __launch_bounds__(kT) void k_compact_visible(const uint64_t *__restri
     }
 }
 
+// The tile records of the visible splats in depth order: the one random
+// gather of per-splat data between the depth sort and the pair emission.
+__global__ __launch_bounds__(kT) void k_gather_tiles(const uint4 *__restrict__ trec,
+                                                     const uint32_t *__restrict__ sorted_vals,
+                                                     const uint32_t *__restrict__ vis_total, uint32_t vis_cap,
+                                                     uint32_t *__restrict__ counts, uint2 *__restrict__ rect)
+{
+    const uint32_t n = min(*vis_total, vis_cap);
+    const uint32_t i = blockIdx.x * kT + threadIdx.x;
+    if (i >= n) return;
+    const uint4 r = trec[sorted_vals[i]];
+    counts[i] = r.z;
+    rect[i] = make_uint2(r.x, r.y);
+}
+
 // Pair emission, balanced by pairs: block b writes pairs [b P, (b + 1) P)
 // of the depth-ordered list, whatever the footprints of the splats they come
 // from (the nearest splats of every view sort first and may cover thousands
 // of tiles each).  k_dup_starts records the splat holding each block's first
-// pair; k_duplicate stages the block's slice of the pair offsets in LDS and
-// finds every pair's splat by binary search there.
-constexpr uint32_t kDupPairs = 2048;
+// pair; k_duplicate stages the block's slice of the pair offsets in LDS.
+// Each thread writes kDupPer consecutive pairs (one vector store per array
+// and thread, contiguous across the wave): a binary search finds the splat
+// of its first pair, then it walks forward tile by tile.
+constexpr int kDupPer = 8;
+constexpr uint32_t kDupPairs = kT * kDupPer;
 
 __global__ __launch_bounds__(kT) void k_dup_starts(const uint32_t *__restrict__ offsets,
                                                    const uint32_t *__restrict__ vis_total, uint32_t vis_cap,
@@ -208,27 +226,61 @@ __global__ __launch_bounds__(kT) void k_duplicate(const uint2 *__restrict__ rect
     for (uint32_t k = threadIdx.x; k < cnt; k += kT) s_off[k] = offsets[j0 + k];
     for (int k = threadIdx.x; k <= nv; k += kT) s_cb[k] = cut_base[k];
     __syncthreads();
-    for (uint32_t o = o0 + threadIdx.x; o < o1; o += kT) {
-        uint32_t lo = 0, hi = cnt - 1;  // the last slot with s_off <= o
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1u) >> 1;
-            if (s_off[mid] <= o) lo = mid;
-            else hi = mid - 1u;
+    const uint32_t ob = o0 + threadIdx.x * kDupPer;
+    if (ob >= o1) return;
+    uint32_t lo = 0, hi = cnt - 1;  // the last slot with s_off <= ob
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1u) >> 1;
+        if (s_off[mid] <= ob) lo = mid;
+        else hi = mid - 1u;
+    }
+    uint32_t key[kDupPer], val[kDupPer];
+    uint32_t cur = ~0u, s = 0, tx = 0, ty = 0, tx0 = 0, tx1 = 0, base = 0, tiles_x = 0;
+#pragma unroll
+    for (int k = 0; k < kDupPer; ++k) {
+        const uint32_t o = ob + k;
+        if (o < o1) {
+            while (lo + 1u < cnt && s_off[lo + 1u] <= o) ++lo;
+            if (lo != cur) {  // first pair of this thread from splat slot lo
+                cur = lo;
+                s = sorted_vals[j0 + lo];
+                int vlo = 0, vhi = nv - 1;  // view of cut entry s
+                while (vlo < vhi) {
+                    const int mid = (vlo + vhi + 1) >> 1;
+                    if (s_cb[mid] <= s) vlo = mid;
+                    else vhi = mid - 1;
+                }
+                const DevView &V = views[vlo];
+                base = V.tile_base;
+                tiles_x = (uint32_t)V.tiles_x;
+                const uint2 r = rect[j0 + lo];
+                tx0 = r.x & 0xFFFFu;
+                tx1 = r.x >> 16;
+                const uint32_t w = tx1 - tx0 + 1u, q = o - s_off[lo];
+                ty = (r.y & 0xFFFFu) + q / w;
+                tx = tx0 + q % w;
+            } else if (++tx > tx1) {  // next tile of the same splat, row by row
+                tx = tx0;
+                ++ty;
+            }
         }
-        const uint32_t s = sorted_vals[j0 + lo];
-        int vlo = 0, vhi = nv - 1;  // view of cut entry s
-        while (vlo < vhi) {
-            const int mid = (vlo + vhi + 1) >> 1;
-            if (s_cb[mid] <= s) vlo = mid;
-            else vhi = mid - 1;
+        key[k] = base + ty * tiles_x + tx;
+        val[k] = s;
+    }
+    if (ob + kDupPer <= o1) {
+        uint4 *kd = reinterpret_cast<uint4 *>(pair_keys + ob), *vd = reinterpret_cast<uint4 *>(pair_vals + ob);
+#pragma unroll
+        for (int k = 0; k < kDupPer / 4; ++k) {
+            kd[k] = make_uint4(key[4 * k], key[4 * k + 1], key[4 * k + 2], key[4 * k + 3]);
+            vd[k] = make_uint4(val[4 * k], val[4 * k + 1], val[4 * k + 2], val[4 * k + 3]);
         }
-        const DevView &V = views[vlo];
-        const uint2 r = rect[s];
-        const uint32_t tx0 = r.x & 0xFFFFu, tx1 = r.x >> 16, ty0 = r.y & 0xFFFFu;
-        const uint32_t w = tx1 - tx0 + 1u, q = o - s_off[lo];
-        const uint32_t ty = ty0 + q / w, tx = tx0 + q % w;
-        pair_keys[o] = V.tile_base + ty * (uint32_t)V.tiles_x + tx;
-        pair_vals[o] = s;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kDupPer; ++k)
+            if (ob + k < o1) {
+                pair_keys[ob + k] = key[k];
+                pair_vals[ob + k] = val[k];
+            }
     }
 }
 
@@ -241,15 +293,37 @@ __global__ __launch_bounds__(kT) void k_zero_rows(double *__restrict__ rows, int
     for (size_t e = (size_t)blockIdx.x * kT + threadIdx.x; e < n; e += (size_t)gridDim.x * kT) rows[e] = 0.0;
 }
 
+// Tile ranges of the sorted pair keys: four keys per thread (one vector
+// load), boundaries found against the neighbours.  Tile ids stay below
+// 2^31, so ~0 marks "no neighbour".
+constexpr int kRangeItems = 4;
+
 __global__ __launch_bounds__(kT) void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ total,
                                                uint32_t cap, uint2 *__restrict__ ranges)
 {
     const uint32_t n = min(*total, cap);
-    const uint32_t i = blockIdx.x * kT + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t t = keys[i];
-    if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
-    if (i == n - 1 || keys[i + 1] != t) ranges[t].y = i + 1;
+    const uint32_t i0 = (blockIdx.x * kT + threadIdx.x) * kRangeItems;
+    if (i0 >= n) return;
+    uint32_t k[kRangeItems + 2];  // keys[i0 - 1 .. i0 + kRangeItems]
+    k[0] = i0 > 0 ? keys[i0 - 1] : ~0u;
+    if (i0 + kRangeItems <= n) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(keys + i0);
+        k[1] = v.x;
+        k[2] = v.y;
+        k[3] = v.z;
+        k[4] = v.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < kRangeItems; ++j) k[1 + j] = i0 + j < n ? keys[i0 + j] : ~0u;
+    }
+    k[kRangeItems + 1] = i0 + kRangeItems < n ? keys[i0 + kRangeItems] : ~0u;
+#pragma unroll
+    for (int j = 0; j < kRangeItems; ++j) {
+        const uint32_t i = i0 + j, t = k[1 + j];
+        if (i >= n) break;
+        if (k[j] != t) ranges[t].x = i;
+        if (k[2 + j] != t) ranges[t].y = i + 1;
+    }
 }
 
 // Scheduling key of every tile: 255 minus 8 log2(list length + 1), so that
@@ -590,14 +664,14 @@ __global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uin
 
 void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                        const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
-                       SplatRec *recs, double4 *axes, uint32_t *depth_key, uint2 *rect, uint32_t *ntiles,
+                       SplatRec *recs, double4 *axes, uint32_t *depth_key, uint4 *trec, uint32_t *ntiles,
                        float *cjac, uint64_t *vis_mask, uint32_t *vis_block_counts, int tile_w, int tile_h,
                        hipStream_t st)
 {
     const uint32_t blocks = (cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(kT), 0, st, h, views, nv, cut_base, cut_ids, cut_t, cut_total,
-                       cap, recs, axes, depth_key, rect, ntiles, cjac, vis_mask, vis_block_counts, tile_w, tile_h);
+                       cap, recs, axes, depth_key, trec, ntiles, cjac, vis_mask, vis_block_counts, tile_w, tile_h);
 }
 
 void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
@@ -616,6 +690,15 @@ void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32
     const uint32_t blocks = (uint32_t)std::min<uint64_t>(need, 8192);
     if (!blocks) return;
     hipLaunchKernelGGL(k_zero_rows, dim3(blocks), dim3(kT), 0, st, rows, width, vis_total, vis_cap);
+}
+
+void launch_gather_tiles(const uint4 *trec, const uint32_t *sorted_vals, const uint32_t *vis_total, uint32_t vis_cap,
+                         uint32_t *counts, uint2 *rect, hipStream_t st)
+{
+    const uint32_t blocks = (vis_cap + kT - 1) / kT;
+    if (!blocks) return;
+    hipLaunchKernelGGL(k_gather_tiles, dim3(blocks), dim3(kT), 0, st, trec, sorted_vals, vis_total, vis_cap, counts,
+                       rect);
 }
 
 void launch_duplicate(const uint2 *rect, const DevView *views, int nv, const uint32_t *cut_base,
@@ -640,7 +723,7 @@ uint32_t duplicate_blocks(uint32_t pair_cap)
 void launch_ranges(const uint32_t *pair_keys, const uint32_t *pair_total, uint32_t pair_cap, uint2 *ranges,
                    hipStream_t st)
 {
-    const uint32_t blocks = (pair_cap + kT - 1) / kT;
+    const uint32_t blocks = (uint32_t)(((uint64_t)pair_cap + kT * kRangeItems - 1) / (kT * kRangeItems));
     if (!blocks) return;
     hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(kT), 0, st, pair_keys, pair_total, pair_cap, ranges);
 }

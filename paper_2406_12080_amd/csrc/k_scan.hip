@@ -50,16 +50,22 @@ __device__ __forceinline__ uint32_t load_in(const uint32_t *in, const uint32_t *
     return in[idx ? idx[i] : i];
 }
 
+// With idx, the gathered values in[idx[i]] are also stored to dense[i], so
+// that the down-sweep reads them in order (one gather instead of two).
 __global__ __launch_bounds__(kT) void k_scan_reduce(const uint32_t *__restrict__ in, const uint32_t *__restrict__ idx,
                                                     uint32_t n_host, const uint32_t *__restrict__ n_dev,
-                                                    uint32_t *__restrict__ partial)
+                                                    uint32_t *__restrict__ partial, uint32_t *__restrict__ dense)
 {
     __shared__ uint32_t s_w[kT / 64];
     const uint32_t n = count_of(n_host, n_dev);
     const uint32_t chunk = (n + kScanBlocks - 1) / kScanBlocks;
     const uint32_t b0 = min(n, blockIdx.x * chunk), b1 = min(n, b0 + chunk);
     uint32_t s = 0;
-    for (uint32_t i = b0 + threadIdx.x; i < b1; i += kT) s += load_in(in, idx, i);
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += kT) {
+        const uint32_t x = load_in(in, idx, i);
+        if (dense) dense[i] = x;
+        s += x;
+    }
     uint32_t tot;
     block_exclusive(s, tot, s_w);
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
@@ -83,9 +89,11 @@ __global__ __launch_bounds__(kScanBlocks) void k_scan_partials(uint32_t *__restr
     if (threadIdx.x == 0 && total) *total = tot;
 }
 
-__global__ __launch_bounds__(kT) void k_scan_down(const uint32_t *__restrict__ in, const uint32_t *__restrict__ idx,
+// May run in place (in == out): each thread reads its elements before it
+// writes them, and no other thread touches them.
+__global__ __launch_bounds__(kT) void k_scan_down(const uint32_t *in, const uint32_t *__restrict__ idx,
                                                   uint32_t n_host, const uint32_t *__restrict__ n_dev,
-                                                  const uint32_t *__restrict__ partial, uint32_t *__restrict__ out)
+                                                  const uint32_t *__restrict__ partial, uint32_t *out)
 {
     __shared__ uint32_t s_w[kT / 64];
     const uint32_t n = count_of(n_host, n_dev);
@@ -118,9 +126,13 @@ __global__ __launch_bounds__(kT) void k_scan_down(const uint32_t *__restrict__ i
 void launch_scan(const uint32_t *in, const uint32_t *idx, uint32_t n_host, const uint32_t *n_dev, uint32_t *out,
                  uint32_t *total, uint32_t *partial, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kT), 0, st, in, idx, n_host, n_dev, partial);
+    // a gathered input is made dense in `out` by the first pass; the
+    // down-sweep then scans `out` in place
+    hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kT), 0, st, in, idx, n_host, n_dev, partial,
+                       idx ? out : nullptr);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanBlocks), 0, st, partial, total);
-    hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kT), 0, st, in, idx, n_host, n_dev, partial, out);
+    hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kT), 0, st, idx ? out : in, nullptr, n_host, n_dev,
+                       partial, out);
 }
 
 }  // namespace hgs
