@@ -205,55 +205,98 @@ __device__ __forceinline__ double cut_weight(const DevHier &h, const DevView &V,
     return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
 }
 
-__global__ __launch_bounds__(kCutThreads) void k_cut_emit(DevHier h, const DevView *__restrict__ views,
+// Index of the r-th set bit of m (r < popcount(m)), by halving.
+__device__ __forceinline__ int nth_set_bit(uint64_t m, uint32_t r)
+{
+    int b = 0;
+#pragma unroll
+    for (int width = 32; width >= 1; width >>= 1) {
+        const uint64_t low = m & ((1ull << width) - 1ull);
+        const uint32_t c = (uint32_t)__popcll(low);
+        if (r >= c) {
+            r -= c;
+            m >>= width;
+            b += width;
+        } else {
+            m = low;
+        }
+    }
+    return b;
+}
+
+// Emits the cut of kEmitViews views over one block of kCutBlock nodes: ids
+// in node order at the positions the scan gave, the weight t, and the
+// position of the first selected node of every mask word (word_off).  The
+// selected nodes of the block are spread densely over its threads, so that
+// every lane works on one of them.
+constexpr int kEmitViews = 8;
+
+__global__ __launch_bounds__(kCutThreads) void k_cut_emit(DevHier h, const DevView *__restrict__ views, int nv,
                                                           const uint64_t *__restrict__ masks,
                                                           const uint32_t *__restrict__ block_offsets, int nblocks,
                                                           uint32_t *__restrict__ word_off,
                                                           int32_t *__restrict__ out_ids, float *__restrict__ out_t,
                                                           double *__restrict__ out_t64, uint32_t cap)
 {
-    constexpr int W = kCutBlock / 64;
-    __shared__ uint64_t s_word[W];
-    __shared__ uint32_t s_pre[W];
-    __shared__ int s_any;
-    const int v = blockIdx.y;
+    constexpr int W = kCutBlock / 64;  // mask words per block and view
+    constexpr int VB = kEmitViews;
+    __shared__ uint64_t s_word[VB][W];
+    __shared__ uint32_t s_pre[VB][W + 1];  // selected nodes of the view before word k; [W]: the view's count
+    __shared__ uint32_t s_vpre[VB + 1];    // selected nodes of the block before view u
+    __shared__ uint32_t s_off[VB];         // cut position of the view's first selected node here
     const int64_t n = h.n;
     const int64_t words = (n + 63) >> 6;
+    const int v0 = blockIdx.y * VB, nvb = min(VB, nv - v0);
     const int64_t w0 = (int64_t)blockIdx.x * W;
-    if (threadIdx.x == 0) s_any = 0;
-    __syncthreads();
-    if (threadIdx.x < W) {
-        const int64_t w = w0 + threadIdx.x;
-        const uint64_t m = w < words ? masks[(int64_t)v * words + w] : 0ull;
-        s_word[threadIdx.x] = m;
-        if (m) s_any = 1;
+    if (threadIdx.x < VB * W) {
+        const int u = threadIdx.x / W, k = threadIdx.x % W;
+        const int64_t w = w0 + k;
+        s_word[u][k] = u < nvb && w < words ? masks[(int64_t)(v0 + u) * words + w] : 0ull;
     }
     __syncthreads();
-    if (!s_any) return;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < VB) {
+        const int u = threadIdx.x;
         uint32_t acc = 0;
         for (int k = 0; k < W; ++k) {
-            s_pre[k] = acc;
-            acc += (uint32_t)__popcll(s_word[k]);
+            s_pre[u][k] = acc;
+            acc += (uint32_t)__popcll(s_word[u][k]);
         }
+        s_pre[u][W] = acc;
+        s_off[u] = acc ? block_offsets[(int64_t)(v0 + u) * nblocks + blockIdx.x] : 0u;
     }
     __syncthreads();
-    const uint32_t off = block_offsets[(int64_t)v * nblocks + blockIdx.x];
-    if (threadIdx.x < W && w0 + threadIdx.x < words)
-        word_off[(int64_t)v * words + w0 + threadIdx.x] = off + s_pre[threadIdx.x];
-    const DevView &V = views[v];
-#pragma unroll 1
-    for (int it = 0; it < kCutItems; ++it) {
-        const int local = it * kCutThreads + threadIdx.x;
-        const int w = local >> 6, bit = local & 63;
-        const uint64_t m = s_word[w];
-        if (!((m >> bit) & 1ull)) continue;
-        const uint32_t pos = off + s_pre[w] + (uint32_t)__popcll(m & ((1ull << bit) - 1ull));
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int u = 0; u < VB; ++u) {
+            s_vpre[u] = acc;
+            acc += s_pre[u][W];
+        }
+        s_vpre[VB] = acc;
+    }
+    __syncthreads();
+    const uint32_t S = s_vpre[VB];
+    if (S == 0) return;
+    if (threadIdx.x < VB * W) {
+        const int u = threadIdx.x / W, k = threadIdx.x % W;
+        if (s_pre[u][W] && w0 + k < words) word_off[(int64_t)(v0 + u) * words + w0 + k] = s_off[u] + s_pre[u][k];
+    }
+    for (uint32_t j = threadIdx.x; j < S; j += kCutThreads) {
+        int u = 0;  // view of the j-th selected node
+        while (u + 1 < VB && s_vpre[u + 1] <= j) ++u;
+        const uint32_t r = j - s_vpre[u];  // its rank among the view's selected nodes here
+        int lo = 0, hi = W - 1;            // its word: the last k with s_pre[u][k] <= r (never empty)
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pre[u][mid] <= r) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t pos = s_off[u] + r;
         if (pos >= cap) continue;
-        const int64_t i = (int64_t)blockIdx.x * kCutBlock + local;
+        const int bit = nth_set_bit(s_word[u][lo], r - s_pre[u][lo]);
+        const int64_t i = (int64_t)blockIdx.x * kCutBlock + lo * 64 + bit;
         out_ids[pos] = (int32_t)i;
         if (out_t || out_t64) {
-            const double t = cut_weight(h, V, i);
+            const double t = cut_weight(h, views[v0 + u], i);
             if (out_t) out_t[pos] = (float)t;
             if (out_t64) out_t64[pos] = t;
         }
@@ -280,8 +323,8 @@ void launch_cut_emit(const DevHier &h, const DevView *views, int nv, const uint6
                      const uint32_t *block_offsets, int nblocks, uint32_t *word_off, int32_t *out_ids, float *out_t,
                      double *out_t64, uint32_t cap, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cut_emit, dim3(nblocks, nv), dim3(kCutThreads), 0, st, h, views, masks, block_offsets,
-                       nblocks, word_off, out_ids, out_t, out_t64, cap);
+    hipLaunchKernelGGL(k_cut_emit, dim3(nblocks, (nv + kEmitViews - 1) / kEmitViews), dim3(kCutThreads), 0, st, h,
+                       views, nv, masks, block_offsets, nblocks, word_off, out_ids, out_t, out_t64, cap);
 }
 
 void launch_cut_finish(const uint32_t *block_offsets, const uint32_t *, int nblocks, int nv, uint32_t *cut_base,

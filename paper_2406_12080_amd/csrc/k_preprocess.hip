@@ -556,7 +556,10 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
 // of view v sits at word_off[v][j / 64] plus the selected nodes below j in
 // its word.  The children of a node are contiguous ids, and those in the
 // cut are consecutive cut entries, so one or two mask words give all of
-// them at once.
+// them at once.  The mask words of kGatherViews views are loaded together;
+// positions and entries are read only for the views that hold one.
+constexpr int kGatherViews = 8;
+
 __global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uint64_t *__restrict__ masks,
                                                     int64_t words, const uint32_t *__restrict__ word_off,
                                                     const uint32_t *__restrict__ cut_total, uint32_t cap,
@@ -579,13 +582,19 @@ __global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uin
 #pragma unroll
     for (int m = 0; m < 48; ++m) ash[m] = 0.0f;
     bool any = false;
-    // adds w x the attribute gradient of entry pos; `op` selects the node
-    // (10) or parent (11) opacity term
-    auto take = [&](uint32_t pos, float w, int op) {
+    // adds the attribute gradient of entry pos, weighted 1 - t as the node's
+    // own entry (op 10: node opacity term) or t as a child's entry (op 11:
+    // parent opacity term; none when t = 0).  The row (all eight vectors at
+    // once) is read only for a visible entry that contributes.
+    auto take = [&](uint32_t pos, int op) {
+        if (pos >= total) return;
+        const uint32_t nt = ntiles[pos];
+        const float t = (float)cut_t[pos];
+        if (nt == 0 || (op == 11 && !(t > 0.0f))) return;
         const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pos * kPG);
-        const float4 r7 = g4[7];
+        const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4], r5 = g4[5], r6 = g4[6], r7 = g4[7];
         if (r7.w == 0.0f) return;  // no live splat
-        const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4], r5 = g4[5], r6 = g4[6];
+        const float w = op == 10 ? 1.0f - t : t;
         const float g[31] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z,
                              r2.w, r3.x, r3.y, r3.z, r3.w, r4.x, r4.y, r4.z, r4.w, r5.x, r5.y,
                              r5.z, r5.w, r6.x, r6.y, r6.z, r6.w, r7.x, r7.y, r7.z};
@@ -601,32 +610,48 @@ __global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uin
         any = true;
     };
     const int64_t wi = i >> 6, wa = c0 >> 6, wb = (c1 - 1) >> 6;
-    const uint64_t below_i = (1ull << (i & 63)) - 1ull;
+    const uint64_t below_i = (1ull << (i & 63)) - 1ull, own_bit = 1ull << (i & 63);
+    // the children's bits in their first word (wa) and last word (wb)
+    const int lo = (int)(c0 & 63), hi = (int)((c1 - 1) & 63);
+    const uint64_t k_lo = ~((1ull << lo) - 1ull), k_hi = hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull);
+    const uint64_t ka = wa == wb ? (k_lo & k_hi) : k_lo, kb = wa == wb ? 0ull : k_hi;
+    const bool wide = wb - wa > 1;  // children over more than two words: every view is looked at
 #pragma unroll 1
-    for (int v = 0; v < nv; ++v) {
-        const uint64_t *mv = masks + (int64_t)v * words;
-        const uint32_t *ov = word_off + (int64_t)v * words;
-        // own entry
-        const uint64_t mo = mv[wi];
-        // children: the selected ones among [c0, c1), first position p0
-        uint32_t p0 = ~0u, nsel = 0;
-        for (int64_t w = wa; w <= wb; ++w) {
-            uint64_t m = mv[w];
-            const int lo = w == wa ? (int)(c0 & 63) : 0, hi = w == wb ? (int)((c1 - 1) & 63) : 63;
-            m &= (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull)) & ~((1ull << lo) - 1ull);
-            if (!m) continue;
-            if (p0 == ~0u) p0 = ov[w] + (uint32_t)__popcll(mv[w] & ((1ull << (__ffsll((long long)m) - 1)) - 1ull));
-            nsel += (uint32_t)__popcll(m);
+    for (int v0 = 0; v0 < nv; v0 += kGatherViews) {
+        // the views of this group that hold the node or one of its children
+        // (their mask words loaded together)
+        uint32_t hit = 0;
+        if (wide) {
+            hit = (1u << min(kGatherViews, nv - v0)) - 1u;
+        } else {
+#pragma unroll
+            for (int u = 0; u < kGatherViews; ++u) {
+                const int v = v0 + u;
+                if (v < nv) {
+                    const uint64_t *mv = masks + (int64_t)v * words;
+                    const uint64_t mo = mv[wi], ma = mv[wa], mb = kb ? mv[wb] : 0ull;
+                    hit |= ((mo & own_bit) || (ma & ka) || (mb & kb)) ? 1u << u : 0u;
+                }
+            }
         }
-        if ((mo >> (i & 63)) & 1ull) {
-            const uint32_t pos = ov[wi] + (uint32_t)__popcll(mo & below_i);
-            if (pos < total && ntiles[pos] != 0) take(pos, 1.0f - (float)cut_t[pos], 10);
-        }
-        for (uint32_t k = 0; k < nsel; ++k) {
-            const uint32_t pos = p0 + k;
-            if (pos >= total || ntiles[pos] == 0) continue;
-            const float t = (float)cut_t[pos];
-            if (t > 0.0f) take(pos, t, 11);
+        while (hit) {
+            const int v = v0 + __ffs(hit) - 1;
+            hit &= hit - 1u;
+            const uint64_t *mv = masks + (int64_t)v * words;
+            const uint32_t *ov = word_off + (int64_t)v * words;
+            // own entry
+            const uint64_t mo = mv[wi];
+            if (mo & own_bit) take(ov[wi] + (uint32_t)__popcll(mo & below_i), 10);
+            // children: the selected ones among [c0, c1) are consecutive entries from p0
+            uint32_t p0 = ~0u, nsel = 0;
+            for (int64_t w = wa; w <= wb; ++w) {
+                const uint64_t mw = mv[w];
+                const uint64_t m = mw & (w == wa ? k_lo : ~0ull) & (w == wb ? k_hi : ~0ull);
+                if (!m) continue;
+                if (p0 == ~0u) p0 = ov[w] + (uint32_t)__popcll(mw & ((m & (~m + 1ull)) - 1ull));
+                nsel += (uint32_t)__popcll(m);
+            }
+            for (uint32_t k = 0; k < nsel; ++k) take(p0 + k, 11);
         }
     }
     if (!any) return;
