@@ -72,6 +72,26 @@ __device__ __forceinline__ void eval_alpha(const float4 &W, const float4 &O, flo
     }
 }
 
+// True when no pixel of an 8x8 block can take the splat at alpha >= 1/255,
+// so that the block may skip it.  On the conic's scaled eigen-axes the
+// block's pixel centres lie in the box c + [0,7] a + [0,7] b (a = (w1x, w2x),
+// b = (w1y, w2y), c = block corner offsets), and alpha <= Amax G with
+// G = 2^-(u1^2 + u2^2) (Amax = A_n, or max(A_n, A_p) when t > 0: the pow
+// of Eq. (alphap) never exceeds its argument).  The distance of the box from
+// the origin is compared with log2(255 Amax) with a margin far above the
+// FP32 rounding of either side; boxes wider than 64 (sub-pixel splats, whose
+// offsets may cancel) are never skipped.
+__device__ __forceinline__ bool block_dead(const float4 &W, float c1, float c2, float Amax)
+{
+    const float a1 = 7.0f * W.x, b1 = 7.0f * W.y, a2 = 7.0f * W.z, b2 = 7.0f * W.w;
+    const float lo1 = c1 + fminf(a1, 0.0f) + fminf(b1, 0.0f), hi1 = c1 + fmaxf(a1, 0.0f) + fmaxf(b1, 0.0f);
+    const float lo2 = c2 + fminf(a2, 0.0f) + fminf(b2, 0.0f), hi2 = c2 + fmaxf(a2, 0.0f) + fmaxf(b2, 0.0f);
+    if (!(hi1 - lo1 <= 64.0f && hi2 - lo2 <= 64.0f)) return false;
+    const float m1 = fmaxf(fmaxf(lo1, -hi1), 0.0f), m2 = fmaxf(fmaxf(lo2, -hi2), 0.0f);
+    const float r2 = __builtin_amdgcn_logf(255.0f * Amax);  // log2
+    return m1 * m1 + m2 * m2 > r2 * 1.001f + 1e-3f;
+}
+
 __device__ __forceinline__ int view_of_tile(const DevView *views, int nv, uint32_t tile)
 {
     int lo = 0, hi = nv - 1;
@@ -87,6 +107,7 @@ __device__ __forceinline__ int view_of_tile(const DevView *views, int nv, uint32
 struct Staged {
     float4 w, o, c;
     float2 u[8];
+    uint32_t dead;  // bit bk: block bk skips the splat
 };
 
 template <int NB, int SX>
@@ -95,11 +116,14 @@ __device__ __forceinline__ void stage_one(const SplatRec &r, const double4 &W64,
     st.w = make_float4(r.w1x, r.w1y, r.w2x, r.w2y);
     st.o = make_float4(r.An, r.Ap, r.t, r.invK);
     st.c = make_float4(r.r, r.g, r.b, 0.0f);
+    const float amax = r.t > 0.0f ? fmaxf(r.An, r.Ap) : r.An;
+    st.dead = 0u;
 #pragma unroll
     for (int bk = 0; bk < NB; ++bk) {
         float c1, c2, d0, d1;
         block_offsets(r, W64, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
         st.u[bk] = make_float2(c1, c2);
+        st.dead |= block_dead(st.w, c1, c2, amax) ? 1u << bk : 0u;
     }
 }
 
@@ -133,6 +157,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
     __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
     __shared__ float2 s_u[NB][BATCH];
     __shared__ uint64_t s_tm[BATCH / 64];  // bit j of word k: entry 64 k + j is interpolated (t > 0)
+    __shared__ uint64_t s_dm[NB][BATCH / 64];  // likewise: block bk skips entry 64 k + j
     const uint32_t tile = tile_order[blockIdx.x];  // longest lists first
     const int vi = view_of_tile(views, nv, tile);
     const DevView &V = views[vi];
@@ -176,10 +201,11 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
             Staged st;
             if (real) {
                 stage_one<NB, SX>(nxt[p], nxw[p], ox, oy, st);
-            } else {  // padding: alpha = 0 everywhere
+            } else {  // padding: alpha = 0 everywhere, skipped by every block
                 st.w = st.o = st.c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
                 for (int bk = 0; bk < NB; ++bk) st.u[bk] = make_float2(0.0f, 0.0f);
+                st.dead = (1u << NB) - 1u;
             }
             s_w[j] = st.w;
             s_o[j] = st.o;
@@ -188,21 +214,30 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
             for (int bk = 0; bk < NB; ++bk) s_u[bk][j] = st.u[bk];
             const uint64_t m = __ballot(real && st.o.z > 0.0f);
             if (lane == 0) s_tm[j >> 6] = m;
+#pragma unroll
+            for (int bk = 0; bk < NB; ++bk) {
+                const uint64_t dm = __ballot((st.dead >> bk) & 1u);
+                if (lane == 0) s_dm[bk][j >> 6] = dm;
+            }
         }
         __syncthreads();
         if (b0 + BATCH < rg.y) fetch(b0 + BATCH);
         if (__ballot(T > 0.0f) == 0ull) continue;
         const int cnt = (int)min((uint32_t)BATCH, rg.y - b0), cnt4 = (cnt + 3) & ~3;
         const uint32_t jb = b0 - rg.x + 1u;  // 1-based list position of entry 0
-        uint64_t tm = 0;
+        uint64_t tm = 0, dm = 0;
         for (int j0 = 0; j0 < cnt4; j0 += 4) {
-            if ((j0 & 63) == 0) tm = uniform_u64(s_tm[j0 >> 6]);
+            if ((j0 & 63) == 0) {
+                tm = uniform_u64(s_tm[j0 >> 6]);
+                dm = uniform_u64(s_dm[w][j0 >> 6]);
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int j = j0 + u;
+                if ((dm >> (j & 63)) & 1ull) continue;  // no pixel of this block reaches 1/255
                 const uint32_t bit = (uint32_t)(tm >> (j & 63)) & 1u;
                 // work counts from the wave's live mask (scalar unit only)
-                const uint32_t n_live = j < cnt ? (uint32_t)__popcll(__ballot(T > 0.0f)) : 0u;
+                const uint32_t n_live = (uint32_t)__popcll(__ballot(T > 0.0f));
                 n_eval += n_live;
                 n_eval_t += bit ? n_live : 0u;
                 AlphaEval e;
