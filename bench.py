@@ -124,6 +124,56 @@ def cpu_baseline(h, view, row_stride: int = 1):
                 seconds=dict(cut=t_cut, render=t_render, backward=t_bwd, full_view_estimate=t_view))
 
 
+# Learning rates per parameter group for the timed optimisation steps (the
+# magnitudes 3D Gaussian Splatting uses; the timing does not depend on them).
+ADAM_LR = dict(mean=1.6e-4, scale=5e-3, rot=1e-3, opacity=5e-2, sh=2.5e-3)
+
+
+def optimize_steps(r, h, P, grads, imgs, dL, workload: str, steps: int) -> dict:
+    """Time `steps` steps of the hierarchy optimisation: per step a new batch
+    of eyes with tau log-uniform over the workload's range (config 5: 32
+    views of 1920x1080, tau in [3, 15] px), render, backward with a fixed
+    synthetic cotangent, and one Adam step on the interior nodes (which also
+    zeroes their gradients).  Cameras are drawn before the timed region."""
+    import torch
+    from paper_2406_12080_amd import synth
+    cfg = WORKLOADS[workload]["config"]
+    if cfg not in (3, 5):
+        raise SystemExit("--optimize needs a corridor workload (configs 3 and 5)")
+    warm = 2
+    batches = [synth.make_views(cfg, seed=1000 * cfg + s) for s in range(warm + steps)]
+    same = all((v.width, v.height) == (o.shape[1], o.shape[0]) for v, o in zip(batches[0], imgs))
+    out = imgs if same else [torch.empty((v.height, v.width, 3), device=imgs[0].device) for v in batches[0]]
+    cot = dL if same else [torch.randn(o.shape, device=o.device) for o in out]
+    M = {k: torch.zeros_like(t) for k, t in P.items()}
+    V = {k: torch.zeros_like(t) for k, t in P.items()}
+    for g in grads.values():
+        g.zero_()
+    n_step = 0
+
+    def one(views):
+        nonlocal n_step
+        n_step += 1
+        r.render(views, out=out)
+        r.backward(cot, grads)
+        r.adam_step(P, grads, M, V, ADAM_LR, n_step)
+
+    for s in range(warm):
+        one(batches[s])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(warm, warm + steps):
+        one(batches[s])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    taus = [v.tau for b in batches[warm:] for v in b]
+    nv = len(batches[0])
+    log(f"[bench] optimisation: {steps} steps, {dt * 1e3:.2f} ms/step")
+    return dict(steps=steps, warmup=warm, ms_per_step=round(dt * 1e3, 3), views_per_s=round(nv / dt, 3),
+                views_per_step=nv, tau_min=round(min(taus), 3), tau_max=round(max(taus), 3),
+                step="new eyes and tau per step; render + backward + Adam on the interior nodes")
+
+
 def kernel_source_sha() -> str:
     p = os.path.join(ROOT, "paper_2406_12080_amd", "csrc", "k_blend.hip")
     with open(p, "rb") as f:
@@ -154,6 +204,10 @@ def main(argv=None):
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-row-stride", type=int, default=1)
+    ap.add_argument("--optimize", type=int, default=0, metavar="K",
+                    help="also time K steps of the hierarchy optimisation (corridor workloads): every step new "
+                         "eyes and tau log-uniform over the workload's range, render, backward and an Adam step "
+                         "on the interior nodes (reported under 'optimize'; `value` stays the fwd+bwd step)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size transfer that calibrates "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
@@ -253,6 +307,10 @@ def main(argv=None):
         t_plain = (time.perf_counter() - t0) / reps
         log(f"[bench] plain fwd+bwd {t_plain * 1e3:.2f} ms/step")
 
+    opt = None
+    if args.optimize > 0:
+        opt = optimize_steps(r, h, P, grads, imgs, dL, args.workload, args.optimize)
+
     # roofline of the dominant kernel (the longer of blend and blend backward)
     ms_blend, n_blend = k_ms[hgs.K_BLEND]
     ms_bwd, n_bwd = k_ms[hgs.K_BLEND_BWD]
@@ -306,6 +364,8 @@ def main(argv=None):
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if opt is not None:
+        out["optimize"] = opt
     print(json.dumps(out), flush=True)
     r.close()
 

@@ -167,6 +167,30 @@ typedef struct {
  * were rebound / re-uploaded).  Does not synchronise. */
 hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_grads *out);
 
+/* One step of the optimiser of the hierarchy optimisation (Sec. 5.1, the
+ * paragraph on optimising the generated hierarchy): interior nodes only,
+ * the leaves stay unchanged; the paper does not name the optimiser for this
+ * stage, so this is Adam as in 3D Gaussian Splatting, per element:
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   p -= lr * (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps),
+ * and g = 0 afterwards (the next hgs_render_backward accumulates a fresh
+ * gradient).  All arrays are device pointers in the parameter layouts of the
+ * header (node-major; index 0..4 = mean, scale, rot, opacity, sh), N nodes
+ * each; m and v must be zero before step 1.  Leaf entries of every array are
+ * left untouched.  Queued on the ctx stream; does not synchronise.
+ * Errors: HGS_ERR_STATE without a hierarchy, HGS_ERR_INVALID_ARG for a NULL
+ * array, step < 1, or a non-finite / out-of-range hyper-parameter. */
+typedef struct {
+    float *param[5];
+    float *grad[5];
+    float *m[5];
+    float *v[5];
+    float lr[5];  /* learning rate per parameter group */
+    float beta1, beta2, eps;
+    int64_t step; /* 1-based, for the bias correction */
+} hgs_adam;
+hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a);
+
 /* Tuning knobs of the blend stage (chosen by the autotuner): tile edge
  * tile_w x tile_h in {8x8, 16x8, 16x16, 32x16} and splats staged per batch
  * (a multiple of 64 up to 1024; 0 = one per thread).  Changing them keeps

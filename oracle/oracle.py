@@ -259,3 +259,26 @@ def sh_basis(d) -> np.ndarray:
     Y = np.zeros(16)
     lib().or_sh_basis(_p(d, ctypes.c_double), _p(Y, ctypes.c_double))
     return Y
+
+
+def adam_step(params: dict, grads: dict, m: dict, v: dict, interior: np.ndarray, lr, step: int,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15) -> None:
+    """One optimiser step of the hierarchy optimisation (Sec. 5.1: the
+    generated hierarchy is optimised with its leaves unchanged; the paper
+    does not name the optimiser of this stage, and this is Adam as in 3D
+    Gaussian Splatting), in FP64, in place on dicts of arrays in the
+    parameter layouts (first axis = node).  ``interior``: boolean mask of the
+    nodes that move.  Gradients of the interior nodes are zeroed afterwards;
+    leaf rows of every array are left alone."""
+    c1 = 1.0 - beta1 ** step
+    c2 = 1.0 - beta2 ** step
+    for name in params:
+        g = np.asarray(grads[name], np.float64)[interior]
+        mm = beta1 * np.asarray(m[name], np.float64)[interior] + (1.0 - beta1) * g
+        vv = beta2 * np.asarray(v[name], np.float64)[interior] + (1.0 - beta2) * g * g
+        rate = lr[name] if isinstance(lr, dict) else lr
+        m[name][interior] = mm
+        v[name][interior] = vv
+        params[name][interior] = np.asarray(params[name], np.float64)[interior] - \
+            rate * (mm / c1) / (np.sqrt(vv / c2) + eps)
+        grads[name][interior] = 0.0

@@ -569,6 +569,31 @@ hgs_status hgs_set_stream(hgs_ctx *ctx, void *hip_stream)
     return HGS_OK;
 }
 
+hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy uploaded");
+    if (!a) return fail(ctx, HGS_ERR_INVALID_ARG, "NULL optimiser arguments");
+    for (int k = 0; k < 5; ++k) {
+        if (!a->param[k] || !a->grad[k] || !a->m[k] || !a->v[k])
+            return fail(ctx, HGS_ERR_INVALID_ARG, "NULL array of parameter group " + std::to_string(k));
+        if (!std::isfinite(a->lr[k]) || a->lr[k] < 0.0f)
+            return fail(ctx, HGS_ERR_INVALID_ARG, "bad learning rate of parameter group " + std::to_string(k));
+    }
+    if (a->step < 1 || !(a->beta1 >= 0.0f && a->beta1 < 1.0f) || !(a->beta2 >= 0.0f && a->beta2 < 1.0f) ||
+        !(a->eps > 0.0f) || !std::isfinite(a->eps))
+        return fail(ctx, HGS_ERR_INVALID_ARG, "bad step, beta1, beta2 or eps");
+    HIPC(hipSetDevice(ctx->device));
+    const double bc1 = 1.0 / (1.0 - std::pow((double)a->beta1, (double)a->step));
+    const double bc2 = 1.0 / (1.0 - std::pow((double)a->beta2, (double)a->step));
+    for (int k = 0; k < 5; ++k) {
+        const AdamScalars sc{a->lr[k], a->beta1, a->beta2, a->eps, (float)bc1, (float)bc2};
+        launch_adam(k, ctx->interior, ctx->n_interior, a->param[k], a->grad[k], a->m[k], a->v[k], sc, ctx->stream);
+    }
+    HIPC(hipGetLastError());
+    return HGS_OK;
+}
+
 hgs_status hgs_set_tuning(hgs_ctx *ctx, int32_t tile_w, int32_t tile_h, int32_t batch)
 {
     if (!ctx) return HGS_ERR_INVALID_ARG;

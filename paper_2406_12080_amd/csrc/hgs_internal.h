@@ -171,6 +171,15 @@ void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, 
                                 const int32_t *interior, int64_t n_interior, float *g_mean, float *g_scale,
                                 float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st);
 
+// optimiser step (Adam) over the interior nodes of one parameter group
+// (0 mean, 1 scale, 2 rotation, 3 opacity, 4 SH); bc1 = 1 / (1 - beta1^t),
+// bc2 = 1 / (1 - beta2^t)
+struct AdamScalars {
+    float lr, beta1, beta2, eps, bc1, bc2;
+};
+void launch_adam(int group, const int32_t *interior, int64_t n_interior, float *p, float *g, float *m, float *v,
+                 const AdamScalars &s, hipStream_t st);
+
 // ------------------------------------------------------------ wave helpers
 // Lane exchange through DPP (no LDS traffic); CTRL is a DPP control word:
 // 0x128 rotates each row of 16 lanes by 8 (lane l reads l ^ 8), 0x141

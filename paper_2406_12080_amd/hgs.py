@@ -19,7 +19,7 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_CAPACITY = range(6)
 _NAMES = {0: "HGS_OK", 1: "HGS_ERR_INVALID_ARG", 2: "HGS_ERR_OOM", 3: "HGS_ERR_HIP", 4: "HGS_ERR_STATE",
           5: "HGS_ERR_CAPACITY"}
 EXPORTS = ("hgs_create", "hgs_destroy", "hgs_last_error", "hgs_set_stream", "hgs_upload", "hgs_bind_params",
-           "hgs_cut", "hgs_render", "hgs_render_backward", "hgs_set_tuning", "hgs_get_buffer",
+           "hgs_cut", "hgs_render", "hgs_render_backward", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer",
            "hgs_set_profiling", "hgs_kernel_time", "hgs_counters")
 COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t", "bwd_evaluated",
                  "bwd_evaluated_t", "bwd_contrib")
@@ -59,6 +59,12 @@ class Stats(ctypes.Structure):
                     blended=self.blended, ms=list(self.ms))
 
 
+class Adam(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_void_p * 5), ("grad", ctypes.c_void_p * 5), ("m", ctypes.c_void_p * 5),
+                ("v", ctypes.c_void_p * 5), ("lr", ctypes.c_float * 5), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("step", ctypes.c_int64)]
+
+
 class Grads(ctypes.Structure):
     _fields_ = [("mean", ctypes.c_void_p), ("scale", ctypes.c_void_p), ("rot", ctypes.c_void_p),
                 ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("dt", ctypes.c_void_p)]
@@ -87,6 +93,7 @@ def lib():
         L.hgs_cut.argtypes = [vp, P(View), vp, vp, ctypes.c_int64, P(ctypes.c_int64)]
         L.hgs_render.argtypes = [vp, P(View), ctypes.c_int32, P(vp), P(Stats)]
         L.hgs_render_backward.argtypes = [vp, P(vp), P(Grads)]
+        L.hgs_adam_step.argtypes = [vp, P(Adam)]
         L.hgs_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.hgs_get_buffer.argtypes = [vp, ctypes.c_int32, P(vp), P(ctypes.c_int64)]
         L.hgs_set_profiling.argtypes = [vp, ctypes.c_int32]
@@ -249,6 +256,21 @@ class Renderer:
         g.dt = dt.data_ptr() if dt is not None else None
         self._keep = dL
         self._check(self.L.hgs_render_backward(self.h, ptrs, ctypes.byref(g)))
+
+    def adam_step(self, params: dict, grads: dict, m: dict, v: dict, lr, step: int, beta1: float = 0.9,
+                  beta2: float = 0.999, eps: float = 1e-15) -> None:
+        """One optimiser step on the interior nodes (``hgs_adam_step``); all
+        dicts hold CUDA tensors keyed like the parameters; ``lr`` is one
+        float or a dict per parameter group.  Zeroes ``grads``."""
+        a = Adam()
+        for k, name in enumerate(PARAM_FIELDS):
+            for arr, d in ((a.param, params), (a.grad, grads), (a.m, m), (a.v, v)):
+                t = d[name]
+                assert t.is_cuda and t.is_contiguous() and t.dtype == self.torch.float32
+                arr[k] = t.data_ptr()
+            a.lr[k] = float(lr[name] if isinstance(lr, dict) else lr)
+        a.beta1, a.beta2, a.eps, a.step = float(beta1), float(beta2), float(eps), int(step)
+        self._check(self.L.hgs_adam_step(self.h, ctypes.byref(a)))
 
     def counters(self) -> dict:
         out = (ctypes.c_int64 * len(COUNTER_NAMES))()

@@ -659,7 +659,10 @@ def make_scene(config: int, seed: int | None = None, n_leaves: int | None = None
 def make_views(config: int, seed: int | None = None, headline: bool = False,
                n_views: int | None = None, tau: float | None = None,
                corridor: float | None = None) -> list[View]:
-    """Cameras of each workload.  ``headline`` switches configs 3 and 5 to
+    """Cameras of each workload.  Config 3: 64 views of uneven resolution,
+    tau log-uniform in [2, 15] px; config 5: 32 views of 1920x1080 (the batch
+    of one optimisation step; ``seed`` draws another step's eyes), tau
+    log-uniform in [3, 15] px.  ``headline`` switches configs 3 and 5 to
     every view at 1920x1080 and tau = 6 px."""
     seed = config if seed is None else seed
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0xCA4])))
@@ -694,7 +697,7 @@ def make_views(config: int, seed: int | None = None, headline: bool = False,
                 w, hh = 1920, 1080
                 t = 6.0
             else:
-                w, hh = res[int(rng.integers(0, 3))]
+                w, hh = res[int(rng.integers(0, 3))] if config == 3 else (1920, 1080)
                 xi = rng.random()
                 lo, hi = (2.0, 15.0) if config == 3 else (3.0, 15.0)
                 t = hi ** xi * lo ** (1.0 - xi)

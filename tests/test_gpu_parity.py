@@ -300,6 +300,47 @@ def test_autograd_l1_matches_oracle(hgs_mod, c1):
     r.close()
 
 
+# -------------------------------------------------------------- optimiser
+def test_adam_step_matches_oracle(hgs_mod, c1):
+    H = hgs_mod
+    r = H.Renderer(0)
+    r.upload(c1)
+    P = H.params_to_device(c1)
+    N = c1.n_nodes
+    inner = np.asarray(c1.child_count) > 0
+    gen = np.random.default_rng(21)
+    M = {k: torch.zeros_like(t) for k, t in P.items()}
+    V = {k: torch.zeros_like(t) for k, t in P.items()}
+    oP = {k: t.cpu().numpy().astype(np.float64).reshape(N, -1) for k, t in P.items()}
+    oM = {k: np.zeros_like(a) for k, a in oP.items()}
+    oV = {k: np.zeros_like(a) for k, a in oP.items()}
+    # the ABI takes FP32 hyper-parameters: the oracle gets the same values
+    f32 = lambda x: float(np.float32(x))  # noqa: E731
+    lr = {k: f32(x) for k, x in dict(mean=1e-3, scale=5e-3, rot=1e-3, opacity=5e-2, sh=2.5e-3).items()}
+    b1, b2, eps = f32(0.9), f32(0.999), f32(1e-15)
+    for step in range(1, 4):
+        g = {k: gen.normal(size=a.shape).astype(np.float32) for k, a in oP.items()}
+        G = {k: torch.from_numpy(a.reshape(P[k].shape)).cuda() for k, a in g.items()}
+        oG = {k: a.astype(np.float64) for k, a in g.items()}
+        r.adam_step(P, G, M, V, lr, step, b1, b2, eps)
+        O.adam_step(oP, oG, oM, oV, inner, lr, step, b1, b2, eps)
+        _sync()
+        for k in P:
+            gp = P[k].cpu().numpy().astype(np.float64).reshape(N, -1)
+            assert np.allclose(gp, oP[k], rtol=1e-6, atol=1e-6), (step, k, np.abs(gp - oP[k]).max())
+            assert np.allclose(M[k].cpu().numpy().reshape(N, -1), oM[k], rtol=1e-5, atol=1e-7), (step, k)
+            assert np.allclose(V[k].cpu().numpy().reshape(N, -1), oV[k], rtol=1e-5, atol=1e-9), (step, k)
+            gg = G[k].cpu().numpy().reshape(N, -1)
+            assert np.all(gg[inner] == 0.0) and np.array_equal(gg[~inner], g[k].reshape(N, -1)[~inner]), (step, k)
+            # leaves never move
+            ref = np.asarray(c1.arrays()[k], np.float32).reshape(-1, N).T.astype(np.float64)
+            assert np.array_equal(gp[~inner], ref[~inner]), (step, k)
+    with pytest.raises(H.HgsError) as e:
+        r.adam_step(P, G, M, V, lr, 0)
+    assert e.value.status == H.ERR_INVALID_ARG
+    r.close()
+
+
 # ------------------------------------------------------------- C-ABI errors
 def test_error_paths(hgs_mod, c1):
     H = hgs_mod

@@ -480,3 +480,79 @@ def test_backward_zero_through_the_099_clamp():
             assert abs(fd - g[slot, i]) <= 1e-5 * max(1.0, abs(fd)), (i, slot, fd, g[slot, i])
             n_checked += 1
     assert n_checked >= 8
+
+
+# ------------------------------------------------------------- optimiser
+def _adam_case(n=64, seed=7):
+    rng = np.random.default_rng(seed)
+    comp = dict(mean=3, scale=3, rot=4, opacity=1, sh=48)
+    P = {k: rng.normal(size=(n, c)).reshape(n, c) for k, c in comp.items()}
+    G = {k: rng.normal(size=(n, c)) for k, c in comp.items()}
+    M = {k: np.zeros((n, c)) for k, c in comp.items()}
+    V = {k: np.zeros((n, c)) for k, c in comp.items()}
+    interior = rng.random(n) < 0.5
+    return P, G, M, V, interior
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    # from zero moments the bias-corrected moments are g and g^2: the first
+    # step moves every interior parameter by lr g / (|g| + eps), leaves none
+    P, G, M, V, inner = _adam_case()
+    P0 = {k: a.copy() for k, a in P.items()}
+    G0 = {k: a.copy() for k, a in G.items()}
+    O.adam_step(P, G, M, V, inner, lr=0.01, step=1, eps=1e-8)
+    for k in P:
+        expect = P0[k][inner] - 0.01 * G0[k][inner] / (np.abs(G0[k][inner]) + 1e-8)
+        assert np.allclose(P[k][inner], expect, rtol=0, atol=1e-14)
+        assert np.array_equal(P[k][~inner], P0[k][~inner])
+        assert np.all(G[k][inner] == 0.0) and np.array_equal(G[k][~inner], G0[k][~inner])
+
+
+def test_adam_constant_gradient_moves_linearly():
+    # a constant gradient keeps the bias-corrected moments at g and g^2, so
+    # every step moves the same distance; a zero gradient moves nothing
+    P, G, M, V, inner = _adam_case(seed=3)
+    G["sh"][:] = 0.0
+    P0 = {k: a.copy() for k, a in P.items()}
+    G0 = {k: a.copy() for k, a in G.items()}
+    steps = 5
+    for s in range(1, steps + 1):
+        Gs = {k: a.copy() for k, a in G0.items()}
+        O.adam_step(P, Gs, M, V, inner, lr=0.003, step=s, beta1=0.8, beta2=0.95, eps=1e-12)
+    for k in P:
+        g = G0[k][inner]
+        expect = P0[k][inner] - steps * 0.003 * g / (np.abs(g) + 1e-12)
+        assert np.allclose(P[k][inner], expect, rtol=0, atol=1e-12)
+    assert np.array_equal(P["sh"], P0["sh"])
+
+
+def test_adam_first_moment_follows_the_current_gradient_with_beta1_zero():
+    # beta1 = 0: the first moment is the current gradient; with |g| fixed
+    # the second moment stays g^2 whatever beta2 does, so a gradient whose
+    # sign alternates moves the parameter back and forth by lr
+    P, G, M, V, inner = _adam_case(seed=11)
+    P0 = {k: a.copy() for k, a in P.items()}
+    g1 = {k: a.copy() for k, a in G.items()}
+    for s in range(1, 4):
+        Gs = {k: (a if s % 2 == 1 else -a).copy() for k, a in g1.items()}
+        O.adam_step(P, Gs, M, V, inner, lr=0.02, step=s, beta1=0.0, beta2=0.999, eps=1e-12)
+        for k in P:
+            moved = 0.0 if s % 2 == 0 else 0.02 * np.sign(g1[k][inner])
+            assert np.allclose(P[k][inner], P0[k][inner] - moved, rtol=0, atol=1e-9), (s, k)
+
+
+def test_oracle_reproduces_its_golden_values():
+    # regression fixture written by tests/golden/make_golden.py (oracle only)
+    import json
+    import os
+    import sys
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, here)
+    import make_golden
+    ref = json.load(open(os.path.join(here, "oracle_c1.json")))
+    now = make_golden.compute()
+    for tau, r in ref["taus"].items():
+        n = now["taus"][tau]
+        assert (n["cut"], n["cut_id_sum"], n["blended"]) == (r["cut"], r["cut_id_sum"], r["blended"]), tau
+        assert abs(n["t_sum"] - r["t_sum"]) <= 1e-9 * max(1.0, abs(r["t_sum"]))
+        assert np.allclose(n["rgb"], r["rgb"], rtol=0, atol=1e-12) and np.allclose(n["T"], r["T"], rtol=0, atol=1e-12)
