@@ -65,26 +65,10 @@ def build_workload(name: str, leaves: int | None = None):
 
 
 def autotune(r, views, step, reps=1):
-    """Pick the (tile, batch) with the fastest fwd+bwd step; images are
-    bit-identical across choices."""
-    import torch
-    from paper_2406_12080_amd import hgs  # noqa: F401
-    best = None
-    for tw, th, b in [(8, 8, 64), (8, 8, 128), (16, 8, 128), (16, 8, 256), (16, 16, 256), (16, 16, 512),
-                      (32, 16, 512)]:
-        r.set_tuning(tw, th, b)
-        step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            step()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        log(f"[bench] autotune tile {tw}x{th} batch {b}: {dt * 1e3:.2f} ms")
-        if best is None or dt < best[0]:
-            best = (dt, tw, th, b)
-    r.set_tuning(best[1], best[2], best[3])
-    return dict(tile_w=best[1], tile_h=best[2], batch=best[3])
+    """The package's autotuner on the fwd+bwd step (images are bit-identical
+    across choices)."""
+    from paper_2406_12080_amd.autotune import autotune as tune
+    return tune(r, views, step, reps, log=lambda m: log(f"[bench] {m}"))
 
 
 def cpu_baseline(h, view, row_stride: int = 1):

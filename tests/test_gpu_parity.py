@@ -172,6 +172,19 @@ def test_tile_and_batch_invariance(r_c1, c1):
     r_c1.set_tuning(16, 16, 0)
 
 
+def test_autotuner_keeps_images(r_c1, c1):
+    from paper_2406_12080_amd.autotune import CANDIDATES, autotune
+    v = synth.make_views(1, tau=4.0)[0]
+    r_c1.set_tuning(16, 16, 0)
+    (ref,), _ = r_c1.render([v])
+    ref = ref.clone()
+    tuning = autotune(r_c1, [v, v.replace(tau=16.0)])
+    assert (tuning["tile_w"], tuning["tile_h"], tuning["batch"]) in CANDIDATES
+    (img,), _ = r_c1.render([v])
+    assert torch.equal(img, ref)
+    r_c1.set_tuning(16, 16, 0)
+
+
 def test_forward_deterministic(r_c2s, c2s):
     v = synth.make_views(2, tau=6.0)[0]
     (a,), sa = r_c2s.render([v])
