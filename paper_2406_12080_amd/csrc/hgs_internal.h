@@ -44,28 +44,28 @@ struct DevHier {
     const float *mean, *scale, *rot, *opacity, *sh;  // node-major: [N][3] [N][3] [N][4] [N] [N][48]
 };
 
-// Blend record of one splat (64 bytes).  The mean is kept as an integer pixel
+// Blend record of one splat (48 bytes).  The mean is kept as an integer pixel
 // anchor plus an FP32 fraction.  The conic (inverse dilated 2D covariance)
-// is stored through its eigen-axes scaled so that, for a pixel offset d from
+// is used through its eigen-axes scaled so that, for a pixel offset d from
 // the mean, u_i = w_i . d and G = exp2(-(u_1^2 + u_2^2)) = exp(-d^T conic d / 2):
 // a sum of squares, which FP32 evaluates without the cancellation the
 // expanded quadratic form suffers for thin splats far from their centre.
 struct __align__(16) SplatRec {
     int32_t ax, ay;
     float fx, fy;          // mean - anchor
-    float w1x, w1y, w2x, w2y;
     float An, Ap;          // kappa |o_n|, kappa |o_p|
     float t, invK;
     float r, g, b;
-    uint32_t node;
+    float unused;
 };
-// The FP64 axes (w1x, w1y, w2x, w2y) are kept beside the record: the
-// per-8x8-block offsets w . (corner - mean) are formed from them in FP64, since
-// a splat's centre can lie far off screen, where the FP32 rounding of the
-// axis direction alone would move the evaluated position by whole 1e-4s.
+// The axes w = (w1x, w1y, w2x, w2y) are kept beside the record in FP64
+// (double4): the per-8x8-block offsets w . (corner - mean) are formed from
+// them in FP64, since a splat's centre can lie far off screen, where the FP32
+// rounding of the axis direction alone would move the evaluated position by
+// whole 1e-4s; the lanes use their FP32 rounding.
 // 1/2 log2(e): exp(-q/2) = exp2(-kHalfLog2e q)
 constexpr double kHalfLog2e = 0.72134752044448170368;
-static_assert(sizeof(SplatRec) == 64, "record layout");
+static_assert(sizeof(SplatRec) == 48, "record layout");
 
 // Device-side counters of one render.
 struct Counters {

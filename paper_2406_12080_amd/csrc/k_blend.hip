@@ -113,7 +113,7 @@ struct Staged {
 template <int NB, int SX>
 __device__ __forceinline__ void stage_one(const SplatRec &r, const double4 &W64, int ox, int oy, Staged &st)
 {
-    st.w = make_float4(r.w1x, r.w1y, r.w2x, r.w2y);
+    st.w = make_float4((float)W64.x, (float)W64.y, (float)W64.z, (float)W64.w);
     st.o = make_float4(r.An, r.Ap, r.t, r.invK);
     st.c = make_float4(r.r, r.g, r.b, 0.0f);
     const float amax = r.t > 0.0f ? fmaxf(r.An, r.Ap) : r.An;
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
             const SplatRec r = recs[sidx];
             const double4 W64 = axes[sidx];
             s_id[j] = vis_rank[sidx];  // gradient row
-            s_w[j] = make_float4(r.w1x, r.w1y, r.w2x, r.w2y);
+            s_w[j] = make_float4((float)W64.x, (float)W64.y, (float)W64.z, (float)W64.w);
             s_o[j] = make_float4(r.An, r.Ap, r.t, r.invK);
             s_c[j] = make_float4(r.r, r.g, r.b, 0.0f);
 #pragma unroll

@@ -86,10 +86,6 @@ __global__ __launch_bounds__(kT, 4) void k_preprocess(DevHier h, const DevView *
                     const double s1 = sqrt(fmax(l1, 0.0) * kHalfLog2e), s2 = sqrt(fmax(l2, 0.0) * kHalfLog2e);
                     const double4 ax4 = make_double4(s1 * cs, s1 * sn, -s2 * sn, s2 * cs);
                     axes[k] = ax4;
-                    r.w1x = (float)ax4.x;
-                    r.w1y = (float)ax4.y;
-                    r.w2x = (float)ax4.z;
-                    r.w2y = (float)ax4.w;
                     r.An = (float)(P.kappa * P.o_n);
                     r.Ap = (float)(P.kappa * P.o_p);
                     r.t = (float)P.t;
@@ -99,7 +95,7 @@ __global__ __launch_bounds__(kT, 4) void k_preprocess(DevHier h, const DevView *
                     r.r = fmaxf(raw[0], 0.0f);
                     r.g = fmaxf(raw[1], 0.0f);
                     r.b = fmaxf(raw[2], 0.0f);
-                    r.node = P.node;
+                    r.unused = 0.0f;
                     recs[k] = r;
                     depth_key[k] = __float_as_uint((float)P.pc[2]);
                     float *cj = cjac + (size_t)k * 12;
