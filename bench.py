@@ -180,8 +180,8 @@ def load_traffic(workload: str, kernel: str):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--leaves", type=int, default=None, help="override the leaf count (smaller runs)")
     ap.add_argument("--tile", default=None, help="WxHxB, skips the autotuner (e.g. 16x16x256)")
@@ -279,6 +279,13 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_fwd = (time.perf_counter() - t0) / args.steps
 
+    # stage times of one view rendered on its own (HIP events between stages)
+    _, st1 = r.render([views[0]], out=[imgs[0]], timed=True)
+    stage_names = ("cut", "preprocess", "visible_and_depth_sort", "duplicate", "tile_sort", "ranges", "blend",
+                   "total")
+    stages_plain = {n: round(float(x), 4) for n, x in zip(stage_names, st1["ms"])}
+    log(f"[bench] stages of one view rendered alone (ms): {stages_plain}")
+
     t_plain = None
     if not args.no_plain:
         step_plain()
@@ -344,6 +351,7 @@ def main(argv=None):
         "views_per_s_fwd_batched": round(nv / t_fwd, 3),
         "blends_per_s_fwd_batched": round(ctr["blended"] / t_fwd, 1),
         "ms_per_step_plain": round(t_plain * 1e3, 3) if t_plain else None,
+        "stages_ms_one_view": stages_plain,
         "counters_per_step": ctr,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -177,7 +177,9 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_gr
  * gradient).  All arrays are device pointers in the parameter layouts of the
  * header (node-major; index 0..4 = mean, scale, rot, opacity, sh), N nodes
  * each; m and v must be zero before step 1.  Leaf entries of every array are
- * left untouched.  Queued on the ctx stream; does not synchronise.
+ * left untouched.  Queued on the ctx stream; does not synchronise.  When
+ * the step updates the parameters the renderer reads (the bound arrays),
+ * the next hgs_render_backward needs a new hgs_render (HGS_ERR_STATE).
  * Errors: HGS_ERR_STATE without a hierarchy, HGS_ERR_INVALID_ARG for a NULL
  * array, step < 1, or a non-finite / out-of-range hyper-parameter. */
 typedef struct {

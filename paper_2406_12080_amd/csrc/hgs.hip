@@ -96,6 +96,8 @@ struct hgs_ctx {
     uint32_t *dup_first = nullptr;  // first splat of every pair-emission block
     uint32_t *k2 = nullptr, *v2 = nullptr;
     uint32_t *hist = nullptr, *hist_scan = nullptr, *partial = nullptr, *scan_total = nullptr;
+    SortBlock *sort_plan = nullptr;  // work of every block of a per-view (segmented) sort
+    uint32_t *vis_bounds = nullptr, *pair_bounds = nullptr, *seg_tile_base = nullptr;  // per view
     uint2 *ranges = nullptr;
     uint32_t *tile_keys = nullptr, *tile_order = nullptr, *tile_k2 = nullptr, *tile_v2 = nullptr;
     uint32_t *tile_n = nullptr;
@@ -453,18 +455,29 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     launch_scan(ctx->vis_counts, nullptr, vblocks, nullptr, ctx->vis_offsets, &ctx->ctr->vis_total, ctx->partial, st);
     launch_compact_visible(ctx->vis_mask, ctx->vis_offsets, &ctx->ctr->cut_total, ctx->cut_cap, ctx->depth_key,
                            ctx->skeys, ctx->svals, ctx->vis_rank, st);
-    SortScratch sc{ctx->k2, ctx->v2, ctx->hist, ctx->hist_scan, ctx->partial, ctx->scan_total};
-    launch_radix_sort(ctx->skeys, ctx->svals, ctx->cut_cap, &ctx->ctr->vis_total, 32, sc, st);  // 4 passes: in place
+    // the visible splats keep the cut's view-major order: each view's run is
+    // sorted by depth on its own (4 passes, in place), so that its pairs are
+    // emitted as one run, which the tile sort then orders by the view's own
+    // tile id (16 bits or fewer: 2 passes)
+    SortScratch sc{ctx->k2, ctx->v2, ctx->hist, ctx->hist_scan, ctx->partial, ctx->scan_total, ctx->sort_plan};
+    launch_vis_bounds(ctx->cut_base, nv, ctx->vis_mask, ctx->vis_offsets, &ctx->ctr->cut_total, ctx->cut_cap,
+                      &ctx->ctr->vis_total, ctx->vis_bounds, st);
+    launch_radix_sort(ctx->skeys, ctx->svals, ctx->cut_cap, &ctx->ctr->vis_total, 32, sc, st, ctx->vis_bounds, nv);
     mark(3);
     launch_gather_tiles(ctx->trec, ctx->svals, &ctx->ctr->vis_total, ctx->cut_cap, ctx->pair_offsets, ctx->rect, st);
     launch_scan(ctx->pair_offsets, nullptr, ctx->cut_cap, &ctx->ctr->vis_total, ctx->pair_offsets,
                 &ctx->ctr->pair_total, ctx->partial, st);  // in place
+    launch_pair_bounds(ctx->vis_bounds, ctx->views_dev, nv, ctx->pair_offsets, &ctx->ctr->vis_total, ctx->cut_cap,
+                       &ctx->ctr->pair_total, ctx->pair_cap, ctx->pair_bounds, ctx->seg_tile_base, st);
     launch_duplicate(ctx->rect, ctx->views_dev, nv, ctx->cut_base, ctx->svals, ctx->pair_offsets, ctx->dup_first,
                      &ctx->ctr->vis_total, ctx->cut_cap, &ctx->ctr->pair_total, ctx->pair_cap, ctx->pkeys,
                      ctx->pvals, ctx->ctr, st);
     mark(4);
-    ctx->pairs_in_scratch =
-        launch_radix_sort(ctx->pkeys, ctx->pvals, ctx->pair_cap, &ctx->ctr->pair_total, bits_for(n_tiles), sc, st);
+    uint32_t view_tiles = 1;  // tiles of the largest view
+    for (int v = 0; v < nv; ++v)
+        view_tiles = std::max(view_tiles, (uint32_t)(ctx->views_host[v].tiles_x * ctx->views_host[v].tiles_y));
+    ctx->pairs_in_scratch = launch_radix_sort(ctx->pkeys, ctx->pvals, ctx->pair_cap, &ctx->ctr->pair_total,
+                                              bits_for(view_tiles), sc, st, ctx->pair_bounds, nv, ctx->seg_tile_base);
     mark(5);
     const uint32_t *keys = ctx->pairs_in_scratch ? ctx->k2 : ctx->pkeys;
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
@@ -473,7 +486,8 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     // longest tile lists first (one stable 8-bit pass over log-scaled lengths)
     launch_tile_keys(ctx->ranges, n_tiles, ctx->tile_keys, ctx->tile_order, ctx->tile_n, st);
     {
-        SortScratch ts{ctx->tile_k2, ctx->tile_v2, ctx->hist, ctx->hist_scan, ctx->partial, ctx->scan_total};
+        SortScratch ts{ctx->tile_k2, ctx->tile_v2, ctx->hist, ctx->hist_scan, ctx->partial, ctx->scan_total,
+                       ctx->sort_plan};
         const bool in_scratch = launch_radix_sort(ctx->tile_keys, ctx->tile_order, n_tiles, ctx->tile_n, 8, ts, st);
         ctx->tile_sorted = in_scratch ? ctx->tile_v2 : ctx->tile_order;
     }
@@ -527,6 +541,10 @@ hgs_status hgs_create(hgs_ctx **out, int device, void *hip_stream)
         if ((s = dalloc(ctx, (void **)&ctx->hist_scan, sizeof(uint32_t) * 256 * kSortBlocksMax))) break;
         if ((s = dalloc(ctx, (void **)&ctx->partial, sizeof(uint32_t) * kScanBlocks))) break;
         if ((s = dalloc(ctx, (void **)&ctx->scan_total, sizeof(uint32_t) * 4))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->sort_plan, sizeof(SortBlock) * kSortBlocksMax))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->vis_bounds, sizeof(uint32_t) * (kMaxViews + 1)))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->pair_bounds, sizeof(uint32_t) * (kMaxViews + 1)))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->seg_tile_base, sizeof(uint32_t) * kMaxViews))) break;
     } while (0);
     if (s != HGS_OK) {
         hgs_destroy(ctx);
@@ -584,6 +602,9 @@ hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a)
         !(a->eps > 0.0f) || !std::isfinite(a->eps))
         return fail(ctx, HGS_ERR_INVALID_ARG, "bad step, beta1, beta2 or eps");
     HIPC(hipSetDevice(ctx->device));
+    // stepping the parameters the renderer reads makes the last render stale
+    for (int k = 0; k < 5; ++k)
+        if (a->param[k] == (ctx->use_bound ? ctx->bound[k] : ctx->own[k])) ctx->have_render = false;
     const double bc1 = 1.0 / (1.0 - std::pow((double)a->beta1, (double)a->step));
     const double bc2 = 1.0 / (1.0 - std::pow((double)a->beta2, (double)a->step));
     for (int k = 0; k < 5; ++k) {

@@ -107,17 +107,30 @@ void launch_scan(const uint32_t *in, const uint32_t *idx, uint32_t n_host, const
 constexpr int kScanBlocks = 512;
 
 // stable LSD radix sort of (uint32 key, uint32 value) over bit range [0, bits)
+struct SortBlock {  // work of one block of a segmented sort
+    uint32_t b0, b1;    // its elements [b0, b1)
+    uint32_t hbase;     // histogram slot of digit 0; digit d at hbase + d * hstride
+    uint32_t hstride;   // 0: the block has no work
+    uint32_t kbase;     // subtracted from every key of its segment before the digits are taken
+    uint32_t pad[3];
+};
 struct SortScratch {
     uint32_t *k2, *v2;   // ping-pong buffers (capacity elements)
     uint32_t *hist;      // 256 * kSortBlocksMax
     uint32_t *hist_scan; // 256 * kSortBlocksMax
     uint32_t *partial;   // kScanBlocks
-    uint32_t *total;     // 1
+    uint32_t *total;     // 2: scan total, histogram length of a segmented sort
+    SortBlock *plan;     // kSortBlocksMax
 };
 constexpr int kSortBlocksMax = 4096;
 // Returns true when the sorted result is in (s.k2, s.v2) (odd pass count).
+// With seg_bounds (device, nseg + 1 positions, ascending; nseg <= kMaxViews)
+// every segment [seg_bounds[i], seg_bounds[i + 1]) is sorted on its own and
+// stays in place, on the digits of key - seg_kbase[i] (seg_kbase may be NULL
+// for zero).
 bool launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t cap, const uint32_t *n_dev, int bits,
-                       const SortScratch &s, hipStream_t st);
+                       const SortScratch &s, hipStream_t st, const uint32_t *seg_bounds = nullptr, int nseg = 0,
+                       const uint32_t *seg_kbase = nullptr);
 
 // preprocess: interpolation, EWA projection, SH colour, footprint, per cut entry
 void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
@@ -136,6 +149,16 @@ void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_
 // tile count, unused; written for visible entries).
 void launch_gather_tiles(const uint4 *trec, const uint32_t *sorted_vals, const uint32_t *vis_total, uint32_t vis_cap,
                          uint32_t *counts, uint2 *rect, hipStream_t st);
+// Per view: the depth-order slot of its first visible splat (vis_bounds,
+// nv + 1 entries, the last = visible total).
+void launch_vis_bounds(const uint32_t *cut_base, int nv, const uint64_t *vis_mask, const uint32_t *vis_offsets,
+                       const uint32_t *cut_total, uint32_t cap, const uint32_t *vis_total, uint32_t *bounds,
+                       hipStream_t st);
+// Per view: the position of its first (tile, splat) pair (nv + 1 entries,
+// the last = pair total) and its first global tile id.
+void launch_pair_bounds(const uint32_t *vis_bounds, const DevView *views, int nv, const uint32_t *pair_offsets,
+                        const uint32_t *vis_total, uint32_t vis_cap, const uint32_t *pair_total, uint32_t pair_cap,
+                        uint32_t *bounds, uint32_t *tile_base, hipStream_t st);
 // block_first: duplicate_blocks(pair_cap) + 1 entries of workspace.  rect:
 // tile rectangles in depth order (launch_gather_tiles).
 void launch_duplicate(const uint2 *rect, const DevView *views, int nv, const uint32_t *cut_base,

@@ -153,6 +153,40 @@ __global__ __launch_bounds__(kT) void k_compact_visible(const uint64_t *__restri
     }
 }
 
+// Per view, the slot of its first visible splat: visible entries before cut
+// position cut_base[v] (the visible list keeps the cut's view-major order).
+__global__ void k_vis_bounds(const uint32_t *__restrict__ cut_base, int nv, const uint64_t *__restrict__ vis_mask,
+                             const uint32_t *__restrict__ vis_offsets, const uint32_t *__restrict__ cut_total,
+                             uint32_t cap, const uint32_t *__restrict__ vis_total, uint32_t *__restrict__ bounds)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > nv) return;
+    const uint32_t total = min(*cut_total, cap);
+    const uint32_t k = v < nv ? cut_base[v] : total;
+    if (k >= total) {
+        bounds[v] = min(*vis_total, cap);
+        return;
+    }
+    uint32_t c = vis_offsets[k / kT];  // visible entries of the preprocess blocks before k's
+    for (uint32_t w = (k / kT) * (kT / 64); w < (k >> 6); ++w) c += (uint32_t)__popcll(vis_mask[w]);
+    if (k & 63u) c += (uint32_t)__popcll(vis_mask[k >> 6] & ((1ull << (k & 63u)) - 1ull));
+    bounds[v] = c;
+}
+
+// Per view, the position of its first pair and its first global tile id.
+__global__ void k_pair_bounds(const uint32_t *__restrict__ vis_bounds, const DevView *__restrict__ views, int nv,
+                              const uint32_t *__restrict__ pair_offsets, const uint32_t *__restrict__ vis_total,
+                              uint32_t vis_cap, const uint32_t *__restrict__ pair_total, uint32_t pair_cap,
+                              uint32_t *__restrict__ bounds, uint32_t *__restrict__ tile_base)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > nv) return;
+    const uint32_t nvis = min(*vis_total, vis_cap), npairs = min(*pair_total, pair_cap);
+    const uint32_t j = vis_bounds[v];
+    bounds[v] = j < nvis ? min(pair_offsets[j], npairs) : npairs;
+    if (v < nv) tile_base[v] = views[v].tile_base;
+}
+
 // The tile records of the visible splats in depth order: the one random
 // gather of per-splat data between the depth sort and the pair emission.
 __global__ __launch_bounds__(kT) void k_gather_tiles(const uint4 *__restrict__ trec,
@@ -711,6 +745,22 @@ void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32
     const uint32_t blocks = (uint32_t)std::min<uint64_t>(need, 8192);
     if (!blocks) return;
     hipLaunchKernelGGL(k_zero_rows, dim3(blocks), dim3(kT), 0, st, rows, width, vis_total, vis_cap);
+}
+
+void launch_vis_bounds(const uint32_t *cut_base, int nv, const uint64_t *vis_mask, const uint32_t *vis_offsets,
+                       const uint32_t *cut_total, uint32_t cap, const uint32_t *vis_total, uint32_t *bounds,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_vis_bounds, dim3((nv + 1 + 255) / 256), dim3(256), 0, st, cut_base, nv, vis_mask,
+                       vis_offsets, cut_total, cap, vis_total, bounds);
+}
+
+void launch_pair_bounds(const uint32_t *vis_bounds, const DevView *views, int nv, const uint32_t *pair_offsets,
+                        const uint32_t *vis_total, uint32_t vis_cap, const uint32_t *pair_total, uint32_t pair_cap,
+                        uint32_t *bounds, uint32_t *tile_base, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pair_bounds, dim3((nv + 1 + 255) / 256), dim3(256), 0, st, vis_bounds, views, nv,
+                       pair_offsets, vis_total, vis_cap, pair_total, pair_cap, bounds, tile_base);
 }
 
 void launch_gather_tiles(const uint4 *trec, const uint32_t *sorted_vals, const uint32_t *vis_total, uint32_t vis_cap,

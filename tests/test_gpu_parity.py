@@ -351,6 +351,14 @@ def test_adam_step_matches_oracle(hgs_mod, c1):
     with pytest.raises(H.HgsError) as e:
         r.adam_step(P, G, M, V, lr, 0)
     assert e.value.status == H.ERR_INVALID_ARG
+    # stepping the bound parameters makes the last render stale for backward
+    r.bind(*[P[k] for k in H.PARAM_FIELDS])
+    v = synth.make_views(1, tau=4.0)[0]
+    r.render([v])
+    r.adam_step(P, G, M, V, lr, 4, b1, b2, eps)
+    with pytest.raises(H.HgsError) as e:
+        r.backward([torch.zeros(v.height, v.width, 3, device="cuda")], G)
+    assert e.value.status == H.ERR_STATE
     r.close()
 
 
