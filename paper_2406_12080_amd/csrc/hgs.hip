@@ -79,7 +79,7 @@ struct hgs_ctx {
     uint32_t cut_cap = 0, pair_cap = 0;
     size_t pix_cap = 0, tile_cap = 0;
     int nblocks_cap = 0, nv_cap = 0;
-    uint64_t *masks = nullptr, *fmask = nullptr;
+    uint64_t *masks = nullptr;
     uint32_t *word_off = nullptr;  // per view and mask word: cut position of its first selected node
     uint32_t *blk_counts = nullptr, *blk_offsets = nullptr, *cut_base = nullptr;
     int32_t *cut_ids = nullptr;
@@ -333,7 +333,6 @@ hgs_status ensure_fixed(hgs_ctx *ctx, int nv, uint32_t n_tiles, size_t n_pix)
         const int nvc = std::max(nv, ctx->nv_cap), nbc = std::max(nb, ctx->nblocks_cap);
         const size_t words = (size_t)((ctx->n + 63) / 64);
         if ((s = realloc_buf(ctx, ctx->masks, words * nvc + 1))) return s;
-        if ((s = realloc_buf(ctx, ctx->fmask, words * nvc + 1))) return s;
         if ((s = realloc_buf(ctx, ctx->word_off, words * nvc + 1))) return s;
         if ((s = realloc_buf(ctx, ctx->blk_counts, (size_t)nbc * nvc))) return s;
         if ((s = realloc_buf(ctx, ctx->blk_offsets, (size_t)nbc * nvc))) return s;
@@ -438,7 +437,7 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     };
     mark(0);
     launch_fill_u32((uint32_t *)ctx->ctr, 0u, sizeof(Counters) / 4, st);
-    launch_cut_flags(h, ctx->views_dev, nv, ctx->fmask, ctx->masks, ctx->blk_counts, nb, st);
+    launch_cut_flags(h, ctx->views_dev, nv, ctx->masks, ctx->blk_counts, nb, st);
     launch_scan(ctx->blk_counts, nullptr, (uint32_t)(nb * nv), nullptr, ctx->blk_offsets, &ctx->ctr->cut_total,
                 ctx->partial, st);
     launch_cut_emit(h, ctx->views_dev, nv, ctx->masks, ctx->blk_offsets, nb, ctx->word_off, ctx->cut_ids, nullptr,
@@ -779,7 +778,7 @@ hgs_status hgs_cut(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *
     const DevHier h = dev_hier(ctx);
     const int nb = cut_blocks(ctx->n);
     launch_fill_u32((uint32_t *)ctx->ctr, 0u, sizeof(Counters) / 4, st);
-    launch_cut_flags(h, ctx->views_dev, 1, ctx->fmask, ctx->masks, ctx->blk_counts, nb, st);
+    launch_cut_flags(h, ctx->views_dev, 1, ctx->masks, ctx->blk_counts, nb, st);
     launch_scan(ctx->blk_counts, nullptr, (uint32_t)nb, nullptr, ctx->blk_offsets, &ctx->ctr->cut_total, ctx->partial,
                 st);
     HIPC(hipGetLastError());

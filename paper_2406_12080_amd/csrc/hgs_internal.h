@@ -89,9 +89,10 @@ struct Counters {
 constexpr int kCutThreads = 256;
 constexpr int kCutItems = 4;
 constexpr int kCutBlock = kCutThreads * kCutItems;  // nodes per block
-// fmask: workspace of the same size as masks (the per-node predicate bits).
-void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *fmask, uint64_t *masks,
-                      uint32_t *block_counts, int nblocks, hipStream_t st);
+// masks: one bit per (view, node), words * nv; block_counts: per view and
+// block of kCutBlock nodes.
+void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *masks, uint32_t *block_counts,
+                      int nblocks, hipStream_t st);
 // Also writes word_off[v][w]: the cut position of the first selected node of
 // mask word w of view v (words holding a selected node only).
 void launch_cut_emit(const DevHier &h, const DevView *views, int nv, const uint64_t *masks,

@@ -10,10 +10,9 @@
 // by the thread that holds the node (the node's box is read once per batch
 // of views).  Selected nodes are compacted in ascending id order with a
 // 64-lane ballot bitmask per wave, a per-block count, one exclusive scan over
-// (view, block), and an emit pass that writes ids and weights.  The
-// predicate F(n) = leaf or eps(n) <= tau is evaluated once per (view, node)
-// into a bit mask; a second sweep combines each node's bit with its
-// parent's (parents of neighbouring nodes are neighbours: cached words).
+// (view, block), and an emit pass that writes ids and weights.  Each lane
+// evaluates F(n) = leaf or eps(n) <= tau for its node and for its node's
+// parent (parents of neighbouring nodes are neighbours: cached boxes).
 //
 // The selection is defined by eps evaluated in FP64 with contraction
 // disabled, from the FP32 stored boxes, so that it does not depend on FP32
@@ -82,64 +81,14 @@ __device__ __forceinline__ void load_box(const DevHier &h, int64_t i, float b[6]
     for (int k = 0; k < 6; ++k) b[k] = h.box[k * h.n + i];
 }
 
-// Pass 1: F(n) = leaf or eps(n) <= tau, one bit per (view, node) in fmask.
-__global__ __launch_bounds__(kCutThreads) void k_cut_meets(DevHier h, const DevView *__restrict__ views, int nv,
-                                                           uint64_t *__restrict__ fmask)
-{
-    const int64_t n = h.n;
-    const int64_t words = (n + 63) >> 6;
-    const int lane = threadIdx.x & 63;
-#pragma unroll 1
-    for (int it = 0; it < kCutItems; ++it) {
-        const int64_t i0 = (int64_t)blockIdx.x * kCutBlock + it * kCutThreads + (threadIdx.x & ~63);
-        const int64_t i = i0 + lane;
-        const bool valid = i < n;
-        if (i0 >= n) break;
-        float b[6] = {0, 0, 0, 0, 0, 0};
-        bool leaf = true;
-        if (valid) {
-            load_box(h, i, b);
-            leaf = (h.pinfo[i] & kLeafBit) != 0;
-        }
-        // leaves (and the padding past n) always meet tau
-        const uint64_t leaves = __ballot(leaf);
-        const bool all_leaves = leaves == ~0ull;
-        float L = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) L = fmaxf(L, b[3 + k] - b[k]);
-        const float L2 = L * L;
-        const uint64_t Lok = __ballot(L2 == 0.0f || L2 >= 1e-30f);
-        // the words of up to 64 views are gathered on lanes (lane u: view
-        // v0 + u) and stored with one instruction
-#pragma unroll 1
-        for (int v0 = 0; v0 < nv; v0 += 64) {
-            uint64_t word = 0;
-            const int nvc = min(64, nv - v0);
-#pragma unroll 2
-            for (int u = 0; u < nvc; ++u) {
-                uint64_t F = ~0ull;
-                if (!all_leaves) {
-                    const DevView &V = views[v0 + u];
-                    const CutTest c = meets_tau_f32(b, L2, Lok, V);
-                    F = leaves | c.yes;
-                    const uint64_t open = ~(F | c.no);
-                    if (open) {  // rare: decide by the FP64 evaluation that defines the cut
-                        const bool m = ((open >> lane) & 1ull) && granularity(b, V) <= (double)V.tau;
-                        F |= __ballot(m);
-                    }
-                }
-                word = lane == u ? F : word;
-            }
-            if (lane < nvc) fmask[(int64_t)(v0 + lane) * words + (i0 >> 6)] = word;
-        }
-    }
-}
-
-// Pass 2: n is in the cut when F(n) holds and F(parent) does not (or n is the
-// root): a test of two bits.  Writes the cut bit masks and per-block counts.
-__global__ __launch_bounds__(kCutThreads) void k_cut_flags(DevHier h, int nv, const uint64_t *__restrict__ fmask,
-                                                           uint64_t *__restrict__ masks,
-                                                           uint32_t *__restrict__ block_counts, int nblocks)
+// The cut in one sweep: each lane tests its node and its node's parent for
+// every view (the FP32 prefilter is a few instructions per test, so testing a
+// parent once per child costs less than a second sweep over stored bits) and
+// keeps F(n) and not F(parent).  Writes the cut bit masks and per-block
+// counts.
+__global__ __launch_bounds__(kCutThreads) void k_cut_onepass(DevHier h, const DevView *__restrict__ views, int nv,
+                                                             uint64_t *__restrict__ masks,
+                                                             uint32_t *__restrict__ block_counts, int nblocks)
 {
     __shared__ uint32_t s_cnt[kMaxViews];
     for (int v = threadIdx.x; v < nv; v += kCutThreads) s_cnt[v] = 0;
@@ -152,37 +101,59 @@ __global__ __launch_bounds__(kCutThreads) void k_cut_flags(DevHier h, int nv, co
         const int64_t i0 = (int64_t)blockIdx.x * kCutBlock + it * kCutThreads + (threadIdx.x & ~63);
         const int64_t i = i0 + lane;
         const bool valid = i < n;
-        uint32_t par = kRootParent;
-        if (valid) par = h.pinfo[i] & ~kLeafBit;
-        const bool root = par == kRootParent;
         if (i0 >= n) break;
-        const int64_t wown = i0 >> 6;                           // this wave's word
-        const int64_t wpar = valid && !root ? (int64_t)(par >> 6) : wown;  // the parent's (in bounds)
-        constexpr int U = 8;  // views per step: their loads are independent
+        float b[6] = {0, 0, 0, 0, 0, 0}, pb[6] = {0, 0, 0, 0, 0, 0};
+        bool leaf = true, root = true;
+        if (valid) {
+            const uint32_t pi = h.pinfo[i];
+            leaf = (pi & kLeafBit) != 0;
+            const uint32_t par = pi & ~kLeafBit;
+            root = par == kRootParent;
+            load_box(h, i, b);
+            if (!root) load_box(h, par, pb);
+        }
+        // leaves (and the padding past n) always meet tau; the root and the
+        // padding have no parent that meets it
+        const uint64_t leaves = __ballot(leaf), no_parent = __ballot(root), live = __ballot(valid);
+        float L = 0.0f, Lp = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            L = fmaxf(L, b[3 + k] - b[k]);
+            Lp = fmaxf(Lp, pb[3 + k] - pb[k]);
+        }
+        const float L2 = L * L, Lp2 = Lp * Lp;
+        const uint64_t Lok = __ballot(L2 == 0.0f || L2 >= 1e-30f), Lpok = __ballot(Lp2 == 0.0f || Lp2 >= 1e-30f);
 #pragma unroll 1
-        for (int c0 = 0; c0 < nv; c0 += 64) {  // up to 64 views gathered on lanes
-            const int nvc = min(64, nv - c0);
+        for (int v0 = 0; v0 < nv; v0 += 64) {  // up to 64 views gathered on lanes
             uint64_t word = 0;
+            const int nvc = min(64, nv - v0);
 #pragma unroll 1
-            for (int u0 = 0; u0 < nvc; u0 += U) {
-                uint64_t own[U], pw[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {  // views past the last re-read the last one (in bounds)
-                    const uint64_t *fv = fmask + (int64_t)(c0 + min(u0 + u, nvc - 1)) * words;
-                    own[u] = fv[wown];
-                    pw[u] = fv[wpar];
+            for (int u = 0; u < nvc; ++u) {
+                const DevView &V = views[v0 + u];
+                const CutTest c = meets_tau_f32(b, L2, Lok, V);
+                uint64_t F = leaves | c.yes;
+                const uint64_t open = ~(F | c.no) & live;
+                if (open) {  // rare: decide by the FP64 evaluation that defines the cut
+                    const bool m = ((open >> lane) & 1ull) && granularity(b, V) <= (double)V.tau;
+                    F |= __ballot(m);
                 }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const bool in =
-                        valid && ((own[u] >> lane) & 1ull) && (root || !((pw[u] >> (par & 63)) & 1ull));
-                    const uint64_t m = __ballot(in);
-                    if (u0 + u < nvc) word = lane == u0 + u ? m : word;
+                uint64_t sel = F & live & ~no_parent;  // nodes whose parent must fail the test
+                uint64_t Fp = 0;
+                if (sel) {
+                    const CutTest cp = meets_tau_f32(pb, Lp2, Lpok, V);
+                    Fp = cp.yes;
+                    const uint64_t openp = ~(cp.yes | cp.no) & sel;
+                    if (openp) {
+                        const bool m = ((openp >> lane) & 1ull) && granularity(pb, V) <= (double)V.tau;
+                        Fp |= __ballot(m);
+                    }
                 }
+                const uint64_t cut = F & live & (no_parent | ~Fp);
+                word = lane == u ? cut : word;
             }
             if (lane < nvc) {
-                masks[(int64_t)(c0 + lane) * words + (i0 >> 6)] = word;
-                if (word) atomicAdd(&s_cnt[c0 + lane], (uint32_t)__popcll(word));
+                masks[(int64_t)(v0 + lane) * words + (i0 >> 6)] = word;
+                if (word) atomicAdd(&s_cnt[v0 + lane], (uint32_t)__popcll(word));
             }
         }
     }
@@ -311,11 +282,10 @@ __global__ void k_cut_finish(const uint32_t *__restrict__ block_offsets, int nbl
     if (v == nv) cut_base[nv] = *total;
 }
 
-void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *fmask, uint64_t *masks,
-                      uint32_t *block_counts, int nblocks, hipStream_t st)
+void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *masks, uint32_t *block_counts,
+                      int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cut_meets, dim3(nblocks), dim3(kCutThreads), 0, st, h, views, nv, fmask);
-    hipLaunchKernelGGL(k_cut_flags, dim3(nblocks), dim3(kCutThreads), 0, st, h, nv, fmask, masks, block_counts,
+    hipLaunchKernelGGL(k_cut_onepass, dim3(nblocks), dim3(kCutThreads), 0, st, h, views, nv, masks, block_counts,
                        nblocks);
 }
 
