@@ -288,6 +288,27 @@ def test_backward_queued_behind_busy_stream(r_c2s, c2s):
         assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a), k
 
 
+def test_second_backward_of_one_render_repeats_the_first(r_c2s, c2s):
+    # the forward clears the screen-gradient rows; a second backward of the
+    # same render clears them again instead of adding to the first one's
+    from paper_2406_12080_amd import hgs as H
+    views = [synth.look_at((0, -40, 1.7), (0, 0, 2.5), (0, 0, 1), 640, 360, 6.0),
+             synth.look_at((30, -30, 1.7), (0, 0, 2.5), (0, 0, 1), 1280, 720, 6.0)]
+    gen = torch.Generator(device="cpu").manual_seed(9)
+    dL = [torch.randn((v.height, v.width, 3), generator=gen).cuda() for v in views]
+    P = H.params_to_device(c2s)
+    r_c2s.render(views)
+    out = []
+    for _ in range(2):
+        grads = {k: torch.zeros_like(P[k]) for k in H.PARAM_FIELDS}
+        r_c2s.backward(dL, grads)
+        _sync()
+        out.append({k: g.cpu().numpy().astype(np.float64) for k, g in grads.items()})
+    for k in out[0]:
+        assert np.linalg.norm(out[0][k]) > 0
+        assert np.linalg.norm(out[0][k] - out[1][k]) <= 1e-5 * np.linalg.norm(out[0][k]), k
+
+
 def test_autograd_l1_matches_oracle(hgs_mod, c1):
     from paper_2406_12080_amd import hgs as H
     from paper_2406_12080_amd.autograd import render
