@@ -320,7 +320,7 @@ def main(argv=None):
                     avg_launch_ms=round(avg_ms, 4), flops_per_launch=int(flops),
                     other_kernels_avg_ms={"k_blend": round(ms_blend / max(n_blend, 1), 4),
                                           "k_blend_bwd": round(ms_bwd / max(n_bwd, 1), 4),
-                                          "k_preprocess_bwd": round(k_ms[hgs.K_PREPROCESS_BWD][0] /
+                                          "k_preprocess_bwd+k_grad_gather": round(k_ms[hgs.K_PREPROCESS_BWD][0] /
                                                                     max(k_ms[hgs.K_PREPROCESS_BWD][1], 1), 4)})
 
     cpu = None

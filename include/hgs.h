@@ -204,7 +204,8 @@ hgs_status hgs_set_tuning(hgs_ctx *ctx, int32_t tile_w, int32_t tile_h, int32_t 
  * the blend then runs right after the graph instead of inside it).
  * hgs_set_profiling resets the totals.  hgs_kernel_time synchronises and
  * returns the summed milliseconds and launch count of kernel `which`:
- * 0 blend, 1 blend backward, 2 preprocess backward. */
+ * 0 blend, 1 blend backward, 2 preprocess backward together with the
+ * gradient gather that follows it. */
 hgs_status hgs_set_profiling(hgs_ctx *ctx, int32_t on);
 hgs_status hgs_kernel_time(hgs_ctx *ctx, int32_t which, double *total_ms, int64_t *launches);
 

@@ -29,7 +29,7 @@ __device__ __forceinline__ int view_of(const uint32_t *cut_base, int nv, uint32_
     return lo;
 }
 
-__global__ __launch_bounds__(kT, 4) void k_preprocess(DevHier h, const DevView *__restrict__ views, int nv,
+__global__ __launch_bounds__(kT, 5) void k_preprocess(DevHier h, const DevView *__restrict__ views, int nv,
                                                    const uint32_t *__restrict__ cut_base,
                                                    const int32_t *__restrict__ cut_ids,
                                                    const double *__restrict__ cut_t,
