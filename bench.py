@@ -153,9 +153,68 @@ def optimize_steps(r, h, P, grads, imgs, dL, workload: str, steps: int) -> dict:
     taus = [v.tau for b in batches[warm:] for v in b]
     nv = len(batches[0])
     log(f"[bench] optimisation: {steps} steps, {dt * 1e3:.2f} ms/step")
+    # the Adam step alone (HBM-bound): per interior node and parameter the
+    # parameter, gradient and both moments are read and written once
+    n_adam = 10
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for s in range(n_adam):
+        r.adam_step(P, grads, M, V, ADAM_LR, n_step + 1 + s)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms_adam = ev[0].elapsed_time(ev[1]) / n_adam
+    per_node = sum(t.numel() for t in P.values()) // h.n_nodes
+    adam_bytes = (h.n_nodes - h.n_leaves) * per_node * 4 * 8
+    gbs = adam_bytes / (ms_adam * 1e-3) / 1e9
+    log(f"[bench] Adam step alone: {ms_adam:.3f} ms, {gbs:.0f} GB/s")
     return dict(steps=steps, warmup=warm, ms_per_step=round(dt * 1e3, 3), views_per_s=round(nv / dt, 3),
                 views_per_step=nv, tau_min=round(min(taus), 3), tau_max=round(max(taus), 3),
-                step="new eyes and tau per step; render + backward + Adam on the interior nodes")
+                step="new eyes and tau per step; render + backward + Adam on the interior nodes",
+                adam=dict(ms=round(ms_adam, 4), bytes=int(adam_bytes), gb_per_s=round(gbs, 1),
+                          frac_hbm=round(gbs / 8000.0, 4), launches_per_step=len(P),
+                          bytes_per_node=per_node * 32))
+
+
+# FP64 operations of one granularity evaluation (per interior node and view,
+# compares counted like arithmetic): per axis the extent, its running
+# maximum, the two-sided clamp of the eye to the box, the difference and its
+# square (6 x 3), the sum of squares (2), sqrt, f L and the division (3), and
+# the running maximum over the views (1)
+F_GRAN = 24
+
+
+def compaction(r, h, workload: str, n_views: int) -> dict:
+    """Time the GPU marking of the hierarchy compaction (Sec. 5.2) for
+    `n_views` training views of the workload (eyes drawn as for its batches),
+    tau from 3 px doubling up to half the image's larger side."""
+    from paper_2406_12080_amd import synth
+    cfg = WORKLOADS[workload]["config"]
+    views = []
+    s = 0
+    while len(views) < n_views:
+        views += synth.make_views(cfg, seed=50000 + s, headline=True)
+        s += 1
+    views = views[:n_views]
+    tau_max = 0.5 * max(max(v.width, v.height) for v in views)
+    keep = r.compact_mark(views, 3.0, tau_max)  # warm-up (allocates its buffer)
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        keep = r.compact_mark(views, 3.0, tau_max)  # synchronises
+    dt = (time.perf_counter() - t0) / reps
+    kept = int(keep.sum().item())
+    levels = 0
+    t = 3.0
+    while t <= tau_max:
+        levels += 1
+        t *= 2.0
+    evals = (h.n_nodes - h.n_leaves) * n_views
+    tflops = evals * F_GRAN / dt / 1e12
+    log(f"[bench] compaction marking: {n_views} views, {dt * 1e3:.2f} ms, kept {kept} of {h.n_nodes}")
+    return dict(views=n_views, tau_min=3.0, tau_max=tau_max, levels=levels, ms=round(dt * 1e3, 3),
+                nodes=h.n_nodes, kept=kept, node_view_evals_per_s=round(evals / dt, 1),
+                roofline=dict(bound="alu", achieved=round(tflops, 3), peak=78.6, unit="TFLOP/s (FP64)",
+                              frac=round(tflops / 78.6, 4), flops_per_eval=F_GRAN))
 
 
 def kernel_source_sha() -> str:
@@ -192,6 +251,9 @@ def main(argv=None):
                     help="also time K steps of the hierarchy optimisation (corridor workloads): every step new "
                          "eyes and tau log-uniform over the workload's range, render, backward and an Adam step "
                          "on the interior nodes (reported under 'optimize'; `value` stays the fwd+bwd step)")
+    ap.add_argument("--compact", type=int, default=0, metavar="V",
+                    help="also time the GPU marking of the hierarchy compaction over V training views "
+                         "(reported under 'compaction')")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size transfer that calibrates "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
@@ -301,6 +363,9 @@ def main(argv=None):
     opt = None
     if args.optimize > 0:
         opt = optimize_steps(r, h, P, grads, imgs, dL, args.workload, args.optimize)
+    cmp = None
+    if args.compact > 0:
+        cmp = compaction(r, h, args.workload, args.compact)
 
     # roofline of the dominant kernel (the longer of blend and blend backward)
     ms_blend, n_blend = k_ms[hgs.K_BLEND]
@@ -358,6 +423,8 @@ def main(argv=None):
     }
     if opt is not None:
         out["optimize"] = opt
+    if cmp is not None:
+        out["compaction"] = cmp
     print(json.dumps(out), flush=True)
     r.close()
 

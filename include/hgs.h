@@ -128,6 +128,26 @@ typedef struct {
 hgs_status hgs_cut(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *out_t, int64_t capacity,
                    int64_t *out_count);
 
+/* Hierarchy compaction (Sec. 5.2, "Compacting the Hierarchy"): marks the
+ * nodes that survive the sparsification for a set of (training) views.  With
+ * the granularity ladder tau_i = tau_min 2^i for every i with tau_i <=
+ * tau_max (the paper: tau_min = 3 px, tau_max = half the image resolution),
+ * a node is kept when it is a leaf, when it is a bottom-most node of the
+ * union of the views' cuts (Sec. 4.2) at some tau_i, or when it lies above
+ * the last of these cuts; every other node lies between two kept levels and
+ * is removed.  Only the views' eye and fx, fy enter (their tau and image
+ * size are not used, but must be valid as for hgs_render); any number of
+ * views (processed in batches of 1024).  keep (device, uint8[n_nodes])
+ * receives 1 (kept) or 0.  The decisions use the cut's FP64 granularity, so
+ * they match it bit for bit.  tau_min <= 0, non-finite taus or more than 64
+ * levels: HGS_ERR_INVALID_ARG; with no level (tau_min > tau_max) every node
+ * is kept.  Invalidates the state kept for hgs_render_backward.
+ * Synchronises the ctx stream.  Rebuilding the tree from the flags (each
+ * kept node's parent becomes its nearest kept ancestor, so a node may get
+ * more than 8 children) is host work: paper_2406_12080_amd.compact. */
+hgs_status hgs_compact_mark(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, float tau_min, float tau_max,
+                            uint8_t *keep);
+
 typedef struct {
     int64_t cut;        /* cut nodes, all views */
     int64_t visible;    /* splats with a non-empty footprint */

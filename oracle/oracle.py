@@ -282,3 +282,52 @@ def adam_step(params: dict, grads: dict, m: dict, v: dict, interior: np.ndarray,
         params[name][interior] = np.asarray(params[name], np.float64)[interior] - \
             rate * (mm / c1) / (np.sqrt(vv / c2) + eps)
         grads[name][interior] = 0.0
+
+
+def compact_keep(h, views, tau_min: float = 3.0, tau_max: float | None = None) -> np.ndarray:
+    """Keep flags of the hierarchy compaction, Sec. 5.2 "Compacting the
+    Hierarchy", taken step by step: the leaves start out marked; for tau =
+    tau_min, 2 tau_min, ... while tau <= tau_max (default: half the largest
+    image side), the union of the views' cuts (Sec. 4.2) is formed, its
+    bottom-most nodes (those with no descendant in the union) are found, every
+    node between one of them and the already marked nodes below it is
+    removed, and they are marked.  The taus are the FP32 arguments widened to
+    FP64, doubled exactly."""
+    H = _H(h)
+    n = H.n
+    parent = np.asarray(h.parent, np.int64)
+    cb = np.asarray(h.child_begin, np.int64)
+    cc = np.asarray(h.child_count, np.int64)
+    views = list(views)
+    if tau_max is None:
+        tau_max = 0.5 * max(max(v.width, v.height) for v in views)
+    marked = cc == 0
+    removed = np.zeros(n, bool)
+    tau = float(np.float32(tau_min))
+    top = float(np.float32(tau_max))
+    while tau <= top:
+        union = np.zeros(n, bool)
+        for v in views:
+            ids, _ = cut(H, v.replace(tau=tau))
+            union[ids] = True
+        # nodes with a descendant in the union: every proper ancestor of a
+        # union node (a walk stops where an earlier one already passed)
+        has_desc = np.zeros(n, bool)
+        for m in np.nonzero(union)[0]:
+            p = parent[m]
+            while p >= 0 and not has_desc[p]:
+                has_desc[p] = True
+                p = parent[p]
+        bottom = union & ~has_desc
+        for b in np.nonzero(bottom)[0]:
+            stack = list(range(cb[b], cb[b] + cc[b]))
+            while stack:
+                c = stack.pop()
+                if marked[c]:
+                    continue
+                removed[c] = True
+                stack.extend(range(cb[c], cb[c] + cc[c]))
+        assert not (removed & bottom).any()
+        marked |= bottom
+        tau *= 2.0
+    return ~removed

@@ -67,6 +67,8 @@ struct hgs_ctx {
     uint64_t layout_gen = 1;
     std::vector<void *> allocs;
     DevView *views_dev = nullptr;
+    double *cmp_emax = nullptr;  // compaction: per-node maximum granularity over the views
+    int64_t cmp_emax_n = 0;
     DevView *views_host = nullptr;  // host records of the current views (pageable, changed freely)
     // pinned staging slots of the asynchronous view copies: a slot is reused
     // only after the copy that reads it has run (its event)
@@ -791,6 +793,41 @@ hgs_status hgs_cut(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *
     if (*out_count > 0)
         launch_cut_emit(h, ctx->views_dev, 1, ctx->masks, ctx->blk_offsets, nb, ctx->word_off, out_ids, out_t, nullptr,
                         (uint32_t)capacity, st);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(st));
+    return HGS_OK;
+}
+
+hgs_status hgs_compact_mark(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, float tau_min, float tau_max,
+                            uint8_t *keep)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy uploaded");
+    if (!views || n_views <= 0 || !keep) return fail(ctx, HGS_ERR_INVALID_ARG, "bad views / n_views / keep");
+    if (!std::isfinite(tau_min) || !std::isfinite(tau_max) || !(tau_min > 0.0f))
+        return fail(ctx, HGS_ERR_INVALID_ARG, "tau_min must be positive and finite, tau_max finite");
+    int levels = 0;
+    for (double t = tau_min; t <= (double)tau_max; t *= 2.0)
+        if (++levels > 64) return fail(ctx, HGS_ERR_INVALID_ARG, "more than 64 granularity levels");
+    HIPC(hipSetDevice(ctx->device));
+    ctx->have_render = false;  // the view records are replaced
+    hgs_status s;
+    if (ctx->cmp_emax_n != ctx->n) {
+        if ((s = realloc_buf(ctx, ctx->cmp_emax, (size_t)ctx->n))) return s;
+        ctx->cmp_emax_n = ctx->n;
+    }
+    hipStream_t st = ctx->stream;
+    const DevHier h = dev_hier(ctx);
+    for (int v0 = 0; v0 < n_views; v0 += kMaxViews) {
+        const int nb = std::min(kMaxViews, n_views - v0);
+        uint32_t n_tiles;
+        size_t n_pix;
+        if ((s = setup_views(ctx, views + v0, nb, nullptr, n_tiles, n_pix))) return s;
+        if ((s = push_views(ctx, nb, st))) return s;
+        launch_compact_emax(h, ctx->views_dev, nb, v0 == 0, ctx->cmp_emax, st);
+        HIPC(hipGetLastError());
+    }
+    launch_compact_keep(h, ctx->cmp_emax, (double)tau_min, levels, keep, st);
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(st));
     return HGS_OK;

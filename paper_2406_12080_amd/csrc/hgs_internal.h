@@ -91,6 +91,12 @@ constexpr int kCutItems = 4;
 constexpr int kCutBlock = kCutThreads * kCutItems;  // nodes per block
 // masks: one bit per (view, node), words * nv; block_counts: per view and
 // block of kCutBlock nodes.
+// Hierarchy compaction: per-node maximum of eps over a batch of views
+// (first batch: written, else folded in), then the keep flags for the
+// granularity ladder tau_min 2^i, i < levels.
+void launch_compact_emax(const DevHier &h, const DevView *views, int nv, bool first, double *emax, hipStream_t st);
+void launch_compact_keep(const DevHier &h, const double *emax, double tau_min, int levels, uint8_t *keep,
+                         hipStream_t st);
 void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *masks, uint32_t *block_counts,
                       int nblocks, hipStream_t st);
 // Also writes word_off[v][w]: the cut position of the first selected node of

@@ -282,6 +282,77 @@ __global__ void k_cut_finish(const uint32_t *__restrict__ block_offsets, int nbl
     if (v == nv) cut_base[nv] = *total;
 }
 
+// Hierarchy compaction (Sec. 5.2, "Compacting the Hierarchy").  For a set
+// of views and the granularity ladder tau_i = tau_min 2^i <= tau_max, the
+// nodes that the paper keeps are the leaves, the bottom-most nodes of the
+// union of the views' cuts at every tau_i, and the nodes above the last of
+// these.  A node of the union has a descendant in it exactly when some view
+// finds the node too coarse (that view's cut then lies below it), so the
+// bottom-most nodes at tau are the cut of G(n) = "every view meets tau at n":
+// n with G(n) and not G(parent).  With e(n) = max over the views of eps(n)
+// (the same FP64 evaluation as the cut), G(n) is e(n) <= tau for an interior
+// node, so one sweep over the views gives every level.
+//
+// k_node_emax: e(n) over one batch of views, folded into emax (first batch:
+// written).  Leaves are not evaluated (they always meet tau).
+__global__ __launch_bounds__(kCutThreads) void k_node_emax(DevHier h, const DevView *__restrict__ views, int nv,
+                                                           int first, double *__restrict__ emax)
+{
+    const int64_t i = (int64_t)blockIdx.x * kCutThreads + threadIdx.x;
+    if (i >= h.n) return;
+    if (h.pinfo[i] & kLeafBit) {
+        emax[i] = 0.0;
+        return;
+    }
+    float b[6];
+    load_box(h, i, b);
+    double e = first ? 0.0 : emax[i];
+    for (int v = 0; v < nv; ++v) {
+        const double g = granularity(b, views[v]);
+        e = g > e ? g : e;
+    }
+    emax[i] = e;
+}
+
+// keep[n] = 1 for a leaf, a node with e(n) <= tau_i < e(parent) for some
+// level i (the root: e(n) <= tau_i), or a node with e(n) > tau_last; with no
+// level at all (tau_min > tau_max) every node is kept.
+__global__ __launch_bounds__(kCutThreads) void k_compact_keep(DevHier h, const double *__restrict__ emax,
+                                                              double tau_min, int levels, uint8_t *__restrict__ keep)
+{
+    const int64_t i = (int64_t)blockIdx.x * kCutThreads + threadIdx.x;
+    if (i >= h.n) return;
+    const uint32_t pi = h.pinfo[i];
+    if ((pi & kLeafBit) || levels == 0) {
+        keep[i] = 1;
+        return;
+    }
+    const uint32_t par = pi & ~kLeafBit;
+    const bool root = par == kRootParent;
+    const double en = emax[i], ep = root ? 0.0 : emax[par];
+    bool k = false;
+    double tau = tau_min;
+    for (int l = 0; l < levels; ++l) {
+        k |= en <= tau && (root || !(ep <= tau));
+        if (l + 1 < levels) tau *= 2.0;
+    }
+    k |= !(en <= tau);
+    keep[i] = k ? 1 : 0;
+}
+
+void launch_compact_emax(const DevHier &h, const DevView *views, int nv, bool first, double *emax, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_node_emax, dim3((uint32_t)((h.n + kCutThreads - 1) / kCutThreads)), dim3(kCutThreads), 0,
+                       st, h, views, nv, first ? 1 : 0, emax);
+}
+
+void launch_compact_keep(const DevHier &h, const double *emax, double tau_min, int levels, uint8_t *keep,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL(k_compact_keep, dim3((uint32_t)((h.n + kCutThreads - 1) / kCutThreads)), dim3(kCutThreads),
+                       0, st, h, emax, tau_min, levels, keep);
+}
+
 void launch_cut_flags(const DevHier &h, const DevView *views, int nv, uint64_t *masks, uint32_t *block_counts,
                       int nblocks, hipStream_t st)
 {

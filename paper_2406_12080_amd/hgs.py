@@ -19,7 +19,7 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_CAPACITY = range(6)
 _NAMES = {0: "HGS_OK", 1: "HGS_ERR_INVALID_ARG", 2: "HGS_ERR_OOM", 3: "HGS_ERR_HIP", 4: "HGS_ERR_STATE",
           5: "HGS_ERR_CAPACITY"}
 EXPORTS = ("hgs_create", "hgs_destroy", "hgs_last_error", "hgs_set_stream", "hgs_upload", "hgs_bind_params",
-           "hgs_cut", "hgs_render", "hgs_render_backward", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer",
+           "hgs_cut", "hgs_compact_mark", "hgs_render", "hgs_render_backward", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer",
            "hgs_set_profiling", "hgs_kernel_time", "hgs_counters")
 COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t", "bwd_evaluated",
                  "bwd_evaluated_t", "bwd_contrib")
@@ -91,6 +91,7 @@ def lib():
         L.hgs_upload.argtypes = [vp, P(HierarchyDesc), c_int]
         L.hgs_bind_params.argtypes = [vp, vp, vp, vp, vp, vp]
         L.hgs_cut.argtypes = [vp, P(View), vp, vp, ctypes.c_int64, P(ctypes.c_int64)]
+        L.hgs_compact_mark.argtypes = [vp, P(View), ctypes.c_int32, ctypes.c_float, ctypes.c_float, vp]
         L.hgs_render.argtypes = [vp, P(View), ctypes.c_int32, P(vp), P(Stats)]
         L.hgs_render_backward.argtypes = [vp, P(vp), P(Grads)]
         L.hgs_adam_step.argtypes = [vp, P(Adam)]
@@ -226,6 +227,20 @@ class Renderer:
         self._check(self.L.hgs_cut(self.h, ctypes.byref(hv), ctypes.c_void_p(ids.data_ptr()),
                                    ctypes.c_void_p(t.data_ptr()), cap, ctypes.byref(cnt)))
         return ids[:cnt.value], t[:cnt.value]
+
+    def compact_mark(self, views, tau_min: float = 3.0, tau_max: float | None = None):
+        """Keep flags of the hierarchy compaction (``hgs_compact_mark``) for
+        these views: a bool CUDA tensor over the nodes.  ``tau_max`` defaults
+        to half the largest image side."""
+        torch = self.torch
+        views = list(views)
+        if tau_max is None:
+            tau_max = 0.5 * max(max(v.width, v.height) for v in views)
+        arr = (View * len(views))(*[make_view(v) for v in views])
+        keep = torch.empty(max(self.n_nodes, 1), dtype=torch.uint8, device=self.device)
+        self._check(self.L.hgs_compact_mark(self.h, arr, len(views), float(tau_min), float(tau_max),
+                                            ctypes.c_void_p(keep.data_ptr())))
+        return keep[:self.n_nodes].bool()
 
     # -- render ----------------------------------------------------------------
     def render(self, views, out=None, timed: bool = False):
