@@ -294,7 +294,25 @@ __global__ void k_cut_finish(const uint32_t *__restrict__ block_offsets, int nbl
 // node, so one sweep over the views gives every level.
 //
 // k_node_emax: e(n) over one batch of views, folded into emax (first batch:
-// written).  Leaves are not evaluated (they always meet tau).
+// written).  Leaves are not evaluated (they always meet tau).  L is the
+// node's own, so the view of largest eps is the one of largest (f / d)^2: a
+// first pass finds that ratio in FP32, and only views within a relative
+// kEmaxBand of it (or with d^2 too small for FP32, where eps may be +inf)
+// get the FP64 evaluation, whose maximum is therefore the exact one: the
+// FP32 ratio is off by a few units in the last place, far inside the band.
+constexpr float kEmaxBand = 2e-5f;
+
+__device__ __forceinline__ float view_ratio(const float b[6], const DevView &V, float &d2)
+{
+    const float ex = V.eye[0], ey = V.eye[1], ez = V.eye[2];
+    const float dx = ex - __builtin_amdgcn_fmed3f(ex, b[0], b[3]);
+    const float dy = ey - __builtin_amdgcn_fmed3f(ey, b[1], b[4]);
+    const float dz = ez - __builtin_amdgcn_fmed3f(ez, b[2], b[5]);
+    d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float f = fmaxf(V.fx, V.fy);
+    return f * f * __builtin_amdgcn_rcpf(d2);
+}
+
 __global__ __launch_bounds__(kCutThreads) void k_node_emax(DevHier h, const DevView *__restrict__ views, int nv,
                                                            int first, double *__restrict__ emax)
 {
@@ -306,10 +324,21 @@ __global__ __launch_bounds__(kCutThreads) void k_node_emax(DevHier h, const DevV
     }
     float b[6];
     load_box(h, i, b);
+    float best = 0.0f;
+    for (int v = 0; v < nv; ++v) {
+        float d2;
+        const float r = view_ratio(b, views[v], d2);
+        if (d2 >= 1e-18f) best = fmaxf(best, r);
+    }
+    const float thr = best * (1.0f - kEmaxBand);
     double e = first ? 0.0 : emax[i];
     for (int v = 0; v < nv; ++v) {
-        const double g = granularity(b, views[v]);
-        e = g > e ? g : e;
+        float d2;
+        const float r = view_ratio(b, views[v], d2);
+        if (d2 < 1e-18f || r >= thr) {
+            const double g = granularity(b, views[v]);
+            e = g > e ? g : e;
+        }
     }
     emax[i] = e;
 }
