@@ -40,7 +40,13 @@ WORKLOADS = {
 DEFAULT = "corridor30m_32x1080p_tau6"
 
 # Algorithmic FP32 operations per (pixel, splat) pair of the blend kernels
-# (transcendentals counted as one); see the design notes for the breakdown.
+# (transcendentals and compares counted as one): an evaluation takes 15 (the
+# pixel's offsets on the two axes 4, the quadratic form 3, exp2 1, A G 1,
+# the 0.99 clamp 1, two compares, T (1 - alpha) 2) and 11 more when t > 0
+# (the parent's term, log2, multiply, exp2, 1 - x, the lerp); a blended pair
+# 10 more (alpha T, three colour FMAs, the T update, bookkeeping).  The
+# backward re-evaluates (15, +11) and takes 47 per contributing pair (+10
+# when t > 0: the alpha' chain).
 F_EVAL, F_EVAL_T, F_BLEND = 15, 11, 10
 F_BWD_CONTRIB, F_BWD_CONTRIB_T = 47, 10
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU, 2.4 GHz)
@@ -260,9 +266,9 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(views shard across GPUs with no communication in the forward; see the design notes)",
-              file=sys.stderr)
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(views would shard across GPUs with no communication in the forward and one reduction of "
+              "interior-node gradients per step, which is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
