@@ -111,7 +111,19 @@ def cpu_baseline(h, view, row_stride: int = 1):
                 sample=(f"1 view of the batch ({view.width}x{view.height}, tau={view.tau:g}): cut ({len(ids)} nodes, "
                         f"{t_cut:.2f}s), forward ({t_render:.2f}s) and backward ({t_bwd:.2f}s) over {what}; FP64 "
                         f"widening of the hierarchy ({t_prep:.1f}s) not counted"),
-                seconds=dict(cut=t_cut, render=t_render, backward=t_bwd, full_view_estimate=t_view))
+                seconds=dict(cut=t_cut, render=t_render, backward=t_bwd, full_view_estimate=t_view),
+                cpu_model=cpu_model())
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # Learning rates per parameter group for the timed optimisation steps (the
