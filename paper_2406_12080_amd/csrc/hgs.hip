@@ -976,7 +976,8 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_gr
         KernelTimer kt(ctx, 1, st);
         launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs,
                               ctx->axes, ctx->T_final,
-                              ctx->n_last, ctx->vis_rank, ctx->sgrad, ctx->wstats, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch, st);
+                              ctx->n_last, ctx->vis_rank, ctx->sgrad, ctx->wstats, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch,
+                              out->dt != nullptr, st);
     }
     const DevHier h = dev_hier(ctx);
     {

@@ -192,7 +192,7 @@ void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const
                            const uint2 *ranges,
                            const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                            const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
-                           Counters *ctr, int tw, int th, int batch, hipStream_t st);
+                           Counters *ctr, int tw, int th, int batch, bool want_dt, hipStream_t st);
 void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32_t vis_cap, hipStream_t st);
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,

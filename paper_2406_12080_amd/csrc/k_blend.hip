@@ -26,7 +26,7 @@ namespace hgs {
 namespace {
 
 struct AlphaEval {
-    float G, an, ap, apr, alpha, u1, u2;
+    float G, an, ap, apr, q, alpha, u1, u2;  // q = (1 - a_p)^(1/K), apr = 1 - q
     bool cn, cp;
 };
 
@@ -62,12 +62,14 @@ __device__ __forceinline__ void eval_alpha(const float4 &W, const float4 &O, flo
     e.alpha = e.an;
     e.ap = 0.0f;
     e.apr = 0.0f;
+    e.q = 1.0f;
     e.cp = false;
     if (interp) {
         const float ap = O.y * e.G;
         e.cp = ap > kAlphaMax;
         e.ap = fminf(ap, kAlphaMax);
-        e.apr = 1.0f - __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(1.0f - e.ap) * O.w);
+        e.q = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(1.0f - e.ap) * O.w);
+        e.apr = 1.0f - e.q;
         e.alpha = (1.0f - O.z) * e.an + O.z * e.apr;
     }
 }
@@ -297,10 +299,12 @@ __device__ __forceinline__ float swap_add16(float x, float y)
 // l ^ 8, then l ^ 7, each keeping one of two values), and a sum over the
 // quad (l ^ 2, l ^ 1).  Every lane of quad q = l >> 2 ends with the total of
 // value wave_slot(l) (-1: nothing).
+template <bool DT>
 __device__ __forceinline__ float wave_reduce11(const float (&v)[11], int lane)
 {
     const float S0 = swap_add32(v[0], v[1]), S1 = swap_add32(v[2], v[3]), S2 = swap_add32(v[4], v[5]);
-    const float S3 = swap_add32(v[6], v[7]), S4 = swap_add32(v[8], v[9]), S5 = swap_add32(v[10], 0.0f);
+    const float S3 = swap_add32(v[6], v[7]), S4 = swap_add32(v[8], v[9]);
+    const float S5 = DT ? swap_add32(v[10], 0.0f) : 0.0f;  // slot 10 (dL/dt) only when asked for
     // rows 0..3 of Z0: v0 v2 v1 v3; Z1: v4 v6 v5 v7; Z2: v8 v10 v9 -
     const float Z0 = swap_add16(S0, S1), Z1 = swap_add16(S2, S3), Z2 = swap_add16(S4, S5);
     const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
@@ -326,7 +330,7 @@ constexpr int kG = 12;  // floats per splat in the screen-space gradient
 //   2..4   Q11, Q12, Q22 = h u1 u1, h u1 u2, h u2 u2
 //   5, 6   dL/dA_n, dL/dA_p (A = kappa |o|)
 //   7..9   dL/d colour
-//   10     dL/dt through alpha
+//   10     dL/dt through alpha (only when the caller asks for dL/dt)
 // The screen-space gradient follows from the tile sums by the splat's
 // (per-tile constant) axes: with g = conic d = (u1 w1 + u2 w2) / kHalfLog2e
 // and G = exp(-q/2), dL/dmean = sum h g and dL/dSigma2' = -sum (h / 2) g g^T
@@ -345,7 +349,7 @@ __device__ __forceinline__ void screen_grad(const float4 &W, const float *sg, do
     out[4] = 0.5 * k * k * (wy * wy * Q11 + 2.0 * wy * ww * Q12 + ww * ww * Q22);
 }
 
-template <int TW, int TH, int BATCH>
+template <int TW, int TH, int BATCH, bool DT>
 __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict__ views, int nv,
                                                       const uint32_t *__restrict__ tile_order,
                                                       const uint2 *__restrict__ ranges,
@@ -460,8 +464,9 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
             if (interp) {
                 dan = (1.0f - Ov.z) * dal;
                 const float dapr = Ov.z * dal;
-                v[10] = (e.apr - e.an) * dal;
-                dap = dapr * Ov.w * __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(1.0f - e.ap) * (Ov.w - 1.0f));
+                if constexpr (DT) v[10] = (e.apr - e.an) * dal;
+                // d apr / d a_p = (1/K) (1 - a_p)^(1/K - 1) = (1/K) q / (1 - a_p)
+                dap = dapr * Ov.w * (e.q * __builtin_amdgcn_rcpf(1.0f - e.ap));
             }
             const float dan_c = e.cn ? 0.0f : dan, dap_c = e.cp ? 0.0f : dap;
             v[5] = dan_c * e.G;
@@ -472,7 +477,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
             v[2] = v[0] * e.u1;
             v[3] = v[0] * e.u2;
             v[4] = v[1] * e.u2;
-            const float tot = wave_reduce11(v, lane);
+            const float tot = wave_reduce11<DT>(v, lane);
             if (writer && tot != 0.0f) {
                 if constexpr (NW == 1) s_g[j][slot] = tot;
                 else atomicAdd(&s_g[j][slot], tot);
@@ -555,15 +560,19 @@ template <int TW, int TH, int BATCH>
 void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                         const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                         const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
-                        hipStream_t st)
+                        bool want_dt, hipStream_t st)
 {
     // the backward stages at most 32 splats per wave and step: its LDS holds
     // the FP32 partial sums and the FP64 flushed terms of every staged
     // splat, and a smaller footprint keeps more tiles resident per CU
     constexpr int BMAX = 32 * (TW * TH / 64);
     constexpr int B = BATCH < BMAX ? BATCH : BMAX;
-    hipLaunchKernelGGL((k_blend_bwd<TW, TH, B>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order, ranges,
-                       pair_vals, recs, axes, T_final, n_last, vis_rank, sgrad, wstats);
+    if (want_dt)
+        hipLaunchKernelGGL((k_blend_bwd<TW, TH, B, true>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order,
+                           ranges, pair_vals, recs, axes, T_final, n_last, vis_rank, sgrad, wstats);
+    else
+        hipLaunchKernelGGL((k_blend_bwd<TW, TH, B, false>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order,
+                           ranges, pair_vals, recs, axes, T_final, n_last, vis_rank, sgrad, wstats);
 }
 
 }  // namespace
@@ -611,14 +620,14 @@ void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order,
                            const uint2 *ranges, const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                            const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
-                           Counters *ctr, int tw, int th, int batch, hipStream_t st)
+                           Counters *ctr, int tw, int th, int batch, bool want_dt, hipStream_t st)
 {
     if (batch == 0) batch = tw * th;
     if (!n_tiles) return;
 #define X(a, b, c)                                                                                                 \
     if (tw == a && th == b && batch == c) {                                                                        \
         launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last,    \
-                                    vis_rank, sgrad, wstats, st);                                                  \
+                                    vis_rank, sgrad, wstats, want_dt, st);                                         \
         hipLaunchKernelGGL(k_stats_reduce, dim3(256), dim3(256), 0, st, wstats,                                    \
                            n_tiles * (uint32_t)(tw * th / 64), &ctr->bwd_evaluated);                               \
         return;                                                                                                    \

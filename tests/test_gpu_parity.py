@@ -309,6 +309,31 @@ def test_second_backward_of_one_render_repeats_the_first(r_c2s, c2s):
         assert np.linalg.norm(out[0][k] - out[1][k]) <= 1e-5 * np.linalg.norm(out[0][k]), k
 
 
+def test_gradients_without_dt_equal_those_with_it(r_c2s, c2s):
+    # without a dL/dt output the blend backward drops that slot; every
+    # parameter gradient stays what it is with it (up to the order of the
+    # FP64 atomic sums)
+    from paper_2406_12080_amd import hgs as H
+    views = [synth.look_at((0, -40, 1.7), (0, 0, 2.5), (0, 0, 1), 640, 360, 3.0),
+             synth.look_at((30, -30, 1.7), (0, 0, 2.5), (0, 0, 1), 1280, 720, 6.0)]
+    gen = torch.Generator(device="cpu").manual_seed(21)
+    dL = [torch.randn((v.height, v.width, 3), generator=gen).cuda() for v in views]
+    P = H.params_to_device(c2s)
+    _, st = r_c2s.render(views)
+    out = []
+    for with_dt in (True, False):
+        grads = {k: torch.zeros_like(P[k]) for k in H.PARAM_FIELDS}
+        dt = torch.zeros(st["cut"], device="cuda") if with_dt else None
+        r_c2s.backward(dL, grads, dt)
+        _sync()
+        if with_dt:
+            assert float(dt.abs().sum()) > 0
+        out.append({k: g.cpu().numpy().astype(np.float64) for k, g in grads.items()})
+    for k in out[0]:
+        assert np.linalg.norm(out[0][k]) > 0
+        assert np.linalg.norm(out[0][k] - out[1][k]) <= 1e-6 * np.linalg.norm(out[0][k]), k
+
+
 def test_autograd_l1_matches_oracle(hgs_mod, c1):
     from paper_2406_12080_amd import hgs as H
     from paper_2406_12080_amd.autograd import render
