@@ -235,6 +235,61 @@ def compaction(r, h, workload: str, n_views: int) -> dict:
                               frac=round(tflops / 78.6, 4), flops_per_eval=F_GRAN))
 
 
+# scale and opacity are stored activated (metres, |o|), so their steps are
+# smaller than the 3DGS rates for the pre-activation values
+CONVERGE_LR = dict(mean=1e-3, scale=5e-4, rot=1e-3, opacity=5e-3, sh=2.5e-3)
+
+
+def converge(r, h, views, steps: int) -> dict:
+    """Convergence of the hierarchy optimisation (Sec. 5.1) on the
+    workload's views, posed as the differentiation workload is: the targets
+    are the images of the hierarchy as generated; the interior nodes' means,
+    log-scales and SH coefficients are then perturbed by N(0, 0.05), and
+    `steps` steps of render, L1 loss, backward and Adam on the interior nodes
+    (leaves frozen) pull the images back.  Returns the loss along the way.
+    Binds a fresh copy of the hierarchy's parameters."""
+    import torch
+    from paper_2406_12080_amd import hgs
+    P = hgs.params_to_device(h)
+    r.bind(*[P[k] for k in hgs.PARAM_FIELDS])
+    dev = P["mean"].device
+    imgs, _ = r.render(views)
+    tgt = [o.clone() for o in imgs]
+    interior = torch.from_numpy(h.child_count > 0).to(dev)
+    gen = torch.Generator(device="cpu").manual_seed(4)
+
+    def noise(t):
+        return torch.randn(t.shape, generator=gen).to(dev) * 0.05
+
+    with torch.no_grad():
+        P["mean"] += noise(P["mean"]) * interior[:, None]
+        P["scale"] *= torch.exp(noise(P["scale"]) * interior[:, None])
+        P["sh"] += noise(P["sh"]) * interior[:, None]
+    M = {k: torch.zeros_like(t) for k, t in P.items()}
+    V = {k: torch.zeros_like(t) for k, t in P.items()}
+    grads = {k: torch.zeros_like(t) for k, t in P.items()}
+    n_val = sum(t.numel() for t in tgt)
+    losses = []
+    t0 = time.perf_counter()
+    for s in range(steps + 1):
+        imgs, _ = r.render(views, out=imgs)
+        with torch.no_grad():
+            diffs = [i - t for i, t in zip(imgs, tgt)]
+            losses.append(sum(float(d.abs().sum()) for d in diffs) / n_val)
+            dL = [torch.sign(d) / n_val for d in diffs]
+        if s == steps:
+            break
+        r.backward(dL, grads)
+        r.adam_step(P, grads, M, V, CONVERGE_LR, s + 1)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    marks = sorted({0, steps} | {steps * k // 10 for k in range(1, 10)})
+    log(f"[bench] convergence: L1 {losses[0]:.6f} -> {losses[-1]:.6f} in {steps} steps ({dt * 1e3:.2f} ms/step)")
+    return dict(steps=steps, ms_per_step=round(dt * 1e3, 3), lr=CONVERGE_LR, perturbation=0.05,
+                l1_unperturbed=0.0, l1={str(k): round(losses[k], 7) for k in marks},
+                reduction=round(losses[-1] / max(losses[0], 1e-30), 4))
+
+
 def kernel_source_sha() -> str:
     p = os.path.join(ROOT, "paper_2406_12080_amd", "csrc", "k_blend.hip")
     with open(p, "rb") as f:
@@ -272,6 +327,9 @@ def main(argv=None):
     ap.add_argument("--compact", type=int, default=0, metavar="V",
                     help="also time the GPU marking of the hierarchy compaction over V training views "
                          "(reported under 'compaction')")
+    ap.add_argument("--converge", type=int, default=0, metavar="K",
+                    help="also K steps of the hierarchy optimisation against targets rendered before the interior "
+                         "nodes are perturbed (L1 loss reported under 'convergence')")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size transfer that calibrates "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
@@ -384,6 +442,9 @@ def main(argv=None):
     cmp = None
     if args.compact > 0:
         cmp = compaction(r, h, args.workload, args.compact)
+    conv = None
+    if args.converge > 0:
+        conv = converge(r, h, views, args.converge)
 
     # roofline of the dominant kernel (the longer of blend and blend backward)
     ms_blend, n_blend = k_ms[hgs.K_BLEND]
@@ -443,6 +504,8 @@ def main(argv=None):
         out["optimize"] = opt
     if cmp is not None:
         out["compaction"] = cmp
+    if conv is not None:
+        out["convergence"] = conv
     print(json.dumps(out), flush=True)
     r.close()
 
