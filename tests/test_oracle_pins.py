@@ -259,6 +259,46 @@ def test_stacked_identical_splats_transmittance_product(N):
     assert abs(T[8, 8] - (1 - a) ** m) < 1e-13
 
 
+@pytest.mark.parametrize("N", [3, 40])
+def test_backward_stacked_splats_closed_form(N):
+    # N identical splats at one depth, cotangent 1 on the red channel of the
+    # centre pixel: splat i (1-based in compositing order, node id breaking
+    # the depth tie) has T_i = (1-a)^(i-1) and colour c behind it composited
+    # to R_i = c (1 - (1-a)^(m-i)), so dC/dc_i = a T_i and dC/da_i =
+    # T_i (c - R_i) = c (1-a)^(m-1) for the m blended splats, 0 after them;
+    # c_r = C0 sh_0 + 1/2 (unclamped) and a = o kappa G (below 0.99)
+    f, z, s, o = 40.0, 4.0, 0.3, 0.35
+    sh = np.zeros(48)
+    sh[0:3] = [0.3, 0.1, -0.2]
+    Nn = N + 1
+    h = S.hierarchy([-1] + [0] * N, np.tile([[0.0, 0.0, z]], (Nn, 1)), np.tile([[s, s, s]], (Nn, 1)),
+                    np.tile([[1, 0, 0, 0]], (Nn, 1)), np.full(Nn, o), np.tile(sh, (Nn, 1)))
+    v = S.axis_view(16, 16, f, tau=0.0)
+    ids, t = O.cut(h, v)
+    w = np.zeros((16 * 16, 3))
+    w[8 * 16 + 8, 0] = 1.0
+    g = O.backward(h, v, ids, t, w)["grad"]
+    s, o = float(np.float32(s)), float(np.float32(o))
+    sig2d = (f * s / z) ** 2 + 0.3
+    kappa = (f * s / z) ** 2 / sig2d
+    G = math.exp(-0.5 / (2 * sig2d))
+    a = o * kappa * G
+    assert a < 0.99
+    m = 0
+    Tm = 1.0
+    while m < N and Tm * (1 - a) >= 1e-4:
+        Tm *= 1 - a
+        m += 1
+    assert (m == N) == (N == 3)
+    c = C0 * float(np.float32(0.3)) + 0.5
+    for i in range(1, Nn):
+        blended = i <= m
+        dc = a * (1 - a) ** (i - 1) if blended else 0.0
+        da = c * (1 - a) ** (m - 1) if blended else 0.0
+        assert abs(g[O.SLOTS["sh"][0], i] - C0 * dc) < 1e-12, i
+        assert abs(g[O.SLOTS["opacity"][0], i] - kappa * G * da) < 1e-12, i
+
+
 def test_order_invariance_equal_colours():
     rng = np.random.default_rng(7)
     N = 12
