@@ -590,7 +590,7 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
 // positions and entries are read only for the views that hold one.
 constexpr int kGatherViews = 8;
 
-__global__ __launch_bounds__(kT) void k_grad_gather(DevHier h, int nv, const uint64_t *__restrict__ masks,
+__global__ __launch_bounds__(kT, 4) void k_grad_gather(DevHier h, int nv, const uint64_t *__restrict__ masks,
                                                     int64_t words, const uint32_t *__restrict__ word_off,
                                                     const uint32_t *__restrict__ cut_total, uint32_t cap,
                                                     const double *__restrict__ cut_t,
