@@ -183,6 +183,8 @@ typedef struct {
  * absolute-value activation and are zero where the 0.99 clamp is active.
  * Per-tile blending state is recomputed from the final transmittance and
  * the index of the last contributor of each pixel (no per-pixel lists).
+ * dL/dt is written (not added) when out->dt is given; with out->dt NULL the
+ * blend backward skips its share of that work.
  * Errors: HGS_ERR_STATE without a preceding render (or after the parameters
  * were rebound / re-uploaded).  Does not synchronise. */
 hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_grads *out);

@@ -145,3 +145,10 @@ def test_rebuild_rejects_a_removed_leaf():
     keep[5] = False
     with pytest.raises(ValueError):
         compact.rebuild(h, keep)
+
+
+def test_rebuild_keeping_every_node_is_the_identity():
+    h = synth.make_scene(1)
+    c = compact.rebuild(h, np.ones(h.n_nodes, bool))
+    for name in ("parent", "child_begin", "child_count", "bmin", "bmax", "mean", "scale", "rot", "opacity", "sh"):
+        assert np.array_equal(getattr(c, name), getattr(h, name)), name
