@@ -142,11 +142,26 @@ hgs_status hgs_cut(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *
  * they match it bit for bit.  tau_min <= 0, non-finite taus or more than 64
  * levels: HGS_ERR_INVALID_ARG; with no level (tau_min > tau_max) every node
  * is kept.  Invalidates the state kept for hgs_render_backward.
- * Synchronises the ctx stream.  Rebuilding the tree from the flags (each
- * kept node's parent becomes its nearest kept ancestor, so a node may get
- * more than 8 children) is host work: paper_2406_12080_amd.compact. */
+ * Synchronises the ctx stream.  hgs_compact_rebuild turns the flags into
+ * the compacted tree. */
 hgs_status hgs_compact_mark(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, float tau_min, float tau_max,
                             uint8_t *keep);
+
+/* The compacted tree (Sec. 5.2) from the keep flags of hgs_compact_mark:
+ * host work only, no context.  In (host): parent and child_count (int32[n],
+ * the breadth-first layout hgs_upload takes) and keep (uint8[n]).  Every
+ * kept node's parent becomes its nearest kept ancestor, so a node may get
+ * more than 8 children (K in Eq. (alphap) is the child count).  Out (host,
+ * each with room for n entries, filled up to *n_out): order (the old index
+ * of every new node: breadth-first, root first, the children of a node
+ * contiguous and in their old order), new_parent (-1 for the root),
+ * new_child_begin (0 for a leaf) and new_child_count.  Node attributes and
+ * boxes carry over unchanged (order indexes them).  HGS_ERR_INVALID_ARG for
+ * NULL pointers, n out of range, a malformed topology, or a removed root or
+ * leaf. */
+hgs_status hgs_compact_rebuild(const int32_t *parent, const int32_t *child_count, const uint8_t *keep, int64_t n,
+                               int32_t *order, int32_t *new_parent, int32_t *new_child_begin,
+                               int32_t *new_child_count, int64_t *n_out);
 
 typedef struct {
     int64_t cut;        /* cut nodes, all views */

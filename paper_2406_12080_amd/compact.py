@@ -1,5 +1,6 @@
 """Hierarchy compaction (Sec. 5.2, "Compacting the Hierarchy"): the tree
-rebuilt from the keep flags of ``hgs_compact_mark``.
+rebuilt from the keep flags of ``hgs_compact_mark``, by the library's
+``hgs_compact_rebuild`` (host code).
 
 Every kept node's parent becomes its nearest kept ancestor, so a node may end
 up with more than eight children (the alpha blending takes K from the child
@@ -11,69 +12,37 @@ and ordered as they were.
 """
 from __future__ import annotations
 
+import ctypes
+
 import numpy as np
 
 from .synth import Hierarchy
 
 
 def rebuild(h: Hierarchy, keep) -> Hierarchy:
-    keep = np.asarray(keep, dtype=bool).reshape(-1)
+    from . import hgs
+    keep = np.ascontiguousarray(np.asarray(keep, dtype=bool).reshape(-1), dtype=np.uint8)
     n = h.n_nodes
     if keep.shape[0] != n:
         raise ValueError(f"keep has {keep.shape[0]} flags for {n} nodes")
-    leaf = h.child_count == 0
-    if not keep[0] or not keep[leaf].all():
-        raise ValueError("the root and every leaf must be kept")
-    parent = h.parent.astype(np.int64)
-    # nearest kept proper ancestor: step over removed nodes until every
-    # ancestor pointer lands on a kept node (or past the root)
-    anc = parent.copy()
-    while True:
-        moved = anc >= 0
-        moved[moved] = ~keep[anc[moved]]
-        if not moved.any():
-            break
-        anc[moved] = parent[anc[moved]]
-    ids = np.nonzero(keep)[0]
-    ids = ids[ids != 0]
-    # depth in the new tree (parents precede children in the old order, so
-    # as many passes as levels settle it)
-    depth = np.zeros(n, np.int64)
-    for _ in range(int(h.info.get("levels", 0)) + 64):
-        nd = depth.copy()
-        nd[ids] = depth[anc[ids]] + 1
-        if np.array_equal(nd, depth):
-            break
-        depth = nd
-    else:
-        raise RuntimeError("depth did not settle")
-    # breadth-first order: level by level, children grouped by their
-    # parent's new position, siblings in their old order
-    newidx = np.full(n, -1, np.int64)
-    newidx[0] = 0
-    order = [np.zeros(1, np.int64)]
-    placed = 1
-    dmax = int(depth[ids].max(initial=0))
-    for d in range(1, dmax + 1):
-        lv = ids[depth[ids] == d]
-        lv = lv[np.lexsort((lv, newidx[anc[lv]]))]
-        newidx[lv] = placed + np.arange(lv.shape[0])
-        placed += lv.shape[0]
-        order.append(lv)
-    order = np.concatenate(order)
-    m = order.shape[0]
-    new_parent = np.full(m, -1, np.int64)
-    new_parent[1:] = newidx[anc[order[1:]]]
-    child_count = np.bincount(new_parent[1:], minlength=m).astype(np.int32)
-    child_begin = np.zeros(m, np.int32)
-    has = child_count > 0
-    child_begin[has] = 1 + np.searchsorted(new_parent[1:], np.nonzero(has)[0], side="left")
+    parent = np.ascontiguousarray(h.parent, np.int32)
+    count = np.ascontiguousarray(h.child_count, np.int32)
+    order, new_parent, child_begin, child_count = (np.empty(n, np.int32) for _ in range(4))
+    m = ctypes.c_int64()
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+    st = hgs.lib().hgs_compact_rebuild(ptr(parent), ptr(count), ptr(keep), n, ptr(order), ptr(new_parent),
+                                       ptr(child_begin), ptr(child_count), ctypes.byref(m))
+    if st != 0:
+        raise ValueError(f"hgs_compact_rebuild failed ({st}): the root and every leaf must be kept, "
+                         "and the topology must be breadth-first")
+    m = m.value
+    order = order[:m].astype(np.int64)
     info = dict(h.info)
-    info.update(compacted_from=n, removed=n - m, max_children=int(child_count.max(initial=0)))
+    info.update(compacted_from=n, removed=n - m, max_children=int(child_count[:m].max(initial=0)))
 
     def take(a):
         return np.ascontiguousarray(a[..., order])
 
-    return Hierarchy(parent=new_parent.astype(np.int32), child_begin=child_begin, child_count=child_count,
-                     bmin=take(h.bmin), bmax=take(h.bmax), mean=take(h.mean), scale=take(h.scale),
-                     rot=take(h.rot), opacity=take(h.opacity), sh=take(h.sh), info=info)
+    return Hierarchy(parent=new_parent[:m].copy(), child_begin=child_begin[:m].copy(),
+                     child_count=child_count[:m].copy(), bmin=take(h.bmin), bmax=take(h.bmax), mean=take(h.mean),
+                     scale=take(h.scale), rot=take(h.rot), opacity=take(h.opacity), sh=take(h.sh), info=info)

@@ -19,7 +19,7 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_CAPACITY = range(6)
 _NAMES = {0: "HGS_OK", 1: "HGS_ERR_INVALID_ARG", 2: "HGS_ERR_OOM", 3: "HGS_ERR_HIP", 4: "HGS_ERR_STATE",
           5: "HGS_ERR_CAPACITY"}
 EXPORTS = ("hgs_create", "hgs_destroy", "hgs_last_error", "hgs_set_stream", "hgs_upload", "hgs_bind_params",
-           "hgs_cut", "hgs_compact_mark", "hgs_render", "hgs_render_backward", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer",
+           "hgs_cut", "hgs_compact_mark", "hgs_compact_rebuild", "hgs_render", "hgs_render_backward", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer",
            "hgs_set_profiling", "hgs_kernel_time", "hgs_counters")
 COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t", "bwd_evaluated",
                  "bwd_evaluated_t", "bwd_contrib")
@@ -92,6 +92,7 @@ def lib():
         L.hgs_bind_params.argtypes = [vp, vp, vp, vp, vp, vp]
         L.hgs_cut.argtypes = [vp, P(View), vp, vp, ctypes.c_int64, P(ctypes.c_int64)]
         L.hgs_compact_mark.argtypes = [vp, P(View), ctypes.c_int32, ctypes.c_float, ctypes.c_float, vp]
+        L.hgs_compact_rebuild.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp, P(ctypes.c_int64)]
         L.hgs_render.argtypes = [vp, P(View), ctypes.c_int32, P(vp), P(Stats)]
         L.hgs_render_backward.argtypes = [vp, P(vp), P(Grads)]
         L.hgs_adam_step.argtypes = [vp, P(Adam)]

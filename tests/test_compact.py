@@ -147,6 +147,89 @@ def test_rebuild_rejects_a_removed_leaf():
         compact.rebuild(h, keep)
 
 
+def _rebuild_numpy(h: Hierarchy, keep) -> Hierarchy:
+    # independent NumPy construction of the same tree (reference for the
+    # library's host code): pointer steps over removed nodes, depth passes,
+    # and a level-by-level lexicographic sort
+    keep = np.asarray(keep, dtype=bool).reshape(-1)
+    n = h.n_nodes
+    if keep.shape[0] != n:
+        raise ValueError(f"keep has {keep.shape[0]} flags for {n} nodes")
+    leaf = h.child_count == 0
+    if not keep[0] or not keep[leaf].all():
+        raise ValueError("the root and every leaf must be kept")
+    parent = h.parent.astype(np.int64)
+    # nearest kept proper ancestor: step over removed nodes until every
+    # ancestor pointer lands on a kept node (or past the root)
+    anc = parent.copy()
+    while True:
+        moved = anc >= 0
+        moved[moved] = ~keep[anc[moved]]
+        if not moved.any():
+            break
+        anc[moved] = parent[anc[moved]]
+    ids = np.nonzero(keep)[0]
+    ids = ids[ids != 0]
+    # depth in the new tree (parents precede children in the old order, so
+    # as many passes as levels settle it)
+    depth = np.zeros(n, np.int64)
+    for _ in range(int(h.info.get("levels", 0)) + 64):
+        nd = depth.copy()
+        nd[ids] = depth[anc[ids]] + 1
+        if np.array_equal(nd, depth):
+            break
+        depth = nd
+    else:
+        raise RuntimeError("depth did not settle")
+    # breadth-first order: level by level, children grouped by their
+    # parent's new position, siblings in their old order
+    newidx = np.full(n, -1, np.int64)
+    newidx[0] = 0
+    order = [np.zeros(1, np.int64)]
+    placed = 1
+    dmax = int(depth[ids].max(initial=0))
+    for d in range(1, dmax + 1):
+        lv = ids[depth[ids] == d]
+        lv = lv[np.lexsort((lv, newidx[anc[lv]]))]
+        newidx[lv] = placed + np.arange(lv.shape[0])
+        placed += lv.shape[0]
+        order.append(lv)
+    order = np.concatenate(order)
+    m = order.shape[0]
+    new_parent = np.full(m, -1, np.int64)
+    new_parent[1:] = newidx[anc[order[1:]]]
+    child_count = np.bincount(new_parent[1:], minlength=m).astype(np.int32)
+    child_begin = np.zeros(m, np.int32)
+    has = child_count > 0
+    child_begin[has] = 1 + np.searchsorted(new_parent[1:], np.nonzero(has)[0], side="left")
+    info = dict(h.info)
+    info.update(compacted_from=n, removed=n - m, max_children=int(child_count.max(initial=0)))
+
+    def take(a):
+        return np.ascontiguousarray(a[..., order])
+
+    return Hierarchy(parent=new_parent.astype(np.int32), child_begin=child_begin, child_count=child_count,
+                     bmin=take(h.bmin), bmax=take(h.bmax), mean=take(h.mean), scale=take(h.scale),
+                     rot=take(h.rot), opacity=take(h.opacity), sh=take(h.sh), info=info)
+
+
+@pytest.mark.parametrize("case", ["c1", "c2"])
+def test_rebuild_matches_an_independent_numpy_construction(case):
+    if case == "c1":
+        h = synth.make_scene(1)
+        views = [synth.look_at(e, (0, 0, 0), (0, 1, 0), 256, 256, 1.0) for e in [(0, 0, 3), (2.5, 0.5, 1.5)]]
+        keep = O.compact_keep(h, views, 3.0, 128.0)
+    else:
+        h = synth.make_scene(2, n_leaves=20_000)
+        rng = np.random.default_rng(5)
+        keep = (h.child_count == 0) | (rng.random(h.n_nodes) < 0.6)  # any mask that keeps root and leaves
+        keep[0] = True
+    a, b = compact.rebuild(h, keep), _rebuild_numpy(h, keep)
+    for name in ("parent", "child_begin", "child_count", "bmin", "bmax", "mean", "scale", "rot", "opacity", "sh"):
+        assert np.array_equal(getattr(a, name), getattr(b, name)), name
+    assert a.child_count.max() > 8 or case == "c1"
+
+
 def test_rebuild_keeping_every_node_is_the_identity():
     h = synth.make_scene(1)
     c = compact.rebuild(h, np.ones(h.n_nodes, bool))
