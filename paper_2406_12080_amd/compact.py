@@ -41,7 +41,7 @@ def rebuild(h: Hierarchy, keep) -> Hierarchy:
     info.update(compacted_from=n, removed=n - m, max_children=int(child_count[:m].max(initial=0)))
 
     def take(a):
-        return np.ascontiguousarray(a[..., order])
+        return np.ascontiguousarray(np.take(a, order, axis=a.ndim - 1))
 
     return Hierarchy(parent=new_parent[:m].copy(), child_begin=child_begin[:m].copy(),
                      child_count=child_count[:m].copy(), bmin=take(h.bmin), bmax=take(h.bmax), mean=take(h.mean),
