@@ -45,6 +45,15 @@ def test_chain_removes_the_nodes_between_two_levels():
     assert keep.tolist() == [True, True, False, False, True, True, True]
 
 
+def test_ladder_includes_tau_max():
+    # the same chain with tau_max = 48 exactly: the level at 48 is taken, so
+    # b and c go; stopping before it would leave them above the last cut
+    h = box_tree([-1, 0, 1, 2, 3, 4, 4], [100, 40, 38, 30, 8, 1, 1])
+    v = [S.axis_view(100, 100, 100.0)]
+    assert O.compact_keep(h, v, 3.0, 48.0).tolist() == [True, True, False, False, True, True, True]
+    assert O.compact_keep(h, v, 3.0, 47.0).all()
+
+
 def test_union_of_cuts_keeps_a_node_one_view_alone_removes():
     # root 100 > A 20 > M 18 > {a1, a2} 8 > two leaves each.  View 1 sees
     # eps = L, view 2 (focal 150) eps = 1.5 L.  Taus 3.5, 7, 14, 28, 56.
