@@ -148,12 +148,18 @@ def test_rebuild_links_each_node_to_its_nearest_kept_ancestor():
     assert np.array_equal(c.opacity, h.opacity[src])
 
 
-def test_rebuild_rejects_a_removed_leaf():
+def test_rebuild_rejects_a_removed_leaf_root_or_a_malformed_tree():
     h = box_tree([-1, 0, 1, 2, 3, 4, 4], [100, 40, 38, 30, 8, 1, 1])
-    keep = np.ones(7, bool)
-    keep[5] = False
+    for bad in (5, 0):
+        keep = np.ones(7, bool)
+        keep[bad] = False
+        with pytest.raises(ValueError):
+            compact.rebuild(h, keep)
+    h.parent[3] = 5  # a parent after its child
     with pytest.raises(ValueError):
-        compact.rebuild(h, keep)
+        compact.rebuild(h, np.ones(7, bool))
+    with pytest.raises(ValueError):
+        compact.rebuild(h, np.ones(6, bool))
 
 
 def _rebuild_numpy(h: Hierarchy, keep) -> Hierarchy:
