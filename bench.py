@@ -70,11 +70,11 @@ def build_workload(name: str, leaves: int | None = None):
     return h, views
 
 
-def autotune(r, views, step, reps=1):
+def autotune(r, views, P):
     """The package's autotuner on the fwd+bwd step (images are bit-identical
     across choices)."""
-    from paper_2406_12080_amd.autotune import autotune as tune
-    return tune(r, views, step, reps, log=lambda m: log(f"[bench] {m}"))
+    from paper_2406_12080_amd.autotune import autotune_step
+    return autotune_step(r, views, P, log=lambda m: log(f"[bench] {m}"))
 
 
 def cpu_baseline(h, view, row_stride: int = 1):
@@ -389,7 +389,7 @@ def main(argv=None):
         r.set_tuning(tw, th, b)
         tuning = dict(tile_w=tw, tile_h=th, batch=b)
     else:
-        tuning = autotune(r, views, step_batched)
+        tuning = autotune(r, views, P)
     log(f"[bench] tuning {tuning}")
 
     r.set_profiling(True)  # the blend then runs right after the graph, bracketed by events

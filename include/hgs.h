@@ -17,7 +17,7 @@
  *     projected Gaussian G): EWA projection with the anti-aliasing low-pass
  *     of Sec. 5.1, degree-3 SH colour, (tile, depth) ordering and
  *     front-to-back compositing with alpha clamped to 0.99 (Sec. 7.3);
- *   - the backward pass to every node's parameters (Sec. 5.1, Sec. 6.1
+ *   - the backward pass to every node's parameters (Sec. 5.1, Sec. 7.1
  *     "Implementation"), with an absolute-value opacity activation and no
  *     opacity gradient through the 0.99 clamp (Sec. 7.3).
  *
@@ -108,7 +108,10 @@ hgs_status hgs_bind_params(hgs_ctx *ctx, float *mean, float *scale, float *rot, 
  * and forward axes in world coordinates: p_cam = R (x - eye).  Pixel (i, j)
  * samples the image-plane point (i + 1/2, j + 1/2) with
  * u = fx p.x / p.z + cx, v = fy p.y / p.z + cy.  Splats with p.z <= z_near
- * are culled.  tau is the target granularity in pixels (>= 0). */
+ * are culled; z_near must be positive (a splat behind the camera is never
+ * drawn).  tau is the target granularity in pixels (>= 0).  A view with a
+ * non-finite field, fx or fy <= 0, z_near <= 0, tau < 0 or a size outside
+ * [1, 32768] is rejected with HGS_ERR_INVALID_ARG. */
 typedef struct {
     float R[9];
     float eye[3];
@@ -171,6 +174,7 @@ typedef struct {
     int64_t blended;    /* (pixel, splat) pairs that passed alpha >= 1/255 and were composited */
     float ms[8];        /* stage times when requested: cut, preprocess, visible+depth sort,
                            duplicate, tile sort, ranges, blend, total (0 when not timed) */
+    uint64_t render_id; /* identifies this render for hgs_render_backward (never 0) */
 } hgs_stats;
 
 /* Render n_views views (host array `views`) into out_rgb[v] (host array of
@@ -180,29 +184,43 @@ typedef struct {
  * the tiles of every view) captured once into a HIP graph and replayed while
  * the view sizes stay the same.  `stats` (host, may be NULL) receives counts;
  * stats->ms is filled when stats->ms[0] < 0 on entry (costs event syncs).
- * Keeps the state hgs_render_backward needs.  Synchronises the ctx stream
- * once at the end (capacity check); grows internal buffers and replays when
- * a capacity was exceeded. */
+ * Keeps the state hgs_render_backward needs, under a new render id (a
+ * per-ctx counter, written to stats->render_id and returned by
+ * hgs_last_render).  Synchronises the ctx stream once at the end (capacity
+ * check); grows internal buffers and replays when a capacity was exceeded. */
 hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, float *const *out_rgb,
                       hgs_stats *stats);
+
+/* Id and view count of the render whose state ctx holds for
+ * hgs_render_backward (host outputs; either may be NULL): *render_id = 0
+ * and *n_views = 0 when there is none (no render yet, or a later call such
+ * as hgs_cut, hgs_bind_params, hgs_upload, hgs_set_tuning, hgs_compact_mark
+ * or an hgs_adam_step on the bound parameters has replaced or invalidated
+ * it).  Does not synchronise. */
+hgs_status hgs_last_render(hgs_ctx *ctx, uint64_t *render_id, int32_t *n_views);
 
 typedef struct {
     float *mean, *scale, *rot, *opacity, *sh; /* device, same layouts as the parameters; accumulated (+=) */
     float *dt;                                /* device, may be NULL: dL/dt per cut entry of the last render */
 } hgs_grads;
 
-/* Backward of the last hgs_render on this ctx: dL_drgb[v] (host array of
- * device pointers, float[height][width][3]) is dL/d(out_rgb[v]).  Gradients
+/* Backward of the render `render_id` (its stats->render_id), which must be
+ * the last hgs_render on this ctx, over its n_views views: dL_drgb[v] (host
+ * array of n_views device pointers, each float[height][width][3] of view v
+ * of that render) is dL/d(out_rgb[v]).  Gradients
  * of every node's parameters are ADDED to `out`; leaves get none (they are
- * frozen, Sec. 6.1); opacity gradients include the sign of the
+ * frozen, Sec. 5.1 and Sec. 7.1); opacity gradients include the sign of the
  * absolute-value activation and are zero where the 0.99 clamp is active.
  * Per-tile blending state is recomputed from the final transmittance and
  * the index of the last contributor of each pixel (no per-pixel lists).
  * dL/dt is written (not added) when out->dt is given; with out->dt NULL the
  * blend backward skips its share of that work.
- * Errors: HGS_ERR_STATE without a preceding render (or after the parameters
- * were rebound / re-uploaded).  Does not synchronise. */
-hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_grads *out);
+ * Errors: HGS_ERR_STATE when render_id is not the render whose state ctx
+ * holds (a later render replaced it, or there is none: see
+ * hgs_last_render); HGS_ERR_INVALID_ARG when n_views differs from that
+ * render's view count or a pointer is NULL.  Does not synchronise. */
+hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const float *const *dL_drgb,
+                               hgs_grads *out);
 
 /* One step of the optimiser of the hierarchy optimisation (Sec. 5.1, the
  * paragraph on optimising the generated hierarchy): interior nodes only,

@@ -27,7 +27,7 @@
  *                   weight of Sec. 4.2, the 0.99 clamp of Sec. 7.3, and
  *                   front-to-back compositing.
  *   or_backward     The adjoint of all of the above with respect to every
- *                   node's parameters (Sec. 5.1, 6.1 "Implementation"):
+ *                   node's parameters (Sec. 5.1, 7.1 "Implementation"):
  *                   gradients reach node and parent through the
  *                   interpolation, and through the pow of Eq. (alphap);
  *                   opacity uses an absolute-value activation and its

@@ -4,6 +4,12 @@ The forward renders every view in one call (one graph launch for several
 views); the backward hands dL/dimage to ``hgs_render_backward``, which
 returns gradients for every interior node's parameters (leaves are frozen)
 through the parent/child interpolation and the opacity transition.
+
+The renderer keeps the state of its last render only: each node of the
+autograd graph records the id of its render, and its backward fails with
+HGS_ERR_STATE when a later render on the same renderer has replaced that
+state (differentiate before rendering again, or use one renderer per
+render that stays in the graph).
 """
 from __future__ import annotations
 
@@ -19,6 +25,7 @@ class HierRender(torch.autograd.Function):
         renderer.bind(*params)
         imgs, stats = renderer.render(views)
         ctx.renderer = renderer
+        ctx.render_id = stats["render_id"]
         ctx.shapes = [p.shape for p in params]
         ctx.stats = stats
         ctx.out_shapes = [i.shape for i in imgs]
@@ -31,7 +38,7 @@ class HierRender(torch.autograd.Function):
         grads = {k: torch.zeros(s, dtype=torch.float32, device=dev) for k, s in zip(PARAM_FIELDS, ctx.shapes)}
         dL = [g if g is not None else torch.zeros(s, dtype=torch.float32, device=dev)
               for g, s in zip(grad_imgs, ctx.out_shapes)]
-        r.backward(dL, grads)
+        r.backward(dL, grads, render_id=ctx.render_id)
         return (None, None) + tuple(grads[k] for k in PARAM_FIELDS)
 
 

@@ -33,3 +33,24 @@ def autotune(r, views, step=None, reps: int = 1, candidates=CANDIDATES, log=None
             best = (dt, tw, th, b)
     r.set_tuning(best[1], best[2], best[3])
     return dict(tile_w=best[1], tile_h=best[2], batch=best[3])
+
+
+def autotune_step(r, views, params, seed: int = 1234, reps: int = 1, log=None) -> dict:
+    """Tune on the differentiable step: one batched render of `views` and one
+    backward with a seeded N(0, 1) cotangent into zeroed gradient buffers
+    shaped like `params` (the dict of bound parameter tensors).  This is the
+    choice the benchmark times."""
+    import torch
+    dev = params["mean"].device
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    dL = [torch.randn((v.height, v.width, 3), device=dev, generator=gen) for v in views]
+    imgs = [torch.empty((v.height, v.width, 3), device=dev) for v in views]
+    grads = {k: torch.zeros_like(t) for k, t in params.items()}
+
+    def step():
+        r.render(views, out=imgs)
+        r.backward(dL, grads)
+
+    step()  # sizes the workspaces
+    torch.cuda.synchronize()
+    return autotune(r, views, step, reps, log=log)

@@ -115,6 +115,7 @@ struct hgs_ctx {
 
     // state of the last render
     bool have_render = false;
+    uint64_t render_seq = 0;  // id of the last successful render (ids start at 1)
     uint64_t render_param_gen = 0;
     int last_nv = 0;
     uint32_t last_tiles = 0;
@@ -278,7 +279,7 @@ bool finite_view(const hgs_view &v)
     for (float x : v.eye)
         if (!std::isfinite(x)) return false;
     return std::isfinite(v.fx) && std::isfinite(v.fy) && std::isfinite(v.cx) && std::isfinite(v.cy) &&
-           std::isfinite(v.z_near) && std::isfinite(v.tau) && v.fx > 0 && v.fy > 0 && v.tau >= 0 &&
+           std::isfinite(v.z_near) && std::isfinite(v.tau) && v.fx > 0 && v.fy > 0 && v.z_near > 0 && v.tau >= 0 &&
            v.width > 0 && v.height > 0 && v.width <= 32768 && v.height <= 32768;
 }
 
@@ -923,6 +924,7 @@ hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, floa
         }
         if (grow) continue;
         ctx->have_render = true;
+        ++ctx->render_seq;
         ctx->render_param_gen = ctx->param_gen;
         ctx->last_nv = n_views;
         ctx->last_tiles = n_tiles;
@@ -938,6 +940,7 @@ hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, floa
             stats->pairs = c.pair_total;
             stats->evaluated = (int64_t)c.evaluated;
             stats->blended = (int64_t)c.blended;
+            stats->render_id = ctx->render_seq;
             for (int k = 0; k < 8; ++k) stats->ms[k] = 0.0f;
             if (timed) {
                 for (int k = 0; k < 7; ++k) (void)hipEventElapsedTime(&stats->ms[k], ev[k], ev[k + 1]);
@@ -953,11 +956,29 @@ hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, floa
     return fail(ctx, HGS_ERR_CAPACITY, "render did not fit after growing buffers");
 }
 
-hgs_status hgs_render_backward(hgs_ctx *ctx, const float *const *dL_drgb, hgs_grads *out)
+hgs_status hgs_last_render(hgs_ctx *ctx, uint64_t *render_id, int32_t *n_views)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    const bool live = ctx->have_render && ctx->render_param_gen == ctx->param_gen;
+    if (render_id) *render_id = live ? ctx->render_seq : 0;
+    if (n_views) *n_views = live ? ctx->last_nv : 0;
+    return HGS_OK;
+}
+
+hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const float *const *dL_drgb,
+                               hgs_grads *out)
 {
     if (!ctx) return HGS_ERR_INVALID_ARG;
     if (!ctx->have_render || ctx->render_param_gen != ctx->param_gen)
         return fail(ctx, HGS_ERR_STATE, "render_backward needs a render with the current parameters");
+    if (render_id != ctx->render_seq)
+        return fail(ctx, HGS_ERR_STATE, "render " + std::to_string(render_id) +
+                                            " has been replaced: the ctx holds the state of render " +
+                                            std::to_string(ctx->render_seq));
+    if (n_views != ctx->last_nv)
+        return fail(ctx, HGS_ERR_INVALID_ARG, "render " + std::to_string(render_id) + " has " +
+                                                  std::to_string(ctx->last_nv) + " views, not " +
+                                                  std::to_string(n_views));
     if (!dL_drgb || !out || !out->mean || !out->scale || !out->rot || !out->opacity || !out->sh)
         return fail(ctx, HGS_ERR_INVALID_ARG, "bad gradient arguments");
     const int nv = ctx->last_nv;

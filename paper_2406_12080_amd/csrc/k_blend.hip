@@ -294,18 +294,18 @@ __device__ __forceinline__ float swap_add16(float x, float y)
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Sum over the 64 lanes of 11 per-lane values v[0..10]: two swap steps
-// (across halves, then across rows), two in-row halvings with DPP (partners
-// l ^ 8, then l ^ 7, each keeping one of two values), and a sum over the
-// quad (l ^ 2, l ^ 1).  Every lane of quad q = l >> 2 ends with the total of
-// value wave_slot(l) (-1: nothing).
+// Sum over the 64 lanes of 12 per-lane values v[0..11] (v[11] only when DT):
+// two swap steps (across halves, then across rows), two in-row halvings with
+// DPP (partners l ^ 8, then l ^ 7, each keeping one of two values), and a sum
+// over the quad (l ^ 2, l ^ 1).  Every lane of quad q = l >> 2 ends with the
+// total of value wave_slot(l) (-1: nothing).
 template <bool DT>
-__device__ __forceinline__ float wave_reduce11(const float (&v)[11], int lane)
+__device__ __forceinline__ float wave_reduce12(const float (&v)[12], int lane)
 {
     const float S0 = swap_add32(v[0], v[1]), S1 = swap_add32(v[2], v[3]), S2 = swap_add32(v[4], v[5]);
     const float S3 = swap_add32(v[6], v[7]), S4 = swap_add32(v[8], v[9]);
-    const float S5 = DT ? swap_add32(v[10], 0.0f) : 0.0f;  // slot 10 (dL/dt) only when asked for
-    // rows 0..3 of Z0: v0 v2 v1 v3; Z1: v4 v6 v5 v7; Z2: v8 v10 v9 -
+    const float S5 = swap_add32(v[10], DT ? v[11] : 0.0f);  // slot 11 (dL/dt) only when asked for
+    // rows 0..3 of Z0: v0 v2 v1 v3; Z1: v4 v6 v5 v7; Z2: v8 v10 v9 v11
     const float Z0 = swap_add16(S0, S1), Z1 = swap_add16(S2, S3), Z2 = swap_add16(S4, S5);
     const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
     const float R0 = (b3 ? Z1 : Z0) + dpp_move<0x128>(b3 ? Z0 : Z1);
@@ -319,27 +319,39 @@ __device__ __forceinline__ float wave_reduce11(const float (&v)[11], int lane)
 __device__ __forceinline__ int wave_slot(int lane)
 {
     // by row (lane >> 4) and (b2, b3) = bits 2 and 3 of the lane
-    constexpr int8_t kSlot[4][4] = {{0, 4, 8, -1}, {2, 6, 10, -1}, {1, 5, 9, -1}, {3, 7, -1, -1}};
+    constexpr int8_t kSlot[4][4] = {{0, 4, 8, -1}, {2, 6, 10, -1}, {1, 5, 9, -1}, {3, 7, 11, -1}};
     return kSlot[lane >> 4][((lane >> 2) & 1) * 2 + ((lane >> 3) & 1)];
 }
 
 constexpr int kG = 12;  // floats per splat in the screen-space gradient
 
 // Per-lane gradient slots of one (pixel, splat) pair, summed over the tile:
-//   0, 1   P1, P2 = h u1, h u2           with h = G dL/dG (G the Gaussian)
-//   2..4   Q11, Q12, Q22 = h u1 u1, h u1 u2, h u2 u2
-//   5, 6   dL/dA_n, dL/dA_p (A = kappa |o|)
-//   7..9   dL/d colour
-//   10     dL/dt through alpha (only when the caller asks for dL/dt)
+//   0       S = h                         with h = G dL/dG (G the Gaussian)
+//   1, 2    P'_i = h v_i
+//   3..5    Q'_11, Q'_12, Q'_22 = h v_1 v_1, h v_1 v_2, h v_2 v_2
+//   6, 7    dL/dA_n, dL/dA_p (A = kappa |o|)
+//   8..10   dL/d colour
+//   11      dL/dt through alpha (only when the caller asks for dL/dt)
+// Here v = u - c is the pixel's position on the conic's scaled eigen-axes
+// relative to the tile's corner pixel (c, formed in FP64 at staging): v is
+// the pixel's offset inside the tile mapped by the axes.  The moments about
+// the splat's centre follow in FP64 at the flush, P = P' + c S and
+// Q = Q' + c P'^T + P' c^T + c c^T S.  Taken directly about the centre, the
+// moments of a large splat whose centre lies far off screen are dominated
+// by c S and c c^T S, and the mean and covariance gradients built from them
+// cancel almost entirely in the chain through the projection: separately
+// rounded FP32 sums of P and Q then leave errors far above the result.  With
+// the moments about the corner both large parts carry the one rounded S, and
+// the cancellation removes its error with it.
 // The screen-space gradient follows from the tile sums by the splat's
 // (per-tile constant) axes: with g = conic d = (u1 w1 + u2 w2) / kHalfLog2e
 // and G = exp(-q/2), dL/dmean = sum h g and dL/dSigma2' = -sum (h / 2) g g^T
 // (the covariance gradient through the conic), both linear in P and Q.
-__device__ __forceinline__ void screen_grad(const float4 &W, const float *sg, double out[5])
+__device__ __forceinline__ void screen_grad(const float4 &W, const double P[2], const double Q[3], double out[5])
 {
     const double k = 1.0 / kHalfLog2e;
     const double wx = W.x, wy = W.y, wz = W.z, ww = W.w;
-    const double P1 = sg[0], P2 = sg[1], Q11 = sg[2], Q12 = sg[3], Q22 = sg[4];
+    const double P1 = P[0], P2 = P[1], Q11 = Q[0], Q12 = Q[1], Q22 = Q[2];
     out[0] = k * (wx * P1 + wz * P2);
     out[1] = k * (wy * P1 + ww * P2);
     // (a, b, c) = (xx, 2 xy, yy) of sum (h / 2) g g^T, entering dL/dSigma2' with a minus
@@ -347,6 +359,15 @@ __device__ __forceinline__ void screen_grad(const float4 &W, const float *sg, do
     out[2] = 0.5 * k * k * (wx * wx * Q11 + 2.0 * wx * wz * Q12 + wz * wz * Q22);
     out[3] = k * k * (wx * wy * Q11 + (wx * ww + wz * wy) * Q12 + wz * ww * Q22);
     out[4] = 0.5 * k * k * (wy * wy * Q11 + 2.0 * wy * ww * Q12 + ww * ww * Q22);
+}
+
+// Offsets of the tile's corner pixel centre on the scaled eigen-axes, in FP64.
+__device__ __forceinline__ double2 corner_offsets(const SplatRec &r, const double4 &W, int ox, int oy)
+{
+#pragma clang fp contract(off)
+    const double dx = ((double)(ox - r.ax) + 0.5) - (double)r.fx;
+    const double dy = ((double)(oy - r.ay) + 0.5) - (double)r.fy;
+    return make_double2(dx * W.x + dy * W.y, dx * W.z + dy * W.w);
 }
 
 template <int TW, int TH, int BATCH, bool DT>
@@ -370,6 +391,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
     __shared__ uint32_t s_id[BATCH];
     __shared__ __align__(16) float s_g[BATCH][kG];
     __shared__ double s_d[BATCH * 11];  // the flushed terms, splat-major
+    __shared__ double2 s_ref[BATCH];    // the tile corner's offsets on the axes (FP64)
     __shared__ uint32_t s_max;
     const uint32_t tile = tile_order[blockIdx.x];  // longest lists first
     const int vi = view_of_tile(views, nv, tile);
@@ -381,6 +403,8 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
     const int px = ox + (w % SX) * 8 + (lane & 7), py = oy + (w / SX) * 8 + (lane >> 3);
     const bool inside = px < V.W && py < V.H;
     const float lx = (float)(lane & 7), ly = (float)(lane >> 3);
+    // the pixel's offset from the tile corner (the moments' reference)
+    const float lxt = (float)(px - ox), lyt = (float)(py - oy);
     const uint2 rg = ranges[tile];
     const int slot = wave_slot(lane);
     const bool writer = (lane & 3) == 0 && slot >= 0;
@@ -424,6 +448,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                 block_offsets(r, W64, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
                 s_u[bk][j] = make_float2(c1, c2);
             }
+            s_ref[j] = corner_offsets(r, W64, ox, oy);
 #pragma unroll
             for (int q = 0; q < kG; ++q) s_g[j][q] = 0.0f;
         }
@@ -452,32 +477,34 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
             const float dal_raw = T * ((Cc.x - R0) * g0 + (Cc.y - R1) * g1 + (Cc.z - R2) * g2);
             const float dal = contrib ? dal_raw : 0.0f;
             const float aT = a * T;
-            float v[11];
-            v[7] = aT * g0;
-            v[8] = aT * g1;
-            v[9] = aT * g2;
+            float v[12];
+            v[8] = aT * g0;
+            v[9] = aT * g1;
+            v[10] = aT * g2;
             R0 = a * Cc.x + (1.0f - a) * R0;
             R1 = a * Cc.y + (1.0f - a) * R1;
             R2 = a * Cc.z + (1.0f - a) * R2;
             float dan = dal, dap = 0.0f;
-            v[10] = 0.0f;
+            v[11] = 0.0f;
             if (interp) {
                 dan = (1.0f - Ov.z) * dal;
                 const float dapr = Ov.z * dal;
-                if constexpr (DT) v[10] = (e.apr - e.an) * dal;
+                if constexpr (DT) v[11] = (e.apr - e.an) * dal;
                 // d apr / d a_p = (1/K) (1 - a_p)^(1/K - 1) = (1/K) q / (1 - a_p)
                 dap = dapr * Ov.w * (e.q * __builtin_amdgcn_rcpf(1.0f - e.ap));
             }
             const float dan_c = e.cn ? 0.0f : dan, dap_c = e.cp ? 0.0f : dap;
-            v[5] = dan_c * e.G;
-            v[6] = dap_c * e.G;
+            v[6] = dan_c * e.G;
+            v[7] = dap_c * e.G;
             const float h = e.G * (dan_c * Ov.x + dap_c * Ov.y);  // G dL/dG
-            v[0] = h * e.u1;
-            v[1] = h * e.u2;
-            v[2] = v[0] * e.u1;
-            v[3] = v[0] * e.u2;
-            v[4] = v[1] * e.u2;
-            const float tot = wave_reduce11<DT>(v, lane);
+            const float v1 = fmaf(lyt, Wv.y, lxt * Wv.x), v2 = fmaf(lyt, Wv.w, lxt * Wv.z);
+            v[0] = h;
+            v[1] = h * v1;
+            v[2] = h * v2;
+            v[3] = v[1] * v1;
+            v[4] = v[1] * v2;
+            v[5] = v[2] * v2;
+            const float tot = wave_reduce12<DT>(v, lane);
             if (writer && tot != 0.0f) {
                 if constexpr (NW == 1) s_g[j][slot] = tot;
                 else atomicAdd(&s_g[j][slot], tot);
@@ -491,18 +518,24 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
             const float4 a = *reinterpret_cast<const float4 *>(&s_g[j][0]);
             const float4 b = *reinterpret_cast<const float4 *>(&s_g[j][4]);
             const float4 c = *reinterpret_cast<const float4 *>(&s_g[j][8]);
-            const float sg5[5] = {a.x, a.y, a.z, a.w, b.x};
+            // moments about the splat's centre from those about the tile corner
+            const double2 cr = s_ref[j];
+            const double S = a.x, P1 = a.y, P2 = a.z, Q11 = a.w, Q12 = b.x, Q22 = b.y;
+            const double P[2] = {P1 + cr.x * S, P2 + cr.y * S};
+            const double Q[3] = {Q11 + 2.0 * cr.x * P1 + cr.x * cr.x * S,
+                                 Q12 + cr.x * P2 + cr.y * P1 + cr.x * cr.y * S,
+                                 Q22 + 2.0 * cr.y * P2 + cr.y * cr.y * S};
             double sc[5];
-            screen_grad(s_w[j], sg5, sc);
+            screen_grad(s_w[j], P, Q, sc);
             double *d = s_d + j * 11;
 #pragma unroll
             for (int q = 0; q < 5; ++q) d[q] = sc[q];
-            d[5] = (double)b.y;
-            d[6] = (double)b.z;
-            d[7] = (double)b.w;
-            d[8] = (double)c.x;
-            d[9] = (double)c.y;
-            d[10] = (double)c.z;
+            d[5] = (double)b.z;
+            d[6] = (double)b.w;
+            d[7] = (double)c.x;
+            d[8] = (double)c.y;
+            d[9] = (double)c.z;
+            d[10] = (double)c.w;
         }
         __syncthreads();
         for (int idx = threadIdx.x; idx < cnt * 11; idx += NT) {

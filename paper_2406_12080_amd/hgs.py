@@ -19,8 +19,9 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_CAPACITY = range(6)
 _NAMES = {0: "HGS_OK", 1: "HGS_ERR_INVALID_ARG", 2: "HGS_ERR_OOM", 3: "HGS_ERR_HIP", 4: "HGS_ERR_STATE",
           5: "HGS_ERR_CAPACITY"}
 EXPORTS = ("hgs_create", "hgs_destroy", "hgs_last_error", "hgs_set_stream", "hgs_upload", "hgs_bind_params",
-           "hgs_cut", "hgs_compact_mark", "hgs_compact_rebuild", "hgs_render", "hgs_render_backward", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer",
-           "hgs_set_profiling", "hgs_kernel_time", "hgs_counters")
+           "hgs_cut", "hgs_compact_mark", "hgs_compact_rebuild", "hgs_render", "hgs_last_render",
+           "hgs_render_backward", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
+           "hgs_kernel_time", "hgs_counters")
 COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t", "bwd_evaluated",
                  "bwd_evaluated_t", "bwd_contrib")
 K_BLEND, K_BLEND_BWD, K_PREPROCESS_BWD = range(3)
@@ -52,11 +53,12 @@ class View(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("cut", ctypes.c_int64), ("visible", ctypes.c_int64), ("pairs", ctypes.c_int64),
-                ("evaluated", ctypes.c_int64), ("blended", ctypes.c_int64), ("ms", ctypes.c_float * 8)]
+                ("evaluated", ctypes.c_int64), ("blended", ctypes.c_int64), ("ms", ctypes.c_float * 8),
+                ("render_id", ctypes.c_uint64)]
 
     def as_dict(self):
         return dict(cut=self.cut, visible=self.visible, pairs=self.pairs, evaluated=self.evaluated,
-                    blended=self.blended, ms=list(self.ms))
+                    blended=self.blended, ms=list(self.ms), render_id=self.render_id)
 
 
 class Adam(ctypes.Structure):
@@ -94,7 +96,8 @@ def lib():
         L.hgs_compact_mark.argtypes = [vp, P(View), ctypes.c_int32, ctypes.c_float, ctypes.c_float, vp]
         L.hgs_compact_rebuild.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp, P(ctypes.c_int64)]
         L.hgs_render.argtypes = [vp, P(View), ctypes.c_int32, P(vp), P(Stats)]
-        L.hgs_render_backward.argtypes = [vp, P(vp), P(Grads)]
+        L.hgs_last_render.argtypes = [vp, P(ctypes.c_uint64), P(ctypes.c_int32)]
+        L.hgs_render_backward.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, P(vp), P(Grads)]
         L.hgs_adam_step.argtypes = [vp, P(Adam)]
         L.hgs_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.hgs_get_buffer.argtypes = [vp, ctypes.c_int32, P(vp), P(ctypes.c_int64)]
@@ -159,6 +162,7 @@ class Renderer:
         self.h = h
         self.n_nodes = 0
         self._keep = []
+        self._last = None  # (render id, image shapes, cut size) of the last render
 
     def close(self):
         if getattr(self, "h", None):
@@ -259,11 +263,44 @@ class Renderer:
             st.ms[0] = -1.0
         self._check(self.L.hgs_render(self.h, arr, nv, ptrs, ctypes.byref(st)))
         self._last_views = views
+        self._last = (st.render_id, [(v.height, v.width, 3) for v in views], st.cut)
         return out, st.as_dict()
 
-    def backward(self, dL, grads: dict, dt=None) -> None:
-        """Accumulate parameter gradients of the last render into ``grads``
-        (dict of CUDA tensors keyed like the parameters)."""
+    def last_render(self):
+        """(render id, view count) of the render whose state the context
+        holds for the backward; (0, 0) when there is none."""
+        rid, nv = ctypes.c_uint64(), ctypes.c_int32()
+        self._check(self.L.hgs_last_render(self.h, ctypes.byref(rid), ctypes.byref(nv)))
+        return rid.value, nv.value
+
+    def backward(self, dL, grads: dict, dt=None, render_id: int | None = None) -> None:
+        """Accumulate parameter gradients of a render into ``grads`` (dict of
+        CUDA tensors keyed like the parameters).  ``render_id`` (default:
+        this renderer's last render) names the render being differentiated;
+        the library rejects it when a later render has replaced its state.
+        ``dL`` holds one float32 [H, W, 3] CUDA tensor per view of that
+        render; ``dt`` (optional) room for dL/dt of every cut entry."""
+        torch = self.torch
+        if self._last is None:
+            raise HgsError(ERR_STATE, "no render on this renderer")
+        rid = self._last[0] if render_id is None else int(render_id)
+        if rid == self._last[0]:
+            shapes, n_cut = self._last[1], self._last[2]
+            if len(dL) != len(shapes):
+                raise HgsError(ERR_INVALID_ARG, f"{len(dL)} cotangents for a render of {len(shapes)} views")
+            for k, (g, shp) in enumerate(zip(dL, shapes)):
+                if not (g.is_cuda and g.dtype == torch.float32 and tuple(g.shape) == shp):
+                    raise HgsError(ERR_INVALID_ARG, f"dL[{k}] must be a float32 CUDA tensor of shape {shp}, "
+                                                    f"not {g.dtype} {tuple(g.shape)}")
+            if dt is not None and not (dt.is_cuda and dt.dtype == torch.float32 and dt.numel() >= n_cut):
+                raise HgsError(ERR_INVALID_ARG, f"dt must be a float32 CUDA tensor of at least {n_cut} entries")
+        comp = dict(mean=3, scale=3, rot=4, opacity=1, sh=48)
+        for k in PARAM_FIELDS:
+            t = grads[k]
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float32 and
+                    t.numel() == comp[k] * self.n_nodes):
+                raise HgsError(ERR_INVALID_ARG, f"grads[{k!r}] must be a contiguous float32 CUDA tensor of "
+                                                f"{comp[k] * self.n_nodes} entries")
         dL = [g.contiguous() for g in dL]
         ptrs = (ctypes.c_void_p * len(dL))(*[g.data_ptr() for g in dL])
         g = Grads()
@@ -271,7 +308,7 @@ class Renderer:
             setattr(g, k, grads[k].data_ptr())
         g.dt = dt.data_ptr() if dt is not None else None
         self._keep = dL
-        self._check(self.L.hgs_render_backward(self.h, ptrs, ctypes.byref(g)))
+        self._check(self.L.hgs_render_backward(self.h, rid, len(dL), ptrs, ctypes.byref(g)))
 
     def adam_step(self, params: dict, grads: dict, m: dict, v: dict, lr, step: int, beta1: float = 0.9,
                   beta2: float = 0.999, eps: float = 1e-15) -> None:

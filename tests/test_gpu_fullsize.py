@@ -24,6 +24,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2406_12080_amd import synth
+from paper_2406_12080_amd.autotune import autotune_step as bench_tuning
 import parity as PR
 
 torch = pytest.importorskip("torch")
@@ -56,6 +57,9 @@ def full(request):
     r.upload(h)
     P = hgs.params_to_device(h)
     r.bind(*[P[k] for k in hgs.PARAM_FIELDS])
+    # the blend configuration the benchmark times: its autotuner, run the
+    # way the benchmark runs it (a forward and backward step per candidate)
+    tuning = bench_tuning(r, views, P)
     imgs, _ = r.render(views)
     first = [i.clone() for i in imgs]
     imgs, st = r.render(views)  # graph replay, as in the timed steps
@@ -70,7 +74,7 @@ def full(request):
     H = O.Hier(h)
     rng = np.random.default_rng(12080)
     pix = [np.sort(rng.choice(v.width * v.height, N_PIX, replace=False)) for v in views]
-    _log(f"rendered {len(views)} views, stats {st} ({time.time() - t0:.0f}s)")
+    _log(f"rendered {len(views)} views with tuning {tuning}, stats {st} ({time.time() - t0:.0f}s)")
     yield dict(name=request.param, h=h, H=H, views=views, r=r, P=P, imgs=imgs, st=st, buf=buf, pix=pix,
                replay_equal=replay_equal, ocut={})
     r.close()
@@ -158,7 +162,7 @@ def test_backward_sampled_two_views(full):
     nodes = np.unique(np.concatenate([np.concatenate([ids, parent[ids][parent[ids] >= 0]]) for ids, _ in
                                       cuts.values()]))
     og = np.zeros((O.NPARAM, nodes.size))
-    near = np.zeros(nodes.size, bool)
+    near = np.zeros(nodes.size, bool)  # reported: nodes whose splat lies within a metre of the eye
     dt_err, dt_ref = 0.0, 0.0
     for k, (oids, ot) in cuts.items():
         v = views[k]
@@ -168,7 +172,7 @@ def test_backward_sampled_two_views(full):
         del ob["grad"]
         near |= PR.near_nodes(H, v, oids, ot)[nodes]
         pr = O.project(H, v, oids, ot)
-        m = (ot > 0) & (pr["depth"] >= PR.NEAR_DEPTH)
+        m = ot > 0
         lo = b["base"][k]
         gd = dt[lo:lo + oids.shape[0]].cpu().numpy().astype(np.float64)
         dt_err += float(np.sum((gd[m] - ob["dt"][m]) ** 2))
@@ -176,14 +180,13 @@ def test_backward_sampled_two_views(full):
     idx = torch.from_numpy(nodes).cuda()
     gpu = {k: grads[k].view(h.n_nodes, -1)[idx].cpu().numpy() for k in hgs.PARAM_FIELDS}
     leaf = (np.asarray(h.child_count) == 0)[nodes]
-    res = PR.check_grads(gpu, og, leaf, exclude=near)
+    res = PR.check_grads(gpu, og, leaf)
     dt_rel = float(np.sqrt(dt_err / max(dt_ref, 1e-60)))
     _log(f"{full['name']}: views {GRAD_VIEWS}, {nodes.size} nodes ({int(near.sum())} near), "
          f"{amb_total} ambiguous pixels without cotangent: {res}, dt rel {dt_rel:.2e}")
     for name, rr in res.items():
         assert rr["norm"] > 0.0, name
-        assert rr["rel"] <= PR.GRAD_REL, (name, rr)
-        assert rr["elem_ok"] >= 0.999, (name, rr)
+    PR.assert_grads(res, full["name"])
     assert dt_ref > 0.0 and dt_rel <= PR.GRAD_REL
     del grads, dt, dL
 
@@ -207,8 +210,9 @@ def c4_full():
     r.upload(h)
     P = hgs.params_to_device(h)
     r.bind(*[P[k] for k in hgs.PARAM_FIELDS])
+    tuning = bench_tuning(r, views, P)
     imgs, st = r.render(views)
-    _log(f"box2m_8x720p: scene {h.info}, rendered ({time.time() - t0:.0f}s)")
+    _log(f"box2m_8x720p: scene {h.info}, tuning {tuning}, rendered ({time.time() - t0:.0f}s)")
     yield dict(h=h, hp=hp, views=views, r=r, P=P, imgs=imgs, st=st)
     r.close()
     torch.cuda.empty_cache()
@@ -247,9 +251,8 @@ def test_l1_gradient_against_perturbed_targets_8x720p(c4_full):
         og += ob["grad"]
         near |= PR.near_nodes(H, v, oids, ot)
     gpu = {k: grads[k].cpu().numpy() for k in hgs.PARAM_FIELDS}
-    res = PR.check_grads(gpu, og, h.child_count == 0, exclude=near)
-    _log(f"box2m_8x720p L1: {int(near.sum())} near nodes excluded: {res}")
+    res = PR.check_grads(gpu, og, h.child_count == 0)
+    _log(f"box2m_8x720p L1: {int(near.sum())} near nodes among those checked: {res}")
     for name, rr in res.items():
         assert rr["norm"] > 0.0, name
-        assert rr["rel"] <= PR.GRAD_REL, (name, rr)
-        assert rr["elem_ok"] >= 0.999, (name, rr)
+    PR.assert_grads(res, "box2m_8x720p")
