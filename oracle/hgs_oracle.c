@@ -508,12 +508,15 @@ static void lists_free(or_lists *L)
 
 /* Composite one pixel front to back.  flip >= 0 inverts the flip-th
  * near-threshold decision (see or_render).  Returns the number of blended
- * splats; near-threshold decisions are counted in *n_near. */
+ * splats; near-threshold decisions are counted in *n_near, and blended
+ * splats whose unclamped a_n or a_p lies within the same relative guard of
+ * the 0.99 clamp in *n_clamp (there the value is continuous but its
+ * derivative is not: either side's gradient is a correct one). */
 static int composite(const or_frame *F, const int32_t *items, int64_t m, int px, int py, int flip,
-                     double rgb[3], double *T_out, int *n_near, uint64_t *sig)
+                     double rgb[3], double *T_out, int *n_near, int *n_clamp, uint64_t *sig)
 {
     double T = 1.0, C[3] = {0, 0, 0};
-    int nb = 0, near = 0;
+    int nb = 0, near = 0, nclamp = 0;
     uint64_t hsh = 1469598103934665603ULL;
     for (int64_t k = 0; k < m; ++k) {
         const or_splat *S = &F->splats[items[k]];
@@ -536,6 +539,9 @@ static int composite(const or_frame *F, const int32_t *items, int64_t m, int px,
         for (int ch = 0; ch < 3; ++ch) C[ch] += S->rgb[ch] * a.alpha * T;
         T = Tn;
         nb++;
+        if (fabs(S->A_n * a.G / OR_ALPHA_MAX - 1.0) < OR_GUARD ||
+            (S->t > 0.0 && fabs(S->A_p * a.G / OR_ALPHA_MAX - 1.0) < OR_GUARD))
+            nclamp++;
         if (sig) {
             uint64_t token = (uint64_t)(uint32_t)S->node * 8u + (uint64_t)(a.clamp_n * 4 + a.clamp_p * 2) +
                              ((uint64_t)((S->raw[0] > 0) | ((S->raw[1] > 0) << 1) | ((S->raw[2] > 0) << 2)) << 40);
@@ -545,6 +551,7 @@ static int composite(const or_frame *F, const int32_t *items, int64_t m, int px,
     for (int ch = 0; ch < 3; ++ch) rgb[ch] = C[ch];
     *T_out = T;
     if (n_near) *n_near = near;
+    if (n_clamp) *n_clamp = nclamp;
     if (sig) *sig = hsh;
     return nb;
 }
@@ -555,10 +562,12 @@ static int composite(const or_frame *F, const int32_t *items, int64_t m, int px,
  *   nalt[npix], alt_rgb[npix*OR_MAX_ALT*3], alt_T[npix*OR_MAX_ALT]
  *       results with one near-threshold decision inverted (decisions whose
  *       quantity lies within a relative 1e-4 of its threshold), at most 4.
+ *   nclamp[npix] (optional) blended splats of the pixel whose unclamped
+ *       opacity term lies within a relative 1e-4 of the 0.99 clamp.
  * Returns the total number of blended (pixel, splat) pairs. */
 int64_t or_render(const or_hier *h, const or_view *v, const int32_t *ids, const double *t, int64_t count,
                   const int64_t *pix, int64_t npix, double *rgb, double *T, int32_t *nblend,
-                  int32_t *nalt, double *alt_rgb, double *alt_T)
+                  int32_t *nalt, double *alt_rgb, double *alt_T, int32_t *nclamp)
 {
     or_frame F;
     frame_build(h, v, ids, t, count, &F);
@@ -570,15 +579,16 @@ int64_t or_render(const or_hier *h, const or_view *v, const int32_t *ids, const 
         const int px = (int)(pix[k] % v->width), py = (int)(pix[k] / v->width);
         const int32_t *items = L.items + L.start[k];
         const int64_t m = L.start[k + 1] - L.start[k];
-        int nn = 0;
-        nblend[k] = composite(&F, items, m, px, py, -1, rgb + 3 * k, T + k, &nn, NULL);
+        int nn = 0, nc = 0;
+        nblend[k] = composite(&F, items, m, px, py, -1, rgb + 3 * k, T + k, &nn, &nc, NULL);
+        if (nclamp) nclamp[k] = nc;
         total += nblend[k];
         int na = nn < OR_MAX_ALT ? nn : OR_MAX_ALT;
         if (nalt) {
             nalt[k] = na;
             for (int f = 0; f < na; ++f)
                 composite(&F, items, m, px, py, f, alt_rgb + (k * OR_MAX_ALT + f) * 3, alt_T + k * OR_MAX_ALT + f,
-                          NULL, NULL);
+                          NULL, NULL, NULL);
         }
     }
     lists_free(&L);
@@ -603,7 +613,7 @@ uint64_t or_signature(const or_hier *h, const or_view *v, const int32_t *ids, co
         double rgb[3], T;
         uint64_t s;
         composite(&F, L.items + L.start[k], L.start[k + 1] - L.start[k], (int)(k % v->width),
-                  (int)(k / v->width), -1, rgb, &T, NULL, &s);
+                  (int)(k / v->width), -1, rgb, &T, NULL, NULL, &s);
         acc = (acc ^ (s + (uint64_t)k * 0x9E3779B97F4A7C15ULL)) * 1099511628211ULL;
     }
     lists_free(&L);

@@ -52,7 +52,7 @@ def lib():
         L.or_cut.restype = i64
         L.or_project.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(d)]
         L.or_render.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(i64), i64, P(d), P(d), P(i32),
-                                P(i32), P(d), P(d)]
+                                P(i32), P(d), P(d), P(i32)]
         L.or_render.restype = i64
         L.or_signature.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64]
         L.or_signature.restype = ctypes.c_uint64
@@ -188,7 +188,12 @@ def project(h, v, ids, t) -> dict:
 
 
 def render(h, v, ids=None, t=None, pix=None, alternatives=True) -> dict:
-    """Render view v (all pixels, or the linear pixel indices ``pix``)."""
+    """Render view v (all pixels, or the linear pixel indices ``pix``).
+    Besides the image: per pixel the number of blended splats, the results
+    with one near-threshold decision inverted (``nalt``, ``alt_rgb``,
+    ``alt_T``), and ``nclamp``, the number of blended splats whose unclamped
+    opacity term lies within a relative 1e-4 of the 0.99 clamp (where the
+    gradient has two correct values)."""
     H = _H(h)
     if ids is None:
         ids, t = cut(H, v)
@@ -204,6 +209,7 @@ def render(h, v, ids=None, t=None, pix=None, alternatives=True) -> dict:
     nalt = np.zeros(m, np.int32)
     alt_rgb = np.zeros((m, MAX_ALT, 3))
     alt_T = np.zeros((m, MAX_ALT))
+    nclamp = np.zeros(m, np.int32)
     hs, vs = H.struct(), view_struct(v)
     P = ctypes.POINTER
     total = lib().or_render(ctypes.byref(hs), ctypes.byref(vs), _p(ids, ctypes.c_int32), _p(t, ctypes.c_double),
@@ -211,9 +217,10 @@ def render(h, v, ids=None, t=None, pix=None, alternatives=True) -> dict:
                             _p(T, ctypes.c_double), _p(nb, ctypes.c_int32),
                             _p(nalt, ctypes.c_int32) if alternatives else P(ctypes.c_int32)(),
                             _p(alt_rgb, ctypes.c_double) if alternatives else P(ctypes.c_double)(),
-                            _p(alt_T, ctypes.c_double) if alternatives else P(ctypes.c_double)())
-    return dict(rgb=rgb, T=T, nblend=nb, nalt=nalt, alt_rgb=alt_rgb, alt_T=alt_T, blended=int(total),
-                pix=pix, ids=ids, t=t)
+                            _p(alt_T, ctypes.c_double) if alternatives else P(ctypes.c_double)(),
+                            _p(nclamp, ctypes.c_int32))
+    return dict(rgb=rgb, T=T, nblend=nb, nalt=nalt, alt_rgb=alt_rgb, alt_T=alt_T, nclamp=nclamp,
+                blended=int(total), pix=pix, ids=ids, t=t)
 
 
 def render_image(h, v, ids=None, t=None):

@@ -45,6 +45,15 @@ def check_pixels(gpu_rgb, gpu_T, o, tol=PIX_TOL):
                 n_alt=int(alt_used.sum()), n_ambiguous=int((o["nalt"] > 0).sum()), m=int(ok.size))
 
 
+def ambiguous(o):
+    """Pixels where the oracle's result or gradient has more than one
+    correct value: a skip or stop decision within the guard band of its
+    threshold, or a blended splat whose opacity term sits on the 0.99 clamp
+    (the value is continuous there, its derivative is not).  The gradient
+    tests give these pixels no cotangent."""
+    return (o["nalt"] > 0) | (o["nclamp"] > 0)
+
+
 NEAR_DEPTH = 1.0  # metres: 5 x the near plane
 
 
@@ -79,8 +88,13 @@ def check_grads(gpu: dict, og: np.ndarray, leaf_mask, rel=GRAD_REL):
         rms = nrm / np.sqrt(ref.size)
         bound = rel * np.maximum(np.abs(ref), 1e-3 * rms) + 1e-30
         elem = np.abs(g - ref) <= bound
+        ratio = np.abs(g - ref) / bound
         out[name] = dict(rel=float(err / max(nrm, 1e-30)), n_bad=int((~elem).sum()), norm=float(nrm),
-                         worst=float((np.abs(g - ref) / bound).max(initial=0.0) * rel))
+                         worst=float(ratio.max(initial=0.0) * rel))
+        if not elem.all():  # where the worst elements are: (component, column, oracle, GPU)
+            top = np.argsort(ratio, axis=None)[::-1][:4]
+            out[name]["at"] = [(int(c), int(j), float(ref[c, j]), float(g[c, j]))
+                               for c, j in zip(*np.unravel_index(top, ratio.shape))]
     return out
 
 

@@ -145,9 +145,9 @@ def test_backward_sampled_two_views(full):
             pix = full["pix"][k]
             o = O.render(H, v, oids, ot, pix=pix, alternatives=True)
             # no cotangent where a decision lies within the guard band of a
-            # threshold: there either side's gradient is a correct one
-            keep = pix[o["nalt"] == 0]
-            amb_total += int((o["nalt"] > 0).sum())
+            # threshold or a clamp: there either side's gradient is a correct one
+            keep = pix[~PR.ambiguous(o)]
+            amb_total += int(PR.ambiguous(o).sum())
             g[keep] = gen.normal(size=(keep.size, 3))
             cuts[k] = (oids, ot)
         dL.append(torch.from_numpy(g.reshape(v.height, v.width, 3)).cuda())
@@ -184,6 +184,10 @@ def test_backward_sampled_two_views(full):
     dt_rel = float(np.sqrt(dt_err / max(dt_ref, 1e-60)))
     _log(f"{full['name']}: views {GRAD_VIEWS}, {nodes.size} nodes ({int(near.sum())} near), "
          f"{amb_total} ambiguous pixels without cotangent: {res}, dt rel {dt_rel:.2e}")
+    for name, rr in res.items():
+        for c, j, ref, got in rr.get("at", []):
+            _log(f"  worst {name}[{c}] node {int(nodes[j])} (near {bool(near[j])}, "
+                 f"children {int(np.asarray(h.child_count)[nodes[j]])}): oracle {ref:.6e} GPU {got:.6e}")
     for name, rr in res.items():
         assert rr["norm"] > 0.0, name
     PR.assert_grads(res, full["name"])
@@ -234,7 +238,7 @@ def test_l1_gradient_against_perturbed_targets_8x720p(c4_full):
         pix = np.sort(rng.choice(v.width * v.height, N_PIX, replace=False))
         tgt = O.render(Hp, v, oids, ot, pix=pix, alternatives=False)["rgb"]
         o = O.render(H, v, oids, ot, pix=pix)
-        keep = o["nalt"] == 0  # no cotangent where a decision sits on a threshold
+        keep = ~PR.ambiguous(o)  # no cotangent where a decision sits on a threshold or the clamp
         # dL/dimage of the L1 loss, from the oracle's own image (the cotangent
         # is an input of both sides)
         g = np.zeros((v.height * v.width, 3), np.float32)

@@ -214,8 +214,8 @@ def _grad_case(h, v, seed=0, tuning=(16, 16, 256)):
     w = torch.randn(img.shape, generator=gen)
     oids, ot = O.cut(h, v)
     # zero cotangent where the forward holds a decision within the guard band
-    # of a threshold: there either side's gradient is a correct one
-    amb = (O.render(h, v, oids, ot)["nalt"] > 0).reshape(v.height, v.width)
+    # of a threshold or of the clamp: there either side's gradient is correct
+    amb = PR.ambiguous(O.render(h, v, oids, ot)).reshape(v.height, v.width)
     w[torch.from_numpy(amb)] = 0.0
     w = w.cuda()
     grads = {k: torch.zeros_like(P[k]) for k in H.PARAM_FIELDS}

@@ -1,0 +1,130 @@
+"""Planted mistakes in copies of the oracle: each must fail at least one pin.
+
+Every case rewrites one passage of a copy of the oracle (the C definition or
+the Python compaction), builds the copy in a scratch directory and runs the
+pin files against it in a child process; the case passes when the pins
+fail.  The mistakes are the plausible ones: a wrong end of the interpolation
+weight, a dropped factor or term, a transposed operand, a wrong sign or
+index, a gradient path left out, a threshold alternative not taken.  The
+real oracle is never modified.  CPU only.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE = os.path.join(ROOT, "oracle")
+PINS = "tests/test_oracle_pins.py"
+COMPACT_PINS = "tests/test_compact.py"
+
+C = "hgs_oracle.c"
+PY = "oracle.py"
+
+# (name, file, passage, replacement, pin file)
+MUTATIONS = [
+    ("alpha with t as the child's weight", C,
+     "o->alpha = (1.0 - S->t) * o->an + S->t * o->apr;", "o->alpha = S->t * o->an + (1.0 - S->t) * o->apr;", PINS),
+    ("no opacity compensation kappa", C, "S->A_n = S->kappa * S->o_n;", "S->A_n = S->o_n;", PINS),
+    ("sign of the Jacobian's x term", C, "-v->fx * x / (z * z)", "v->fx * x / (z * z)", PINS),
+    ("view rotation transposed", C,
+     "S->pc[i] = v->R[3 * i] * S->mu_rel[0] + v->R[3 * i + 1] * S->mu_rel[1] + v->R[3 * i + 2] * S->mu_rel[2];",
+     "S->pc[i] = v->R[i] * S->mu_rel[0] + v->R[3 + i] * S->mu_rel[1] + v->R[6 + i] * S->mu_rel[2];", PINS),
+    ("SH basis index", C, "Y[1] = c1 * y;", "Y[1] = c1 * x;", PINS),
+    ("transmittance dropped from the colour sum", C,
+     "C[ch] += S->rgb[ch] * a.alpha * T;", "C[ch] += S->rgb[ch] * a.alpha;", PINS),
+    ("pow with K = 2 fixed", C,
+     "o->apr = 1.0 - pow(1.0 - o->ap, 1.0 / S->K);", "o->apr = 1.0 - pow(1.0 - o->ap, 0.5);", PINS),
+    ("dilation 0.1 px^2", C, "#define OR_DILATION 0.3", "#define OR_DILATION 0.1", PINS),
+    ("(1 - t) dropped from the scale lerp", C,
+     "S->s[k] = w0 * h->scale[k * n + node] + w1 * h->scale[k * n + pp];",
+     "S->s[k] = h->scale[k * n + node] + w1 * h->scale[k * n + pp];", PINS),
+    ("sign of the kappa gradient", C, "da += dkappa * k2 * (c / D - cd / Dd);", "da -= dkappa * k2 * (c / D - cd / Dd);",
+     PINS),
+    ("compositing adjoint without 1 / (1 - alpha)", C,
+     "dal += (Ti * S->rgb[ch] - after[ch] / (1.0 - al)) * gC[ch];", "dal += (Ti * S->rgb[ch] - after[ch]) * gC[ch];",
+     PINS),
+    ("mean lerp swapped", C,
+     "S->mu_rel[k] = (mn - v->eye[k]) + t * (mp - mn);", "S->mu_rel[k] = (mp - v->eye[k]) + t * (mn - mp);", PINS),
+    ("quaternion not normalised", C,
+     "for (int k = 0; k < 4; ++k) S->q[k] = S->qraw[k] / S->qnorm;",
+     "for (int k = 0; k < 4; ++k) S->q[k] = S->qraw[k];", PINS),
+    ("stop after the splat instead of before", C, "int stop = Tn < OR_T_MIN;", "int stop = T < OR_T_MIN;", PINS),
+    ("gradient through the 0.99 clamp", C, "if (!a.clamp_n) {", "if (1) {", PINS),
+    ("Sigma3 = M^T M", C, "acc += M[3 * i + k] * M[3 * j + k];", "acc += M[3 * k + i] * M[3 * k + j];", PINS),
+    ("parent's share of the SH gradient dropped", C,
+     "if (p >= 0) grad[(11 + k) * n + p] += w1 * dsh[k];", ";", PINS),
+    ("parent's share of the mean gradient dropped", C,
+     "if (p >= 0) grad[(0 + k) * n + p] += w1 * dmu[k];", ";", PINS),
+    ("parent's share of the rotation gradient dropped", C,
+     "if (p >= 0) grad[(6 + k) * n + p] += w1 * dqraw[k];", ";", PINS),
+    ("1/K dropped from the alpha' derivative", C,
+     "dap = dapr * (1.0 / S->K) * pow(1.0 - a.ap, 1.0 / S->K - 1.0);",
+     "dap = dapr * pow(1.0 - a.ap, 1.0 / S->K - 1.0);", PINS),
+    ("sign of the opacity activation ignored", C,
+     "grad[10 * n + node] += (on > 0 ? 1.0 : (on < 0 ? -1.0 : 0.0)) * don;", "grad[10 * n + node] += don;", PINS),
+    ("skip alternative not inverted", C, "if (near == flip) skip = !skip;", ";", PINS),
+    ("stop alternative not inverted", C, "if (near == flip) stop = !stop;", ";", PINS),
+    ("skip guard taken on the absolute difference", C,
+     "if (fabs(a.alpha / OR_ALPHA_MIN - 1.0) < OR_GUARD) {", "if (fabs(a.alpha - OR_ALPHA_MIN) < OR_GUARD) {", PINS),
+    ("clamp ambiguity not reported", C, "            nclamp++;", "            ;", PINS),
+    # the compaction of Sec. 5.2, step by step
+    ("removal does not stop at marked nodes", PY,
+     "                if marked[c]:\n                    continue\n", "", COMPACT_PINS),
+    ("whole union taken as the bottom-most nodes", PY, "bottom = union & ~has_desc", "bottom = union", COMPACT_PINS),
+    ("top-most nodes of the union instead", PY, "bottom = union & ~has_desc",
+     "bottom = union.copy()\n"
+     "        for m in np.nonzero(union)[0]:\n"
+     "            p = parent[m]\n"
+     "            while p >= 0 and not union[p]:\n"
+     "                p = parent[p]\n"
+     "            bottom[m] = p < 0", COMPACT_PINS),
+    ("first view only", PY, "        for v in views:\n            ids, _ = cut(H, v.replace(tau=tau))",
+     "        for v in views[:1]:\n            ids, _ = cut(H, v.replace(tau=tau))", COMPACT_PINS),
+    ("levels never marked", PY, "        marked |= bottom\n", "", COMPACT_PINS),
+    ("ladder excludes tau_max", PY, "while tau <= top:", "while tau < top:", COMPACT_PINS),
+    ("ladder tripling", PY, "tau *= 2.0", "tau *= 3.0", COMPACT_PINS),
+]
+
+
+def _run_mutant(idx: int) -> tuple[str, int, str]:
+    name, fname, old, new, pins = MUTATIONS[idx]
+    work = tempfile.mkdtemp(prefix="oracle_mutant_")
+    try:
+        shutil.copytree(ORACLE, os.path.join(work, "oracle"), ignore=shutil.ignore_patterns("_build", "__pycache__"))
+        for d in ("tests", "paper_2406_12080_amd"):
+            os.symlink(os.path.join(ROOT, d), os.path.join(work, d))
+        path = os.path.join(work, "oracle", fname)
+        src = open(path).read()
+        assert src.count(old) == 1, (name, src.count(old))
+        open(path, "w").write(src.replace(old, new))
+        if fname == C:
+            os.makedirs(os.path.join(work, "oracle", "_build"))
+            subprocess.check_call(["gcc", "-O1", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                                   "-o", os.path.join(work, "oracle", "_build", "liboracle.so"), path, "-lm"])
+        else:
+            os.makedirs(os.path.join(work, "oracle", "_build"))
+            shutil.copy(os.path.join(ORACLE, "_build", "liboracle.so"), os.path.join(work, "oracle", "_build"))
+        env = dict(os.environ, PYTHONDONTWRITEBYTECODE="1", OMP_NUM_THREADS="2")
+        r = subprocess.run([sys.executable, "-m", "pytest", pins, "-x", "-q", "-m", "not gpu", "-p", "no:cacheprovider",
+                            "-p", "no:randomly"], cwd=work, env=env, capture_output=True, text=True, timeout=900)
+        return name, r.returncode, r.stdout[-400:]
+    finally:
+        shutil.rmtree(work, ignore_errors=True)
+
+
+@pytest.mark.slow
+def test_every_planted_mistake_fails_a_pin():
+    from oracle import oracle as O
+    if not os.path.exists(O.LIB):
+        O.build()
+    with cf.ThreadPoolExecutor(4) as ex:
+        results = list(ex.map(_run_mutant, range(len(MUTATIONS))))
+    survivors = [(name, out) for name, rc, out in results if rc != 1]
+    assert not survivors, survivors

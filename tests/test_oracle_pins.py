@@ -299,6 +299,132 @@ def test_backward_stacked_splats_closed_form(N):
         assert abs(g[O.SLOTS["opacity"][0], i] - kappa * G * da) < 1e-12, i
 
 
+# ---------------------------------------------------------------------------
+# near-threshold alternatives: a decision whose quantity lies within a
+# relative 1e-4 of the 1/255 skip or of the 1e-4 stop is inverted in the
+# oracle's alternative results; the values here are derived by hand from the
+# isotropic closed form
+# ---------------------------------------------------------------------------
+CENTRE = [(7, 7), (7, 8), (8, 7), (8, 8)]  # the pixels (1/2, 1/2) px off the axis
+
+
+def _axis_kG(f, z, s):
+    """kappa G of an isotropic splat of scale s at depth z on the optical axis,
+    at a pixel centre (1/2, 1/2) px from the axis: alpha = min(0.99, o kappa G)."""
+    sig2 = (f * s / z) ** 2
+    sig2d = sig2 + 0.3
+    return sig2 / sig2d * math.exp(-0.5 / (2 * sig2d))
+
+
+def _axis_stack(f, zs, s, ops, dcs):
+    n = len(zs)
+    sh = np.zeros((n + 1, 48))
+    sh[1:, 0:3] = dcs
+    mean = [[0.0, 0.0, zs[0]]] + [[0.0, 0.0, z] for z in zs]
+    return S.hierarchy([-1] + [0] * n, mean, np.full((n + 1, 3), s), np.tile([[1, 0, 0, 0]], (n + 1, 1)),
+                       [ops[0]] + list(ops), sh)
+
+
+@pytest.mark.parametrize("rel", [5e-5, -5e-5, 1e-2, -1e-2])
+def test_alternative_at_the_skip_threshold(rel):
+    # one splat whose alpha at the four centre pixels is (1/255)(1 + rel):
+    # blended when rel > 0, skipped when rel < 0.  Within the relative guard
+    # of 1e-4 the alternative takes the other decision; 1% away there is no
+    # alternative.  Blended: C = c alpha, T = 1 - alpha; skipped: C = 0, T = 1.
+    f, z, s = 40.0, 4.0, float(np.float32(0.3))
+    kG = _axis_kG(f, z, s)
+    o = float(np.float32((1.0 / 255.0) * (1.0 + rel) / kG))
+    a = o * kG
+    near = abs(rel) < 1e-4
+    assert (abs(a * 255.0 - 1.0) < 1e-4) == near and (a >= 1.0 / 255.0) == (rel > 0)
+    dc = np.array([0.3, 0.1, -0.2])
+    h = _axis_stack(f, [z], s, [o], [dc])
+    v = S.axis_view(16, 16, f, tau=0.0)
+    ids, t = O.cut(h, v)
+    assert list(ids) == [1] and t[0] == 0.0
+    r = O.render(h, v, ids, t)
+    c = np.maximum(0.0, C0 * dc.astype(np.float32).astype(np.float64) + 0.5)
+    blended, skipped = (c * a, 1.0 - a), (np.zeros(3), 1.0)
+    nom, alt = (blended, skipped) if rel > 0 else (skipped, blended)
+    for x, y in CENTRE:
+        k = y * 16 + x
+        assert r["nalt"][k] == int(near)
+        assert np.allclose(r["rgb"][k], nom[0], rtol=0, atol=1e-14) and abs(r["T"][k] - nom[1]) < 1e-14
+        if near:
+            assert np.allclose(r["alt_rgb"][k, 0], alt[0], rtol=0, atol=1e-14)
+            assert abs(r["alt_T"][k, 0] - alt[1]) < 1e-14
+    others = np.ones(256, bool)
+    others[[y * 16 + x for x, y in CENTRE]] = False
+    assert np.all(r["nalt"][others] == 0) and np.all(r["rgb"][others] == 0.0)
+
+
+@pytest.mark.parametrize("rel", [5e-5, -5e-5, 1e-2])
+def test_clamp_ambiguity_is_reported(rel):
+    # one splat whose unclamped kappa o G at the four centre pixels is
+    # 0.99 (1 + rel): within the relative guard of 1e-4 the pixel reports a
+    # clamp decision on the edge (the value is continuous there, its
+    # derivative is not); 1% away it does not
+    f, z, s = 40.0, 4.0, float(np.float32(0.3))
+    kG = _axis_kG(f, z, s)
+    o = float(np.float32(0.99 * (1.0 + rel) / kG))
+    near = abs(o * kG / 0.99 - 1.0) < 1e-4
+    assert near == (abs(rel) < 1e-4)
+    h = _axis_stack(f, [z], s, [o], [np.array([0.3, 0.1, -0.2])])
+    v = S.axis_view(16, 16, f, tau=0.0)
+    ids, t = O.cut(h, v)
+    r = O.render(h, v, ids, t)
+    centre = [y * 16 + x for x, y in CENTRE]
+    assert np.all(r["nclamp"][centre] == int(near)) and np.all(r["nalt"][centre] == 0)
+    others = np.ones(256, bool)
+    others[centre] = False
+    assert np.all(r["nclamp"][others] == 0)
+    assert np.allclose(r["T"][centre], 1.0 - min(0.99, o * kG), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("side", [+1, -1])
+def test_alternative_at_the_stop_threshold(side):
+    # four splats on the axis, front to back alpha_1 = alpha_2 = 0.9,
+    # alpha_3 = 0.5, and alpha_4 chosen so that T_3 (1 - alpha_4) =
+    # 1e-4 (1 +- 5e-5): nominally the fourth is blended (side +1) or the
+    # pixel stops before it (side -1); the alternative does the other.
+    # With T_0 = 1, T_i = T_(i-1) (1 - alpha_i), blending m splats gives
+    # C = sum_(i <= m) c_i alpha_i T_(i-1) and T = T_m.
+    f, s = 40.0, float(np.float32(0.3))
+    zs = [3.0, 4.0, 5.0, 6.0]
+    kG = [_axis_kG(f, z, s) for z in zs]
+    ops = [float(np.float32(a / k)) for a, k in zip([0.9, 0.9, 0.5], kG[:3])]
+    al = [o * k for o, k in zip(ops, kG[:3])]
+    T3 = (1 - al[0]) * (1 - al[1]) * (1 - al[2])
+    ops.append(float(np.float32((1.0 - 1e-4 * (1.0 + side * 5e-5) / T3) / kG[3])))
+    al.append(ops[3] * kG[3])
+    assert max(al) < 0.99
+    rel = T3 * (1 - al[3]) / 1e-4 - 1.0
+    assert abs(rel) < 1e-4 and (rel >= 0) == (side > 0)
+    dcs = np.array([[0.3, 0.1, -0.2], [-0.1, 0.4, 0.2], [0.2, -0.3, 0.5], [0.6, 0.2, -0.4]])
+    h = _axis_stack(f, zs, s, ops, dcs)
+    v = S.axis_view(16, 16, f, tau=0.0)
+    ids, t = O.cut(h, v)
+    assert list(ids) == [1, 2, 3, 4] and np.all(t == 0.0)
+    r = O.render(h, v, ids, t)
+    c = np.maximum(0.0, C0 * dcs.astype(np.float32).astype(np.float64) + 0.5)
+
+    def blend(m):
+        C, T = np.zeros(3), 1.0
+        for i in range(m):
+            C += c[i] * al[i] * T
+            T *= 1 - al[i]
+        return C, T
+
+    four, three = blend(4), blend(3)
+    nom, alt = (four, three) if side > 0 else (three, four)
+    for x, y in CENTRE:
+        k = y * 16 + x
+        assert r["nalt"][k] == 1
+        assert r["nblend"][k] == (4 if side > 0 else 3)
+        assert np.allclose(r["rgb"][k], nom[0], rtol=0, atol=1e-14) and abs(r["T"][k] - nom[1]) < 1e-16
+        assert np.allclose(r["alt_rgb"][k, 0], alt[0], rtol=0, atol=1e-14) and abs(r["alt_T"][k, 0] - alt[1]) < 1e-16
+
+
 def test_order_invariance_equal_colours():
     rng = np.random.default_rng(7)
     N = 12
@@ -435,27 +561,19 @@ def _fd_setup():
     return H, v, ids, t, w
 
 
-def test_backward_matches_central_differences():
-    H, v, ids, t, w = _fd_setup()
-    assert (t > 0).sum() >= 5
-    g = O.backward(H, v, ids, t, w)["grad"]
-    sig0 = O.signature(H, v, ids, t)
-
+def _fd_check(H, v, ids, t, w, g, picks, sig0, rms):
+    """Central differences of L = sum(img * w) at each (slot, node) pick,
+    against the oracle's gradient g.  A pick whose step changes the decision
+    signature is rejected.  Returns (checked, rejected, |fd| of each checked
+    pick)."""
     def loss(Hx):
         img, _ = O.render_image(Hx, v, ids, t)
         return float((img * w).sum())
 
-    rng = np.random.default_rng(17)
-    touched = np.unique(np.concatenate([ids, H.parent[ids][H.parent[ids] >= 0]]))
-    cands = [(s, i) for s in range(O.NPARAM) for i in touched if g[s, i] != 0.0]
-    picks = [cands[k] for k in rng.choice(len(cands), 64, replace=False)]
-    rms = {}
-    for name, (a, b) in O.SLOTS.items():
-        rms[name] = math.sqrt(np.mean(g[a:b][:, touched] ** 2))
     checked = rejected = 0
+    mags = []
     for slot, i in picks:
-        arr = H.param_flat(slot)
-        th = arr[i]
+        th = H.param_flat(slot)[i]
         hstep = 1e-6 * max(1.0, abs(th))
         Hp = H.copy()
         Hp.param_flat(slot)[i] = th + hstep
@@ -469,7 +587,74 @@ def test_backward_matches_central_differences():
         tol = 1e-4 * max(abs(g[slot, i]), 1e-3 * rms[group])
         assert abs(fd - g[slot, i]) <= tol, (slot, i, fd, g[slot, i])
         checked += 1
+        mags.append(abs(fd))
+    return checked, rejected, mags
+
+
+def test_backward_matches_central_differences():
+    H, v, ids, t, w = _fd_setup()
+    assert (t > 0).sum() >= 5
+    g = O.backward(H, v, ids, t, w)["grad"]
+    sig0 = O.signature(H, v, ids, t)
+    rng = np.random.default_rng(17)
+    touched = np.unique(np.concatenate([ids, H.parent[ids][H.parent[ids] >= 0]]))
+    rms = {name: math.sqrt(np.mean(g[a:b][:, touched] ** 2)) for name, (a, b) in O.SLOTS.items()}
+    # 64 picks among the entries with a nonzero oracle gradient
+    cands = [(s, i) for s in range(O.NPARAM) for i in touched if g[s, i] != 0.0]
+    picks = [cands[k] for k in rng.choice(len(cands), 64, replace=False)]
+    checked, rejected, _ = _fd_check(H, v, ids, t, w, g, picks, sig0, rms)
     assert checked >= 48, (checked, rejected)
+
+
+def test_backward_central_differences_uniform_over_interior_nodes():
+    # picks that ignore the oracle's gradient, zeros included: a dropped
+    # gradient path leaves exact zeros, which only such picks can expose.
+    # Fifteen are parents of cut nodes with t > 0 (their share arrives
+    # through the interpolation weight alone), three in every parameter
+    # group; ten are any touched interior node.
+    H, v, ids, t, w = _fd_setup()
+    g = O.backward(H, v, ids, t, w)["grad"]
+    sig0 = O.signature(H, v, ids, t)
+    rng = np.random.default_rng(29)
+    par = H.parent[ids]
+    touched = np.unique(np.concatenate([ids, par[par >= 0]]))
+    interior = touched[H.child_count[touched] > 0]
+    lerp_parents = np.unique(par[(t > 0) & (par >= 0)])
+    assert len(lerp_parents) >= 3
+    rms = {name: math.sqrt(np.mean(g[a:b][:, touched] ** 2)) for name, (a, b) in O.SLOTS.items()}
+    # parents: three picks in every parameter group
+    for name, (a, b) in O.SLOTS.items():
+        pp = [(int(rng.integers(a, b)), int(rng.choice(lerp_parents))) for _ in range(3)]
+        n_p, rej_p, mags = _fd_check(H, v, ids, t, w, g, pp, sig0, rms)
+        # the parents' picks carry real gradient: a dropped share would show
+        assert n_p >= 1 and max(mags) > 1e-6, (name, n_p, rej_p, mags)
+    pi = [(int(rng.integers(O.NPARAM)), int(rng.choice(interior))) for _ in range(10)]
+    n_i, rej_i, _ = _fd_check(H, v, ids, t, w, g, pi, sig0, rms)
+    assert n_i >= 8, (n_i, rej_i)
+
+
+def test_absolute_value_opacity_activation():
+    # the renderer uses |o| (Sec. 7.3): flipping the sign of interior
+    # opacities leaves the image unchanged and negates exactly their opacity
+    # gradients, every other gradient unchanged
+    H, v, ids, t, w = _fd_setup()
+    par = H.parent[ids]
+    flip = np.unique(np.concatenate([par[(t > 0) & (par >= 0)], ids[H.child_count[ids] > 0]]))
+    assert len(flip) >= 3
+    Hn = H.copy()
+    Hn.opacity[flip] = -Hn.opacity[flip]
+    img, T = O.render_image(H, v, ids, t)
+    imgn, Tn = O.render_image(Hn, v, ids, t)
+    assert np.array_equal(img, imgn) and np.array_equal(T, Tn)
+    g = O.backward(H, v, ids, t, w)["grad"]
+    gn = O.backward(Hn, v, ids, t, w)["grad"]
+    k = O.SLOTS["opacity"][0]
+    sign = np.ones(H.n)
+    sign[flip] = -1.0
+    assert np.array_equal(gn[k], sign * g[k]) and np.abs(g[k][flip]).max() > 0
+    rest = np.ones(O.NPARAM, bool)
+    rest[k] = False
+    assert np.array_equal(gn[rest], g[rest])
 
 
 def test_backward_dt_matches_finite_difference_in_t():
