@@ -468,13 +468,25 @@ static void lists_build(const or_frame *F, const or_view *v, const int64_t *pix,
     const int64_t W = v->width, H = v->height;
     int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * W * H);
     for (int64_t i = 0; i < W * H; ++i) slot[i] = -1;
-    for (int64_t k = 0; k < npix; ++k) slot[pix[k]] = k;
+    /* the requested pixels' bounding box: footprint ranges are visited only
+     * inside it (pixels outside it are not requested) */
+    int bx0 = (int)W, bx1 = -1, by0 = (int)H, by1 = -1;
+    for (int64_t k = 0; k < npix; ++k) {
+        slot[pix[k]] = k;
+        const int x = (int)(pix[k] % W), y = (int)(pix[k] / W);
+        if (x < bx0) bx0 = x;
+        if (x > bx1) bx1 = x;
+        if (y < by0) by0 = y;
+        if (y > by1) by1 = y;
+    }
     int64_t *cnt = (int64_t *)calloc((size_t)npix + 1, sizeof(int64_t));
     for (int64_t oi = 0; oi < F->nsplat; ++oi) {
         const or_splat *S = &F->splats[F->order[oi]];
         if (!S->valid) continue;
-        for (int y = S->y0; y <= S->y1; ++y)
-            for (int x = S->x0; x <= S->x1; ++x) {
+        const int y0 = S->y0 > by0 ? S->y0 : by0, y1 = S->y1 < by1 ? S->y1 : by1;
+        const int x0 = S->x0 > bx0 ? S->x0 : bx0, x1 = S->x1 < bx1 ? S->x1 : bx1;
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
                 int64_t s = slot[(int64_t)y * W + x];
                 if (s >= 0) cnt[s + 1]++;
             }
@@ -487,8 +499,10 @@ static void lists_build(const or_frame *F, const or_view *v, const int64_t *pix,
         int32_t si = F->order[oi];
         const or_splat *S = &F->splats[si];
         if (!S->valid) continue;
-        for (int y = S->y0; y <= S->y1; ++y)
-            for (int x = S->x0; x <= S->x1; ++x) {
+        const int y0 = S->y0 > by0 ? S->y0 : by0, y1 = S->y1 < by1 ? S->y1 : by1;
+        const int x0 = S->x0 > bx0 ? S->x0 : bx0, x1 = S->x1 < bx1 ? S->x1 : bx1;
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
                 int64_t s = slot[(int64_t)y * W + x];
                 if (s >= 0) items[fill[s]++] = si;
             }
@@ -596,28 +610,36 @@ int64_t or_render(const or_hier *h, const or_view *v, const int32_t *ids, const 
     return total;
 }
 
-/* Hash of every decision the image depends on (contributing set and order,
- * clamp states, colour clamps), used to reject finite-difference steps that
- * cross a discontinuity. */
-uint64_t or_signature(const or_hier *h, const or_view *v, const int32_t *ids, const double *t, int64_t count)
+/* Hash of every decision the listed pixels pix[npix] depend on (contributing
+ * set and order, clamp states, colour clamps), used to reject
+ * finite-difference steps that cross a discontinuity. */
+uint64_t or_signature_pix(const or_hier *h, const or_view *v, const int32_t *ids, const double *t, int64_t count,
+                          const int64_t *pix, int64_t npix)
 {
     or_frame F;
     frame_build(h, v, ids, t, count, &F);
-    const int64_t npix = (int64_t)v->width * v->height;
-    int64_t *pix = (int64_t *)malloc(sizeof(int64_t) * npix);
-    for (int64_t k = 0; k < npix; ++k) pix[k] = k;
     or_lists L;
     lists_build(&F, v, pix, npix, &L);
     uint64_t acc = 0;
     for (int64_t k = 0; k < npix; ++k) {
         double rgb[3], T;
         uint64_t s;
-        composite(&F, L.items + L.start[k], L.start[k + 1] - L.start[k], (int)(k % v->width),
-                  (int)(k / v->width), -1, rgb, &T, NULL, NULL, &s);
-        acc = (acc ^ (s + (uint64_t)k * 0x9E3779B97F4A7C15ULL)) * 1099511628211ULL;
+        composite(&F, L.items + L.start[k], L.start[k + 1] - L.start[k], (int)(pix[k] % v->width),
+                  (int)(pix[k] / v->width), -1, rgb, &T, NULL, NULL, &s);
+        acc = (acc ^ (s + (uint64_t)pix[k] * 0x9E3779B97F4A7C15ULL)) * 1099511628211ULL;
     }
     lists_free(&L);
     frame_free(&F);
+    return acc;
+}
+
+/* The same over every pixel of the view. */
+uint64_t or_signature(const or_hier *h, const or_view *v, const int32_t *ids, const double *t, int64_t count)
+{
+    const int64_t npix = (int64_t)v->width * v->height;
+    int64_t *pix = (int64_t *)malloc(sizeof(int64_t) * (npix > 0 ? npix : 1));
+    for (int64_t k = 0; k < npix; ++k) pix[k] = k;
+    const uint64_t acc = or_signature_pix(h, v, ids, t, count, pix, npix);
     free(pix);
     return acc;
 }

@@ -56,6 +56,8 @@ def lib():
         L.or_render.restype = i64
         L.or_signature.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64]
         L.or_signature.restype = ctypes.c_uint64
+        L.or_signature_pix.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(i64), i64]
+        L.or_signature_pix.restype = ctypes.c_uint64
         L.or_backward.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(i64), i64, P(d), P(d), P(d), P(d)]
         L.or_sh_basis.argtypes = [P(d), P(d)]
         _lib = L
@@ -228,13 +230,19 @@ def render_image(h, v, ids=None, t=None):
     return r["rgb"].reshape(v.height, v.width, 3), r["T"].reshape(v.height, v.width)
 
 
-def signature(h, v, ids, t) -> int:
+def signature(h, v, ids, t, pix=None) -> int:
+    """Hash of the decisions (contributing sets and order, clamp states,
+    colour clamps) of every pixel, or of the linear pixel indices ``pix``."""
     H = _H(h)
     hs, vs = H.struct(), view_struct(v)
     ids = np.ascontiguousarray(ids, np.int32)
     t = np.ascontiguousarray(t, np.float64)
-    return int(lib().or_signature(ctypes.byref(hs), ctypes.byref(vs), _p(ids, ctypes.c_int32),
-                                  _p(t, ctypes.c_double), ids.shape[0]))
+    if pix is None:
+        return int(lib().or_signature(ctypes.byref(hs), ctypes.byref(vs), _p(ids, ctypes.c_int32),
+                                      _p(t, ctypes.c_double), ids.shape[0]))
+    pix = np.ascontiguousarray(pix, np.int64)
+    return int(lib().or_signature_pix(ctypes.byref(hs), ctypes.byref(vs), _p(ids, ctypes.c_int32),
+                                      _p(t, ctypes.c_double), ids.shape[0], _p(pix, ctypes.c_int64), pix.shape[0]))
 
 
 def backward(h, v, ids, t, dL_drgb, pix=None) -> dict:

@@ -706,3 +706,19 @@ def make_views(config: int, seed: int | None = None, headline: bool = False,
             out.append(look_dir((x, y, 1.7), yaw, pitch, w, hh, t))
         return out
     raise ValueError(config)
+
+
+def perturb_interior(h: Hierarchy, seed: int = 2024, sigma: float = 0.05) -> Hierarchy:
+    """The differentiation workload's target hierarchy: a copy of ``h`` whose
+    interior nodes have their means moved by N(0, sigma), their scales
+    multiplied by exp(N(0, sigma)) (a log-scale perturbation) and their SH
+    coefficients moved by N(0, sigma); leaves, boxes and topology unchanged."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    inner = h.child_count > 0
+    m = int(inner.sum())
+    hp = dataclasses.replace(h, mean=h.mean.copy(), scale=h.scale.copy(), sh=h.sh.copy())
+    hp.mean[:, inner] += rng.normal(0.0, sigma, size=(3, m)).astype(np.float32)
+    hp.scale[:, inner] *= np.exp(rng.normal(0.0, sigma, size=(3, m))).astype(np.float32)
+    hp.sh[:, inner] += rng.normal(0.0, sigma, size=(48, m)).astype(np.float32)
+    return hp

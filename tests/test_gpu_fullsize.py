@@ -16,7 +16,6 @@ against targets rendered from a perturbed hierarchy.
 """
 from __future__ import annotations
 
-import dataclasses
 import time
 
 import numpy as np
@@ -204,12 +203,7 @@ def c4_full():
     views = synth.make_views(4)
     # targets come from the same hierarchy with interior-node means, scales
     # and SH coefficients perturbed by N(0, 0.05) (log scale for the scales)
-    rng = np.random.default_rng(2024)
-    inner = h.child_count > 0
-    hp = dataclasses.replace(h, mean=h.mean.copy(), scale=h.scale.copy(), sh=h.sh.copy())
-    hp.mean[:, inner] += rng.normal(0.0, 0.05, size=(3, int(inner.sum()))).astype(np.float32)
-    hp.scale[:, inner] *= np.exp(rng.normal(0.0, 0.05, size=(3, int(inner.sum())))).astype(np.float32)
-    hp.sh[:, inner] += rng.normal(0.0, 0.05, size=(48, int(inner.sum()))).astype(np.float32)
+    hp = synth.perturb_interior(h, seed=2024)
     r = hgs.Renderer(0)
     r.upload(h)
     P = hgs.params_to_device(h)
