@@ -929,3 +929,161 @@ void or_backward(const or_hier *h, const or_view *v, const int32_t *ids, const d
     frame_free(&F);
 }
 
+
+/* ---------------------------------------------------------------------- */
+/* rounding budget of the gradient (test helper)                            */
+/* ---------------------------------------------------------------------- */
+/* A renderer that composites in FP32 (as the paper's rasteriser does) gets
+ * every per-pixel term of the gradient with an error of a few units in the
+ * last place of the quantities it is formed from, and the transmittance in
+ * front of a splat, recovered over the pixel's list, with an error that
+ * grows with the list: about one rounding per contributor in the forward
+ * product and one in each backward division.  A gradient element that sums
+ * many such terms of both signs can therefore be far smaller than the error
+ * those terms carry.  or_backward_budget returns, per parameter element,
+ *     B_e = sum over (pixel, splat) terms of (nc + 16) |term reaching e|,
+ * nc = the pixel's contributor count: every factor of the chain of
+ * or_backward taken in absolute value (a difference such as c - R counted
+ * as |c| + |R|), and the per-splat map from screen-space adjoints to the
+ * node and parent parameters taken column by column in absolute value
+ * (splat_backward applied to each unit screen adjoint).  An FP32 result
+ * then lies within about u B_e of the exact one (u = 2^-24 per rounding and
+ * a small constant per step); the caller chooses the constant.  Same
+ * arguments as or_backward; budget[OR_NPARAM * n] accumulates. */
+static void unit_param_adjoint(const or_hier *h, const or_view *v, const or_splat *S, int k, double out[2][OR_NPARAM])
+{
+    /* the splat's node (slot 1) and parent (slot 0) copied into a two-node
+     * hierarchy, so that splat_backward writes into a 2-column array */
+    double mean[6], scale[6], rot[8], op[2], sh[96];
+    int32_t par[2] = {-1, 0}, cb[2] = {1, 0}, cc[2] = {1, 0};
+    double bmn[6] = {0}, bmx[6] = {0};
+    const int64_t n = h->n;
+    const int32_t node = S->node, p = S->parent, pp = p >= 0 ? p : node;
+    for (int c = 0; c < 3; ++c) {
+        mean[2 * c] = h->mean[c * n + pp]; mean[2 * c + 1] = h->mean[c * n + node];
+        scale[2 * c] = h->scale[c * n + pp]; scale[2 * c + 1] = h->scale[c * n + node];
+    }
+    for (int c = 0; c < 4; ++c) { rot[2 * c] = h->rot[c * n + pp]; rot[2 * c + 1] = h->rot[c * n + node]; }
+    op[0] = h->opacity[pp]; op[1] = h->opacity[node];
+    for (int c = 0; c < 48; ++c) { sh[2 * c] = h->sh[c * n + pp]; sh[2 * c + 1] = h->sh[c * n + node]; }
+    or_hier h2 = {2, par, cb, cc, bmn, bmx, mean, scale, rot, op, sh};
+    or_splat S2 = *S;
+    S2.node = 1;
+    S2.parent = p >= 0 ? 0 : -1;
+    or_sgrad g;
+    memset(&g, 0, sizeof g);
+    switch (k) {  /* the 11 adjoints in the order du, dv, dconic, dA_n, dA_p, drgb, dt_alpha */
+    case 0: g.du = 1.0; break;
+    case 1: g.dv = 1.0; break;
+    case 2: case 3: case 4: g.dconic[k - 2] = 1.0; break;
+    case 5: g.dAn = 1.0; break;
+    case 6: g.dAp = 1.0; break;
+    case 7: case 8: case 9: g.drgb[k - 7] = 1.0; break;
+    default: g.dt_alpha = 1.0; break;
+    }
+    double tmp[OR_NPARAM * 2];
+    memset(tmp, 0, sizeof tmp);
+    splat_backward(&h2, v, &S2, &g, tmp, NULL);
+    for (int q = 0; q < OR_NPARAM; ++q) {
+        out[0][q] = tmp[q * 2 + 1];  /* node */
+        out[1][q] = p >= 0 ? tmp[q * 2] : 0.0;
+    }
+}
+
+void or_backward_budget(const or_hier *h, const or_view *v, const int32_t *ids, const double *t, int64_t count,
+                        const int64_t *pix, int64_t npix, const double *dL_drgb, double *budget)
+{
+    or_frame F;
+    frame_build(h, v, ids, t, count, &F);
+    or_lists L;
+    lists_build(&F, v, pix, npix, &L);
+    double *m = (double *)calloc((size_t)(count > 0 ? count : 1) * 11, sizeof(double));
+    int32_t *inc = NULL;
+    double *alph = NULL, *Tb = NULL;
+    int64_t cap = 0;
+    for (int64_t k = 0; k < npix; ++k) {
+        const int px = (int)(pix[k] % v->width), py = (int)(pix[k] / v->width);
+        const int32_t *items = L.items + L.start[k];
+        const int64_t mm = L.start[k + 1] - L.start[k];
+        const double *gC = dL_drgb + 3 * k;
+        if (mm > cap) {
+            cap = 2 * mm;
+            inc = (int32_t *)realloc(inc, sizeof(int32_t) * cap);
+            alph = (double *)realloc(alph, sizeof(double) * cap);
+            Tb = (double *)realloc(Tb, sizeof(double) * cap);
+        }
+        double T = 1.0;
+        int64_t nc = 0;
+        for (int64_t j = 0; j < mm; ++j) {
+            or_alpha_t a;
+            splat_alpha(&F.splats[items[j]], px, py, &a);
+            if (a.alpha < OR_ALPHA_MIN) continue;
+            const double Tn = T * (1.0 - a.alpha);
+            if (Tn < OR_T_MIN) break;
+            inc[nc] = items[j];
+            alph[nc] = a.alpha;
+            Tb[nc] = T;
+            nc++;
+            T = Tn;
+        }
+        const double wgt = (double)(nc + 16);
+        double after[3] = {0, 0, 0};
+        for (int64_t j = nc - 1; j >= 0; --j) {
+            const or_splat *S = &F.splats[inc[j]];
+            double *M = m + 11 * (int64_t)inc[j];
+            const double al = alph[j], Ti = Tb[j];
+            double dal = 0.0;
+            for (int ch = 0; ch < 3; ++ch) {
+                M[7 + ch] += wgt * fabs(al * Ti * gC[ch]);
+                dal += (Ti * S->rgb[ch] + fabs(after[ch]) / (1.0 - al)) * fabs(gC[ch]);
+            }
+            for (int ch = 0; ch < 3; ++ch) after[ch] += S->rgb[ch] * al * Ti;
+            or_alpha_t a;
+            splat_alpha(S, px, py, &a);
+            double dan, dap = 0.0;
+            if (S->t > 0.0) {
+                dan = (1.0 - S->t) * dal;
+                M[10] += wgt * (fabs(a.apr) + fabs(a.an)) * dal;
+                dap = S->t * dal * (1.0 / S->K) * pow(1.0 - a.ap, 1.0 / S->K - 1.0);
+            } else {
+                dan = dal;
+            }
+            double dG = 0.0;
+            if (!a.clamp_n) {
+                M[5] += wgt * dan * a.G;
+                dG += dan * S->A_n;
+            }
+            if (S->t > 0.0 && !a.clamp_p) {
+                M[6] += wgt * dap * a.G;
+                dG += dap * S->A_p;
+            }
+            const double dQ = 0.5 * a.G * dG;
+            M[0] += wgt * dQ * (2.0 * fabs(S->conic[0] * a.dx) + 2.0 * fabs(S->conic[1] * a.dy));
+            M[1] += wgt * dQ * (2.0 * fabs(S->conic[1] * a.dx) + 2.0 * fabs(S->conic[2] * a.dy));
+            M[2] += wgt * dQ * a.dx * a.dx;
+            M[3] += wgt * dQ * 2.0 * fabs(a.dx * a.dy);
+            M[4] += wgt * dQ * a.dy * a.dy;
+        }
+    }
+    free(inc);
+    free(alph);
+    free(Tb);
+    const int64_t n = h->n;
+    for (int64_t s = 0; s < count; ++s) {
+        const or_splat *S = &F.splats[s];
+        if (!S->valid) continue;
+        const double *M = m + 11 * s;
+        for (int k = 0; k < 11; ++k) {
+            if (M[k] == 0.0) continue;
+            double col[2][OR_NPARAM];
+            unit_param_adjoint(h, v, S, k, col);
+            for (int q = 0; q < OR_NPARAM; ++q) {
+                budget[(int64_t)q * n + S->node] += M[k] * fabs(col[0][q]);
+                if (S->parent >= 0) budget[(int64_t)q * n + S->parent] += M[k] * fabs(col[1][q]);
+            }
+        }
+    }
+    free(m);
+    lists_free(&L);
+    frame_free(&F);
+}

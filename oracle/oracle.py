@@ -59,6 +59,7 @@ def lib():
         L.or_signature_pix.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(i64), i64]
         L.or_signature_pix.restype = ctypes.c_uint64
         L.or_backward.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(i64), i64, P(d), P(d), P(d), P(d)]
+        L.or_backward_budget.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(i64), i64, P(d), P(d)]
         L.or_sh_basis.argtypes = [P(d), P(d)]
         _lib = L
     return _lib
@@ -267,6 +268,29 @@ def backward(h, v, ids, t, dL_drgb, pix=None) -> dict:
                       ids.shape[0], _p(pix, ctypes.c_int64), pix.shape[0], _p(gp, ctypes.c_double),
                       _p(grad, ctypes.c_double), _p(dt, ctypes.c_double), _p(scr, ctypes.c_double))
     return dict(grad=grad, dt=dt, screen=scr)
+
+
+def backward_budget(h, v, ids, t, dL_drgb, pix=None) -> np.ndarray:
+    """Rounding budget of the gradient of ``backward`` (same arguments):
+    per parameter element [59, n], the sum over its (pixel, splat) terms of
+    (contributors of the pixel + 16) times the term's magnitude with every
+    factor of the chain in absolute value.  A result composited in FP32 is
+    expected within a few 2^-24 of this of the exact gradient."""
+    H = _H(h)
+    ids = np.ascontiguousarray(ids, np.int32)
+    t = np.ascontiguousarray(t, np.float64)
+    g = np.ascontiguousarray(dL_drgb, np.float64).reshape(-1, 3)
+    assert g.shape[0] == v.width * v.height
+    if pix is None:
+        pix = np.arange(v.width * v.height, dtype=np.int64)
+    pix = np.ascontiguousarray(pix, np.int64)
+    gp = np.ascontiguousarray(g[pix])
+    out = np.zeros((NPARAM, H.n))
+    hs, vs = H.struct(), view_struct(v)
+    lib().or_backward_budget(ctypes.byref(hs), ctypes.byref(vs), _p(ids, ctypes.c_int32), _p(t, ctypes.c_double),
+                             ids.shape[0], _p(pix, ctypes.c_int64), pix.shape[0], _p(gp, ctypes.c_double),
+                             _p(out, ctypes.c_double))
+    return out
 
 
 def sh_basis(d) -> np.ndarray:

@@ -73,10 +73,22 @@ def near_nodes(h, v, ids, t, depth=NEAR_DEPTH):
     return m
 
 
-def check_grads(gpu: dict, og: np.ndarray, leaf_mask, rel=GRAD_REL):
+# Rounding of an FP32 composite, per unit of the oracle's rounding budget
+# (oracle.backward_budget weighs every term by its pixel's contributor count
+# + 16): the transmittance in front of a splat carries about one rounding
+# per contributor from the forward product and one and a half from each
+# backward division, and a term's own chain (G, alpha, the products) a
+# handful; four units of 2^-24 per weight unit cover both.
+BUDGET_U = 4.0 * 2.0 ** -24
+
+
+def check_grads(gpu: dict, og: np.ndarray, leaf_mask, rel=GRAD_REL, budget=None):
     """Per parameter group: relative L2 error (`rel`, to be <= GRAD_REL) and
-    the per-element bound |diff| <= GRAD_REL * max(|g|, 1e-3 rms(group)) over
-    every node (`n_bad` elements violate it)."""
+    the per-element bound over every node (`n_bad` elements violate it):
+        |diff| <= GRAD_REL * max(|g|, 1e-3 rms(group)) + BUDGET_U * B,
+    B = the oracle's rounding budget of the element (oracle.backward_budget,
+    same layout as og), which only matters where the element is a sum of
+    terms that cancel far below their own size; None: no budget term."""
     out = {}
     for name, (a, b) in O.SLOTS.items():
         ref = og[a:b].copy()
@@ -87,10 +99,16 @@ def check_grads(gpu: dict, og: np.ndarray, leaf_mask, rel=GRAD_REL):
         err = np.linalg.norm(g - ref)
         rms = nrm / np.sqrt(ref.size)
         bound = rel * np.maximum(np.abs(ref), 1e-3 * rms) + 1e-30
+        plain = np.abs(g - ref) <= bound
+        if budget is not None:
+            bb = BUDGET_U * budget[a:b].copy()
+            bb[:, leaf_mask] = 0.0
+            bound = bound + bb
         elem = np.abs(g - ref) <= bound
         ratio = np.abs(g - ref) / bound
+        # n_budget: elements within the bound only thanks to the budget term
         out[name] = dict(rel=float(err / max(nrm, 1e-30)), n_bad=int((~elem).sum()), norm=float(nrm),
-                         worst=float(ratio.max(initial=0.0) * rel))
+                         worst=float(ratio.max(initial=0.0) * rel), n_budget=int((elem & ~plain).sum()))
         if not elem.all():  # where the worst elements are: (component, column, oracle, GPU)
             top = np.argsort(ratio, axis=None)[::-1][:4]
             out[name]["at"] = [(int(c), int(j), float(ref[c, j]), float(g[c, j]))

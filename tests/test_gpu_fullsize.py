@@ -161,14 +161,16 @@ def test_backward_sampled_two_views(full):
     nodes = np.unique(np.concatenate([np.concatenate([ids, parent[ids][parent[ids] >= 0]]) for ids, _ in
                                       cuts.values()]))
     og = np.zeros((O.NPARAM, nodes.size))
+    ob_budget = np.zeros((O.NPARAM, nodes.size))
     near = np.zeros(nodes.size, bool)  # reported: nodes whose splat lies within a metre of the eye
     dt_err, dt_ref = 0.0, 0.0
     for k, (oids, ot) in cuts.items():
         v = views[k]
-        ob = O.backward(H, v, oids, ot, dL[k].cpu().numpy().astype(np.float64).reshape(-1, 3),
-                        pix=full["pix"][k])
+        cot = dL[k].cpu().numpy().astype(np.float64).reshape(-1, 3)
+        ob = O.backward(H, v, oids, ot, cot, pix=full["pix"][k])
         og += ob["grad"][:, nodes]
         del ob["grad"]
+        ob_budget += O.backward_budget(H, v, oids, ot, cot, pix=full["pix"][k])[:, nodes]
         near |= PR.near_nodes(H, v, oids, ot)[nodes]
         pr = O.project(H, v, oids, ot)
         m = ot > 0
@@ -179,7 +181,7 @@ def test_backward_sampled_two_views(full):
     idx = torch.from_numpy(nodes).cuda()
     gpu = {k: grads[k].view(h.n_nodes, -1)[idx].cpu().numpy() for k in hgs.PARAM_FIELDS}
     leaf = (np.asarray(h.child_count) == 0)[nodes]
-    res = PR.check_grads(gpu, og, leaf)
+    res = PR.check_grads(gpu, og, leaf, budget=ob_budget)
     dt_rel = float(np.sqrt(dt_err / max(dt_ref, 1e-60)))
     _log(f"{full['name']}: views {GRAD_VIEWS}, {nodes.size} nodes ({int(near.sum())} near), "
          f"{amb_total} ambiguous pixels without cotangent: {res}, dt rel {dt_rel:.2e}")
@@ -243,13 +245,15 @@ def test_l1_gradient_against_perturbed_targets_8x720p(c4_full):
     r.backward(dL, grads)
     torch.cuda.synchronize()
     og = np.zeros((O.NPARAM, h.n_nodes))
+    budget = np.zeros((O.NPARAM, h.n_nodes))
     near = np.zeros(h.n_nodes, bool)
     for (v, oids, ot, pix), g in zip(per_view, dL):
-        ob = O.backward(H, v, oids, ot, g.cpu().numpy().astype(np.float64).reshape(-1, 3), pix=pix)
-        og += ob["grad"]
+        cot = g.cpu().numpy().astype(np.float64).reshape(-1, 3)
+        og += O.backward(H, v, oids, ot, cot, pix=pix)["grad"]
+        budget += O.backward_budget(H, v, oids, ot, cot, pix=pix)
         near |= PR.near_nodes(H, v, oids, ot)
     gpu = {k: grads[k].cpu().numpy() for k in hgs.PARAM_FIELDS}
-    res = PR.check_grads(gpu, og, h.child_count == 0)
+    res = PR.check_grads(gpu, og, h.child_count == 0, budget=budget)
     _log(f"box2m_8x720p L1: {int(near.sum())} near nodes among those checked: {res}")
     for name, rr in res.items():
         assert rr["norm"] > 0.0, name

@@ -74,6 +74,14 @@ MUTATIONS = [
     ("skip guard taken on the absolute difference", C,
      "if (fabs(a.alpha / OR_ALPHA_MIN - 1.0) < OR_GUARD) {", "if (fabs(a.alpha - OR_ALPHA_MIN) < OR_GUARD) {", PINS),
     ("clamp ambiguity not reported", C, "            nclamp++;", "            ;", PINS),
+    # the rounding budget that sizes the per-element gradient tolerance
+    ("budget drops the parent's share", C,
+     "if (S->parent >= 0) budget[(int64_t)q * n + S->parent] += M[k] * fabs(col[1][q]);", ";", PINS),
+    ("budget takes c - R with its sign", C,
+     "dal += (Ti * S->rgb[ch] + fabs(after[ch]) / (1.0 - al)) * fabs(gC[ch]);",
+     "dal += (Ti * S->rgb[ch] - after[ch] / (1.0 - al)) * gC[ch];", PINS),
+    ("budget without the contributor weight", C, "const double wgt = (double)(nc + 16);", "const double wgt = 1.0;",
+     PINS),
     # the compaction of Sec. 5.2, step by step
     ("removal does not stop at marked nodes", PY,
      "                if marked[c]:\n                    continue\n", "", COMPACT_PINS),

@@ -633,6 +633,47 @@ def test_backward_central_differences_uniform_over_interior_nodes():
     assert n_i >= 8, (n_i, rej_i)
 
 
+def test_rounding_budget_bounds_every_gradient_element():
+    # the budget sums (contributors + 16) |term| over the same terms as the
+    # gradient, so it is at least 16 |gradient| on every element, and it is
+    # nonzero wherever a term reaches an element (a node or parent share
+    # that it dropped would show as B = 0 under a nonzero gradient); on a
+    # pixel stack of one splat it has no cancellation to absorb
+    H, v, ids, t, w = _fd_setup()
+    g = O.backward(H, v, ids, t, w)["grad"]
+    B = O.backward_budget(H, v, ids, t, w)
+    assert (B >= 16.0 * np.abs(g) * (1.0 - 1e-12)).all()
+    par = H.parent[ids]
+    touched = np.unique(np.concatenate([ids, par[par >= 0]]))
+    untouched = np.setdiff1d(np.arange(H.n), touched)
+    assert (B[:, untouched] == 0.0).all()
+    lerp_parents = np.unique(par[(t > 0) & (par >= 0)])
+    assert (B[:, lerp_parents].max(0) > 0.0).all()
+    # cancellation shows as B far above 16 |g| on some elements
+    ratio = B[:, touched].ravel() / np.maximum(16.0 * np.abs(g[:, touched]).ravel(), 1e-300)
+    assert np.quantile(ratio[np.abs(g[:, touched]).ravel() > 0], 0.99) > 10.0
+
+
+def test_rounding_budget_single_pixel_single_splat():
+    # one isotropic splat on the optical axis, one pixel, cotangent (1, 0, 0)
+    # on red only: every term reaches each element once, with one sign, so
+    # the budget is exactly (1 + 16) times the gradient's magnitude on the
+    # colour (SH) elements the red channel reaches
+    h = S.hierarchy([-1], [[0.0, 0.0, 4.0]], [[0.05, 0.05, 0.05]], [[1, 0, 0, 0]], [0.8],
+                    np.full((1, 48), 0.1))
+    v = S.axis_view(8, 8, 40.0)
+    H = O.Hier(h)
+    ids, t = O.cut(H, v)
+    w = np.zeros((8, 8, 3))
+    w[4, 4, 0] = 1.0
+    pix = np.array([4 * 8 + 4])
+    g = O.backward(H, v, ids, t, w, pix=pix)["grad"]
+    B = O.backward_budget(H, v, ids, t, w, pix=pix)
+    red = [11 + 3 * k for k in range(16)]
+    assert np.abs(g[red, 0]).max() > 0
+    np.testing.assert_allclose(B[red, 0], 17.0 * np.abs(g[red, 0]), rtol=1e-12, atol=0)
+
+
 def test_absolute_value_opacity_activation():
     # the renderer uses |o| (Sec. 7.3): flipping the sign of interior
     # opacities leaves the image unchanged and negates exactly their opacity
