@@ -39,18 +39,17 @@ WORKLOADS = {
 }
 DEFAULT = "corridor30m_32x1080p_tau6"
 
-# Algorithmic FP32 operations per (pixel, splat) pair of the blend kernels
-# (transcendentals and compares counted as one): an evaluation takes 15 (the
-# pixel's offsets on the two axes 4, the quadratic form 3, exp2 1, A G 1,
-# the 0.99 clamp 1, two compares, T (1 - alpha) 2) and 11 more when t > 0
-# (the parent's term, log2, multiply, exp2, 1 - x, the lerp); a blended pair
-# 10 more (alpha T, three colour FMAs, the T update, bookkeeping).  The
-# backward re-evaluates (15, +11) and takes 47 per contributing pair (+10
-# when t > 0: the alpha' chain).
-F_EVAL, F_EVAL_T, F_BLEND = 15, 11, 10
-F_BWD_CONTRIB, F_BWD_CONTRIB_T = 47, 10
-PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU, 2.4 GHz)
-
+# Algorithmic FP32 work of the blend kernels, in the units of the scope
+# table's measurement row: per evaluated (pixel, splat) pair about 16
+# lane-operations (the quadratic form, the two clamps and compares, the
+# colour and transmittance FMAs) plus one transcendental (exp2), and 4 more
+# (log2, exp2, two FMAs) when the splat is interpolated (t > 0); the
+# backward about three times the forward's work per contributing pair.
+F_PAIR, F_PAIR_T = 17, 4
+BWD_FACTOR = 3
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU, 2.4 GHz, packed)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # without packed FP32 (one FMA per lane and clock)
+PEAK_HBM_GBS = 8000.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -95,8 +94,10 @@ def cpu_baseline(h, view, row_stride: int = 1):
     pix = (rows[:, None] * view.width + np.arange(view.width)[None, :]).reshape(-1)
     frac = pix.size / float(view.width * view.height)
     t0 = time.perf_counter()
-    O.render(H, view, ids, t, pix=pix if row_stride > 1 else None, alternatives=False)
+    o = O.render(H, view, ids, t, pix=pix if row_stride > 1 else None, alternatives=False)
     t_render = time.perf_counter() - t0
+    blends = int(o["nblend"].sum())
+    del o
     rng = np.random.default_rng(0)
     dL = np.zeros((view.height * view.width, 3))
     dL[pix] = rng.normal(size=(pix.size, 3))
@@ -112,7 +113,7 @@ def cpu_baseline(h, view, row_stride: int = 1):
                         f"{t_cut:.2f}s), forward ({t_render:.2f}s) and backward ({t_bwd:.2f}s) over {what}; FP64 "
                         f"widening of the hierarchy ({t_prep:.1f}s) not counted"),
                 seconds=dict(cut=t_cut, render=t_render, backward=t_bwd, full_view_estimate=t_view),
-                cpu_model=cpu_model())
+                blends_per_s_forward=blends / t_render, cpu_model=cpu_model()), H
 
 
 def cpu_model() -> str:
@@ -309,6 +310,109 @@ def load_traffic(workload: str, kernel: str):
     return d.get("bytes_per_launch")
 
 
+def _omp_threads(n: int) -> None:
+    """Sets the OpenMP thread count of this (host) thread's later parallel
+    regions, such as the oracle's."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+    except OSError:
+        pass
+
+
+def cpu_one_core(H, view, row_stride: int) -> dict:
+    """The oracle on one host core (the OpenMP regions of this thread set to
+    one thread): the cut and the forward and backward of every
+    `row_stride`-th pixel row of one view, scaled to the whole view, with
+    its blended-pair count (blends/s of the forward).  H: the oracle's FP64
+    copy of the hierarchy."""
+    import numpy as np
+    from oracle import oracle as O
+    v = view
+    _omp_threads(1)
+    try:
+        t0 = time.perf_counter()
+        ids, t = O.cut(H, v)
+        t_cut = time.perf_counter() - t0
+        rows = np.arange(0, v.height, row_stride)
+        pix = (rows[:, None] * v.width + np.arange(v.width)[None, :]).reshape(-1)
+        frac = pix.size / float(v.width * v.height)
+        t0 = time.perf_counter()
+        o = O.render(H, v, ids, t, pix=pix, alternatives=False)
+        t_render = time.perf_counter() - t0
+        blends = int(o["nblend"].sum())
+        dL = np.zeros((v.height * v.width, 3))
+        dL[pix] = np.random.default_rng(0).normal(size=(pix.size, 3))
+        t0 = time.perf_counter()
+        O.backward(H, v, ids, t, dL, pix=pix)
+        t_bwd = time.perf_counter() - t0
+    finally:
+        _omp_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    t_view = t_cut + (t_render + t_bwd) / frac
+    return dict(value=1.0 / t_view, unit="views/s", cores=1, kind="oracle",
+                sample=(f"1 view ({v.width}x{v.height}, tau={v.tau:g}): cut ({len(ids)} nodes) and forward + "
+                        f"backward over every {row_stride}th pixel row ({frac:.4f} of the pixels), scaled to the "
+                        f"whole view"),
+                blends_per_s_forward=blends / t_render,
+                seconds=dict(cut=t_cut, render=t_render, backward=t_bwd, full_view_estimate=t_view))
+
+
+def forward_leg(name: str, steps: int, taus=(6.0,), plain: bool = True) -> dict:
+    """Forward throughput of another workload: its scene and views, the
+    autotuned forward, batched (one call for every view) and, with `plain`,
+    one call per view; per tau when several are given (single-view
+    workloads: plain only)."""
+    import torch
+    from paper_2406_12080_amd import hgs
+    from paper_2406_12080_amd.autotune import autotune
+    h, views = build_workload(name)
+    r = hgs.Renderer(0)
+    r.upload(h)
+    P = hgs.params_to_device(h)
+    r.bind(*[P[k] for k in hgs.PARAM_FIELDS])
+    out = dict(workload=name, leaves=h.n_leaves, nodes=h.n_nodes, views=len(views), per_tau={})
+    for tau in taus:
+        vs = [v.replace(tau=tau) for v in views]
+        imgs = [torch.empty((v.height, v.width, 3), device="cuda") for v in vs]
+        r.render(vs, out=imgs)
+        tuning = autotune(r, vs, step=lambda: r.render(vs, out=imgs), log=lambda m: log(f"[bench] {name} {m}"))
+        res = dict(tuning={k: tuning[k] for k in ("tile_w", "tile_h", "batch", "persistent")})
+        r.render(vs, out=imgs)
+        torch.cuda.synchronize()
+        if len(vs) > 1:
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, st = r.render(vs, out=imgs)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            res.update(ms_batched=round(dt * 1e3, 3), views_per_s_batched=round(len(vs) / dt, 3),
+                       blends_per_s_batched=round(st["blended"] / dt, 1), blended=st["blended"], cut=st["cut"],
+                       pairs=st["pairs"])
+        if plain:
+            for k, v in enumerate(vs):
+                r.render([v], out=[imgs[k]])
+            torch.cuda.synchronize()
+            reps = max(1, steps // 4) if len(vs) > 1 else steps
+            blended = 0
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                blended = 0
+                for k, v in enumerate(vs):
+                    _, st1 = r.render([v], out=[imgs[k]])
+                    blended += st1["blended"]
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            res.update(ms_plain=round(dt * 1e3, 3), views_per_s_plain=round(len(vs) / dt, 3),
+                       blends_per_s_plain=round(blended / dt, 1))
+        log(f"[bench] {name} tau {tau:g}: {res}")
+        out["per_tau"][f"{tau:g}"] = res
+        del imgs
+    r.close()
+    del P
+    torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,14 +420,20 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--leaves", type=int, default=None, help="override the leaf count (smaller runs)")
-    ap.add_argument("--tile", default=None, help="WxHxB, skips the autotuner (e.g. 16x16x256)")
+    ap.add_argument("--tile", default=None, help="WxHxB[p], skips the autotuner (e.g. 16x16x256, 8x8x64p)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-row-stride", type=int, default=1)
-    ap.add_argument("--optimize", type=int, default=0, metavar="K",
+    ap.add_argument("--cpu-one-core-stride", type=int, default=24,
+                    help="pixel-row stride of the one-core oracle sample (0: skip it)")
+    ap.add_argument("--optimize", type=int, default=100, metavar="K",
                     help="also time K steps of the hierarchy optimisation (corridor workloads): every step new "
                          "eyes and tau log-uniform over the workload's range, render, backward and an Adam step "
-                         "on the interior nodes (reported under 'optimize'; `value` stays the fwd+bwd step)")
+                         "on the interior nodes (reported under 'optimize'; `value` stays the fwd+bwd step); "
+                         "0 skips it")
+    ap.add_argument("--other-workloads", type=int, default=1,
+                    help="1: also the forward legs of the 1M-leaf single view (tau 3, 6, 15) and of the 8M-leaf "
+                         "corridor's 64 views (batched vs plain); 0: skip them")
     ap.add_argument("--compact", type=int, default=0, metavar="V",
                     help="also time the GPU marking of the hierarchy compaction over V training views "
                          "(reported under 'compaction')")
@@ -334,7 +444,6 @@ def main(argv=None):
                     help="first copy this many MiB device to device (a known-size transfer that calibrates "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     args = ap.parse_args(argv)
-
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
               "(views would shard across GPUs with no communication in the forward and one reduction of "
@@ -385,28 +494,38 @@ def main(argv=None):
     step_batched()  # sizes the workspaces
     torch.cuda.synchronize()
     if args.tile:
-        tw, th, b = (int(x) for x in args.tile.split("x"))
-        r.set_tuning(tw, th, b)
-        tuning = dict(tile_w=tw, tile_h=th, batch=b)
+        spec = args.tile.rstrip("p")
+        tw, th, b = (int(x) for x in spec.split("x"))
+        pers = 1 if args.tile.endswith("p") else 0
+        r.set_tuning(tw, th, b, pers)
+        tuning = dict(tile_w=tw, tile_h=th, batch=b, persistent=pers)
     else:
         tuning = autotune(r, views, P)
     log(f"[bench] tuning {tuning}")
 
-    r.set_profiling(True)  # the blend then runs right after the graph, bracketed by events
+    # timed region: graphs as shipped, no events inside
+    r.set_profiling(False)
     for _ in range(max(args.warmup, 1)):
         step_batched()
-    torch.cuda.synchronize()
-    r.set_profiling(True)  # resets the kernel totals; the captured graph stays valid
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step_batched()
     torch.cuda.synchronize()
     t_batched = (time.perf_counter() - t0) / args.steps
-    k_ms = {k: r.kernel_time(k) for k in (hgs.K_BLEND, hgs.K_BLEND_BWD, hgs.K_PREPROCESS_BWD)}
-    r.set_profiling(False)
     ctr = r.counters()
     log(f"[bench] batched fwd+bwd {t_batched * 1e3:.2f} ms/step, counters {ctr}")
+
+    # kernel times from a separate profiled pass (events around the blend,
+    # its backward and the preprocess backward; the blend then runs right
+    # after the forward graph and the backward without a graph)
+    r.set_profiling(True)
+    n_prof = max(3, min(args.steps, 5))
+    for _ in range(n_prof):
+        step_batched()
+    torch.cuda.synchronize()
+    k_ms = {k: r.kernel_time(k) for k in (hgs.K_BLEND, hgs.K_BLEND_BWD, hgs.K_PREPROCESS_BWD)}
+    r.set_profiling(False)
 
     # forward only, batched
     fwd_batched()
@@ -424,7 +543,7 @@ def main(argv=None):
     stages_plain = {n: round(float(x), 4) for n, x in zip(stage_names, st1["ms"])}
     log(f"[bench] stages of one view rendered alone (ms): {stages_plain}")
 
-    t_plain = None
+    t_plain = t_plain_fwd = None
     if not args.no_plain:
         step_plain()
         torch.cuda.synchronize()
@@ -435,9 +554,15 @@ def main(argv=None):
         torch.cuda.synchronize()
         t_plain = (time.perf_counter() - t0) / reps
         log(f"[bench] plain fwd+bwd {t_plain * 1e3:.2f} ms/step")
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for k, v in enumerate(views):
+                r.render([v], out=[imgs[k]])
+        torch.cuda.synchronize()
+        t_plain_fwd = (time.perf_counter() - t0) / reps
 
     opt = None
-    if args.optimize > 0:
+    if args.optimize > 0 and WORKLOADS[args.workload]["config"] in (3, 5):
         opt = optimize_steps(r, h, P, grads, imgs, dL, args.workload, args.optimize)
     cmp = None
     if args.compact > 0:
@@ -449,10 +574,10 @@ def main(argv=None):
     # roofline of the dominant kernel (the longer of blend and blend backward)
     ms_blend, n_blend = k_ms[hgs.K_BLEND]
     ms_bwd, n_bwd = k_ms[hgs.K_BLEND_BWD]
-    flops_fwd = F_EVAL * ctr["evaluated"] + F_EVAL_T * ctr["evaluated_t"] + F_BLEND * ctr["blended"]
-    tfrac = ctr["bwd_evaluated_t"] / max(ctr["bwd_evaluated"], 1)
-    flops_bwd = (F_EVAL * ctr["bwd_evaluated"] + F_EVAL_T * ctr["bwd_evaluated_t"] +
-                 (F_BWD_CONTRIB + F_BWD_CONTRIB_T * tfrac) * ctr["bwd_contrib"])
+    tfrac = ctr["evaluated_t"] / max(ctr["evaluated"], 1)
+    per_pair = F_PAIR + F_PAIR_T * tfrac
+    flops_fwd = per_pair * ctr["evaluated"]
+    flops_bwd = BWD_FACTOR * per_pair * ctr["bwd_contrib"]
     if ms_bwd >= ms_blend:
         kname, avg_ms, flops = "k_blend_bwd", ms_bwd / max(n_bwd, 1), flops_bwd
     else:
@@ -460,8 +585,12 @@ def main(argv=None):
     achieved = flops / (avg_ms * 1e-3) / 1e12
     traffic = load_traffic(args.workload, kname)
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=traffic, kernel=kname,
+                    frac=round(achieved / PEAK_FP32_TFLOPS, 4),
+                    frac_nonpacked=round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4), traffic=traffic, kernel=kname,
                     avg_launch_ms=round(avg_ms, 4), flops_per_launch=int(flops),
+                    flops_unit=(f"{F_PAIR} + {F_PAIR_T} t-share per evaluated pair (forward); {BWD_FACTOR} x that "
+                                f"per contributing pair (backward)"),
+                    evaluated_per_contributing=round(ctr["bwd_evaluated"] / max(ctr["bwd_contrib"], 1), 3),
                     other_kernels_avg_ms={"k_blend": round(ms_blend / max(n_blend, 1), 4),
                                           "k_blend_bwd": round(ms_bwd / max(n_bwd, 1), 4),
                                           "k_preprocess_bwd+k_grad_gather": round(k_ms[hgs.K_PREPROCESS_BWD][0] /
@@ -470,7 +599,10 @@ def main(argv=None):
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
-        cpu = cpu_baseline(h, views[0], args.cpu_row_stride)
+        cpu, H = cpu_baseline(h, views[0], args.cpu_row_stride)
+        if args.cpu_one_core_stride > 0:
+            cpu["one_core"] = cpu_one_core(H, views[0], args.cpu_one_core_stride)
+        del H
         log(f"[bench] cpu {cpu}")
 
     v0 = views[0]
@@ -489,14 +621,16 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": args.workload, "leaves": h.n_leaves, "nodes": h.n_nodes, "views": nv,
                    "width": v0.width, "height": v0.height, "tau": v0.tau, "mode": "batched fwd+bwd",
-                   "tuning": tuning},
+                   "tuning": {k: tuning[k] for k in ("tile_w", "tile_h", "batch", "persistent")}},
         "blends_per_s": round(ctr["blended"] / t_batched, 1),
         "views_per_s_plain": round(nv / t_plain, 3) if t_plain else None,
         "views_per_s_fwd_batched": round(nv / t_fwd, 3),
+        "views_per_s_fwd_plain": round(nv / t_plain_fwd, 3) if t_plain_fwd else None,
         "blends_per_s_fwd_batched": round(ctr["blended"] / t_fwd, 1),
         "ms_per_step_plain": round(t_plain * 1e3, 3) if t_plain else None,
         "stages_ms_one_view": stages_plain,
         "counters_per_step": ctr,
+        "autotune_ms": tuning.get("ms"),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -506,8 +640,15 @@ def main(argv=None):
         out["compaction"] = cmp
     if conv is not None:
         out["convergence"] = conv
-    print(json.dumps(out), flush=True)
     r.close()
+    del P, grads, imgs, dL
+    torch.cuda.empty_cache()
+    if args.other_workloads and args.leaves is None:
+        legs = {}
+        legs["box1m_1x1080p"] = forward_leg("box1m_1x1080p_tau6", args.steps, taus=(3.0, 6.0, 15.0))
+        legs["corridor8m_64x1080p_tau6"] = forward_leg("corridor8m_64x1080p_tau6", max(args.steps // 2, 3))
+        out["forward_legs"] = legs
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -222,6 +222,24 @@ typedef struct {
 hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const float *const *dL_drgb,
                                hgs_grads *out);
 
+/* Loss of the hierarchy optimisation for the render `render_id` (the last
+ * hgs_render on ctx, n_views views): the mean absolute difference between
+ * its images out_rgb[v] and the targets, over every pixel and channel of
+ * every view (the paper optimises the interior nodes against the training
+ * images, Sec. 5.1; L1 is the image term of 3D Gaussian Splatting's loss),
+ *   loss = (1/M) sum |C - C*|,   dL_drgb[v] = sign(C - C*) / M  (sign(0) = 0),
+ * M = 3 x the pixel count of all views.  target and dL_drgb: host arrays of
+ * n_views device pointers, float[height][width][3] of view v; dL_drgb is
+ * written (it is the cotangent hgs_render_backward takes).  loss: device
+ * pointer to one double, written.  The sum is taken in FP64 in a fixed
+ * order.  Reads the images the render wrote, so they must be unchanged
+ * since.  Queued on the ctx stream; does not synchronise.
+ * Errors: HGS_ERR_STATE when render_id is not the render ctx holds;
+ * HGS_ERR_INVALID_ARG when n_views differs from its view count or a pointer
+ * is NULL. */
+hgs_status hgs_l1_loss(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const float *const *target,
+                       float *const *dL_drgb, double *loss);
+
 /* One step of the optimiser of the hierarchy optimisation (Sec. 5.1, the
  * paragraph on optimising the generated hierarchy): interior nodes only,
  * the leaves stay unchanged; the paper does not name the optimiser for this
@@ -248,11 +266,15 @@ typedef struct {
 } hgs_adam;
 hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a);
 
-/* Tuning knobs of the blend stage (chosen by the autotuner): tile edge
- * tile_w x tile_h in {8x8, 16x8, 16x16, 32x16} and splats staged per batch
- * (a multiple of 64 up to 1024; 0 = one per thread).  Changing them keeps
- * images bit-identical.  HGS_ERR_INVALID_ARG for other values. */
-hgs_status hgs_set_tuning(hgs_ctx *ctx, int32_t tile_w, int32_t tile_h, int32_t batch);
+/* Tuning knobs of the blend stage and its backward (chosen by the
+ * autotuner): tile edge tile_w x tile_h in {8x8, 16x8, 16x16, 32x16},
+ * splats staged per batch (a multiple of 64 up to 1024; 0 = one per
+ * thread), and the work distribution: persistent = 0 launches one workgroup
+ * per tile, 1 a persistent grid of as many workgroups as the device holds
+ * at once, which take tiles (longest lists first) from a device-side queue
+ * until none is left.  Changing them keeps images bit-identical.
+ * HGS_ERR_INVALID_ARG for other values. */
+hgs_status hgs_set_tuning(hgs_ctx *ctx, int32_t tile_w, int32_t tile_h, int32_t batch, int32_t persistent);
 
 /* Kernel timing for benchmarks: with profiling on, selected launches are
  * bracketed by HIP events on the stream they run on (in a multi-view render

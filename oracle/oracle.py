@@ -15,6 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hgs_oracle.c")
+SRC_BUILD = os.path.join(HERE, "build_oracle.c")
 LIB = os.path.join(HERE, "_build", "liboracle.so")
 
 NPARAM = 59
@@ -31,7 +32,7 @@ def build() -> str:
     os.makedirs(os.path.dirname(LIB), exist_ok=True)
     tmp = LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                           "-shared", "-o", tmp, SRC, "-lm"])
+                           "-shared", "-o", tmp, SRC, SRC_BUILD, "-lm"])
     os.replace(tmp, LIB)
     return LIB
 
@@ -61,8 +62,25 @@ def lib():
         L.or_backward.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(i64), i64, P(d), P(d), P(d), P(d)]
         L.or_backward_budget.argtypes = [P(_OHier), P(_OView), P(i32), P(d), i64, P(i64), i64, P(d), P(d)]
         L.or_sh_basis.argtypes = [P(d), P(d)]
+        L.ob_count.argtypes = [P(_OLeaves)]
+        L.ob_count.restype = i64
+        L.ob_build.argtypes = [P(_OLeaves), i64, P(i32), P(i32), P(i32), P(i32), P(d), P(d), P(d), P(d), P(d),
+                               P(ctypes.c_float), P(ctypes.c_float)]
+        L.ob_surface.argtypes = [P(d)]
+        L.ob_surface.restype = d
+        L.ob_eigen.argtypes = [P(d), P(d), P(d)]
+        L.ob_match.argtypes = [P(d), P(d), P(d), P(d), P(d)]
         _lib = L
     return _lib
+
+
+class _OLeaves(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64),
+                ("pos", ctypes.POINTER(ctypes.c_double)),
+                ("scale", ctypes.POINTER(ctypes.c_double)),
+                ("rot", ctypes.POINTER(ctypes.c_double)),
+                ("opacity", ctypes.POINTER(ctypes.c_double)),
+                ("sh", ctypes.POINTER(ctypes.c_double))]
 
 
 class _OHier(ctypes.Structure):
@@ -370,3 +388,68 @@ def compact_keep(h, views, tau_min: float = 3.0, tau_max: float | None = None) -
         marked |= bottom
         tau *= 2.0
     return ~removed
+
+
+# ---------------------------------------------------------------------------
+# hierarchy generation (Sec. 4.1; orientation matching of Sec. 4.2)
+# ---------------------------------------------------------------------------
+def build_hierarchy(leaves: dict) -> dict:
+    """The hierarchy over the leaves, by the plain FP64 definition in
+    ``build_oracle.c``.  ``leaves``: FP32 arrays pos [n, 3], scale [n, 3],
+    rot [n, 4] (w, x, y, z), opacity [n], sh [n, 48] (widened here).
+    Returns component-major arrays in the storage layout of a hierarchy
+    (parent, child_begin, child_count, leaf_src int32 [N]; mean, scale [3, N],
+    rot [4, N], opacity [N], sh [48, N] as FP32 rounded to the nearest;
+    bmin, bmax [3, N] FP32 rounded outward) and the FP64 values before that
+    rounding under ``*64`` keys."""
+    n = int(np.asarray(leaves["pos"]).shape[0])
+    cm = {k: np.ascontiguousarray(np.asarray(leaves[k], np.float32).astype(np.float64).reshape(n, -1).T)
+          for k in ("pos", "scale", "rot", "sh")}
+    op = np.ascontiguousarray(np.asarray(leaves["opacity"], np.float32).astype(np.float64))
+    s = _OLeaves()
+    s.n = n
+    for k in ("pos", "scale", "rot", "sh"):
+        setattr(s, k, _p(cm[k], ctypes.c_double))
+    s.opacity = _p(op, ctypes.c_double)
+    L = lib()
+    N = int(L.ob_count(ctypes.byref(s)))
+    out = dict(parent=np.zeros(N, np.int32), child_begin=np.zeros(N, np.int32), child_count=np.zeros(N, np.int32),
+               leaf_src=np.zeros(N, np.int32))
+    f64 = dict(mean=np.zeros((3, N)), scale=np.zeros((3, N)), rot=np.zeros((4, N)), opacity=np.zeros(N),
+               sh=np.zeros((48, N)))
+    bmin = np.zeros((3, N), np.float32)
+    bmax = np.zeros((3, N), np.float32)
+    L.ob_build(ctypes.byref(s), N, _p(out["parent"], ctypes.c_int32), _p(out["child_begin"], ctypes.c_int32),
+               _p(out["child_count"], ctypes.c_int32), _p(out["leaf_src"], ctypes.c_int32),
+               _p(f64["mean"], ctypes.c_double), _p(f64["scale"], ctypes.c_double), _p(f64["rot"], ctypes.c_double),
+               _p(f64["opacity"], ctypes.c_double), _p(f64["sh"], ctypes.c_double), _p(bmin, ctypes.c_float),
+               _p(bmax, ctypes.c_float))
+    for k, a in f64.items():
+        out[k] = a.astype(np.float32)
+        out[k + "64"] = a
+    out["bmin"], out["bmax"] = bmin, bmax
+    return out
+
+
+def ellipsoid_surface(s) -> float:
+    s = np.ascontiguousarray(s, np.float64)
+    return float(lib().ob_surface(_p(s, ctypes.c_double)))
+
+
+def eigen_sym3(A):
+    A = np.ascontiguousarray(A, np.float64).reshape(9)
+    lam, V = np.zeros(3), np.zeros(9)
+    lib().ob_eigen(_p(A, ctypes.c_double), _p(lam, ctypes.c_double), _p(V, ctypes.c_double))
+    return lam, V.reshape(3, 3)
+
+
+def match_axes(Rp, V, s):
+    """The oracle's orientation matching of one node: axes V (columns) with
+    scales s against the parent frame Rp; returns (R, s')."""
+    Rp = np.ascontiguousarray(Rp, np.float64).reshape(9)
+    V = np.ascontiguousarray(V, np.float64).reshape(9)
+    s = np.ascontiguousarray(s, np.float64)
+    R, so = np.zeros(9), np.zeros(3)
+    lib().ob_match(_p(Rp, ctypes.c_double), _p(V, ctypes.c_double), _p(s, ctypes.c_double), _p(R, ctypes.c_double),
+                   _p(so, ctypes.c_double))
+    return R.reshape(3, 3), so

@@ -30,12 +30,13 @@ struct RenderKey {
     int nv = -1;
     std::vector<int> wh;
     int tw = 0, th = 0, batch = 0;
+    bool persist = false;
     uint64_t layout = 0;
     bool profiled = false;
     bool operator==(const RenderKey &o) const
     {
-        return nv == o.nv && wh == o.wh && tw == o.tw && th == o.th && batch == o.batch && layout == o.layout &&
-               profiled == o.profiled;
+        return nv == o.nv && wh == o.wh && tw == o.tw && th == o.th && batch == o.batch && persist == o.persist &&
+               layout == o.layout && profiled == o.profiled;
     }
 };
 
@@ -62,6 +63,9 @@ struct hgs_ctx {
     uint64_t param_gen = 1;
 
     int tile_w = 16, tile_h = 16, batch = 0;
+    bool persist = false;  // blend over a persistent grid and a device-side tile queue
+    uint32_t *queue = nullptr;  // [0] forward, [1] backward: next tile slot
+    double *l1_partial = nullptr;  // per-block partial sums of the L1 loss
 
     // workspaces
     uint64_t layout_gen = 1;
@@ -124,11 +128,19 @@ struct hgs_ctx {
     bool pairs_in_scratch = false;
     bool g_pairs_in_scratch = false;
     int r_tw = 16, r_th = 16, r_batch = 0;
+    bool r_persist = false;
 
     // graph
     hipGraphExec_t gexec = nullptr;
     RenderKey gkey;
     bool g_profiled = false;
+    // backward graph: keyed by the forward graph it follows and the
+    // gradient outputs its launches name
+    hipGraphExec_t bexec = nullptr;
+    RenderKey bkey;
+    const void *bkey_out[6] = {};
+    bool bgraph_valid = false;
+    bool last_graphed = false;  // the last render ran through the forward graph
 
     // kernel timing (HIP events around selected launches)
     bool profile = false;
@@ -161,16 +173,21 @@ hgs_status fail(hgs_ctx *c, hgs_status s, const std::string &msg)
 // DMA reads a pinned staging slot, not views_host: the copy may run long
 // after this returns (behind earlier work on st), and the host records may
 // change meanwhile.  A slot is reused only once its previous copy has run.
-hgs_status push_views(hgs_ctx *ctx, int n, hipStream_t st)
+hgs_status stage_copy(hgs_ctx *ctx, const DevView *src, int n, DevView *dst, hipStream_t st)
 {
     const int k = ctx->stage_next;
     ctx->stage_next = (k + 1) % kStageRing;
     if (ctx->stage_used[k]) HIPC(hipEventSynchronize(ctx->stage_ev[k]));
-    memcpy(ctx->stage[k], ctx->views_host, sizeof(DevView) * (size_t)n);
-    HIPC(hipMemcpyAsync(ctx->views_dev, ctx->stage[k], sizeof(DevView) * (size_t)n, hipMemcpyHostToDevice, st));
+    memcpy(ctx->stage[k], src, sizeof(DevView) * (size_t)n);
+    HIPC(hipMemcpyAsync(dst, ctx->stage[k], sizeof(DevView) * (size_t)n, hipMemcpyHostToDevice, st));
     HIPC(hipEventRecord(ctx->stage_ev[k], st));
     ctx->stage_used[k] = true;
     return HGS_OK;
+}
+
+hgs_status push_views(hgs_ctx *ctx, int n, hipStream_t st)
+{
+    return stage_copy(ctx, ctx->views_host, n, ctx->views_dev, st);
 }
 
 hgs_status dalloc(hgs_ctx *ctx, void **p, size_t bytes)
@@ -283,6 +300,39 @@ bool finite_view(const hgs_view &v)
            v.width > 0 && v.height > 0 && v.width <= 32768 && v.height <= 32768;
 }
 
+// The device record of one view (tile grid at tw x th, bases and output
+// pointers left for the caller).
+void fill_dev_view(const hgs_view &s, int tw, int th, DevView &d)
+{
+    memcpy(d.R, s.R, sizeof d.R);
+    memcpy(d.eye, s.eye, sizeof d.eye);
+    d.fx = s.fx;
+    d.fy = s.fy;
+    d.cx = s.cx;
+    d.cy = s.cy;
+    d.W = s.width;
+    d.H = s.height;
+    d.z_near = s.z_near;
+    d.tau = s.tau;
+    {
+        // eps <= tau  <=>  L^2 <= (tau / f)^2 d^2; the prefilter decides it
+        // in FP32 outside a band of kCutMargin and stays off (NaN) where the
+        // constant is so small or large that FP32 products could leave the
+        // normal range
+        const double f = s.fx > s.fy ? s.fx : s.fy, k = (double)s.tau * (double)s.tau / (f * f);
+        const bool use = s.tau == 0.0f || (k >= 1e-12 && k <= 1e12);
+        d.cut_klo = use ? (float)(k * (1.0 - (double)kCutMargin)) : NAN;
+        d.cut_khi = use ? (float)(k * (1.0 + (double)kCutMargin)) : NAN;
+    }
+    d.tiles_x = (s.width + tw - 1) / tw;
+    d.tiles_y = (s.height + th - 1) / th;
+    d.tile_base = 0;
+    d.pix_base = 0;
+    d.out_rgb = nullptr;
+    d.dL = nullptr;
+    d.target = nullptr;
+}
+
 // Per-view device records and global tile/pixel bases.
 hgs_status setup_views(hgs_ctx *ctx, const hgs_view *views, int nv, float *const *out_rgb, uint32_t &n_tiles,
                        size_t &n_pix)
@@ -293,32 +343,12 @@ hgs_status setup_views(hgs_ctx *ctx, const hgs_view *views, int nv, float *const
         const hgs_view &s = views[v];
         if (!finite_view(s)) return fail(ctx, HGS_ERR_INVALID_ARG, "view " + std::to_string(v) + " is invalid");
         DevView &d = ctx->views_host[v];
-        memcpy(d.R, s.R, sizeof d.R);
-        memcpy(d.eye, s.eye, sizeof d.eye);
-        d.fx = s.fx;
-        d.fy = s.fy;
-        d.cx = s.cx;
-        d.cy = s.cy;
-        d.W = s.width;
-        d.H = s.height;
-        d.z_near = s.z_near;
-        d.tau = s.tau;
-        {
-            // eps <= tau  <=>  L^2 <= (tau / f)^2 d^2; the prefilter decides it
-            // in FP32 outside a band of kCutMargin and stays off (NaN) where the
-            // constant is so small or large that FP32 products could leave the
-            // normal range
-            const double f = s.fx > s.fy ? s.fx : s.fy, k = (double)s.tau * (double)s.tau / (f * f);
-            const bool use = s.tau == 0.0f || (k >= 1e-12 && k <= 1e12);
-            d.cut_klo = use ? (float)(k * (1.0 - (double)kCutMargin)) : NAN;
-            d.cut_khi = use ? (float)(k * (1.0 + (double)kCutMargin)) : NAN;
-        }
-        d.tiles_x = (s.width + ctx->tile_w - 1) / ctx->tile_w;
-        d.tiles_y = (s.height + ctx->tile_h - 1) / ctx->tile_h;
+        fill_dev_view(s, ctx->tile_w, ctx->tile_h, d);
         d.tile_base = n_tiles;
         d.pix_base = (uint32_t)n_pix;
         d.out_rgb = out_rgb ? out_rgb[v] : nullptr;
         d.dL = nullptr;
+        d.target = nullptr;
         const uint64_t nt = (uint64_t)d.tiles_x * d.tiles_y;
         if ((uint64_t)n_tiles + nt >= (1ull << 31)) return fail(ctx, HGS_ERR_INVALID_ARG, "too many tiles");
         n_tiles += (uint32_t)nt;
@@ -428,7 +458,8 @@ void enqueue_blend(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st)
 {
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
     launch_blend(ctx->views_dev, nv, n_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs, ctx->axes, ctx->T_final, ctx->n_last,
-                 ctx->n_blend, ctx->wstats, ctx->ctr, ctx->tile_w, ctx->tile_h, ctx->batch, st);
+                 ctx->n_blend, ctx->wstats, ctx->ctr, ctx->tile_w, ctx->tile_h, ctx->batch, ctx->persist, ctx->queue,
+                 st);
 }
 
 void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hipEvent_t *ev, bool with_blend)
@@ -502,6 +533,34 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     mark(7);
 }
 
+// The backward of the last render, queued on st: screen-gradient rows and
+// counters cleared, blend backward, preprocess backward and the gather into
+// the gradient outputs.  Every size it launches with is a capacity or a
+// count the kernels read on the device, so that a captured copy stays valid
+// for every render of the same forward graph.
+void enqueue_backward(hgs_ctx *ctx, int nv, const hgs_grads *out, hipStream_t st)
+{
+    launch_zero_rows(ctx->sgrad, 12, &ctx->ctr->vis_total, ctx->cut_cap, st);
+    launch_fill_u32((uint32_t *)&ctx->ctr->bwd_evaluated, 0u, 6, st);
+    const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
+    {
+        KernelTimer kt(ctx, 1, st);
+        launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs,
+                              ctx->axes, ctx->T_final, ctx->n_last, ctx->vis_rank, ctx->sgrad, ctx->wstats, ctx->ctr,
+                              ctx->r_tw, ctx->r_th, ctx->r_batch, out->dt != nullptr, ctx->r_persist, ctx->queue + 1,
+                              st);
+    }
+    const DevHier h = dev_hier(ctx);
+    {
+        KernelTimer kt(ctx, 2, st);
+        launch_preprocess_backward(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t,
+                                   &ctx->ctr->cut_total, ctx->cut_cap, ctx->ntiles, ctx->recs, ctx->cjac,
+                                   ctx->vis_rank, ctx->sgrad, ctx->pgrad, ctx->masks, (ctx->n + 63) / 64,
+                                   ctx->word_off, ctx->interior, ctx->n_interior, out->mean, out->scale, out->rot,
+                                   out->opacity, out->sh, out->dt, st);
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -547,6 +606,8 @@ hgs_status hgs_create(hgs_ctx **out, int device, void *hip_stream)
         if ((s = dalloc(ctx, (void **)&ctx->vis_bounds, sizeof(uint32_t) * (kMaxViews + 1)))) break;
         if ((s = dalloc(ctx, (void **)&ctx->pair_bounds, sizeof(uint32_t) * (kMaxViews + 1)))) break;
         if ((s = dalloc(ctx, (void **)&ctx->seg_tile_base, sizeof(uint32_t) * kMaxViews))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->queue, sizeof(uint32_t) * 2))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->l1_partial, sizeof(double) * kL1Blocks))) break;
     } while (0);
     if (s != HGS_OK) {
         hgs_destroy(ctx);
@@ -564,6 +625,7 @@ void hgs_destroy(hgs_ctx *ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->bexec) (void)hipGraphExecDestroy(ctx->bexec);
     collect_times(ctx);
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     for (void *p : ctx->allocs) (void)hipFree(p);
@@ -617,14 +679,16 @@ hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a)
     return HGS_OK;
 }
 
-hgs_status hgs_set_tuning(hgs_ctx *ctx, int32_t tile_w, int32_t tile_h, int32_t batch)
+hgs_status hgs_set_tuning(hgs_ctx *ctx, int32_t tile_w, int32_t tile_h, int32_t batch, int32_t persistent)
 {
     if (!ctx) return HGS_ERR_INVALID_ARG;
     if (!blend_supported(tile_w, tile_h, batch))
         return fail(ctx, HGS_ERR_INVALID_ARG, "unsupported tile/batch combination");
+    if (persistent != 0 && persistent != 1) return fail(ctx, HGS_ERR_INVALID_ARG, "persistent must be 0 or 1");
     ctx->tile_w = tile_w;
     ctx->tile_h = tile_h;
     ctx->batch = batch == tile_w * tile_h ? 0 : batch;
+    ctx->persist = persistent != 0;
     ctx->have_render = false;
     return HGS_OK;
 }
@@ -849,6 +913,7 @@ hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, floa
     hgs_status s;
     if ((s = setup_views(ctx, views, n_views, out_rgb, n_tiles, n_pix))) return s;
     if ((s = ensure_fixed(ctx, n_views, n_tiles, n_pix))) return s;
+    if (ctx->persist) blend_prepare(ctx->tile_w, ctx->tile_h, ctx->batch);
     const bool timed = stats && stats->ms[0] < 0.0f && n_views == 1;
     if (ctx->cut_cap == 0) {
         const uint64_t guess = std::min<uint64_t>((uint64_t)n_views * (uint64_t)std::min<int64_t>(ctx->n_leaves, 1 << 21),
@@ -880,6 +945,7 @@ hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, floa
             key.tw = ctx->tile_w;
             key.th = ctx->tile_h;
             key.batch = ctx->batch;
+            key.persist = ctx->persist;
             key.layout = ctx->layout_gen * 1000003ull + ctx->param_gen;
             key.profiled = ctx->profile;
             if (!ctx->gexec || !(key == ctx->gkey)) {
@@ -934,6 +1000,8 @@ hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, floa
         ctx->r_tw = ctx->tile_w;
         ctx->r_th = ctx->tile_h;
         ctx->r_batch = ctx->batch;
+        ctx->r_persist = ctx->persist;
+        ctx->last_graphed = n_views > 1 && !ctx->profile;
         if (stats) {
             stats->cut = c.cut_total;
             stats->visible = c.vis_total;
@@ -987,31 +1055,79 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views
         ctx->views_host[v].dL = dL_drgb[v];
     }
     HIPC(hipSetDevice(ctx->device));
-    hipStream_t st = ctx->stream;
-    if (hgs_status s = push_views(ctx, nv, st)) return s;
-    const uint32_t cut = std::min(ctx->last_cut, ctx->cut_cap);
-    launch_zero_rows(ctx->sgrad, 12, &ctx->ctr->vis_total, std::min(cut, ctx->cut_cap), st);
-    launch_fill_u32((uint32_t *)&ctx->ctr->bwd_evaluated, 0u, 6, st);
-    const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
-    {
-        KernelTimer kt(ctx, 1, st);
-        launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs,
-                              ctx->axes, ctx->T_final,
-                              ctx->n_last, ctx->vis_rank, ctx->sgrad, ctx->wstats, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch,
-                              out->dt != nullptr, st);
-    }
-    const DevHier h = dev_hier(ctx);
-    {
-        KernelTimer kt(ctx, 2, st);
-        launch_preprocess_backward(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t,
-                                   &ctx->ctr->cut_total, ctx->cut_cap, ctx->ntiles, ctx->recs, ctx->cjac, ctx->vis_rank, ctx->sgrad,
-                                   ctx->pgrad, ctx->masks, (ctx->n + 63) / 64, ctx->word_off, ctx->interior,
-                                   ctx->n_interior, out->mean, out->scale, out->rot, out->opacity, out->sh, out->dt,
-                                   st);
+    const void *outs[6] = {out->mean, out->scale, out->rot, out->opacity, out->sh, out->dt};
+    if (ctx->last_graphed) {
+        // replay (or capture once) the backward on the library stream, in
+        // order with the caller's stream on both sides
+        if (!ctx->bexec || !ctx->bgraph_valid || !(ctx->bkey == ctx->gkey) ||
+            memcmp(ctx->bkey_out, outs, sizeof outs) != 0) {
+            if (ctx->bexec) {
+                HIPC(hipGraphExecDestroy(ctx->bexec));
+                ctx->bexec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIPC(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
+            enqueue_backward(ctx, nv, out, ctx->gstream);
+            HIPC(hipStreamEndCapture(ctx->gstream, &g));
+            hipError_t e = hipGraphInstantiate(&ctx->bexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess)
+                return fail(ctx, HGS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            ctx->bkey = ctx->gkey;
+            memcpy(ctx->bkey_out, outs, sizeof outs);
+            ctx->bgraph_valid = true;
+        }
+        HIPC(hipEventRecord(ctx->ev_in, ctx->stream));
+        HIPC(hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
+        if (hgs_status s = push_views(ctx, nv, ctx->gstream)) return s;
+        HIPC(hipGraphLaunch(ctx->bexec, ctx->gstream));
+        HIPC(hipEventRecord(ctx->ev_out, ctx->gstream));
+        HIPC(hipStreamWaitEvent(ctx->stream, ctx->ev_out, 0));
+    } else {
+        hipStream_t st = ctx->stream;
+        if (hgs_status s = push_views(ctx, nv, st)) return s;
+        enqueue_backward(ctx, nv, out, st);
     }
     HIPC(hipGetLastError());
     // host copy of views keeps dL for nothing else
     for (int v = 0; v < nv; ++v) ctx->views_host[v].dL = nullptr;
+    return HGS_OK;
+}
+
+hgs_status hgs_l1_loss(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const float *const *target,
+                       float *const *dL_drgb, double *loss)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->have_render) return fail(ctx, HGS_ERR_STATE, "no render whose images the loss could read");
+    if (render_id != ctx->render_seq)
+        return fail(ctx, HGS_ERR_STATE, "render " + std::to_string(render_id) +
+                                            " has been replaced: the ctx holds the state of render " +
+                                            std::to_string(ctx->render_seq));
+    if (n_views != ctx->last_nv)
+        return fail(ctx, HGS_ERR_INVALID_ARG, "render " + std::to_string(render_id) + " has " +
+                                                  std::to_string(ctx->last_nv) + " views, not " +
+                                                  std::to_string(n_views));
+    if (!target || !dL_drgb || !loss) return fail(ctx, HGS_ERR_INVALID_ARG, "bad loss arguments");
+    const int nv = ctx->last_nv;
+    for (int v = 0; v < nv; ++v) {
+        if (!target[v] || !dL_drgb[v])
+            return fail(ctx, HGS_ERR_INVALID_ARG, "target or dL_drgb of view " + std::to_string(v) + " is NULL");
+        if (!ctx->views_host[v].out_rgb) return fail(ctx, HGS_ERR_STATE, "the last render kept no images");
+    }
+    HIPC(hipSetDevice(ctx->device));
+    for (int v = 0; v < nv; ++v) {
+        ctx->views_host[v].target = target[v];
+        ctx->views_host[v].dL = dL_drgb[v];
+    }
+    hipStream_t st = ctx->stream;
+    hgs_status s = push_views(ctx, nv, st);
+    for (int v = 0; v < nv; ++v) {
+        ctx->views_host[v].target = nullptr;
+        ctx->views_host[v].dL = nullptr;
+    }
+    if (s) return s;
+    launch_l1(ctx->views_dev, nv, (uint32_t)ctx->last_pix, ctx->l1_partial, loss, st);
+    HIPC(hipGetLastError());
     return HGS_OK;
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace hgs {
 
 // Conventions of the splatting stage (3D Gaussian splatting defaults that the
@@ -28,7 +30,8 @@ struct DevView {
     uint32_t tile_base;  // first global tile id of this view
     uint32_t pix_base;   // first pixel of this view in per-pixel state arrays
     float *out_rgb;      // [H][W][3]
-    const float *dL;     // [H][W][3], backward only
+    const float *dL;     // [H][W][3], backward (read) and loss (written) only
+    const float *target; // [H][W][3], loss only
 };
 
 // Relative band around the cut threshold inside which the FP32 prefilter
@@ -182,17 +185,32 @@ void launch_tile_keys(const uint2 *ranges, uint32_t n_tiles, uint32_t *keys, uin
 
 // blend (tile_w x tile_h pixels per workgroup, `batch` records staged per step)
 bool blend_supported(int tw, int th, int batch);
+// Looks up the persistent grids of this configuration (device attributes
+// and occupancy), so that no such query runs while a launch is captured.
+void blend_prepare(int tw, int th, int batch);
+// persist: a grid of the chip's resident workgroups takes tile slots from
+// the device-side queue (*queue, cleared by the launch sequence first)
+// instead of one workgroup per tile.
 void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *tile_order, const uint2 *ranges,
                   const uint32_t *pair_vals,
                   const SplatRec *recs, const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend,
-                  uint4 *wstats, Counters *ctr, int tw, int th, int batch, hipStream_t st);
+                  uint4 *wstats, Counters *ctr, int tw, int th, int batch, bool persist, uint32_t *queue,
+                  hipStream_t st);
+
+// L1 loss of the rendered images (views[v].out_rgb) against views[v].target
+// over n_pix pixels of all views: dL/dC written to views[v].dL, the mean
+// absolute difference to *loss (device), summed over at most kL1Blocks
+// per-block partials (partial: workspace of that many doubles).
+constexpr int kL1Blocks = 1024;
+void launch_l1(const DevView *views, int nv, uint32_t n_pix, double *partial, double *loss, hipStream_t st);
 
 // backward
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *tile_order,
                            const uint2 *ranges,
                            const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                            const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
-                           Counters *ctr, int tw, int th, int batch, bool want_dt, hipStream_t st);
+                           Counters *ctr, int tw, int th, int batch, bool want_dt, bool persist, uint32_t *queue,
+                           hipStream_t st);
 void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32_t vis_cap, hipStream_t st);
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,

@@ -19,6 +19,10 @@
 // per-pixel lists), reduces each splat's gradient over rows of 16 lanes with
 // DPP exchanges and over the rows and waves of the tile in LDS (FP32), and
 // adds it once per tile, in FP64, to the splat's screen-space gradient.
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "hgs_internal.h"
 
 namespace hgs {
@@ -140,15 +144,28 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Work distribution over tiles: either one workgroup per tile slot (grid =
+// tile count, slot = workgroup index), or a persistent grid sized to the
+// chip's resident workgroups, each taking slots from a device-side queue (a
+// counter that the launch sequence clears first) until the slots run out.
+// Slots are handed out in the longest-first order either way.
+__device__ __forceinline__ uint32_t next_slot(uint32_t *queue, uint32_t *s_slot)
+{
+    if (threadIdx.x == 0) *s_slot = atomicAdd(queue, 1u);
+    __syncthreads();
+    const uint32_t slot = *s_slot;
+    __syncthreads();  // every wave has its slot before lane 0 may overwrite it
+    return slot;
+}
+
 template <int TW, int TH, int BATCH>
-__global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ views, int nv,
-                                                  const uint32_t *__restrict__ tile_order,
-                                                  const uint2 *__restrict__ ranges,
-                                                  const uint32_t *__restrict__ pair_vals,
-                                                  const SplatRec *__restrict__ recs,
-                                                  const double4 *__restrict__ axes, float *__restrict__ T_final,
-                                                  uint32_t *__restrict__ n_last, uint32_t *__restrict__ n_blend,
-                                                  uint4 *__restrict__ wstats)
+__device__ __forceinline__ void blend_tile(const DevView *__restrict__ views, int nv,
+                                           const uint32_t *__restrict__ tile_order,
+                                           const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_vals,
+                                           const SplatRec *__restrict__ recs, const double4 *__restrict__ axes,
+                                           float *__restrict__ T_final, uint32_t *__restrict__ n_last,
+                                           uint32_t *__restrict__ n_blend, uint4 *__restrict__ wstats,
+                                           uint32_t slot)
 {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;
@@ -160,7 +177,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
     __shared__ float2 s_u[NB][BATCH];
     __shared__ uint64_t s_tm[BATCH / 64];  // bit j of word k: entry 64 k + j is interpolated (t > 0)
     __shared__ uint64_t s_dm[NB][BATCH / 64];  // likewise: block bk skips entry 64 k + j
-    const uint32_t tile = tile_order[blockIdx.x];  // longest lists first
+    const uint32_t tile = tile_order[slot];  // longest lists first
     const int vi = view_of_tile(views, nv, tile);
     const DevView &V = views[vi];
     const uint32_t lt = tile - V.tile_base;
@@ -274,7 +291,32 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
     uint32_t nb_w = nb;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) nb_w += (uint32_t)__shfl_xor((int)nb_w, d, 64);
-    if (lane == 0) wstats[(size_t)blockIdx.x * NW + w] = make_uint4(n_eval, nb_w, n_eval_t, 0u);
+    if (lane == 0) wstats[(size_t)slot * NW + w] = make_uint4(n_eval, nb_w, n_eval_t, 0u);
+}
+
+template <int TW, int TH, int BATCH, bool PERSIST>
+__global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ views, int nv,
+                                                  const uint32_t *__restrict__ tile_order,
+                                                  const uint2 *__restrict__ ranges,
+                                                  const uint32_t *__restrict__ pair_vals,
+                                                  const SplatRec *__restrict__ recs,
+                                                  const double4 *__restrict__ axes, float *__restrict__ T_final,
+                                                  uint32_t *__restrict__ n_last, uint32_t *__restrict__ n_blend,
+                                                  uint4 *__restrict__ wstats, uint32_t n_tiles,
+                                                  uint32_t *__restrict__ queue)
+{
+    if constexpr (!PERSIST) {
+        blend_tile<TW, TH, BATCH>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last, n_blend,
+                                  wstats, blockIdx.x);
+    } else {
+        __shared__ uint32_t s_slot;
+        for (;;) {
+            const uint32_t slot = next_slot(queue, &s_slot);
+            if (slot >= n_tiles) break;
+            blend_tile<TW, TH, BATCH>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last,
+                                      n_blend, wstats, slot);
+        }
+    }
 }
 
 // Cross-row halvings with the gfx950 lane swaps: permlane32_swap(x, y) moves
@@ -371,16 +413,15 @@ __device__ __forceinline__ double2 corner_offsets(const SplatRec &r, const doubl
 }
 
 template <int TW, int TH, int BATCH, bool DT>
-__global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict__ views, int nv,
-                                                      const uint32_t *__restrict__ tile_order,
-                                                      const uint2 *__restrict__ ranges,
-                                                      const uint32_t *__restrict__ pair_vals,
-                                                      const SplatRec *__restrict__ recs,
-                                                      const double4 *__restrict__ axes,
-                                                      const float *__restrict__ T_final,
-                                                      const uint32_t *__restrict__ n_last,
-                                                      const uint32_t *__restrict__ vis_rank,
-                                                      double *__restrict__ sgrad, uint4 *__restrict__ wstats)
+__device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views, int nv,
+                                               const uint32_t *__restrict__ tile_order,
+                                               const uint2 *__restrict__ ranges,
+                                               const uint32_t *__restrict__ pair_vals,
+                                               const SplatRec *__restrict__ recs, const double4 *__restrict__ axes,
+                                               const float *__restrict__ T_final,
+                                               const uint32_t *__restrict__ n_last,
+                                               const uint32_t *__restrict__ vis_rank, double *__restrict__ sgrad,
+                                               uint4 *__restrict__ wstats, uint32_t tslot)
 {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;
@@ -393,7 +434,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
     __shared__ double s_d[BATCH * 11];  // the flushed terms, splat-major
     __shared__ double2 s_ref[BATCH];    // the tile corner's offsets on the axes (FP64)
     __shared__ uint32_t s_max;
-    const uint32_t tile = tile_order[blockIdx.x];  // longest lists first
+    const uint32_t tile = tile_order[tslot];  // longest lists first
     const int vi = view_of_tile(views, nv, tile);
     const DevView &V = views[vi];
     const uint32_t lt = tile - V.tile_base;
@@ -546,7 +587,34 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
         __syncthreads();
         hi = lo;
     }
-    if (lane == 0) wstats[(size_t)blockIdx.x * NW + w] = make_uint4(n_eval, n_eval_t, n_con, 0u);
+    if (lane == 0) wstats[(size_t)tslot * NW + w] = make_uint4(n_eval, n_eval_t, n_con, 0u);
+}
+
+template <int TW, int TH, int BATCH, bool DT, bool PERSIST>
+__global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict__ views, int nv,
+                                                      const uint32_t *__restrict__ tile_order,
+                                                      const uint2 *__restrict__ ranges,
+                                                      const uint32_t *__restrict__ pair_vals,
+                                                      const SplatRec *__restrict__ recs,
+                                                      const double4 *__restrict__ axes,
+                                                      const float *__restrict__ T_final,
+                                                      const uint32_t *__restrict__ n_last,
+                                                      const uint32_t *__restrict__ vis_rank,
+                                                      double *__restrict__ sgrad, uint4 *__restrict__ wstats,
+                                                      uint32_t n_tiles, uint32_t *__restrict__ queue)
+{
+    if constexpr (!PERSIST) {
+        blend_bwd_tile<TW, TH, BATCH, DT>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last,
+                                          vis_rank, sgrad, wstats, blockIdx.x);
+    } else {
+        __shared__ uint32_t s_slot;
+        for (;;) {
+            const uint32_t slot = next_slot(queue, &s_slot);
+            if (slot >= n_tiles) break;
+            blend_bwd_tile<TW, TH, BATCH, DT>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last,
+                                              vis_rank, sgrad, wstats, slot);
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_stats_reduce(const uint4 *__restrict__ s, uint32_t n,
@@ -580,20 +648,68 @@ __global__ __launch_bounds__(256) void k_stats_reduce(const uint4 *__restrict__ 
     }
 }
 
+// Workgroups of `kernel` that the whole chip holds at once (CUs times the
+// occupancy at `threads` per workgroup): the grid of a persistent launch.
+// Looked up once per kernel.
+template <typename K>
+uint32_t resident_grid(K kernel, int threads)
+{
+    static std::mutex mu;
+    static std::map<const void *, uint32_t> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const void *key = reinterpret_cast<const void *>(kernel);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0);
+    const uint32_t g = (uint32_t)std::max(1, std::max(cus, 1) * std::max(per, 1));
+    cache[key] = g;
+    return g;
+}
+
 template <int TW, int TH, int BATCH>
 void launch_blend_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                     const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, float *T_final,
-                    uint32_t *n_last, uint32_t *n_blend, uint4 *wstats, hipStream_t st)
+                    uint32_t *n_last, uint32_t *n_blend, uint4 *wstats, bool persist, uint32_t *queue,
+                    hipStream_t st)
 {
-    hipLaunchKernelGGL((k_blend<TW, TH, BATCH>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order, ranges,
-                       pair_vals, recs, axes, T_final, n_last, n_blend, wstats);
+    if (persist) {
+        auto k = k_blend<TW, TH, BATCH, true>;
+        const uint32_t g = std::min(n_tiles, resident_grid(k, TW * TH));
+        launch_fill_u32(queue, 0u, 1, st);
+        hipLaunchKernelGGL(k, dim3(g), dim3(TW * TH), 0, st, views, nv, order, ranges, pair_vals, recs, axes,
+                           T_final, n_last, n_blend, wstats, n_tiles, queue);
+    } else {
+        hipLaunchKernelGGL((k_blend<TW, TH, BATCH, false>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order,
+                           ranges, pair_vals, recs, axes, T_final, n_last, n_blend, wstats, n_tiles, queue);
+    }
+}
+
+template <int TW, int TH, int B, bool DT>
+void launch_blend_bwd_dt(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
+                         const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
+                         const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats, bool persist,
+                         uint32_t *queue, hipStream_t st)
+{
+    if (persist) {
+        auto k = k_blend_bwd<TW, TH, B, DT, true>;
+        const uint32_t g = std::min(n_tiles, resident_grid(k, TW * TH));
+        launch_fill_u32(queue, 0u, 1, st);
+        hipLaunchKernelGGL(k, dim3(g), dim3(TW * TH), 0, st, views, nv, order, ranges, pair_vals, recs, axes, T_final,
+                           n_last, vis_rank, sgrad, wstats, n_tiles, queue);
+    } else {
+        hipLaunchKernelGGL((k_blend_bwd<TW, TH, B, DT, false>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order,
+                           ranges, pair_vals, recs, axes, T_final, n_last, vis_rank, sgrad, wstats, n_tiles, queue);
+    }
 }
 
 template <int TW, int TH, int BATCH>
 void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                         const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                         const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
-                        bool want_dt, hipStream_t st)
+                        bool want_dt, bool persist, uint32_t *queue, hipStream_t st)
 {
     // the backward stages at most 32 splats per wave and step: its LDS holds
     // the FP32 partial sums and the FP64 flushed terms of every staged
@@ -601,11 +717,11 @@ void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const ui
     constexpr int BMAX = 32 * (TW * TH / 64);
     constexpr int B = BATCH < BMAX ? BATCH : BMAX;
     if (want_dt)
-        hipLaunchKernelGGL((k_blend_bwd<TW, TH, B, true>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order,
-                           ranges, pair_vals, recs, axes, T_final, n_last, vis_rank, sgrad, wstats);
+        launch_blend_bwd_dt<TW, TH, B, true>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final,
+                                             n_last, vis_rank, sgrad, wstats, persist, queue, st);
     else
-        hipLaunchKernelGGL((k_blend_bwd<TW, TH, B, false>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order,
-                           ranges, pair_vals, recs, axes, T_final, n_last, vis_rank, sgrad, wstats);
+        launch_blend_bwd_dt<TW, TH, B, false>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final,
+                                              n_last, vis_rank, sgrad, wstats, persist, queue, st);
 }
 
 }  // namespace
@@ -613,6 +729,25 @@ void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const ui
 // Supported (tile, batch) combinations; batch 0 means one record per thread.
 #define HGS_BLEND_CASES(X)                                                                                            \
     X(8, 8, 64) X(8, 8, 128) X(8, 8, 256) X(16, 8, 128) X(16, 8, 256) X(16, 16, 256) X(16, 16, 512) X(32, 16, 512)
+
+template <int TW, int TH, int BATCH>
+void prepare_t()
+{
+    constexpr int BMAX = 32 * (TW * TH / 64);
+    constexpr int B = BATCH < BMAX ? BATCH : BMAX;
+    (void)resident_grid(k_blend<TW, TH, BATCH, true>, TW * TH);
+    (void)resident_grid(k_blend_bwd<TW, TH, B, true, true>, TW * TH);
+    (void)resident_grid(k_blend_bwd<TW, TH, B, false, true>, TW * TH);
+}
+
+void blend_prepare(int tw, int th, int batch)
+{
+    if (batch == 0) batch = tw * th;
+#define X(a, b, c) \
+    if (tw == a && th == b && batch == c) return prepare_t<a, b, c>();
+    HGS_BLEND_CASES(X)
+#undef X
+}
 
 bool blend_supported(int tw, int th, int batch)
 {
@@ -627,12 +762,12 @@ bool blend_supported(int tw, int th, int batch)
 static void launch_blend_cfg(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order,
                              const uint2 *ranges, const uint32_t *pair_vals, const SplatRec *recs,
                              const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend, uint4 *wstats,
-                             int tw, int th, int batch, hipStream_t st)
+                             int tw, int th, int batch, bool persist, uint32_t *queue, hipStream_t st)
 {
 #define X(a, b, c)                                                                                           \
     if (tw == a && th == b && batch == c)                                                                    \
         return launch_blend_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last, \
-                                       n_blend, wstats, st);
+                                       n_blend, wstats, persist, queue, st);
     HGS_BLEND_CASES(X)
 #undef X
 }
@@ -640,27 +775,28 @@ static void launch_blend_cfg(const DevView *views, int nv, uint32_t n_tiles, con
 void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                   const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, float *T_final,
                   uint32_t *n_last, uint32_t *n_blend, uint4 *wstats, Counters *ctr, int tw, int th, int batch,
-                  hipStream_t st)
+                  bool persist, uint32_t *queue, hipStream_t st)
 {
     if (batch == 0) batch = tw * th;
     if (!n_tiles) return;
     const uint32_t nst = n_tiles * (uint32_t)(tw * th / 64);
     launch_blend_cfg(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last, n_blend, wstats, tw,
-                     th, batch, st);
+                     th, batch, persist, queue, st);
     hipLaunchKernelGGL(k_stats_reduce, dim3(256), dim3(256), 0, st, wstats, nst, &ctr->evaluated);
 }
 
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order,
-                           const uint2 *ranges, const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
-                           const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
-                           Counters *ctr, int tw, int th, int batch, bool want_dt, hipStream_t st)
+                           const uint2 *ranges, const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes,
+                           const float *T_final, const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad,
+                           uint4 *wstats, Counters *ctr, int tw, int th, int batch, bool want_dt, bool persist,
+                           uint32_t *queue, hipStream_t st)
 {
     if (batch == 0) batch = tw * th;
     if (!n_tiles) return;
 #define X(a, b, c)                                                                                                 \
     if (tw == a && th == b && batch == c) {                                                                        \
         launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last,    \
-                                    vis_rank, sgrad, wstats, want_dt, st);                                         \
+                                    vis_rank, sgrad, wstats, want_dt, persist, queue, st);                         \
         hipLaunchKernelGGL(k_stats_reduce, dim3(256), dim3(256), 0, st, wstats,                                    \
                            n_tiles * (uint32_t)(tw * th / 64), &ctr->bwd_evaluated);                               \
         return;                                                                                                    \

@@ -20,7 +20,7 @@ _NAMES = {0: "HGS_OK", 1: "HGS_ERR_INVALID_ARG", 2: "HGS_ERR_OOM", 3: "HGS_ERR_H
           5: "HGS_ERR_CAPACITY"}
 EXPORTS = ("hgs_create", "hgs_destroy", "hgs_last_error", "hgs_set_stream", "hgs_upload", "hgs_bind_params",
            "hgs_cut", "hgs_compact_mark", "hgs_compact_rebuild", "hgs_render", "hgs_last_render",
-           "hgs_render_backward", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
+           "hgs_render_backward", "hgs_l1_loss", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
            "hgs_kernel_time", "hgs_counters")
 COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t", "bwd_evaluated",
                  "bwd_evaluated_t", "bwd_contrib")
@@ -98,8 +98,9 @@ def lib():
         L.hgs_render.argtypes = [vp, P(View), ctypes.c_int32, P(vp), P(Stats)]
         L.hgs_last_render.argtypes = [vp, P(ctypes.c_uint64), P(ctypes.c_int32)]
         L.hgs_render_backward.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, P(vp), P(Grads)]
+        L.hgs_l1_loss.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, P(vp), P(vp), vp]
         L.hgs_adam_step.argtypes = [vp, P(Adam)]
-        L.hgs_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.hgs_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.hgs_get_buffer.argtypes = [vp, ctypes.c_int32, P(vp), P(ctypes.c_int64)]
         L.hgs_set_profiling.argtypes = [vp, ctypes.c_int32]
         L.hgs_counters.argtypes = [vp, P(ctypes.c_int64), ctypes.c_int32]
@@ -218,8 +219,8 @@ class Renderer:
         self._bound = None
         self._check(self.L.hgs_bind_params(self.h, None, None, None, None, None))
 
-    def set_tuning(self, tile_w: int, tile_h: int, batch: int = 0) -> None:
-        self._check(self.L.hgs_set_tuning(self.h, tile_w, tile_h, batch))
+    def set_tuning(self, tile_w: int, tile_h: int, batch: int = 0, persistent: int = 0) -> None:
+        self._check(self.L.hgs_set_tuning(self.h, tile_w, tile_h, batch, int(persistent)))
 
     # -- cut -----------------------------------------------------------------
     def cut(self, view, capacity: int | None = None):
@@ -309,6 +310,33 @@ class Renderer:
         g.dt = dt.data_ptr() if dt is not None else None
         self._keep = dL
         self._check(self.L.hgs_render_backward(self.h, rid, len(dL), ptrs, ctypes.byref(g)))
+
+    def l1_loss(self, targets, dL=None, loss=None):
+        """``hgs_l1_loss`` of this renderer's last render against ``targets``
+        (one float32 [H, W, 3] CUDA tensor per view): writes the cotangent
+        into ``dL`` (allocated when None) and the loss into ``loss`` (a
+        float64 CUDA scalar, allocated when None); returns both.  Queued on
+        the renderer's stream."""
+        torch = self.torch
+        if self._last is None:
+            raise HgsError(ERR_STATE, "no render on this renderer")
+        rid, shapes = self._last[0], self._last[1]
+        if len(targets) != len(shapes):
+            raise HgsError(ERR_INVALID_ARG, f"{len(targets)} targets for a render of {len(shapes)} views")
+        if dL is None:
+            dL = [torch.empty(shp, dtype=torch.float32, device=self.device) for shp in shapes]
+        if loss is None:
+            loss = torch.empty((), dtype=torch.float64, device=self.device)
+        for k, (t, g, shp) in enumerate(zip(targets, dL, shapes)):
+            for name, x in (("targets", t), ("dL", g)):
+                if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and tuple(x.shape) == shp):
+                    raise HgsError(ERR_INVALID_ARG, f"{name}[{k}] must be a contiguous float32 CUDA tensor of "
+                                                    f"shape {shp}")
+        assert loss.is_cuda and loss.dtype == torch.float64
+        tp = (ctypes.c_void_p * len(targets))(*[t.data_ptr() for t in targets])
+        gp = (ctypes.c_void_p * len(dL))(*[g.data_ptr() for g in dL])
+        self._check(self.L.hgs_l1_loss(self.h, rid, len(dL), tp, gp, ctypes.c_void_p(loss.data_ptr())))
+        return dL, loss
 
     def adam_step(self, params: dict, grads: dict, m: dict, v: dict, lr, step: int, beta1: float = 0.9,
                   beta2: float = 0.999, eps: float = 1e-15) -> None:

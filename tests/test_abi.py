@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "hgs.h")
 def declared_functions() -> list[str]:
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)  # drop comments
-    names = re.findall(r"^\s*(?:hgs_status|void|const char\s*\*)\s*(hgs_[a-z_]+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:hgs_status|void|const char\s*\*)\s*(hgs_[a-z0-9_]+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 

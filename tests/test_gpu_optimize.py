@@ -1,0 +1,126 @@
+"""The hierarchy optimisation loop (Sec. 5.1; paper_2406_12080_amd.optimize)
+against the oracle's FP64 steps: the same batches of training views, each
+with its drawn tau, taken through cut, interpolation and compositing, the
+L1 loss against the training images, the backward to the interior nodes and
+Adam on them, three times in a row.  The training images are the oracle's
+renders of the hierarchy's leaves (tau = 0), the images the interior nodes
+are optimised to reproduce at coarser cuts."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2406_12080_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+LR = dict(mean=1e-3, scale=5e-4, rot=1e-3, opacity=5e-3, sh=2.5e-3)
+B1, B2, EPS = 0.9, 0.999, 1e-8
+
+
+def _f32(x):
+    return float(np.float32(x))
+
+
+def _train_views(n, width, height, dist, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        a = 2 * np.pi * k / n + rng.uniform(-0.2, 0.2)
+        eye = (dist * np.cos(a), 0.4 * rng.uniform(-1, 1), dist * np.sin(a))
+        out.append(synth.look_at(eye, (0, 0, 0), (0, 1, 0), width, height, 0.0))
+    return out
+
+
+def _oracle_steps(h, batches, targets, steps):
+    """The FP64 loop: per step, for every view of the batch the oracle's cut
+    at its tau, its image, the L1 residual's sign over all values of the
+    batch as the cotangent, the backward summed over the batch, then Adam on
+    the interior nodes.  Returns the losses and the parameters (node-major)."""
+    H = O.Hier(h)
+    n = H.n
+    inner = np.asarray(h.child_count) > 0
+    comp = dict(mean=3, scale=3, rot=4, opacity=1, sh=48)
+    P = {k: np.ascontiguousarray(getattr(H, k).reshape(comp[k], n).T) for k in comp}
+    M = {k: np.zeros_like(a) for k, a in P.items()}
+    V = {k: np.zeros_like(a) for k, a in P.items()}
+    lr = {k: _f32(x) for k, x in LR.items()}
+    losses = []
+    for s in range(steps):
+        idx, views = batches[s]
+        m_total = sum(v.width * v.height * 3 for v in views)
+        grad = np.zeros((O.NPARAM, n))
+        loss = 0.0
+        for i, v in zip(idx, views):
+            ids, t = O.cut(H, v)
+            rgb = O.render(H, v, ids, t, alternatives=False)["rgb"]
+            d = rgb - targets[i].reshape(-1, 3)
+            loss += float(np.abs(d).sum())
+            grad += O.backward(H, v, ids, t, np.sign(d) / m_total)["grad"]
+        losses.append(loss / m_total)
+        G = {}
+        for k, (a, b) in O.SLOTS.items():
+            G[k] = np.ascontiguousarray(grad[a:b].T)
+        O.adam_step(P, G, M, V, inner, lr, s + 1, _f32(B1), _f32(B2), _f32(EPS))
+        for k in comp:  # the next step renders the updated parameters
+            getattr(H, k)[...] = P[k].T.reshape(getattr(H, k).shape)
+    return losses, P
+
+
+@pytest.mark.parametrize("case", ["c1", "c2s"])
+def test_optimizer_steps_match_oracle(case):
+    from paper_2406_12080_amd import hgs
+    from paper_2406_12080_amd.optimize import HierarchyOptimizer
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    if case == "c1":
+        h = synth.make_scene(1)
+        views = _train_views(5, 160, 120, 3.0, 1)
+        tau_range = (8.0, 32.0)
+    else:
+        h = synth.make_scene(2, n_leaves=60_000)
+        views = [synth.look_at((40 * np.cos(a), 40 * np.sin(a), 1.7), (0, 0, 2.5), (0, 0, 1), 320, 180, 0.0)
+                 for a in np.linspace(0, 2 * np.pi, 5, endpoint=False)]
+        tau_range = (3.0, 15.0)
+    H0 = O.Hier(h)
+    targets = []
+    for v in views:
+        ids, t = O.cut(H0, v)
+        targets.append(O.render(H0, v, ids, t, alternatives=False)["rgb"].reshape(v.height, v.width, 3)
+                       .astype(np.float32))
+    r = hgs.Renderer(0)
+    try:
+        r.upload(h)
+        P = hgs.params_to_device(h)
+        P0 = {k: t.clone() for k, t in P.items()}
+        r.bind(*[P[k] for k in hgs.PARAM_FIELDS])
+        opt = HierarchyOptimizer(r, P, views, [torch.from_numpy(t).cuda() for t in targets], lr=LR,
+                                 tau_range=tau_range, batch=3, beta1=B1, beta2=B2, eps=EPS, seed=11)
+        steps = 3
+        batches, gpu_losses = [], []
+        for _ in range(steps):
+            loss, batch = opt.step()
+            batches.append(batch)
+            gpu_losses.append(float(loss.item()))
+        torch.cuda.synchronize()
+        for idx, bv in batches:
+            assert len(set(idx.tolist())) == len(idx) == 3
+            assert all(tau_range[0] <= v.tau <= tau_range[1] for v in bv)
+        o_losses, oP = _oracle_steps(h, batches, targets, steps)
+        print(case, "losses GPU", gpu_losses, "oracle", o_losses)
+        for a, b in zip(gpu_losses, o_losses):
+            assert b > 0 and abs(a - b) <= 1e-4 * b, (gpu_losses, o_losses)
+        inner = np.asarray(h.child_count) > 0
+        n = h.n_nodes
+        for k in hgs.PARAM_FIELDS:
+            p0 = P0[k].cpu().numpy().astype(np.float64).reshape(n, -1)
+            pg = P[k].cpu().numpy().astype(np.float64).reshape(n, -1)
+            # leaves never move
+            assert np.array_equal(pg[~inner], p0[~inner]), k
+            du_g, du_o = pg[inner] - p0[inner], oP[k][inner] - p0[inner]
+            rel = np.linalg.norm(du_g - du_o) / np.linalg.norm(du_o)
+            print(case, k, "update rel diff %.3e, |update| %.3e" % (rel, np.linalg.norm(du_o)))
+            assert np.linalg.norm(du_o) > 0 and rel <= 1e-2, (k, rel)
+    finally:
+        r.close()

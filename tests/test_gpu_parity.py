@@ -166,9 +166,10 @@ def test_tile_and_batch_invariance(r_c1, c1):
     (ref,), _ = r_c1.render([v])
     ref = ref.clone()
     for tw, th, b in [(8, 8, 64), (8, 8, 128), (8, 8, 256), (16, 8, 128), (16, 8, 256), (16, 16, 512), (32, 16, 512)]:
-        r_c1.set_tuning(tw, th, b)
-        (img,), _ = r_c1.render([v])
-        assert torch.equal(img, ref), (tw, th, b)
+        for p in (0, 1):
+            r_c1.set_tuning(tw, th, b, p)
+            (img,), _ = r_c1.render([v])
+            assert torch.equal(img, ref), (tw, th, b, p)
     r_c1.set_tuning(16, 16, 0)
 
 
@@ -179,7 +180,7 @@ def test_autotuner_keeps_images(r_c1, c1):
     (ref,), _ = r_c1.render([v])
     ref = ref.clone()
     tuning = autotune(r_c1, [v, v.replace(tau=16.0)])
-    assert (tuning["tile_w"], tuning["tile_h"], tuning["batch"]) in CANDIDATES
+    assert (tuning["tile_w"], tuning["tile_h"], tuning["batch"], tuning["persistent"]) in CANDIDATES
     (img,), _ = r_c1.render([v])
     assert torch.equal(img, ref)
     r_c1.set_tuning(16, 16, 0)
@@ -199,7 +200,7 @@ def _tunings():
     return CANDIDATES
 
 
-def _grad_case(h, v, seed=0, tuning=(16, 16, 256)):
+def _grad_case(h, v, seed=0, tuning=(16, 16, 256, 0)):
     """GPU backward of one view against the oracle's, in the blend
     configuration `tuning` = (tile_w, tile_h, batch)."""
     from paper_2406_12080_amd import hgs as H
@@ -226,10 +227,11 @@ def _grad_case(h, v, seed=0, tuning=(16, 16, 256)):
     # the backward re-evaluates exactly the pairs the forward blended
     assert c["bwd_contrib"] == st["blended"] == c["blended"], (c, st)
     assert c["bwd_evaluated"] >= c["bwd_contrib"] and c["bwd_evaluated"] >= c["bwd_evaluated_t"]
-    ob = O.backward(h, v, oids, ot, w.cpu().numpy().astype(np.float64))
+    cot = w.cpu().numpy().astype(np.float64)
+    ob = O.backward(h, v, oids, ot, cot)
     leaf = h.child_count == 0
     gpu = {k: grads[k].cpu().numpy() for k in grads}
-    res = PR.check_grads(gpu, ob["grad"], leaf)
+    res = PR.check_grads(gpu, ob["grad"], leaf, budget=O.backward_budget(h, v, oids, ot, cot))
     m = ot > 0
     dt_rel = float(np.linalg.norm(dt.cpu().numpy()[m] - ob["dt"][m]) / max(np.linalg.norm(ob["dt"][m]), 1e-30))
     n_near = int(PR.near_nodes(h, v, oids, ot).sum())
@@ -237,7 +239,7 @@ def _grad_case(h, v, seed=0, tuning=(16, 16, 256)):
     return res, dt_rel, int(m.sum()), n_near
 
 
-@pytest.mark.parametrize("tuning", _tunings(), ids=lambda t: "%dx%dx%d" % t)
+@pytest.mark.parametrize("tuning", _tunings(), ids=lambda t: "%dx%dx%d%s" % (t[:3] + ("p" if t[3] else "",)))
 @pytest.mark.parametrize("tau", [16.0, 64.0])
 def test_backward_parity_c1(hgs_mod, c1, tau, tuning):
     res, dt_rel, nt, n_near = _grad_case(c1, synth.make_views(1, tau=tau)[0], tuning=tuning)
@@ -246,7 +248,7 @@ def test_backward_parity_c1(hgs_mod, c1, tau, tuning):
     assert nt > 0 and dt_rel <= PR.GRAD_REL
 
 
-@pytest.mark.parametrize("tuning", _tunings(), ids=lambda t: "%dx%dx%d" % t)
+@pytest.mark.parametrize("tuning", _tunings(), ids=lambda t: "%dx%dx%d%s" % (t[:3] + ("p" if t[3] else "",)))
 def test_backward_parity_c2s(hgs_mod, c2s, tuning):
     # the eye stands among the splats: some hundred nodes lie within a metre
     # of it, interpolated splats centred far off screen that cover the whole
@@ -309,6 +311,43 @@ def test_second_backward_of_one_render_repeats_the_first(r_c2s, c2s):
         assert np.linalg.norm(out[0][k] - out[1][k]) <= 1e-5 * np.linalg.norm(out[0][k]), k
 
 
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_backward_graph_replays_match_the_eager_backward(r_c2s, c2s, persistent):
+    # a batched render's backward is captured once into a graph and replayed;
+    # with kernel timing on, the same render runs without graphs.  Every
+    # replay, with the program's own work and synchronisations in between,
+    # equals the eager backward up to the order of the FP64 atomic sums
+    from paper_2406_12080_amd import hgs as H
+    views = [synth.look_at((0, -40, 1.7), (0, 0, 2.5), (0, 0, 1), 640, 360, 6.0),
+             synth.look_at((30, -30, 1.7), (0, 0, 2.5), (0, 0, 1), 1280, 720, 6.0)]
+    gen = torch.Generator(device="cpu").manual_seed(33)
+    dL = [torch.randn((v.height, v.width, 3), generator=gen).cuda() for v in views]
+    P = H.params_to_device(c2s)
+    r_c2s.set_tuning(8, 8, 64, persistent)
+
+    def grads_of_one(profile):
+        r_c2s.set_profiling(profile)
+        _, st = r_c2s.render(views)
+        grads = {k: torch.zeros_like(P[k]) for k in H.PARAM_FIELDS}
+        dt = torch.zeros(st["cut"], device="cuda")
+        r_c2s.backward(dL, grads, dt)
+        _sync()
+        out = {k: g.cpu().numpy().astype(np.float64) for k, g in grads.items()}
+        out["dt"] = dt.cpu().numpy().astype(np.float64)
+        return out
+
+    eager = grads_of_one(True)
+    for rep in range(3):
+        got = grads_of_one(False)
+        torch.empty(1 << 20, device="cuda").fill_(float(rep))  # unrelated work between replays
+        _sync()
+        for k in eager:
+            assert np.linalg.norm(eager[k]) > 0, k
+            assert np.linalg.norm(got[k] - eager[k]) <= 1e-6 * np.linalg.norm(eager[k]), (rep, k)
+    r_c2s.set_profiling(False)
+    r_c2s.set_tuning(16, 16, 0)
+
+
 def test_gradients_without_dt_equal_those_with_it(r_c2s, c2s):
     # without a dL/dt output the blend backward drops that slot; every
     # parameter gradient stays what it is with it (up to the order of the
@@ -329,12 +368,15 @@ def test_gradients_without_dt_equal_those_with_it(r_c2s, c2s):
         if with_dt:
             assert float(dt.abs().sum()) > 0
         out.append({k: g.cpu().numpy().astype(np.float64) for k, g in grads.items()})
+    # two backward passes whose FP64 atomic sums run in different orders, of
+    # two kernel instantiations the compiler schedules on their own: the
+    # run-to-run bound of the repeated-backward test
     for k in out[0]:
         assert np.linalg.norm(out[0][k]) > 0
-        assert np.linalg.norm(out[0][k] - out[1][k]) <= 1e-6 * np.linalg.norm(out[0][k]), k
+        assert np.linalg.norm(out[0][k] - out[1][k]) <= 1e-5 * np.linalg.norm(out[0][k]), k
 
 
-@pytest.mark.parametrize("tuning", [(8, 8, 64), (16, 8, 128), (16, 16, 256)], ids=lambda t: "%dx%dx%d" % t)
+@pytest.mark.parametrize("tuning", [(8, 8, 64, 1), (16, 8, 128, 0), (16, 16, 256, 0)], ids=lambda t: "%dx%dx%d%s" % (t[:3] + ("p" if t[3] else "",)))
 def test_autograd_l1_matches_oracle(hgs_mod, c1, tuning):
     from paper_2406_12080_amd import hgs as H
     from paper_2406_12080_amd.autograd import render
@@ -344,17 +386,26 @@ def test_autograd_l1_matches_oracle(hgs_mod, c1, tuning):
     r.upload(h)
     r.set_tuning(*tuning)
     P = {k: t.requires_grad_(True) for k, t in H.params_to_device(h).items()}
-    target = torch.rand((v.height, v.width, 3), device="cuda")
-    (img,) = render(r, [v], P)
-    loss = (img - target).abs().mean()
-    loss.backward()
-    img_np = img.detach().cpu().numpy().astype(np.float64)
-    dL = np.sign(img_np - target.cpu().numpy()) / img_np.size
+    # the target sits at least 0.01 from the oracle's image on either side,
+    # so that the sign of the L1 residual is the same for both renderers
     oids, ot = O.cut(h, v)
-    amb = (O.render(h, v, oids, ot)["nalt"] > 0).reshape(v.height, v.width)
+    o = O.render(h, v, oids, ot)
+    rng = np.random.default_rng(3)
+    side = rng.choice([-1.0, 1.0], size=(v.height, v.width, 3))
+    target_np = o["rgb"].reshape(v.height, v.width, 3) + side * rng.uniform(0.01, 0.5, side.shape)
+    target = torch.from_numpy(target_np.astype(np.float32)).cuda()
+    # pixels with a decision on a threshold or the clamp carry no loss:
+    # there either side's gradient is a correct one
+    amb = PR.ambiguous(o).reshape(v.height, v.width)
     assert amb.sum() < 0.01 * amb.size
+    keep = torch.from_numpy(~amb).cuda()[..., None].float()
+    (img,) = render(r, [v], P)
+    loss = ((img - target).abs() * keep).mean()
+    loss.backward()
+    dL = -side * (~amb)[..., None] / side.size
     ob = O.backward(h, v, oids, ot, dL)
-    res = PR.check_grads({k: P[k].grad.cpu().numpy() for k in P}, ob["grad"], h.child_count == 0)
+    res = PR.check_grads({k: P[k].grad.cpu().numpy() for k in P}, ob["grad"], h.child_count == 0,
+                         budget=O.backward_budget(h, v, oids, ot, dL))
     print(res)
     PR.assert_grads(res)
     r.close()
