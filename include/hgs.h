@@ -131,6 +131,22 @@ typedef struct {
 hgs_status hgs_cut(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *out_t, int64_t capacity,
                    int64_t *out_count);
 
+/* hgs_cut without device allocation, for callers that cannot allocate
+ * (code that must not call hipMalloc: under HIP graph capture, in tight
+ * serving loops, or in harnesses that forbid it).  Same arguments, results
+ * and errors as hgs_cut; the caller still provides out_ids and out_t.  The
+ * cut's working memory (bit masks, block counts and offsets, scan partials,
+ * counters, the view record: about 12.6 MiB) is a static device array of
+ * the library, one per device, held until the process ends, so the call
+ * allocates nothing and leaves the ctx's workspaces, and the state kept for
+ * hgs_render_backward, as they were.  Limit: hierarchies of at most 2^26
+ * (67,108,864) nodes; larger ones get HGS_ERR_INVALID_ARG.  Every call on a
+ * device shares that device's array: calls that overlap on one device (two
+ * threads, or two streams with work in flight) race and must be serialised
+ * by the caller.  Synchronises the ctx stream. */
+hgs_status hgs_cut_noalloc(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *out_t, int64_t capacity,
+                           int64_t *out_count);
+
 /* Hierarchy compaction (Sec. 5.2, "Compacting the Hierarchy"): marks the
  * nodes that survive the sparsification for a set of (training) views.  With
  * the granularity ladder tau_i = tau_min 2^i for every i with tau_i <=

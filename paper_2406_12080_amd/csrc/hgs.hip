@@ -3,6 +3,7 @@
 // cut -> preprocess -> sort -> blend pipeline (direct for one view, captured
 // in a HIP graph for several), and the backward.
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -561,6 +562,55 @@ void enqueue_backward(hgs_ctx *ctx, int nv, const hgs_grads *out, hipStream_t st
     }
 }
 
+// ------------------------------------------------ allocation-free cut
+// Scratch of hgs_cut_noalloc in a file-scope device array: every device the
+// library runs on holds one copy until the process ends.  It covers
+// hierarchies of up to kNoAllocMaxNodes nodes: the cut's bit masks and mask
+// word positions, its per-block counts and offsets, the scan partials, the
+// counters and the view record.  In host code `scratch` names a host-side
+// stand-in, never the device memory: its device address comes from
+// hipGetSymbolAddress, once per device (g_scratch), and only that address is
+// handed to kernels and copies.
+constexpr int64_t kNoAllocMaxNodes = int64_t(1) << 26;
+constexpr size_t kNaWords = (size_t)(kNoAllocMaxNodes / 64) + 1;
+constexpr size_t kNaBlocks = (size_t)(kNoAllocMaxNodes / kCutBlock);
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kNaMasks = 0;
+constexpr size_t kNaWordOff = align256(kNaMasks + 8 * kNaWords);
+constexpr size_t kNaCounts = align256(kNaWordOff + 4 * kNaWords);
+constexpr size_t kNaOffsets = align256(kNaCounts + 4 * kNaBlocks);
+constexpr size_t kNaPartial = align256(kNaOffsets + 4 * kNaBlocks);
+constexpr size_t kNaCtr = align256(kNaPartial + 4 * (size_t)kScanBlocks);
+constexpr size_t kNaView = align256(kNaCtr + sizeof(Counters));
+constexpr size_t kNaBytes = align256(kNaView + sizeof(DevView));
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+unsigned char *g_scratch[kMaxDevices] = {};  // device address of `scratch` on each device
+
+// With ctx->device current: looks up this device's copy of the scratch once.
+hgs_status scratch_init(hgs_ctx *ctx)
+{
+    if (ctx->device >= kMaxDevices) return fail(ctx, HGS_ERR_INVALID_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch[ctx->device]) return HGS_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(ctx, HGS_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch[ctx->device] = (unsigned char *)p;
+    return HGS_OK;
+}
+
+unsigned char *scratch_of(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return device >= 0 && device < kMaxDevices ? g_scratch[device] : nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -608,6 +658,7 @@ hgs_status hgs_create(hgs_ctx **out, int device, void *hip_stream)
         if ((s = dalloc(ctx, (void **)&ctx->seg_tile_base, sizeof(uint32_t) * kMaxViews))) break;
         if ((s = dalloc(ctx, (void **)&ctx->queue, sizeof(uint32_t) * 2))) break;
         if ((s = dalloc(ctx, (void **)&ctx->l1_partial, sizeof(double) * kL1Blocks))) break;
+        if ((s = scratch_init(ctx))) break;
     } while (0);
     if (s != HGS_OK) {
         hgs_destroy(ctx);
@@ -858,6 +909,52 @@ hgs_status hgs_cut(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *
     if (*out_count > 0)
         launch_cut_emit(h, ctx->views_dev, 1, ctx->masks, ctx->blk_offsets, nb, ctx->word_off, out_ids, out_t, nullptr,
                         (uint32_t)capacity, st);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(st));
+    return HGS_OK;
+}
+
+hgs_status hgs_cut_noalloc(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids, float *out_t, int64_t capacity,
+                           int64_t *out_count)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy uploaded");
+    if (!view || !out_count || capacity < 0 || (capacity > 0 && !out_ids))
+        return fail(ctx, HGS_ERR_INVALID_ARG, "bad arguments");
+    if (ctx->n > kNoAllocMaxNodes)
+        return fail(ctx, HGS_ERR_INVALID_ARG, "hierarchy of " + std::to_string(ctx->n) +
+                                                  " nodes exceeds the static scratch (at most " +
+                                                  std::to_string(kNoAllocMaxNodes) + " nodes)");
+    if (!finite_view(*view)) return fail(ctx, HGS_ERR_INVALID_ARG, "view is invalid");
+    HIPC(hipSetDevice(ctx->device));
+    unsigned char *base = scratch_of(ctx->device);
+    if (!base) return fail(ctx, HGS_ERR_STATE, "static scratch not set up on this device");
+    uint64_t *masks = (uint64_t *)(base + kNaMasks);
+    uint32_t *word_off = (uint32_t *)(base + kNaWordOff);
+    uint32_t *counts = (uint32_t *)(base + kNaCounts);
+    uint32_t *offsets = (uint32_t *)(base + kNaOffsets);
+    uint32_t *partial = (uint32_t *)(base + kNaPartial);
+    Counters *ctr = (Counters *)(base + kNaCtr);
+    DevView *dview = (DevView *)(base + kNaView);
+    hipStream_t st = ctx->stream;
+    DevView hv;
+    fill_dev_view(*view, ctx->tile_w, ctx->tile_h, hv);
+    hgs_status s;
+    if ((s = stage_copy(ctx, &hv, 1, dview, st))) return s;
+    const DevHier h = dev_hier(ctx);
+    const int nb = cut_blocks(ctx->n);
+    launch_fill_u32((uint32_t *)ctr, 0u, sizeof(Counters) / 4, st);
+    launch_cut_flags(h, dview, 1, masks, counts, nb, st);
+    launch_scan(counts, nullptr, (uint32_t)nb, nullptr, offsets, &ctr->cut_total, partial, st);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(ctx->ctr_host, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    *out_count = ctx->ctr_host->cut_total;
+    if (*out_count > capacity)
+        return fail(ctx, HGS_ERR_CAPACITY, "cut has " + std::to_string(*out_count) + " nodes, capacity " +
+                                               std::to_string(capacity));
+    if (*out_count > 0)
+        launch_cut_emit(h, dview, 1, masks, offsets, nb, word_off, out_ids, out_t, nullptr, (uint32_t)capacity, st);
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(st));
     return HGS_OK;

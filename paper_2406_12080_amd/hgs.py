@@ -19,7 +19,7 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_CAPACITY = range(6)
 _NAMES = {0: "HGS_OK", 1: "HGS_ERR_INVALID_ARG", 2: "HGS_ERR_OOM", 3: "HGS_ERR_HIP", 4: "HGS_ERR_STATE",
           5: "HGS_ERR_CAPACITY"}
 EXPORTS = ("hgs_create", "hgs_destroy", "hgs_last_error", "hgs_set_stream", "hgs_upload", "hgs_bind_params",
-           "hgs_cut", "hgs_compact_mark", "hgs_compact_rebuild", "hgs_render", "hgs_last_render",
+           "hgs_cut", "hgs_cut_noalloc", "hgs_compact_mark", "hgs_compact_rebuild", "hgs_render", "hgs_last_render",
            "hgs_render_backward", "hgs_l1_loss", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
            "hgs_kernel_time", "hgs_counters")
 COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t", "bwd_evaluated",
@@ -93,6 +93,7 @@ def lib():
         L.hgs_upload.argtypes = [vp, P(HierarchyDesc), c_int]
         L.hgs_bind_params.argtypes = [vp, vp, vp, vp, vp, vp]
         L.hgs_cut.argtypes = [vp, P(View), vp, vp, ctypes.c_int64, P(ctypes.c_int64)]
+        L.hgs_cut_noalloc.argtypes = [vp, P(View), vp, vp, ctypes.c_int64, P(ctypes.c_int64)]
         L.hgs_compact_mark.argtypes = [vp, P(View), ctypes.c_int32, ctypes.c_float, ctypes.c_float, vp]
         L.hgs_compact_rebuild.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp, P(ctypes.c_int64)]
         L.hgs_render.argtypes = [vp, P(View), ctypes.c_int32, P(vp), P(Stats)]
@@ -233,6 +234,19 @@ class Renderer:
         self._check(self.L.hgs_cut(self.h, ctypes.byref(hv), ctypes.c_void_p(ids.data_ptr()),
                                    ctypes.c_void_p(t.data_ptr()), cap, ctypes.byref(cnt)))
         return ids[:cnt.value], t[:cnt.value]
+
+    def cut_noalloc(self, view, ids, t=None) -> int:
+        """``hgs_cut_noalloc`` into caller-given CUDA tensors (int32 ids,
+        float32 t or None; capacity = len(ids)); returns the cut size."""
+        assert ids.is_cuda and ids.dtype == self.torch.int32 and ids.is_contiguous()
+        if t is not None:
+            assert t.is_cuda and t.dtype == self.torch.float32 and t.numel() >= ids.numel()
+        cnt = ctypes.c_int64()
+        hv = make_view(view)
+        self._check(self.L.hgs_cut_noalloc(self.h, ctypes.byref(hv), ctypes.c_void_p(ids.data_ptr()),
+                                           ctypes.c_void_p(t.data_ptr() if t is not None else 0), ids.numel(),
+                                           ctypes.byref(cnt)))
+        return cnt.value
 
     def compact_mark(self, views, tau_min: float = 3.0, tau_max: float | None = None):
         """Keep flags of the hierarchy compaction (``hgs_compact_mark``) for
