@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
 PINS = "tests/test_oracle_pins.py"
 COMPACT_PINS = "tests/test_compact.py"
+BUILD_PINS = "tests/test_build_oracle.py"
 
 C = "hgs_oracle.c"
 PY = "oracle.py"
@@ -56,7 +57,8 @@ MUTATIONS = [
      "for (int k = 0; k < 4; ++k) S->q[k] = S->qraw[k] / S->qnorm;",
      "for (int k = 0; k < 4; ++k) S->q[k] = S->qraw[k];", PINS),
     ("stop after the splat instead of before", C, "int stop = Tn < OR_T_MIN;", "int stop = T < OR_T_MIN;", PINS),
-    ("gradient through the 0.99 clamp", C, "if (!a.clamp_n) {", "if (1) {", PINS),
+    ("gradient through the 0.99 clamp", C, "if (!a.clamp_n) {\n                G->dAn += dan * a.G;",
+     "if (1) {\n                G->dAn += dan * a.G;", PINS),
     ("Sigma3 = M^T M", C, "acc += M[3 * i + k] * M[3 * j + k];", "acc += M[3 * k + i] * M[3 * k + j];", PINS),
     ("parent's share of the SH gradient dropped", C,
      "if (p >= 0) grad[(11 + k) * n + p] += w1 * dsh[k];", ";", PINS),
@@ -82,6 +84,20 @@ MUTATIONS = [
      "dal += (Ti * S->rgb[ch] - after[ch] / (1.0 - al)) * gC[ch];", PINS),
     ("budget without the contributor weight", C, "const double wgt = (double)(nc + 16);", "const double wgt = 1.0;",
      PINS),
+    # hierarchy generation (Sec. 4.1) and orientation matching (Sec. 4.2)
+    ("merge weights without the surface", "build_oracle.c",
+     "for (int64_t c = c0; c < c0 + cc; ++c) W += opacity[c] * surf[c];",
+     "for (int64_t c = c0; c < c0 + cc; ++c) W += opacity[c];", BUILD_PINS),
+    ("merged covariance without the spread of the means", "build_oracle.c",
+     "S[3 * a + b] += w * (cov[9 * c + 3 * a + b] + d[a] * d[b]);", "S[3 * a + b] += w * cov[9 * c + 3 * a + b];",
+     BUILD_PINS),
+    ("falloff as the mean opacity", "build_oracle.c", "opacity[id] = W / surf[id];",
+     "opacity[id] = W / surf[id] / (double)cc;", BUILD_PINS),
+    ("matching keeps the largest rotation", "build_oracle.c", "if (tr > bt) {", "if (-tr > bt) {", BUILD_PINS),
+    ("split on the parent's own prefix", "build_oracle.c", "const int shift = 3 * (OB_BITS - (depth + 1));",
+     "const int shift = 3 * (OB_BITS - depth);", BUILD_PINS),
+    ("leaf box at two sigma", "build_oracle.c", "3.0 * sqrt(R[3 * a] * R[3 * a] * s[0] * s[0]",
+     "2.0 * sqrt(R[3 * a] * R[3 * a] * s[0] * s[0]", BUILD_PINS),
     # the compaction of Sec. 5.2, step by step
     ("removal does not stop at marked nodes", PY,
      "                if marked[c]:\n                    continue\n", "", COMPACT_PINS),
@@ -112,10 +128,11 @@ def _run_mutant(idx: int) -> tuple[str, int, str]:
         src = open(path).read()
         assert src.count(old) == 1, (name, src.count(old))
         open(path, "w").write(src.replace(old, new))
-        if fname == C:
+        if fname.endswith(".c"):
             os.makedirs(os.path.join(work, "oracle", "_build"))
+            srcs = [os.path.join(work, "oracle", f) for f in (C, "build_oracle.c")]
             subprocess.check_call(["gcc", "-O1", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                                   "-o", os.path.join(work, "oracle", "_build", "liboracle.so"), path, "-lm"])
+                                   "-o", os.path.join(work, "oracle", "_build", "liboracle.so"), *srcs, "-lm"])
         else:
             os.makedirs(os.path.join(work, "oracle", "_build"))
             shutil.copy(os.path.join(ORACLE, "_build", "liboracle.so"), os.path.join(work, "oracle", "_build"))
