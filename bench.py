@@ -413,6 +413,82 @@ def forward_leg(name: str, steps: int, taus=(6.0,), plain: bool = True) -> dict:
     return out
 
 
+def stream_leg(r, h, frames: int = 120, step_m: float = 0.5, cache_nodes: int = 8_000_000,
+               cleanup_every: int = 100, max_age: int = 50) -> dict:
+    """Out-of-core rendering (Sec. 6.3) along a camera path down the
+    corridor: one 1920x1080 view per frame at tau = 6 px, the eye moving
+    `step_m` metres a frame; the parameters stay in pinned host memory and a
+    device cache of `cache_nodes` records takes what each frame's cut needs
+    (cleanup every `cleanup_every` frames of records older than `max_age`).
+    Reports per frame the cut size (#Render), the records transferred
+    (#Trans) and the time, against the same path rendered in core."""
+    import torch
+    from paper_2406_12080_amd import synth
+    path = [synth.look_dir((100.0 + step_m * f, 0.0, 1.7), 0.0, 0.0, 1920, 1080, 6.0) for f in range(frames)]
+    img = [torch.empty((1080, 1920, 3), device="cuda")]
+    r.unbind()
+    r.render([path[0]], out=img)  # in core, the same path
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cut = []
+    for v in path:
+        _, st = r.render([v], out=img)
+        cut.append(st["cut"])
+    torch.cuda.synchronize()
+    t_core = (time.perf_counter() - t0) / frames
+    r.stream_begin(min(cache_nodes, h.n_nodes))
+    trans, ms = [], []
+    try:
+        for f, v in enumerate(path, start=1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r.render([v], out=img)  # synchronises at its end
+            ms.append((time.perf_counter() - t0) * 1e3)
+            trans.append(r.stream_info()["requested"])
+            if f % cleanup_every == 0:
+                r.stream_cleanup(max_age)
+        info = r.stream_info()
+    finally:
+        r.stream_end()
+    res = dict(frames=frames, step_m=step_m, cache_nodes=min(cache_nodes, h.n_nodes), cleanup_every=cleanup_every,
+               max_age=max_age, render_per_frame_mean=round(float(sum(cut)) / frames, 1),
+               trans_per_frame_mean=round(float(sum(trans[1:])) / max(frames - 1, 1), 1),
+               trans_first_frame=trans[0], trans_max=max(trans[1:]) if frames > 1 else trans[0],
+               ms_per_frame_stream=round(sum(ms[1:]) / max(frames - 1, 1), 3), ms_first_frame=round(ms[0], 3),
+               ms_per_frame_in_core=round(t_core * 1e3, 3), resident_end=info["resident"],
+               transferred_total=info["transferred_total"], host_bytes_per_node=236)
+    log(f"[bench] stream leg: {res}")
+    return res
+
+
+def build_leg(workload: str) -> dict:
+    """Hierarchy generation on the GPU (hgs_build) over the workload's leaves,
+    already in device memory: the octree, the merges, the orientation
+    matching and the boxes.  Timed on the second of two builds."""
+    import torch
+    from paper_2406_12080_amd import hgs, synth
+    cfg = synth.CONFIGS[WORKLOADS[workload]["config"]]
+    t0 = time.time()
+    lv = synth.make_leaves(cfg["leaves"], cfg["layout"], WORKLOADS[workload]["config"])
+    log(f"[bench] build leg: {cfg['leaves']} leaves drawn ({time.time() - t0:.1f}s)")
+    dl = {("mean" if k == "pos" else k): torch.from_numpy(v).cuda() for k, v in lv.items()}
+    del lv
+    r = hgs.Renderer(0)
+    times = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_nodes = r.build(dl)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    r.close()
+    del dl
+    torch.cuda.empty_cache()
+    log(f"[bench] build leg: {n_nodes} nodes in {times[-1] * 1e3:.1f} ms")
+    return dict(leaves=cfg["leaves"], nodes=n_nodes, ms=round(times[-1] * 1e3, 2),
+                nodes_per_s=round(n_nodes / times[-1], 1), first_ms=round(times[0] * 1e3, 2))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,6 +510,10 @@ def main(argv=None):
     ap.add_argument("--other-workloads", type=int, default=1,
                     help="1: also the forward legs of the 1M-leaf single view (tau 3, 6, 15) and of the 8M-leaf "
                          "corridor's 64 views (batched vs plain); 0: skip them")
+    ap.add_argument("--stream", type=int, default=120, metavar="F",
+                    help="also render F frames of a camera path out of core (corridor workloads; 0: skip)")
+    ap.add_argument("--build", type=int, default=1,
+                    help="1: also time the GPU hierarchy generation over the workload's leaves (0: skip)")
     ap.add_argument("--compact", type=int, default=0, metavar="V",
                     help="also time the GPU marking of the hierarchy compaction over V training views "
                          "(reported under 'compaction')")
@@ -465,7 +545,9 @@ def main(argv=None):
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
         del src, dst
+    t_host = time.time()
     h, views = build_workload(args.workload, args.leaves)
+    host_build_s = time.time() - t_host  # the NumPy generation of the input scene, for comparison
     nv = len(views)
     dev = torch.device("cuda", 0)
     r = hgs.Renderer(0)
@@ -570,6 +652,9 @@ def main(argv=None):
     conv = None
     if args.converge > 0:
         conv = converge(r, h, views, args.converge)
+    stream = None
+    if args.stream > 0 and WORKLOADS[args.workload]["config"] in (3, 5):
+        stream = stream_leg(r, h, frames=args.stream)
 
     # roofline of the dominant kernel (the longer of blend and blend backward)
     ms_blend, n_blend = k_ms[hgs.K_BLEND]
@@ -640,9 +725,14 @@ def main(argv=None):
         out["compaction"] = cmp
     if conv is not None:
         out["convergence"] = conv
+    if stream is not None:
+        out["stream"] = stream
     r.close()
     del P, grads, imgs, dL
     torch.cuda.empty_cache()
+    if args.build and args.leaves is None:
+        out["build"] = build_leg(args.workload)
+        out["build"]["host_numpy_s"] = round(host_build_s, 1)
     if args.other_workloads and args.leaves is None:
         legs = {}
         legs["box1m_1x1080p"] = forward_leg("box1m_1x1080p_tau6", args.steps, taus=(3.0, 6.0, 15.0))

@@ -98,6 +98,51 @@ typedef struct {
  * boxes from the Gaussians). */
 hgs_status hgs_upload(hgs_ctx *ctx, const hgs_hierarchy_desc *desc, int src_on_device);
 
+/* Leaf Gaussians for hgs_build (node-major, FP32): mean [n][3], scale
+ * [n][3] (activated, world units), rot [n][4] (w, x, y, z), opacity [n],
+ * sh [n][48] (coefficient k of channel c at 3 k + c). */
+typedef struct {
+    int64_t n_leaves;
+    const float *mean, *scale, *rot, *opacity, *sh;
+} hgs_leaves_desc;
+
+/* Hierarchy generation (Sec. 4.1 "Hierarchy Generation", with the
+ * orientation matching of Sec. 4.2) on the device, replacing ctx's
+ * hierarchy as hgs_upload would (parameters unbound, render state dropped).
+ * The tree: the leaves' means on a 2^21 grid per axis over their bounding
+ * cube (cell = floor((x - min) (2^21 - 1) / largest extent + 1/2)), sorted
+ * by (Morton code, leaf index); breadth first from the root, a node with
+ * two or more leaves at depth d < 21 has one child per non-empty octant of
+ * its cell (in code order; one child when all share it), at depth 21 and
+ * beyond (leaves in one finest cell) k = min(8, m) children of m j / k ..
+ * leaves each.  Interior Gaussians by Eq. (merge) with the weights o_i S_i
+ * (S = Thomsen's ellipsoid surface from the scales, o the child's opacity
+ * or falloff), SH with the same weights, falloff = sum w' / S_p, scales
+ * and axes from the eigen-decomposition of the merged covariance; then top
+ * down every node's axes re-assigned by the proper signed axis permutation
+ * closest to its parent's (the world axes at the root), quaternions with
+ * q . q_parent >= 0 (w >= 0 at the root).  Boxes: a leaf's mean +- 3
+ * sqrt(diag Sigma) from its stored values, rounded outward to FP32; an
+ * interior node's the union of its children's.  All arithmetic in FP64,
+ * stored in FP32.  `src_on_device`: 0 = host pointers, 1 = device pointers.
+ * *n_nodes (host) receives the node count.  n_leaves in [1, 2^29];
+ * non-finite means: HGS_ERR_INVALID_ARG.  Synchronises the ctx stream;
+ * allocates its working memory (FP64, about 0.5 kB per node) for the call. */
+hgs_status hgs_build(hgs_ctx *ctx, const hgs_leaves_desc *leaves, int src_on_device, int64_t *n_nodes);
+
+/* Copies ctx's hierarchy out in the layouts of hgs_hierarchy_desc
+ * (node-major; boxes [N][3]); every pointer may be NULL (not copied).
+ * leaf_src [N]: the hgs_build input index of every leaf node, -1 for an
+ * interior node (HGS_ERR_STATE for a hierarchy that came from hgs_upload).
+ * The parameters are the ones the renderer reads (the bound arrays when
+ * bound).  `dst_on_device`: 0 = host pointers, 1 = device pointers.
+ * Synchronises the ctx stream. */
+typedef struct {
+    int32_t *parent, *child_begin, *child_count, *leaf_src;
+    float *bmin, *bmax, *mean, *scale, *rot, *opacity, *sh;
+} hgs_hierarchy_out;
+hgs_status hgs_download(hgs_ctx *ctx, const hgs_hierarchy_out *out, int dst_on_device);
+
 /* Render from caller-owned device parameter arrays instead of the copies
  * made by hgs_upload (same layouts, N = n_nodes).  Pointers stay owned by the
  * caller and must stay valid while used.  Passing all NULL reverts to the
@@ -255,6 +300,40 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views
  * is NULL. */
 hgs_status hgs_l1_loss(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const float *const *target,
                        float *const *dL_drgb, double *loss);
+
+/* Out-of-core rendering (Sec. 6.3: as the camera moves the cut is updated
+ * and the nodes it needs are transferred to the GPU from CPU RAM, with a
+ * cleanup every so many frames).  hgs_stream_begin moves ctx's Gaussian
+ * parameters (236 B per node) to library-owned pinned host memory and keeps
+ * on the device the topology and boxes (28 B per node, every cut reads
+ * them) and a cache of `cache_nodes` parameter records.  Every later
+ * hgs_render then, after its cut and before projecting, transfers the
+ * records of the cut nodes and their parents that are not resident (the
+ * GPU reads them from host memory), stamps every record it uses with the
+ * frame (one frame per hgs_render), and renders from the cache: images are
+ * those of the in-core render.  A render whose nodes do not fit in the free
+ * slots returns HGS_ERR_CAPACITY (its image lacks them).  Parameters must
+ * not be bound; hgs_render_backward, hgs_bind_params and hgs_adam_step
+ * return HGS_ERR_STATE until hgs_stream_end, which copies the parameters
+ * back to the device; hgs_upload and hgs_build also end it.  cache_nodes in
+ * [1, n_nodes].  Both synchronise the ctx stream. */
+hgs_status hgs_stream_begin(hgs_ctx *ctx, int64_t cache_nodes);
+hgs_status hgs_stream_end(hgs_ctx *ctx);
+
+/* Frees the cache slots whose records no render has used for more than
+ * max_age frames (the paper's periodic cleanup).  Queued on the ctx stream. */
+hgs_status hgs_stream_cleanup(hgs_ctx *ctx, int32_t max_age);
+
+typedef struct {
+    int64_t cache_nodes;        /* capacity */
+    int64_t resident;           /* records in the cache */
+    int64_t frame;              /* renders since hgs_stream_begin */
+    int64_t requested;          /* records the last render requested (transferred unless overflow) */
+    int64_t transferred_total;  /* records transferred since hgs_stream_begin */
+    int32_t overflow;           /* the last render needed more free slots than there were */
+} hgs_stream_stats;
+/* State of the cache (synchronises the ctx stream). */
+hgs_status hgs_stream_info(hgs_ctx *ctx, hgs_stream_stats *out);
 
 /* One step of the optimiser of the hierarchy optimisation (Sec. 5.1, the
  * paragraph on optimising the generated hierarchy): interior nodes only,

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhgs.so")
-SOURCES = ["k_cut.hip", "k_scan.hip", "k_sort.hip", "k_preprocess.hip", "k_blend.hip", "k_adam.hip", "k_loss.hip", "hgs.hip",
+SOURCES = ["k_cut.hip", "k_scan.hip", "k_sort.hip", "k_preprocess.hip", "k_blend.hip", "k_adam.hip", "k_loss.hip", "k_build.hip", "k_stream.hip", "hgs.hip",
            "compact_host.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

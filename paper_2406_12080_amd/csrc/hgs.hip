@@ -57,6 +57,13 @@ struct hgs_ctx {
     float *box = nullptr;
     int32_t *child_count = nullptr, *child_begin = nullptr;
     int32_t *interior = nullptr;  // ids of the interior nodes, ascending
+    int32_t *leaf_src = nullptr;  // after hgs_build: input index of every leaf node (-1 interior)
+    // out-of-core rendering: parameters in pinned host memory, a device cache
+    bool streaming = false;
+    StreamDev sd{};
+    StreamParams host_params{}, host_params_dev{}, cache_params{};
+    void *host_block = nullptr;          // the pinned allocation behind host_params
+    uint32_t *stream_host = nullptr;     // pinned readback: free_top, frame, req_count, overflow, transferred (2)
     int64_t n_interior = 0;
     float *own[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float *bound[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -285,6 +292,15 @@ DevHier dev_hier(const hgs_ctx *c)
     h.rot = P[2];
     h.opacity = P[3];
     h.sh = P[4];
+    h.slot = nullptr;
+    if (c->streaming) {
+        h.mean = c->cache_params.mean;
+        h.scale = c->cache_params.scale;
+        h.rot = c->cache_params.rot;
+        h.opacity = c->cache_params.opacity;
+        h.sh = c->cache_params.sh;
+        h.slot = c->sd.slot;
+    }
     return h;
 }
 
@@ -479,6 +495,9 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
                     ctx->cut_t,
                     ctx->cut_cap, st);
     launch_cut_finish(ctx->blk_offsets, ctx->blk_counts, nb, nv, ctx->cut_base, ctx->ctr, st);
+    if (ctx->streaming)  // the cut's nodes and parents made resident in the cache
+        launch_stream_frame(ctx->sd, ctx->pinfo, ctx->cut_ids, &ctx->ctr->cut_total, ctx->cut_cap,
+                            ctx->host_params_dev, ctx->cache_params, st);
     mark(1);
     launch_preprocess(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t, &ctx->ctr->cut_total,
                       ctx->cut_cap, ctx->recs, ctx->axes, ctx->depth_key, ctx->trec, ctx->ntiles, ctx->cjac,
@@ -532,6 +551,45 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
         enqueue_blend(ctx, nv, n_tiles, st);
     }
     mark(7);
+}
+
+// Frees the hierarchy's buffers (topology, boxes, parameters, interior list).
+void stream_release(hgs_ctx *ctx)
+{
+    if (!ctx->streaming) return;
+    void **bufs[] = {(void **)&ctx->sd.slot, (void **)&ctx->sd.node_in_slot, (void **)&ctx->sd.last_used,
+                     (void **)&ctx->sd.free_stack, (void **)&ctx->sd.free_top, (void **)&ctx->sd.req,
+                     (void **)&ctx->cache_params.mean, (void **)&ctx->cache_params.scale,
+                     (void **)&ctx->cache_params.rot, (void **)&ctx->cache_params.opacity,
+                     (void **)&ctx->cache_params.sh};
+    for (void **b : bufs) {
+        dfree(ctx, *b);
+        *b = nullptr;
+    }
+    if (ctx->host_block) (void)hipHostFree(ctx->host_block);
+    ctx->host_block = nullptr;
+    ctx->host_params = ctx->host_params_dev = StreamParams{};
+    ctx->sd = StreamDev{};
+    ctx->streaming = false;
+}
+
+void drop_hierarchy(hgs_ctx *ctx)
+{
+    stream_release(ctx);
+    for (int k = 0; k < 5; ++k) {
+        dfree(ctx, ctx->own[k]);
+        ctx->own[k] = nullptr;
+        ctx->bound[k] = nullptr;
+    }
+    void **bufs[] = {(void **)&ctx->pinfo, (void **)&ctx->box, (void **)&ctx->child_count,
+                     (void **)&ctx->child_begin, (void **)&ctx->interior, (void **)&ctx->leaf_src};
+    for (void **b : bufs) {
+        dfree(ctx, *b);
+        *b = nullptr;
+    }
+    ctx->use_bound = false;
+    ctx->has_hier = false;
+    ctx->have_render = false;
 }
 
 // The backward of the last render, queued on st: screen-gradient rows and
@@ -642,7 +700,8 @@ hgs_status hgs_create(hgs_ctx **out, int device, void *hip_stream)
                 s = HGS_ERR_HIP;
         }
         if (s != HGS_OK) break;
-        if (hipHostMalloc((void **)&ctx->ctr_host, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void **)&ctx->ctr_host, sizeof(Counters), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&ctx->stream_host, 32, hipHostMallocDefault) != hipSuccess) {
             s = HGS_ERR_OOM;
             break;
         }
@@ -677,6 +736,8 @@ void hgs_destroy(hgs_ctx *ctx)
     else (void)hipDeviceSynchronize();
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->bexec) (void)hipGraphExecDestroy(ctx->bexec);
+    if (ctx->host_block) (void)hipHostFree(ctx->host_block);
+    if (ctx->stream_host) (void)hipHostFree(ctx->stream_host);
     collect_times(ctx);
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     for (void *p : ctx->allocs) (void)hipFree(p);
@@ -706,6 +767,7 @@ hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a)
 {
     if (!ctx) return HGS_ERR_INVALID_ARG;
     if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy uploaded");
+    if (ctx->streaming) return fail(ctx, HGS_ERR_STATE, "no optimiser step while rendering out of core");
     if (!a) return fail(ctx, HGS_ERR_INVALID_ARG, "NULL optimiser arguments");
     for (int k = 0; k < 5; ++k) {
         if (!a->param[k] || !a->grad[k] || !a->m[k] || !a->v[k])
@@ -796,22 +858,7 @@ hgs_status hgs_upload(hgs_ctx *ctx, const hgs_hierarchy_desc *d, int src_on_devi
         pinfo[i] = (i == 0 ? kRootParent : (uint32_t)par[i]) | (cc[i] == 0 ? kLeafBit : 0u);
 
     // (re)allocate hierarchy buffers
-    for (int k = 0; k < 5; ++k) {
-        dfree(ctx, ctx->own[k]);
-        ctx->own[k] = nullptr;
-        ctx->bound[k] = nullptr;
-    }
-    dfree(ctx, ctx->pinfo);
-    dfree(ctx, ctx->box);
-    dfree(ctx, ctx->child_count);
-    dfree(ctx, ctx->child_begin);
-    dfree(ctx, ctx->interior);
-    ctx->pinfo = nullptr;
-    ctx->box = nullptr;
-    ctx->child_count = nullptr;
-    ctx->child_begin = nullptr;
-    ctx->interior = nullptr;
-    ctx->use_bound = false;
+    drop_hierarchy(ctx);
     hgs_status s;
     if ((s = dalloc(ctx, (void **)&ctx->pinfo, 4 * N))) return s;
     if ((s = dalloc(ctx, (void **)&ctx->box, 24 * N))) return s;
@@ -858,10 +905,278 @@ hgs_status hgs_upload(hgs_ctx *ctx, const hgs_hierarchy_desc *d, int src_on_devi
     return HGS_OK;
 }
 
+hgs_status hgs_build(hgs_ctx *ctx, const hgs_leaves_desc *L, int src_on_device, int64_t *n_nodes)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!L || !n_nodes) return fail(ctx, HGS_ERR_INVALID_ARG, "leaves or n_nodes is NULL");
+    const int64_t n = L->n_leaves;
+    if (n < 1 || n > (int64_t)1 << 29) return fail(ctx, HGS_ERR_INVALID_ARG, "n_leaves out of [1, 2^29]");
+    const void *in_ptrs[] = {L->mean, L->scale, L->rot, L->opacity, L->sh};
+    for (const void *p : in_ptrs)
+        if (!p) return fail(ctx, HGS_ERR_INVALID_ARG, "NULL leaf array");
+    HIPC(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    HIPC(hipStreamSynchronize(st));
+    // temporaries: freed on every exit
+    std::vector<void *> tmp;
+    auto talloc = [&](void **p, size_t bytes) -> hgs_status {
+        *p = nullptr;
+        const hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, HGS_ERR_OOM, "hipMalloc(" + std::to_string(bytes) + ") in the hierarchy build");
+        }
+        tmp.push_back(*p);
+        return HGS_OK;
+    };
+    struct Cleanup {
+        std::vector<void *> &v;
+        ~Cleanup()
+        {
+            for (void *p : v) (void)hipFree(p);
+        }
+    } cleanup{tmp};
+    hgs_status s;
+    const size_t comp[5] = {3, 3, 4, 1, 48};
+    const float *in[5];
+    for (int k = 0; k < 5; ++k) {
+        if (src_on_device) {
+            in[k] = (const float *)in_ptrs[k];
+        } else {
+            void *d = nullptr;
+            if ((s = talloc(&d, 4 * comp[k] * (size_t)n))) return s;
+            HIPC(hipMemcpyAsync(d, in_ptrs[k], 4 * comp[k] * (size_t)n, hipMemcpyHostToDevice, st));
+            in[k] = (const float *)d;
+        }
+    }
+    const BuildLeaves leaves{in[0], in[1], in[2], in[3], in[4]};
+    // 1. the grid: per-axis minimum and the largest extent of the means
+    const int nbb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    float *part = nullptr;
+    if ((s = talloc((void **)&part, sizeof(float) * 6 * nbb))) return s;
+    launch_build_bounds(in[0], n, part, nbb, st);
+    std::vector<float> hp(6 * (size_t)nbb);
+    HIPC(hipMemcpyAsync(hp.data(), part, sizeof(float) * hp.size(), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        float a = hp[k], b = hp[3 + k];
+        for (int j = 1; j < nbb; ++j) {
+            a = std::min(a, hp[6 * j + k]);
+            b = std::max(b, hp[6 * j + 3 + k]);
+        }
+        lo[k] = a;
+        hi[k] = b;
+    }
+    double ext = 0.0;
+    for (int k = 0; k < 3; ++k) ext = std::max(ext, hi[k] - lo[k]);
+    if (ext == 0.0) ext = 1.0;
+    if (!std::isfinite(ext)) return fail(ctx, HGS_ERR_INVALID_ARG, "leaf means must be finite");
+    const double scale = (double)((1u << 21) - 1u) / ext;
+    // 2. Morton codes, sorted by (code, leaf index): two stable passes over
+    // the low and the high 32 bits
+    uint32_t *lo0, *hi0, *keyA, *valA, *keyB, *tk, *tv, *ndev;
+    for (uint32_t **p : {&lo0, &hi0, &keyA, &valA, &keyB, &tk, &tv})
+        if ((s = talloc((void **)p, 4 * (size_t)n))) return s;
+    if ((s = talloc((void **)&ndev, 16))) return s;
+    const uint32_t nn = (uint32_t)n;
+    HIPC(hipMemcpyAsync(ndev, &nn, 4, hipMemcpyHostToDevice, st));
+    launch_build_morton(in[0], n, lo, scale, lo0, hi0, valA, st);
+    HIPC(hipMemcpyAsync(keyA, lo0, 4 * (size_t)n, hipMemcpyDeviceToDevice, st));
+    const SortScratch sc1{tk, tv, ctx->hist, ctx->hist_scan, ctx->partial, ctx->scan_total, ctx->sort_plan};
+    const bool sw1 = launch_radix_sort(keyA, valA, nn, ndev, 32, sc1, st);
+    uint32_t *idx1 = sw1 ? tv : valA;
+    uint32_t *spare = sw1 ? valA : tv;  // the values buffer the first pass left free
+    launch_gather_u32(hi0, idx1, n, keyB, st);
+    const SortScratch sc2{tk, spare, ctx->hist, ctx->hist_scan, ctx->partial, ctx->scan_total, ctx->sort_plan};
+    const bool sw2 = launch_radix_sort(keyB, idx1, nn, ndev, 31, sc2, st);
+    uint32_t *idx2 = sw2 ? spare : idx1;  // leaves in (code, index) order
+    uint32_t *slo = keyA, *shi = tk;       // their codes (both buffers are free again)
+    launch_gather_u32(lo0, idx2, n, slo, st);
+    launch_gather_u32(hi0, idx2, n, shi, st);
+    uint8_t *sl = nullptr;
+    if ((s = talloc((void **)&sl, (size_t)n))) return s;
+    launch_split_level(slo, shi, n, sl, st);
+    // 3. the tree, one level at a time
+    int64_t cap = 2 * n + 64;
+    BuildTree t{};
+    int32_t *leaf_src = nullptr;
+    auto grow = [&](int64_t need) -> hgs_status {
+        if (need <= cap && t.start) return HGS_OK;
+        int64_t nc = std::max<int64_t>(need, t.start ? cap + cap / 2 : cap);
+        int32_t **arrs[] = {&t.start, &t.size, &t.parent, &t.child_begin, &t.child_count, &leaf_src};
+        for (int32_t **a : arrs) {
+            int32_t *q = nullptr;
+            hgs_status e = talloc((void **)&q, 4 * (size_t)nc);
+            if (e) return e;
+            if (*a) HIPC(hipMemcpyAsync(q, *a, 4 * (size_t)cap, hipMemcpyDeviceToDevice, st));
+            *a = q;
+        }
+        cap = nc;
+        return HGS_OK;
+    };
+    if ((s = grow(cap))) return s;
+    {
+        // the root holds every leaf; with one leaf it is that leaf (index 0)
+        static const int32_t root1[6] = {0, 1, -1, 0, 0, 0};
+        const int32_t root[6] = {0, (int32_t)n, -1, 0, 0, n == 1 ? 0 : -1};
+        int32_t *dst[6] = {t.start, t.size, t.parent, t.child_begin, t.child_count, leaf_src};
+        for (int k = 0; k < 6; ++k)
+            HIPC(hipMemcpyAsync(dst[k], n == 1 ? &root1[k] : &root[k], 4, hipMemcpyHostToDevice, st));
+        HIPC(hipStreamSynchronize(st));  // the host values above are locals
+    }
+    int32_t *node_of = nullptr, *node_next = nullptr;
+    uint32_t *flag = nullptr, *rank = nullptr, *cnt = nullptr;
+    if ((s = talloc((void **)&node_of, 4 * (size_t)n))) return s;
+    if ((s = talloc((void **)&node_next, 4 * (size_t)n))) return s;
+    if ((s = talloc((void **)&flag, 4 * (size_t)n))) return s;
+    if ((s = talloc((void **)&rank, 4 * (size_t)n))) return s;
+    if ((s = talloc((void **)&cnt, 16))) return s;
+    launch_fill_i32(node_of, 0, n, st);
+    std::vector<int64_t> base{0, 1};
+    int64_t total = 1;
+    for (int level = 1;; ++level) {
+        if (level > 4096) return fail(ctx, HGS_ERR_INVALID_ARG, "hierarchy deeper than 4096 levels");
+        launch_level_starts(node_of, sl, t, n, level, flag, st);
+        launch_scan(flag, nullptr, nn, nullptr, rank, cnt, ctx->partial, st);
+        uint32_t c = 0;
+        HIPC(hipMemcpyAsync(&c, cnt, 4, hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        if (c == 0) break;
+        if (total + c >= (int64_t)kRootParent) return fail(ctx, HGS_ERR_INVALID_ARG, "too many nodes");
+        if ((s = grow(total + c))) return s;
+        launch_level_nodes(node_of, flag, rank, t, n, (int32_t)total, node_next, st);
+        launch_level_sizes(t, (int32_t)total, (int32_t)c, n, idx2, leaf_src, st);
+        std::swap(node_of, node_next);
+        total += c;
+        base.push_back(total);
+    }
+    const int64_t N = total;
+    const int nlev = (int)base.size() - 1;
+    // interior ranks and the interior list
+    uint32_t *irank = nullptr;
+    if ((s = talloc((void **)&irank, 4 * (size_t)N))) return s;
+    {
+        uint32_t *ifl = nullptr;
+        if ((s = talloc((void **)&ifl, 4 * (size_t)N))) return s;
+        launch_interior_ranks(t.child_count, N, ifl, st);
+        launch_scan(ifl, nullptr, (uint32_t)N, nullptr, irank, cnt, ctx->partial, st);
+    }
+    uint32_t n_int = 0;
+    HIPC(hipMemcpyAsync(&n_int, cnt, 4, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    // 4. merges bottom up (FP64 working values)
+    BuildWork w{};
+    {
+        double **arrs[] = {&w.mean, &w.cov, &w.op, &w.surf, &w.axes, &w.sc, &w.R, &w.q};
+        const size_t per[] = {3, 6, 1, 1, 9, 3, 9, 4};
+        for (int k = 0; k < 8; ++k)
+            if ((s = talloc((void **)arrs[k], 8 * per[k] * (size_t)N))) return s;
+        if ((s = talloc((void **)&w.sh, 8 * 48 * (size_t)std::max<uint32_t>(n_int, 1)))) return s;
+        w.irank = (int32_t *)irank;
+    }
+    for (int d = nlev - 1; d >= 0; --d)
+        launch_merge_level(t, leaf_src, leaves, w, (int32_t)base[d], (int32_t)(base[d + 1] - base[d]), st);
+    // 5. the hierarchy's own buffers, then matching top down and boxes bottom up
+    drop_hierarchy(ctx);
+    float *bmin = nullptr, *bmax = nullptr;
+    if ((s = talloc((void **)&bmin, 12 * (size_t)N))) return s;
+    if ((s = talloc((void **)&bmax, 12 * (size_t)N))) return s;
+    for (int k = 0; k < 5; ++k)
+        if ((s = dalloc(ctx, (void **)&ctx->own[k], 4 * comp[k] * (size_t)N))) return s;
+    const BuildOut o{ctx->own[0], ctx->own[1], ctx->own[2], ctx->own[3], ctx->own[4], bmin, bmax};
+    build_axis_maps_upload(st);
+    for (int d = 0; d < nlev; ++d)
+        launch_match_level(t, w, (int32_t)base[d], (int32_t)(base[d + 1] - base[d]), o, leaf_src, in[4], st);
+    for (int d = nlev - 1; d >= 0; --d)
+        launch_box_level(t, (int32_t)base[d], (int32_t)(base[d + 1] - base[d]), bmin, bmax, st);
+    if ((s = dalloc(ctx, (void **)&ctx->pinfo, 4 * (size_t)N))) return s;
+    if ((s = dalloc(ctx, (void **)&ctx->box, 24 * (size_t)N))) return s;
+    if ((s = dalloc(ctx, (void **)&ctx->child_count, 4 * (size_t)N))) return s;
+    if ((s = dalloc(ctx, (void **)&ctx->child_begin, 4 * (size_t)N))) return s;
+    if ((s = dalloc(ctx, (void **)&ctx->interior, 4 * (size_t)std::max<uint32_t>(n_int, 1)))) return s;
+    if ((s = dalloc(ctx, (void **)&ctx->leaf_src, 4 * (size_t)N))) return s;
+    launch_build_finish(t, N, bmin, bmax, ctx->pinfo, ctx->box, st);
+    HIPC(hipMemcpyAsync(ctx->child_count, t.child_count, 4 * (size_t)N, hipMemcpyDeviceToDevice, st));
+    HIPC(hipMemcpyAsync(ctx->child_begin, t.child_begin, 4 * (size_t)N, hipMemcpyDeviceToDevice, st));
+    HIPC(hipMemcpyAsync(ctx->leaf_src, leaf_src, 4 * (size_t)N, hipMemcpyDeviceToDevice, st));
+    launch_interior_list(t.child_count, irank, N, ctx->interior, st);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(st));
+    ctx->n = N;
+    ctx->n_leaves = n;
+    ctx->n_interior = n_int;
+    ctx->has_hier = true;
+    ctx->param_gen++;
+    ctx->layout_gen++;
+    ctx->nblocks_cap = 0;
+    ctx->nv_cap = 0;
+    *n_nodes = N;
+    return HGS_OK;
+}
+
+hgs_status hgs_download(hgs_ctx *ctx, const hgs_hierarchy_out *o, int dst_on_device)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy");
+    if (!o) return fail(ctx, HGS_ERR_INVALID_ARG, "out is NULL");
+    if (o->leaf_src && !ctx->leaf_src)
+        return fail(ctx, HGS_ERR_STATE, "leaf_src exists only for a hierarchy made by hgs_build");
+    HIPC(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int64_t N = ctx->n;
+    const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    // parent and node-major boxes: unpacked on the device first
+    int32_t *par = nullptr;
+    float *bmn = nullptr, *bmx = nullptr;
+    std::vector<void *> tmp;
+    struct Cleanup {
+        std::vector<void *> &v;
+        ~Cleanup()
+        {
+            for (void *p : v) (void)hipFree(p);
+        }
+    } cleanup{tmp};
+    if (o->parent || o->bmin || o->bmax) {
+        if (dst_on_device) {
+            par = o->parent;
+            bmn = o->bmin;
+            bmx = o->bmax;
+        } else {
+            for (void **p : {(void **)&par, (void **)&bmn, (void **)&bmx}) {
+                if (hipMalloc(p, 12 * (size_t)N) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return fail(ctx, HGS_ERR_OOM, "hipMalloc in hgs_download");
+                }
+                tmp.push_back(*p);
+            }
+        }
+        launch_unpack_nodes(ctx->pinfo, ctx->box, N, o->parent ? par : nullptr, o->bmin ? bmn : nullptr,
+                            o->bmax ? bmx : nullptr, st);
+        if (!dst_on_device) {
+            if (o->parent) HIPC(hipMemcpyAsync(o->parent, par, 4 * (size_t)N, kind, st));
+            if (o->bmin) HIPC(hipMemcpyAsync(o->bmin, bmn, 12 * (size_t)N, kind, st));
+            if (o->bmax) HIPC(hipMemcpyAsync(o->bmax, bmx, 12 * (size_t)N, kind, st));
+        }
+    }
+    if (o->child_begin) HIPC(hipMemcpyAsync(o->child_begin, ctx->child_begin, 4 * (size_t)N, kind, st));
+    if (o->child_count) HIPC(hipMemcpyAsync(o->child_count, ctx->child_count, 4 * (size_t)N, kind, st));
+    if (o->leaf_src) HIPC(hipMemcpyAsync(o->leaf_src, ctx->leaf_src, 4 * (size_t)N, kind, st));
+    float *const *P = ctx->use_bound ? ctx->bound : ctx->own;
+    float *dst[5] = {o->mean, o->scale, o->rot, o->opacity, o->sh};
+    const size_t comp[5] = {3, 3, 4, 1, 48};
+    for (int k = 0; k < 5; ++k)
+        if (dst[k]) HIPC(hipMemcpyAsync(dst[k], P[k], 4 * comp[k] * (size_t)N, kind, st));
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(st));
+    return HGS_OK;
+}
+
 hgs_status hgs_bind_params(hgs_ctx *ctx, float *mean, float *scale, float *rot, float *opacity, float *sh)
 {
     if (!ctx) return HGS_ERR_INVALID_ARG;
     if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy uploaded");
+    if (ctx->streaming) return fail(ctx, HGS_ERR_STATE, "parameters cannot be bound while rendering out of core");
     float *p[5] = {mean, scale, rot, opacity, sh};
     bool same = true;
     for (int k = 0; k < 5; ++k) same = same && ctx->bound[k] == p[k];
@@ -1072,6 +1387,8 @@ hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, floa
         }
         HIPC(hipGetLastError());
         HIPC(hipMemcpyAsync(ctx->ctr_host, ctx->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        if (ctx->streaming)
+            HIPC(hipMemcpyAsync(ctx->stream_host + 3, ctx->sd.overflow, 4, hipMemcpyDeviceToHost, st));
         HIPC(hipStreamSynchronize(st));
         const Counters c = *ctx->ctr_host;
         bool grow = false;
@@ -1086,6 +1403,12 @@ hgs_status hgs_render(hgs_ctx *ctx, const hgs_view *views, int32_t n_views, floa
             grow = true;
         }
         if (grow) continue;
+        if (ctx->streaming && ctx->stream_host[3]) {
+            if (timed)
+                for (auto &e : ev) (void)hipEventDestroy(e);
+            return fail(ctx, HGS_ERR_CAPACITY, "the parameter cache cannot hold the nodes this render needs "
+                                               "(the image lacks them): hgs_stream_cleanup or a larger cache");
+        }
         ctx->have_render = true;
         ++ctx->render_seq;
         ctx->render_param_gen = ctx->param_gen;
@@ -1134,6 +1457,7 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views
                                hgs_grads *out)
 {
     if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (ctx->streaming) return fail(ctx, HGS_ERR_STATE, "no backward while rendering out of core");
     if (!ctx->have_render || ctx->render_param_gen != ctx->param_gen)
         return fail(ctx, HGS_ERR_STATE, "render_backward needs a render with the current parameters");
     if (render_id != ctx->render_seq)
@@ -1225,6 +1549,142 @@ hgs_status hgs_l1_loss(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const 
     if (s) return s;
     launch_l1(ctx->views_dev, nv, (uint32_t)ctx->last_pix, ctx->l1_partial, loss, st);
     HIPC(hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_stream_begin(hgs_ctx *ctx, int64_t cache_nodes)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy");
+    if (ctx->streaming) return fail(ctx, HGS_ERR_STATE, "already rendering out of core");
+    if (ctx->use_bound) return fail(ctx, HGS_ERR_STATE, "unbind the parameters first");
+    if (cache_nodes < 1 || cache_nodes > ctx->n || cache_nodes >= ((int64_t)1 << 31))
+        return fail(ctx, HGS_ERR_INVALID_ARG, "cache_nodes must lie in [1, n_nodes]");
+    HIPC(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    HIPC(hipStreamSynchronize(st));
+    const int64_t N = ctx->n;
+    const size_t comp[5] = {3, 3, 4, 1, 48};
+    size_t total = 0;
+    for (int k = 0; k < 5; ++k) total += 4 * comp[k] * (size_t)N;
+    void *block = nullptr;
+    if (hipHostMalloc(&block, total, hipHostMallocMapped) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, HGS_ERR_OOM, "hipHostMalloc(" + std::to_string(total) + ") for the host parameters");
+    }
+    void *block_dev = nullptr;
+    if (hipHostGetDevicePointer(&block_dev, block, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(block);
+        return fail(ctx, HGS_ERR_HIP, "hipHostGetDevicePointer of the host parameters");
+    }
+    float *hp[5], *dp[5];
+    size_t off = 0;
+    for (int k = 0; k < 5; ++k) {
+        hp[k] = (float *)((char *)block + off);
+        dp[k] = (float *)((char *)block_dev + off);
+        off += 4 * comp[k] * (size_t)N;
+        if (hipMemcpy(hp[k], ctx->own[k], 4 * comp[k] * (size_t)N, hipMemcpyDeviceToHost) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipHostFree(block);
+            return fail(ctx, HGS_ERR_HIP, "copying the parameters to host memory");
+        }
+    }
+    // device side first; on failure everything allocated here goes again
+    const size_t C = (size_t)cache_nodes;
+    StreamParams cache{};
+    StreamDev d{};
+    std::vector<void *> mine;
+    auto take = [&](void **p, size_t bytes) -> bool {
+        if (dalloc(ctx, p, bytes) != HGS_OK) return false;
+        mine.push_back(*p);
+        return true;
+    };
+    bool ok = take((void **)&cache.mean, 12 * C) && take((void **)&cache.scale, 12 * C) &&
+              take((void **)&cache.rot, 16 * C) && take((void **)&cache.opacity, 4 * C) &&
+              take((void **)&cache.sh, 192 * C) && take((void **)&d.slot, 4 * (size_t)N) &&
+              take((void **)&d.node_in_slot, 4 * C) && take((void **)&d.last_used, 4 * C) &&
+              take((void **)&d.free_stack, 4 * C) && take((void **)&d.req, 4 * C) &&
+              take((void **)&d.free_top, 64);
+    if (!ok) {
+        const std::string msg = ctx->err;
+        for (void *p : mine) dfree(ctx, p);
+        (void)hipHostFree(block);
+        return fail(ctx, HGS_ERR_OOM, msg);
+    }
+    d.frame = d.free_top + 1;
+    d.req_count = d.free_top + 2;
+    d.overflow = d.free_top + 3;
+    d.transferred = (unsigned long long *)(d.free_top + 4);
+    d.cap = (uint32_t)C;
+    d.req_cap = (uint32_t)C;
+    ctx->host_block = block;
+    ctx->host_params = StreamParams{hp[0], hp[1], hp[2], hp[3], hp[4]};
+    ctx->host_params_dev = StreamParams{dp[0], dp[1], dp[2], dp[3], dp[4]};
+    ctx->cache_params = cache;
+    ctx->sd = d;
+    ctx->streaming = true;
+    for (int k = 0; k < 5; ++k) {
+        dfree(ctx, ctx->own[k]);
+        ctx->own[k] = nullptr;
+    }
+    launch_stream_init(d, N, st);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(st));
+    ctx->have_render = false;
+    ctx->param_gen++;
+    ctx->layout_gen++;
+    return HGS_OK;
+}
+
+hgs_status hgs_stream_end(hgs_ctx *ctx)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->streaming) return fail(ctx, HGS_ERR_STATE, "not rendering out of core");
+    HIPC(hipSetDevice(ctx->device));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    const size_t comp[5] = {3, 3, 4, 1, 48};
+    float *hp[5] = {ctx->host_params.mean, ctx->host_params.scale, ctx->host_params.rot, ctx->host_params.opacity,
+                    ctx->host_params.sh};
+    hgs_status s;
+    for (int k = 0; k < 5; ++k) {
+        if ((s = dalloc(ctx, (void **)&ctx->own[k], 4 * comp[k] * (size_t)ctx->n))) return s;
+        HIPC(hipMemcpy(ctx->own[k], hp[k], 4 * comp[k] * (size_t)ctx->n, hipMemcpyHostToDevice));
+    }
+    stream_release(ctx);
+    ctx->have_render = false;
+    ctx->param_gen++;
+    ctx->layout_gen++;
+    return HGS_OK;
+}
+
+hgs_status hgs_stream_cleanup(hgs_ctx *ctx, int32_t max_age)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (!ctx->streaming) return fail(ctx, HGS_ERR_STATE, "not rendering out of core");
+    if (max_age < 0) return fail(ctx, HGS_ERR_INVALID_ARG, "max_age must be >= 0");
+    HIPC(hipSetDevice(ctx->device));
+    launch_stream_cleanup(ctx->sd, (uint32_t)max_age, ctx->stream);
+    HIPC(hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_stream_info(hgs_ctx *ctx, hgs_stream_stats *out)
+{
+    if (!ctx || !out) return HGS_ERR_INVALID_ARG;
+    if (!ctx->streaming) return fail(ctx, HGS_ERR_STATE, "not rendering out of core");
+    HIPC(hipSetDevice(ctx->device));
+    HIPC(hipMemcpyAsync(ctx->stream_host, ctx->sd.free_top, 24, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    const uint32_t *h = ctx->stream_host;
+    out->cache_nodes = ctx->sd.cap;
+    out->resident = (int64_t)ctx->sd.cap - h[0];
+    out->frame = h[1];
+    out->requested = h[2];
+    out->overflow = (int32_t)h[3];
+    uint64_t tr = 0;
+    memcpy(&tr, h + 4, 8);
+    out->transferred_total = (int64_t)tr;
     return HGS_OK;
 }
 

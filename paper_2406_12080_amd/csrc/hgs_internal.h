@@ -45,7 +45,36 @@ struct DevHier {
     const int32_t *child_count;
     const int32_t *child_begin;  // first child (children are contiguous); 0 for leaves
     const float *mean, *scale, *rot, *opacity, *sh;  // node-major: [N][3] [N][3] [N][4] [N] [N][48]
+    // out-of-core rendering: the parameters above are a cache indexed by
+    // slot[node] (< 0: not resident); nullptr: indexed by node id
+    const int32_t *slot;
 };
+
+// Index of a node's parameters (its cache slot when rendering out of core).
+__device__ __forceinline__ size_t param_index(const DevHier &h, uint32_t node)
+{
+    return h.slot ? (size_t)h.slot[node] : (size_t)node;
+}
+
+// ---------------------------------------------------- out-of-core rendering
+struct StreamParams {
+    float *mean, *scale, *rot, *opacity, *sh;  // node-major records (host: N nodes, cache: cap slots)
+};
+struct StreamDev {
+    int32_t *slot;          // [N] cache slot of every node (-1 absent, -2 claimed)
+    int32_t *node_in_slot;  // [cap] (-1 free)
+    uint32_t *last_used;    // [cap] frame of the last cut that used the slot
+    uint32_t *free_stack;   // [cap], free_top entries valid
+    uint32_t *free_top, *frame, *req_count, *overflow;
+    unsigned long long *transferred;  // total nodes transferred
+    uint32_t *req;          // [req_cap] nodes requested this frame
+    uint32_t cap, req_cap;
+};
+void launch_stream_init(const StreamDev &s, int64_t n_nodes, hipStream_t st);
+void launch_stream_frame(const StreamDev &s, const uint32_t *pinfo, const int32_t *cut_ids,
+                         const uint32_t *cut_total, uint32_t cap, const StreamParams &host,
+                         const StreamParams &cache, hipStream_t st);
+void launch_stream_cleanup(const StreamDev &s, uint32_t max_age, hipStream_t st);
 
 // Blend record of one splat (48 bytes).  The mean is kept as an integer pixel
 // anchor plus an FP32 fraction.  The conic (inverse dilated 2D covariance)
@@ -196,6 +225,57 @@ void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t
                   const SplatRec *recs, const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend,
                   uint4 *wstats, Counters *ctr, int tw, int th, int batch, bool persist, uint32_t *queue,
                   hipStream_t st);
+
+// ---------------------------------------------------- hierarchy generation
+// Node arrays of the tree under construction (breadth-first ids).
+struct BuildTree {
+    int32_t *start, *size;  // first sorted leaf position and leaf count
+    int32_t *parent, *child_begin, *child_count;
+};
+// Leaf inputs, node-major: pos [n][3], scale [n][3], rot [n][4], opacity [n], sh [n][48].
+struct BuildLeaves {
+    const float *pos, *scale, *rot, *opacity, *sh;
+};
+// FP64 working values per node (mean [3], cov [6], op, surf, axes [9],
+// scales [3], matched R [9] and q [4]) and the interior nodes' SH [48] by
+// interior rank.
+struct BuildWork {
+    double *mean, *cov, *op, *surf, *axes, *sc;
+    double *sh;
+    int32_t *irank;
+    double *R, *q;
+};
+// FP32 outputs, node-major (bmin / bmax [N][3]).
+struct BuildOut {
+    float *mean, *scale, *rot, *opacity, *sh, *bmin, *bmax;
+};
+void build_axis_maps_upload(hipStream_t st);
+void launch_build_bounds(const float *pos, int64_t n, float *part, int nblocks, hipStream_t st);
+void launch_build_morton(const float *pos, int64_t n, const double lo[3], double s, uint32_t *key_lo,
+                         uint32_t *key_hi, uint32_t *idx, hipStream_t st);
+void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t n, uint32_t *dst, hipStream_t st);
+void launch_split_level(const uint32_t *lo, const uint32_t *hi, int64_t n, uint8_t *sl, hipStream_t st);
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+void launch_level_starts(const int32_t *node_of, const uint8_t *sl, const BuildTree &t, int64_t n, int next_level,
+                         uint32_t *flag, hipStream_t st);
+void launch_level_nodes(const int32_t *node_of, const uint32_t *flag, const uint32_t *rank, const BuildTree &t,
+                        int64_t n, int32_t base, int32_t *node_of_next, hipStream_t st);
+void launch_level_sizes(const BuildTree &t, int32_t base, int32_t count, int64_t n, const uint32_t *sorted_idx,
+                        int32_t *leaf_src, hipStream_t st);
+void launch_interior_ranks(const int32_t *child_count, int64_t N, uint32_t *flag, hipStream_t st);
+void launch_interior_list(const int32_t *child_count, const uint32_t *irank, int64_t N, int32_t *interior,
+                          hipStream_t st);
+void launch_merge_level(const BuildTree &t, const int32_t *leaf_src, const BuildLeaves &in, const BuildWork &w,
+                        int32_t base, int32_t count, hipStream_t st);
+void launch_match_level(const BuildTree &t, const BuildWork &w, int32_t base, int32_t count, const BuildOut &o,
+                        const int32_t *leaf_src, const float *in_sh, hipStream_t st);
+void launch_box_level(const BuildTree &t, int32_t base, int32_t count, float *bmin, float *bmax, hipStream_t st);
+// pinfo (parent | leaf bit) and the component-major boxes [6][N] of a built tree
+void launch_build_finish(const BuildTree &t, int64_t N, const float *bmin, const float *bmax, uint32_t *pinfo,
+                         float *box, hipStream_t st);
+// the inverse, for downloads: parent and node-major boxes from pinfo and [6][N]
+void launch_unpack_nodes(const uint32_t *pinfo, const float *box, int64_t N, int32_t *parent, float *bmin,
+                         float *bmax, hipStream_t st);
 
 // L1 loss of the rendered images (views[v].out_rgb) against views[v].target
 // over n_pix pixels of all views: dL/dC written to views[v].dL, the mean

@@ -146,12 +146,14 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
 
 // Work distribution over tiles: either one workgroup per tile slot (grid =
 // tile count, slot = workgroup index), or a persistent grid sized to the
-// chip's resident workgroups, each taking slots from a device-side queue (a
-// counter that the launch sequence clears first) until the slots run out.
-// Slots are handed out in the longest-first order either way.
-__device__ __forceinline__ uint32_t next_slot(uint32_t *queue, uint32_t *s_slot)
+// chip's resident workgroups, each taking runs of `chunk` consecutive slots
+// from a device-side queue (a counter that the launch sequence clears first)
+// until the slots run out.  Slots are handed out in the longest-first order
+// either way; runs keep the one queue counter from serialising a million
+// small tiles.
+__device__ __forceinline__ uint32_t next_run(uint32_t *queue, uint32_t chunk, uint32_t *s_slot)
 {
-    if (threadIdx.x == 0) *s_slot = atomicAdd(queue, 1u);
+    if (threadIdx.x == 0) *s_slot = atomicAdd(queue, chunk);
     __syncthreads();
     const uint32_t slot = *s_slot;
     __syncthreads();  // every wave has its slot before lane 0 may overwrite it
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
                                                   const double4 *__restrict__ axes, float *__restrict__ T_final,
                                                   uint32_t *__restrict__ n_last, uint32_t *__restrict__ n_blend,
                                                   uint4 *__restrict__ wstats, uint32_t n_tiles,
-                                                  uint32_t *__restrict__ queue)
+                                                  uint32_t *__restrict__ queue, uint32_t chunk)
 {
     if constexpr (!PERSIST) {
         blend_tile<TW, TH, BATCH>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last, n_blend,
@@ -311,10 +313,14 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
     } else {
         __shared__ uint32_t s_slot;
         for (;;) {
-            const uint32_t slot = next_slot(queue, &s_slot);
-            if (slot >= n_tiles) break;
-            blend_tile<TW, TH, BATCH>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last,
-                                      n_blend, wstats, slot);
+            const uint32_t first = next_run(queue, chunk, &s_slot);
+            if (first >= n_tiles) break;
+            const uint32_t last = min(n_tiles, first + chunk);
+            for (uint32_t slot = first; slot < last; ++slot) {
+                blend_tile<TW, TH, BATCH>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last,
+                                          n_blend, wstats, slot);
+                __syncthreads();  // LDS of this tile read by every wave before the next stages
+            }
         }
     }
 }
@@ -601,7 +607,8 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                                                       const uint32_t *__restrict__ n_last,
                                                       const uint32_t *__restrict__ vis_rank,
                                                       double *__restrict__ sgrad, uint4 *__restrict__ wstats,
-                                                      uint32_t n_tiles, uint32_t *__restrict__ queue)
+                                                      uint32_t n_tiles, uint32_t *__restrict__ queue,
+                                                      uint32_t chunk)
 {
     if constexpr (!PERSIST) {
         blend_bwd_tile<TW, TH, BATCH, DT>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last,
@@ -609,10 +616,14 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
     } else {
         __shared__ uint32_t s_slot;
         for (;;) {
-            const uint32_t slot = next_slot(queue, &s_slot);
-            if (slot >= n_tiles) break;
-            blend_bwd_tile<TW, TH, BATCH, DT>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last,
-                                              vis_rank, sgrad, wstats, slot);
+            const uint32_t first = next_run(queue, chunk, &s_slot);
+            if (first >= n_tiles) break;
+            const uint32_t last = min(n_tiles, first + chunk);
+            for (uint32_t slot = first; slot < last; ++slot) {
+                blend_bwd_tile<TW, TH, BATCH, DT>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final,
+                                                  n_last, vis_rank, sgrad, wstats, slot);
+                __syncthreads();  // LDS of this tile read by every wave before the next stages
+            }
         }
     }
 }
@@ -669,6 +680,15 @@ uint32_t resident_grid(K kernel, int threads)
     return g;
 }
 
+// Slots per queue ticket of a persistent launch of g workgroups over
+// n_tiles slots: about a sixteenth of each workgroup's share, so that the
+// last tickets still spread over the grid, and at most 32.
+uint32_t queue_run(uint32_t n_tiles, uint32_t g)
+{
+    const uint32_t share = n_tiles / std::max(g, 1u);
+    return std::min(32u, std::max(1u, share / 16u));
+}
+
 template <int TW, int TH, int BATCH>
 void launch_blend_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                     const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, float *T_final,
@@ -680,10 +700,10 @@ void launch_blend_t(const DevView *views, int nv, uint32_t n_tiles, const uint32
         const uint32_t g = std::min(n_tiles, resident_grid(k, TW * TH));
         launch_fill_u32(queue, 0u, 1, st);
         hipLaunchKernelGGL(k, dim3(g), dim3(TW * TH), 0, st, views, nv, order, ranges, pair_vals, recs, axes,
-                           T_final, n_last, n_blend, wstats, n_tiles, queue);
+                           T_final, n_last, n_blend, wstats, n_tiles, queue, queue_run(n_tiles, g));
     } else {
         hipLaunchKernelGGL((k_blend<TW, TH, BATCH, false>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order,
-                           ranges, pair_vals, recs, axes, T_final, n_last, n_blend, wstats, n_tiles, queue);
+                           ranges, pair_vals, recs, axes, T_final, n_last, n_blend, wstats, n_tiles, queue, 1u);
     }
 }
 
@@ -698,10 +718,11 @@ void launch_blend_bwd_dt(const DevView *views, int nv, uint32_t n_tiles, const u
         const uint32_t g = std::min(n_tiles, resident_grid(k, TW * TH));
         launch_fill_u32(queue, 0u, 1, st);
         hipLaunchKernelGGL(k, dim3(g), dim3(TW * TH), 0, st, views, nv, order, ranges, pair_vals, recs, axes, T_final,
-                           n_last, vis_rank, sgrad, wstats, n_tiles, queue);
+                           n_last, vis_rank, sgrad, wstats, n_tiles, queue, queue_run(n_tiles, g));
     } else {
         hipLaunchKernelGGL((k_blend_bwd<TW, TH, B, DT, false>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order,
-                           ranges, pair_vals, recs, axes, T_final, n_last, vis_rank, sgrad, wstats, n_tiles, queue);
+                           ranges, pair_vals, recs, axes, T_final, n_last, vis_rank, sgrad, wstats, n_tiles, queue,
+                           1u);
     }
 }
 

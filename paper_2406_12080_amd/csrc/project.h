@@ -115,6 +115,7 @@ __device__ __forceinline__ void quat_rot(const double q[4], double R[9])
 
 struct Proj {
     uint32_t node, par;
+    size_t pn, pp;  // parameter indices of node and parent (cache slots out of core)
     bool has_par;
     int K;
     double t;
@@ -146,14 +147,22 @@ __device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V
     P.par = P.has_par ? par : node;
     P.K = P.has_par ? h.child_count[par] : 1;
     const uint32_t src = use_par ? par : node;  // the node itself when t = 0: same values
+    // parameter records: by node id, or by cache slot out of core (a node or
+    // parent that is not resident leaves the splat out)
+    P.pn = param_index(h, node);
+    P.pp = P.has_par ? param_index(h, par) : P.pn;
+    P.front = false;
+    P.ok = false;
+    if (h.slot && ((int64_t)P.pn < 0 || (int64_t)P.pp < 0)) return;
+    const size_t in = P.pn, is = use_par ? P.pp : P.pn;
     const double t = P.t, w0 = 1.0 - t;
     // node-major records: one vector load per attribute
-    const float3 mn3 = *reinterpret_cast<const float3 *>(h.mean + 3 * (size_t)node);
-    const float3 mp3 = *reinterpret_cast<const float3 *>(h.mean + 3 * (size_t)src);
-    const float3 sn3 = *reinterpret_cast<const float3 *>(h.scale + 3 * (size_t)node);
-    const float3 sp3 = *reinterpret_cast<const float3 *>(h.scale + 3 * (size_t)src);
-    const float4 qn4 = *reinterpret_cast<const float4 *>(h.rot + 4 * (size_t)node);
-    const float4 qp4 = *reinterpret_cast<const float4 *>(h.rot + 4 * (size_t)src);
+    const float3 mn3 = *reinterpret_cast<const float3 *>(h.mean + 3 * in);
+    const float3 mp3 = *reinterpret_cast<const float3 *>(h.mean + 3 * is);
+    const float3 sn3 = *reinterpret_cast<const float3 *>(h.scale + 3 * in);
+    const float3 sp3 = *reinterpret_cast<const float3 *>(h.scale + 3 * is);
+    const float4 qn4 = *reinterpret_cast<const float4 *>(h.rot + 4 * in);
+    const float4 qp4 = *reinterpret_cast<const float4 *>(h.rot + 4 * is);
     const float mn[3] = {mn3.x, mn3.y, mn3.z}, mp[3] = {mp3.x, mp3.y, mp3.z};
     const float sn[3] = {sn3.x, sn3.y, sn3.z}, sp[3] = {sp3.x, sp3.y, sp3.z};
     const float qn[4] = {qn4.x, qn4.y, qn4.z, qn4.w}, qp[4] = {qp4.x, qp4.y, qp4.z, qp4.w};
@@ -171,8 +180,8 @@ __device__ __forceinline__ void project_splat(const DevHier &h, const DevView &V
     P.qlen = sqrt(ql);
 #pragma unroll
     for (int k = 0; k < 4; ++k) P.q[k] = P.qraw[k] / P.qlen;
-    P.on_raw = h.opacity[node];
-    P.op_raw = P.has_par ? (double)h.opacity[par] : 0.0;
+    P.on_raw = h.opacity[in];
+    P.op_raw = P.has_par ? (double)h.opacity[P.pp] : 0.0;
     P.o_n = fabs(P.on_raw);
     P.o_p = use_par ? fabs(P.op_raw) : 0.0;
 
@@ -243,8 +252,8 @@ __device__ __forceinline__ void splat_colour(const DevHier &h, const Proj &P, fl
     const float x = (float)P.dir[0], y = (float)P.dir[1], z = (float)P.dir[2];
     const float t = (float)P.t, w0 = 1.0f - t;
     // 48 coefficients per node, 192 B: twelve 16-byte loads per record
-    const float4 *a4 = reinterpret_cast<const float4 *>(h.sh + (size_t)48 * P.node);
-    const float4 *b4 = reinterpret_cast<const float4 *>(h.sh + (size_t)48 * (P.use_par ? P.par : P.node));
+    const float4 *a4 = reinterpret_cast<const float4 *>(h.sh + (size_t)48 * P.pn);
+    const float4 *b4 = reinterpret_cast<const float4 *>(h.sh + (size_t)48 * (P.use_par ? P.pp : P.pn));
     float Y[16];
     sh_eval_f(x, y, z, Y);
     float sht[48];

@@ -19,8 +19,9 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_CAPACITY = range(6)
 _NAMES = {0: "HGS_OK", 1: "HGS_ERR_INVALID_ARG", 2: "HGS_ERR_OOM", 3: "HGS_ERR_HIP", 4: "HGS_ERR_STATE",
           5: "HGS_ERR_CAPACITY"}
 EXPORTS = ("hgs_create", "hgs_destroy", "hgs_last_error", "hgs_set_stream", "hgs_upload", "hgs_bind_params",
-           "hgs_cut", "hgs_cut_noalloc", "hgs_compact_mark", "hgs_compact_rebuild", "hgs_render", "hgs_last_render",
-           "hgs_render_backward", "hgs_l1_loss", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
+           "hgs_build", "hgs_download", "hgs_cut", "hgs_cut_noalloc", "hgs_compact_mark", "hgs_compact_rebuild", "hgs_render", "hgs_last_render",
+           "hgs_render_backward", "hgs_l1_loss", "hgs_stream_begin", "hgs_stream_end", "hgs_stream_cleanup",
+           "hgs_stream_info", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
            "hgs_kernel_time", "hgs_counters")
 COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t", "bwd_evaluated",
                  "bwd_evaluated_t", "bwd_contrib")
@@ -34,6 +35,21 @@ class HgsError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{_NAMES.get(status, status)}: {msg}")
         self.status = status
+
+
+class LeavesDesc(ctypes.Structure):
+    _fields_ = [("n_leaves", ctypes.c_int64), ("mean", ctypes.c_void_p), ("scale", ctypes.c_void_p),
+                ("rot", ctypes.c_void_p), ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class HierarchyOut(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("parent", "child_begin", "child_count", "leaf_src", "bmin", "bmax",
+                                               "mean", "scale", "rot", "opacity", "sh")]
+
+
+class StreamStats(ctypes.Structure):
+    _fields_ = [("cache_nodes", ctypes.c_int64), ("resident", ctypes.c_int64), ("frame", ctypes.c_int64),
+                ("requested", ctypes.c_int64), ("transferred_total", ctypes.c_int64), ("overflow", ctypes.c_int32)]
 
 
 class HierarchyDesc(ctypes.Structure):
@@ -92,6 +108,8 @@ def lib():
         L.hgs_set_stream.argtypes = [vp, vp]
         L.hgs_upload.argtypes = [vp, P(HierarchyDesc), c_int]
         L.hgs_bind_params.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.hgs_build.argtypes = [vp, P(LeavesDesc), c_int, P(ctypes.c_int64)]
+        L.hgs_download.argtypes = [vp, P(HierarchyOut), c_int]
         L.hgs_cut.argtypes = [vp, P(View), vp, vp, ctypes.c_int64, P(ctypes.c_int64)]
         L.hgs_cut_noalloc.argtypes = [vp, P(View), vp, vp, ctypes.c_int64, P(ctypes.c_int64)]
         L.hgs_compact_mark.argtypes = [vp, P(View), ctypes.c_int32, ctypes.c_float, ctypes.c_float, vp]
@@ -101,6 +119,10 @@ def lib():
         L.hgs_render_backward.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, P(vp), P(Grads)]
         L.hgs_l1_loss.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, P(vp), P(vp), vp]
         L.hgs_adam_step.argtypes = [vp, P(Adam)]
+        L.hgs_stream_begin.argtypes = [vp, ctypes.c_int64]
+        L.hgs_stream_end.argtypes = [vp]
+        L.hgs_stream_cleanup.argtypes = [vp, ctypes.c_int32]
+        L.hgs_stream_info.argtypes = [vp, P(StreamStats)]
         L.hgs_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.hgs_get_buffer.argtypes = [vp, ctypes.c_int32, P(vp), P(ctypes.c_int64)]
         L.hgs_set_profiling.argtypes = [vp, ctypes.c_int32]
@@ -208,6 +230,58 @@ class Renderer:
             setattr(d, k, keep[k][1])
         self._check(self.L.hgs_upload(self.h, ctypes.byref(d), 1 if on_dev else 0))
         self.n_nodes = d.n_nodes
+
+    def build(self, leaves) -> int:
+        """Build the hierarchy over ``leaves`` on the device (``hgs_build``)
+        and make it this renderer's.  ``leaves``: dict of node-major arrays
+        pos or mean [n, 3], scale [n, 3], rot [n, 4], opacity [n], sh [n, 48]
+        (numpy: host, CUDA tensors: device).  Returns the node count."""
+        torch = self.torch
+        a = dict(leaves)
+        if "mean" not in a:
+            a["mean"] = a["pos"]
+        on_dev = isinstance(a["mean"], torch.Tensor) and a["mean"].is_cuda
+        keep = {}
+        for k in ("mean", "scale", "rot", "opacity", "sh"):
+            x = a[k]
+            if on_dev:
+                x = x.contiguous()
+                assert x.dtype == torch.float32, k
+                keep[k] = (x, x.data_ptr())
+            else:
+                x = np.ascontiguousarray(x, np.float32)
+                keep[k] = (x, x.ctypes.data)
+        d = LeavesDesc()
+        d.n_leaves = int(keep["opacity"][0].shape[0])
+        for k in keep:
+            setattr(d, k, keep[k][1])
+        nn = ctypes.c_int64()
+        self._check(self.L.hgs_build(self.h, ctypes.byref(d), 1 if on_dev else 0, ctypes.byref(nn)))
+        self.n_nodes = int(nn.value)
+        self._bound = None
+        self._last = None
+        return self.n_nodes
+
+    def download(self, leaf_src: bool = False) -> dict:
+        """The renderer's hierarchy as host numpy arrays in the hierarchy's
+        storage layout (component-major, as ``synth.Hierarchy``): parent,
+        child_begin, child_count (int32 [N]), bmin, bmax, mean, scale [3, N],
+        rot [4, N], opacity [N], sh [48, N]; with ``leaf_src`` also the
+        build's input index of every leaf node (-1 for interior nodes)."""
+        N = self.n_nodes
+        nm = dict(parent=np.zeros(N, np.int32), child_begin=np.zeros(N, np.int32),
+                  child_count=np.zeros(N, np.int32), bmin=np.zeros((N, 3), np.float32),
+                  bmax=np.zeros((N, 3), np.float32), mean=np.zeros((N, 3), np.float32),
+                  scale=np.zeros((N, 3), np.float32), rot=np.zeros((N, 4), np.float32),
+                  opacity=np.zeros(N, np.float32), sh=np.zeros((N, 48), np.float32))
+        if leaf_src:
+            nm["leaf_src"] = np.zeros(N, np.int32)
+        o = HierarchyOut()
+        for k, x in nm.items():
+            setattr(o, k, x.ctypes.data)
+        self._check(self.L.hgs_download(self.h, ctypes.byref(o), 0))
+        out = {k: (np.ascontiguousarray(x.T) if x.ndim == 2 else x) for k, x in nm.items()}
+        return out
 
     def bind(self, mean, scale, rot, opacity, sh) -> None:
         ts = (mean, scale, rot, opacity, sh)
@@ -351,6 +425,25 @@ class Renderer:
         gp = (ctypes.c_void_p * len(dL))(*[g.data_ptr() for g in dL])
         self._check(self.L.hgs_l1_loss(self.h, rid, len(dL), tp, gp, ctypes.c_void_p(loss.data_ptr())))
         return dL, loss
+
+    # -- out-of-core rendering (hgs_stream_*) -------------------------------
+    def stream_begin(self, cache_nodes: int) -> None:
+        """Keep the parameters in pinned host memory and a device cache of
+        ``cache_nodes`` records; renders transfer what their cuts need."""
+        self._check(self.L.hgs_stream_begin(self.h, int(cache_nodes)))
+        self._last = None
+
+    def stream_end(self) -> None:
+        self._check(self.L.hgs_stream_end(self.h))
+        self._last = None
+
+    def stream_cleanup(self, max_age: int) -> None:
+        self._check(self.L.hgs_stream_cleanup(self.h, int(max_age)))
+
+    def stream_info(self) -> dict:
+        st = StreamStats()
+        self._check(self.L.hgs_stream_info(self.h, ctypes.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in StreamStats._fields_}
 
     def adam_step(self, params: dict, grads: dict, m: dict, v: dict, lr, step: int, beta1: float = 0.9,
                   beta2: float = 0.999, eps: float = 1e-15) -> None:
