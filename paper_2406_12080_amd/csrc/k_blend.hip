@@ -1,9 +1,13 @@
 // Per-tile alpha blending (forward) and its backward.
 //
 // One workgroup per tile of TW x TH pixels; each 64-lane wave owns an 8x8
-// sub-tile, one lane per pixel.  The tile's splats (sorted front to back)
-// are staged through LDS in batches of BATCH records; every lane walks the
-// batch in order.  Per pixel and splat (Sec. 3 Eq. (alpha) with the
+// sub-tile, one lane per pixel, and each row of 16 lanes one 4x4 quarter of
+// it.  The tile's splats (sorted front to back) are staged through LDS in
+// batches of BATCH records, each with one bit per quarter telling whether
+// any pixel of the quarter can reach alpha = 1/255.  Every quarter walks the
+// batch in order over the splats it may take only (a small splat touches
+// one or two of them), so that the four quarters of a wave step through
+// different splats together.  Per pixel and splat (Sec. 3 Eq. (alpha) with the
 // projected Gaussian G; Eq. (alphap) generalised to K children, Sec. 5.2;
 // the weight t of Eq. (t_interp) as the parent's weight; clamp of Sec. 7.3):
 //   G     = exp(-q/2),  q = d^T conic d  (d = pixel centre - mean), evaluated
@@ -17,7 +21,7 @@
 // and the index of the last contributor of each pixel, recovering the
 // transmittance in front of every splat by dividing by (1 - alpha) (no
 // per-pixel lists), reduces each splat's gradient over rows of 16 lanes with
-// DPP exchanges and over the rows and waves of the tile in LDS (FP32), and
+// DPP exchanges and over the rows and waves of the tile in LDS (FP64 atomics), and
 // adds it once per tile, in FP64, to the splat's screen-space gradient.
 #include <algorithm>
 #include <map>
@@ -78,24 +82,49 @@ __device__ __forceinline__ void eval_alpha(const float4 &W, const float4 &O, flo
     }
 }
 
-// True when no pixel of an 8x8 block can take the splat at alpha >= 1/255,
-// so that the block may skip it.  On the conic's scaled eigen-axes the
-// block's pixel centres lie in the box c + [0,7] a + [0,7] b (a = (w1x, w2x),
-// b = (w1y, w2y), c = block corner offsets), and alpha <= Amax G with
-// G = 2^-(u1^2 + u2^2) (Amax = A_n, or max(A_n, A_p) when t > 0: the pow
-// of Eq. (alphap) never exceeds its argument).  The distance of the box from
-// the origin is compared with log2(255 Amax) with a margin far above the
-// FP32 rounding of either side; boxes wider than 64 (sub-pixel splats, whose
-// offsets may cancel) are never skipped.
-__device__ __forceinline__ bool block_dead(const float4 &W, float c1, float c2, float Amax)
+// True when no pixel of a square of (E + 1) x (E + 1) pixels can take the
+// splat at alpha >= 1/255, so that the square may skip it.  On the conic's
+// scaled eigen-axes the square's pixel centres lie in the box
+// c + [0,E] a + [0,E] b (a = (w1x, w2x), b = (w1y, w2y), c = the offsets of
+// its corner pixel), and alpha <= Amax G with G = 2^-(u1^2 + u2^2)
+// (Amax = A_n, or max(A_n, A_p) when t > 0: the pow of Eq. (alphap) never
+// exceeds its argument).  The distance of the box from the origin is
+// compared with log2(255 Amax) with a margin far above the FP32 rounding of
+// either side; boxes wider than 64 (sub-pixel splats, whose offsets may
+// cancel) are never skipped.
+template <int E>
+__device__ __forceinline__ bool square_dead(const float4 &W, float c1, float c2, float Amax)
 {
-    const float a1 = 7.0f * W.x, b1 = 7.0f * W.y, a2 = 7.0f * W.z, b2 = 7.0f * W.w;
+    constexpr float e = (float)E;
+    const float a1 = e * W.x, b1 = e * W.y, a2 = e * W.z, b2 = e * W.w;
     const float lo1 = c1 + fminf(a1, 0.0f) + fminf(b1, 0.0f), hi1 = c1 + fmaxf(a1, 0.0f) + fmaxf(b1, 0.0f);
     const float lo2 = c2 + fminf(a2, 0.0f) + fminf(b2, 0.0f), hi2 = c2 + fmaxf(a2, 0.0f) + fmaxf(b2, 0.0f);
     if (!(hi1 - lo1 <= 64.0f && hi2 - lo2 <= 64.0f)) return false;
     const float m1 = fmaxf(fmaxf(lo1, -hi1), 0.0f), m2 = fmaxf(fmaxf(lo2, -hi2), 0.0f);
     const float r2 = __builtin_amdgcn_logf(255.0f * Amax);  // log2
     return m1 * m1 + m2 * m2 > r2 * 1.001f + 1e-3f;
+}
+
+// Pixel of lane l inside its wave's 8x8 block: quarter l >> 4 is the 4x4
+// square at ((q & 1) 4, (q >> 1) 4), rows of four lanes inside it.
+__device__ __forceinline__ int quarter_x(int lane) { return ((lane >> 4) & 1) * 4 + (lane & 3); }
+__device__ __forceinline__ int quarter_y(int lane) { return (lane >> 5) * 4 + ((lane >> 2) & 3); }
+
+// Quarter mask of a staged splat: bit 4 bk + q set when some pixel of
+// quarter q of block bk may take the splat (square_dead on the quarter).
+template <int NB>
+__device__ __forceinline__ uint32_t quarter_live(const float4 &W, const float2 (&u)[8], float amax)
+{
+    uint32_t live = 0u;
+#pragma unroll
+    for (int bk = 0; bk < NB; ++bk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float sx = (float)((q & 1) * 4), sy = (float)((q >> 1) * 4);
+            const float c1 = fmaf(sy, W.y, fmaf(sx, W.x, u[bk].x)), c2 = fmaf(sy, W.w, fmaf(sx, W.z, u[bk].y));
+            live |= square_dead<3>(W, c1, c2, amax) ? 0u : 1u << (4 * bk + q);
+        }
+    return live;
 }
 
 __device__ __forceinline__ int view_of_tile(const DevView *views, int nv, uint32_t tile)
@@ -113,7 +142,7 @@ __device__ __forceinline__ int view_of_tile(const DevView *views, int nv, uint32
 struct Staged {
     float4 w, o, c;
     float2 u[8];
-    uint32_t dead;  // bit bk: block bk skips the splat
+    uint32_t live;  // bit 4 bk + q: quarter q of block bk may take the splat
 };
 
 template <int NB, int SX>
@@ -122,27 +151,19 @@ __device__ __forceinline__ void stage_one(const SplatRec &r, const double4 &W64,
     st.w = make_float4((float)W64.x, (float)W64.y, (float)W64.z, (float)W64.w);
     st.o = make_float4(r.An, r.Ap, r.t, r.invK);
     st.c = make_float4(r.r, r.g, r.b, 0.0f);
-    const float amax = r.t > 0.0f ? fmaxf(r.An, r.Ap) : r.An;
-    st.dead = 0u;
 #pragma unroll
     for (int bk = 0; bk < NB; ++bk) {
         float c1, c2, d0, d1;
         block_offsets(r, W64, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
         st.u[bk] = make_float2(c1, c2);
-        st.dead |= block_dead(st.w, c1, c2, amax) ? 1u << bk : 0u;
     }
+    st.live = quarter_live<NB>(st.w, st.u, r.t > 0.0f ? fmaxf(r.An, r.Ap) : r.An);
 }
 
 // Per-wave work counts (uint4 per wave, plain stores) are summed by
 // k_stats_reduce into three consecutive counters: forward (evaluated,
 // blended, evaluated with t > 0), backward (evaluated, evaluated with t > 0,
 // contributing).  No contended atomics on the hot path.
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
 
 // Work distribution over tiles: either one workgroup per tile slot (grid =
 // tile count, slot = workgroup index), or a persistent grid sized to the
@@ -177,18 +198,18 @@ __device__ __forceinline__ void blend_tile(const DevView *__restrict__ views, in
     static_assert(BATCH % NT == 0 && BATCH % 64 == 0 && NB <= 8, "tile/batch combination");
     __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
     __shared__ float2 s_u[NB][BATCH];
-    __shared__ uint64_t s_tm[BATCH / 64];  // bit j of word k: entry 64 k + j is interpolated (t > 0)
-    __shared__ uint64_t s_dm[NB][BATCH / 64];  // likewise: block bk skips entry 64 k + j
+    __shared__ uint32_t s_qm[NB][4][BATCH / 32];  // bit b of word k: quarter q of block bk may take entry 32 k + b
     const uint32_t tile = tile_order[slot];  // longest lists first
     const int vi = view_of_tile(views, nv, tile);
     const DevView &V = views[vi];
     const uint32_t lt = tile - V.tile_base;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4;
     const int ox = tx * TW, oy = ty * TH;
-    const int px = ox + (w % SX) * 8 + (lane & 7), py = oy + (w / SX) * 8 + (lane >> 3);
+    const int bx = quarter_x(lane), by = quarter_y(lane);
+    const int px = ox + (w % SX) * 8 + bx, py = oy + (w / SX) * 8 + by;
     const bool inside = px < V.W && py < V.H;
-    const float lx = (float)(lane & 7), ly = (float)(lane >> 3);
+    const float lx = (float)bx, ly = (float)by;
     const uint2 rg = ranges[tile];
 
     // T < 0 marks a finished pixel (or one outside the image); |T| is its
@@ -222,48 +243,52 @@ __device__ __forceinline__ void blend_tile(const DevView *__restrict__ views, in
             Staged st;
             if (real) {
                 stage_one<NB, SX>(nxt[p], nxw[p], ox, oy, st);
-            } else {  // padding: alpha = 0 everywhere, skipped by every block
+            } else {  // padding: alpha = 0 everywhere, taken by no quarter
                 st.w = st.o = st.c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
                 for (int bk = 0; bk < NB; ++bk) st.u[bk] = make_float2(0.0f, 0.0f);
-                st.dead = (1u << NB) - 1u;
+                st.live = 0u;
             }
             s_w[j] = st.w;
             s_o[j] = st.o;
             s_c[j] = st.c;
 #pragma unroll
             for (int bk = 0; bk < NB; ++bk) s_u[bk][j] = st.u[bk];
-            const uint64_t m = __ballot(real && st.o.z > 0.0f);
-            if (lane == 0) s_tm[j >> 6] = m;
+            const int e0 = p * NT + 64 * w;  // first entry of this wave's 64
 #pragma unroll
-            for (int bk = 0; bk < NB; ++bk) {
-                const uint64_t dm = __ballot((st.dead >> bk) & 1u);
-                if (lane == 0) s_dm[bk][j >> 6] = dm;
+            for (int bq = 0; bq < 4 * NB; ++bq) {
+                const uint64_t m = __ballot((st.live >> bq) & 1u);
+                if (lane == 0) {
+                    s_qm[bq >> 2][bq & 3][e0 >> 5] = (uint32_t)m;
+                    s_qm[bq >> 2][bq & 3][(e0 >> 5) + 1] = (uint32_t)(m >> 32);
+                }
             }
         }
         __syncthreads();
         if (b0 + BATCH < rg.y) fetch(b0 + BATCH);
-        if (__ballot(T > 0.0f) == 0ull) continue;
-        const int cnt = (int)min((uint32_t)BATCH, rg.y - b0), cnt4 = (cnt + 3) & ~3;
+        uint64_t alive = __ballot(T > 0.0f);
+        if (alive == 0ull) continue;
+        const int cnt = (int)min((uint32_t)BATCH, rg.y - b0);
         const uint32_t jb = b0 - rg.x + 1u;  // 1-based list position of entry 0
-        uint64_t tm = 0, dm = 0;
-        for (int j0 = 0; j0 < cnt4; j0 += 4) {
-            if ((j0 & 63) == 0) {
-                tm = uniform_u64(s_tm[j0 >> 6]);
-                dm = uniform_u64(s_dm[w][j0 >> 6]);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = j0 + u;
-                if ((dm >> (j & 63)) & 1ull) continue;  // no pixel of this block reaches 1/255
-                const uint32_t bit = (uint32_t)(tm >> (j & 63)) & 1u;
-                // work counts from the wave's live mask (scalar unit only)
-                const uint32_t n_live = (uint32_t)__popcll(__ballot(T > 0.0f));
-                n_eval += n_live;
-                n_eval_t += bit ? n_live : 0u;
+        // each quarter walks, front to back, the entries it may take, until
+        // its pixels are all finished; the four quarters of a wave step together
+        for (int k = 0; 32 * k < cnt; ++k) {
+            uint32_t m = s_qm[w][q][k];
+            for (;;) {
+                m = ((alive >> (lane & 48)) & 0xFFFFull) ? m : 0u;  // nothing left for a finished quarter
+                const bool has = m != 0u;
+                if (__ballot(has) == 0ull) break;
+                const int j = 32 * k + (has ? __builtin_ctz(m) : 0);
+                m &= m - 1u;
+                const bool go = has && T > 0.0f;
+                const float4 Ov = s_o[j];
+                const bool interp = Ov.z > 0.0f;
+                // work counts from the wave's masks (scalar unit only)
+                n_eval += (uint32_t)__popcll(__ballot(go));
+                n_eval_t += (uint32_t)__popcll(__ballot(go && interp));
                 AlphaEval e;
-                eval_alpha(s_w[j], s_o[j], s_u[w][j], lx, ly, bit != 0u, e);
-                if (T > 0.0f && e.alpha >= kAlphaMin) {
+                eval_alpha(s_w[j], Ov, s_u[w][j], lx, ly, interp, e);
+                if (go && e.alpha >= kAlphaMin) {
                     const float Tn = T * (1.0f - e.alpha);
                     const bool stop = Tn < kTMin;
                     const float4 Cc = s_c[j];
@@ -275,8 +300,9 @@ __device__ __forceinline__ void blend_tile(const DevView *__restrict__ views, in
                     last = stop ? last : jb + (uint32_t)j;
                     T = stop ? -T : Tn;
                 }
+                alive = __ballot(T > 0.0f);
             }
-            if (__ballot(T > 0.0f) == 0ull) break;
+            if (alive == 0ull) break;
         }
     }
     if (inside) {
@@ -295,7 +321,6 @@ __device__ __forceinline__ void blend_tile(const DevView *__restrict__ views, in
     for (int d = 32; d >= 1; d >>= 1) nb_w += (uint32_t)__shfl_xor((int)nb_w, d, 64);
     if (lane == 0) wstats[(size_t)slot * NW + w] = make_uint4(n_eval, nb_w, n_eval_t, 0u);
 }
-
 template <int TW, int TH, int BATCH, bool PERSIST>
 __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ views, int nv,
                                                   const uint32_t *__restrict__ tile_order,
@@ -325,72 +350,61 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
     }
 }
 
-// Cross-row halvings with the gfx950 lane swaps: permlane32_swap(x, y) moves
-// the upper half of x and the lower half of y into each other's place, so
-// x + y afterwards holds, on lanes 0-31, x summed over lanes l and l + 32
-// and, on lanes 32-63, y summed likewise (permlane16_swap does the same for
-// odd and even rows of 16): one swap and one add per pair of values.
-__device__ __forceinline__ float swap_add32(float x, float y)
-{
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
-    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-__device__ __forceinline__ float swap_add16(float x, float y)
-{
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
-    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-// Sum over the 64 lanes of 12 per-lane values v[0..11] (v[11] only when DT):
-// two swap steps (across halves, then across rows), two in-row halvings with
-// DPP (partners l ^ 8, then l ^ 7, each keeping one of two values), and a sum
-// over the quad (l ^ 2, l ^ 1).  Every lane of quad q = l >> 2 ends with the
-// total of value wave_slot(l) (-1: nothing).
+// Sum over each row of 16 lanes (one 4x4 quarter of the wave's block) of 12
+// per-lane values v[0..11]: four halvings with DPP inside the row (partners
+// l ^ 8, l ^ 7, l ^ 2 and l ^ 1), each keeping one of the two values of a
+// pair per lane.  Lane l of the row ends with the row's total of value
+// row_slot(l) (-1: a copy of another lane's total).  v[11] is zero unless
+// DT.
 template <bool DT>
-__device__ __forceinline__ float wave_reduce12(const float (&v)[12], int lane)
+__device__ __forceinline__ float row_reduce12(const float (&v)[12], int lane)
 {
-    const float S0 = swap_add32(v[0], v[1]), S1 = swap_add32(v[2], v[3]), S2 = swap_add32(v[4], v[5]);
-    const float S3 = swap_add32(v[6], v[7]), S4 = swap_add32(v[8], v[9]);
-    const float S5 = swap_add32(v[10], DT ? v[11] : 0.0f);  // slot 11 (dL/dt) only when asked for
-    // rows 0..3 of Z0: v0 v2 v1 v3; Z1: v4 v6 v5 v7; Z2: v8 v10 v9 v11
-    const float Z0 = swap_add16(S0, S1), Z1 = swap_add16(S2, S3), Z2 = swap_add16(S4, S5);
-    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
-    const float R0 = (b3 ? Z1 : Z0) + dpp_move<0x128>(b3 ? Z0 : Z1);
-    const float R1 = (b3 ? 0.0f : Z2) + dpp_move<0x128>(b3 ? Z2 : 0.0f);
-    float F = (b2 ? R1 : R0) + dpp_move<0x141>(b2 ? R0 : R1);
-    F += dpp_move<0x4E>(F);
-    F += dpp_move<0xB1>(F);
-    return F;
+    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+    float A[6], B[3];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+        A[k] = (b3 ? v[2 * k + 1] : v[2 * k]) + dpp_move<0x128>(b3 ? v[2 * k] : v[2 * k + 1]);  // row_ror:8
+    A[5] = DT ? (b3 ? v[11] : v[10]) + dpp_move<0x128>(b3 ? v[10] : v[11])
+              : (b3 ? 0.0f : v[10]) + dpp_move<0x128>(b3 ? v[10] : 0.0f);
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+        B[m] = (b2 ? A[2 * m + 1] : A[2 * m]) + dpp_move<0x141>(b2 ? A[2 * m] : A[2 * m + 1]);  // half mirror
+    const float C0 = (b1 ? B[1] : B[0]) + dpp_move<0x4E>(b1 ? B[0] : B[1]);
+    const float C1 = B[2] + dpp_move<0x4E>(B[2]);
+    return (b0 ? C1 : C0) + dpp_move<0xB1>(b0 ? C0 : C1);
 }
 
-__device__ __forceinline__ int wave_slot(int lane)
+__device__ __forceinline__ int row_slot(int lane)
 {
-    // by row (lane >> 4) and (b2, b3) = bits 2 and 3 of the lane
-    constexpr int8_t kSlot[4][4] = {{0, 4, 8, -1}, {2, 6, 10, -1}, {1, 5, 9, -1}, {3, 7, 11, -1}};
-    return kSlot[lane >> 4][((lane >> 2) & 1) * 2 + ((lane >> 3) & 1)];
+    const int b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1, b1 = (lane >> 1) & 1, b0 = lane & 1;
+    return b0 == 0 ? 4 * b1 + 2 * b2 + b3 : (b1 == 0 ? 8 + 2 * b2 + b3 : -1);
 }
 
 constexpr int kG = 12;  // floats per splat in the screen-space gradient
 
 // Per-lane gradient slots of one (pixel, splat) pair, summed over the tile:
-//   0       S = h                         with h = G dL/dG (G the Gaussian)
-//   1, 2    P'_i = h v_i
-//   3..5    Q'_11, Q'_12, Q'_22 = h v_1 v_1, h v_1 v_2, h v_2 v_2
-//   6, 7    dL/dA_n, dL/dA_p (A = kappa |o|)
-//   8..10   dL/d colour
+//   0, 1    P'_i = h v_i                  with h = G dL/dG (G the Gaussian)
+//   2..4    Q'_11, Q'_12, Q'_22 = h v_1 v_1, h v_1 v_2, h v_2 v_2
+//   5, 6    dL/dA_n, dL/dA_p (A = kappa |o|)
+//   7..9    dL/d colour
+//   10      S = h
 //   11      dL/dt through alpha (only when the caller asks for dL/dt)
 // Here v = u - c is the pixel's position on the conic's scaled eigen-axes
-// relative to the tile's corner pixel (c, formed in FP64 at staging): v is
-// the pixel's offset inside the tile mapped by the axes.  The moments about
-// the splat's centre follow in FP64 at the flush, P = P' + c S and
-// Q = Q' + c P'^T + P' c^T + c c^T S.  Taken directly about the centre, the
-// moments of a large splat whose centre lies far off screen are dominated
-// by c S and c c^T S, and the mean and covariance gradients built from them
-// cancel almost entirely in the chain through the projection: separately
-// rounded FP32 sums of P and Q then leave errors far above the result.  With
-// the moments about the corner both large parts carry the one rounded S, and
-// the cancellation removes its error with it.
+// relative to the tile's centre (c, formed in FP64 at staging): v is the
+// pixel's offset from the tile centre mapped by the axes.  The moments
+// about the splat's centre follow in FP64 at the flush, P = P' + c S and
+// Q = Q' + c P'^T + P' c^T + c c^T S.  Taken directly about the splat's
+// centre, the moments of a large splat whose centre lies far off screen are
+// dominated by c S and c c^T S, and the mean and covariance gradients built
+// from them cancel almost entirely in the chain through the projection:
+// separately rounded FP32 sums of P and Q then leave errors far above the
+// result.  With the moments about the tile both large parts carry the one
+// rounded S, and the cancellation removes its error with it.  What remains
+// is the FP32 rounding of P' and Q', which grows with |v|^2: hence the
+// tile's centre (|v| at most half the tile's diagonal) rather than a
+// corner, and S summed from the same per-pixel h as P' and Q' (forming it
+// from slots 5 and 6 instead, equal in exact arithmetic, leaves per-pixel
+// differences that c c^T amplifies).
 // The screen-space gradient follows from the tile sums by the splat's
 // (per-tile constant) axes: with g = conic d = (u1 w1 + u2 w2) / kHalfLog2e
 // and G = exp(-q/2), dL/dmean = sum h g and dL/dSigma2' = -sum (h / 2) g g^T
@@ -409,12 +423,14 @@ __device__ __forceinline__ void screen_grad(const float4 &W, const double P[2], 
     out[4] = 0.5 * k * k * (wy * wy * Q11 + 2.0 * wy * ww * Q12 + ww * ww * Q22);
 }
 
-// Offsets of the tile's corner pixel centre on the scaled eigen-axes, in FP64.
-__device__ __forceinline__ double2 corner_offsets(const SplatRec &r, const double4 &W, int ox, int oy)
+// Offsets of the centre of the TW x TH tile at (ox, oy) on the scaled
+// eigen-axes, in FP64.
+template <int TW, int TH>
+__device__ __forceinline__ double2 centre_offsets(const SplatRec &r, const double4 &W, int ox, int oy)
 {
 #pragma clang fp contract(off)
-    const double dx = ((double)(ox - r.ax) + 0.5) - (double)r.fx;
-    const double dy = ((double)(oy - r.ay) + 0.5) - (double)r.fy;
+    const double dx = ((double)(ox - r.ax) + 0.5 * TW) - (double)r.fx;
+    const double dy = ((double)(oy - r.ay) + 0.5 * TH) - (double)r.fy;
     return make_double2(dx * W.x + dy * W.y, dx * W.z + dy * W.w);
 }
 
@@ -433,28 +449,33 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
     constexpr int NW = NT / 64;
     constexpr int SX = TW / 8;
     constexpr int NB = (TW / 8) * (TH / 8);
+    constexpr int NQW = BATCH / 32;  // 32-entry words of a quarter's mask
+    static_assert(BATCH % 32 == 0 && NB <= 8, "tile/batch combination");
     __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
     __shared__ float2 s_u[NB][BATCH];  // c1, c2
     __shared__ uint32_t s_id[BATCH];
-    __shared__ __align__(16) float s_g[BATCH][kG];
+    __shared__ __align__(16) double s_g[BATCH][kG];  // the quarters' partial sums, added in FP64
     __shared__ double s_d[BATCH * 11];  // the flushed terms, splat-major
-    __shared__ double2 s_ref[BATCH];    // the tile corner's offsets on the axes (FP64)
+    __shared__ double2 s_ref[BATCH];    // the tile centre's offsets on the axes (FP64)
+    // bit b of word k: quarter q of block bk may take entry 32 k + 31 - b
+    // (reversed, so that the lowest set bit is the next entry back to front)
+    __shared__ uint32_t s_qm[NB][4][NQW];
     __shared__ uint32_t s_max;
     const uint32_t tile = tile_order[tslot];  // longest lists first
     const int vi = view_of_tile(views, nv, tile);
     const DevView &V = views[vi];
     const uint32_t lt = tile - V.tile_base;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4;
     const int ox = tx * TW, oy = ty * TH;
-    const int px = ox + (w % SX) * 8 + (lane & 7), py = oy + (w / SX) * 8 + (lane >> 3);
+    const int bx = quarter_x(lane), by = quarter_y(lane);
+    const int px = ox + (w % SX) * 8 + bx, py = oy + (w / SX) * 8 + by;
     const bool inside = px < V.W && py < V.H;
-    const float lx = (float)(lane & 7), ly = (float)(lane >> 3);
-    // the pixel's offset from the tile corner (the moments' reference)
-    const float lxt = (float)(px - ox), lyt = (float)(py - oy);
+    const float lx = (float)bx, ly = (float)by;
+    // the pixel's offset from the tile centre (the moments' reference; exact)
+    const float lxt = (float)(px - ox) - 0.5f * (TW - 1), lyt = (float)(py - oy) - 0.5f * (TH - 1);
     const uint2 rg = ranges[tile];
-    const int slot = wave_slot(lane);
-    const bool writer = (lane & 3) == 0 && slot >= 0;
+    const int slot = row_slot(lane);
 
     float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
     uint32_t last = 0;
@@ -469,9 +490,12 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
     }
     if (threadIdx.x == 0) s_max = 0;
     __syncthreads();
-    uint32_t wm = last;
+    // the quarter's last contributor (rows of 16 lanes), then the tile's
+    uint32_t qm = last;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) wm = max(wm, (uint32_t)__shfl_xor((int)wm, d, 64));
+    for (int d = 8; d >= 1; d >>= 1) qm = max(qm, (uint32_t)__shfl_xor((int)qm, d, 64));
+    uint32_t wm = max(qm, (uint32_t)__shfl_xor((int)qm, 16, 64));
+    wm = max(wm, (uint32_t)__shfl_xor((int)wm, 32, 64));
     if (lane == 0) atomicMax(&s_max, wm);
     __syncthreads();
     const uint32_t end = rg.x + s_max;
@@ -481,80 +505,111 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
     for (uint32_t hi = end; hi > rg.x;) {
         const uint32_t lo = hi - rg.x > (uint32_t)BATCH ? hi - BATCH : rg.x;
         const int cnt = (int)(hi - lo);
-        for (int j = threadIdx.x; j < cnt; j += NT) {
-            const uint32_t sidx = pair_vals[lo + j];
-            const SplatRec r = recs[sidx];
-            const double4 W64 = axes[sidx];
-            s_id[j] = vis_rank[sidx];  // gradient row
-            s_w[j] = make_float4((float)W64.x, (float)W64.y, (float)W64.z, (float)W64.w);
-            s_o[j] = make_float4(r.An, r.Ap, r.t, r.invK);
-            s_c[j] = make_float4(r.r, r.g, r.b, 0.0f);
+        for (int j0 = 0; j0 < BATCH; j0 += NT) {
+            const int j = j0 + (int)threadIdx.x;
+            uint32_t live = 0u;
+            if (j < cnt) {
+                const uint32_t sidx = pair_vals[lo + j];
+                const SplatRec r = recs[sidx];
+                const double4 W64 = axes[sidx];
+                const float4 W = make_float4((float)W64.x, (float)W64.y, (float)W64.z, (float)W64.w);
+                float2 u[8];
 #pragma unroll
-            for (int bk = 0; bk < NB; ++bk) {
-                float c1, c2, d0, d1;
-                block_offsets(r, W64, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
-                s_u[bk][j] = make_float2(c1, c2);
+                for (int bk = 0; bk < NB; ++bk) {
+                    float c1, c2, d0, d1;
+                    block_offsets(r, W64, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
+                    u[bk] = make_float2(c1, c2);
+                    s_u[bk][j] = u[bk];
+                }
+                live = quarter_live<NB>(W, u, r.t > 0.0f ? fmaxf(r.An, r.Ap) : r.An);
+                s_id[j] = vis_rank[sidx];  // gradient row
+                s_w[j] = W;
+                s_o[j] = make_float4(r.An, r.Ap, r.t, r.invK);
+                s_c[j] = make_float4(r.r, r.g, r.b, 0.0f);
+                s_ref[j] = centre_offsets<TW, TH>(r, W64, ox, oy);
+#pragma unroll
+                for (int k = 0; k < kG; ++k) s_g[j][k] = 0.0;
+            } else if (j < BATCH) {  // padding read by quarters with nothing left: alpha = 0
+                s_w[j] = s_o[j] = s_c[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+                for (int bk = 0; bk < NB; ++bk) s_u[bk][j] = make_float2(0.0f, 0.0f);
             }
-            s_ref[j] = corner_offsets(r, W64, ox, oy);
+            const int e0 = j0 + 64 * w;  // first entry of this wave's 64
+            if (e0 < BATCH) {
 #pragma unroll
-            for (int q = 0; q < kG; ++q) s_g[j][q] = 0.0f;
+                for (int bq = 0; bq < 4 * NB; ++bq) {
+                    const uint64_t m = __ballot((live >> bq) & 1u);
+                    if (lane == 0) {
+                        s_qm[bq >> 2][bq & 3][e0 >> 5] = __builtin_bitreverse32((uint32_t)m);
+                        if (e0 + 32 < BATCH) s_qm[bq >> 2][bq & 3][(e0 >> 5) + 1] = __builtin_bitreverse32((uint32_t)(m >> 32));
+                    }
+                }
+            }
         }
         __syncthreads();
-        for (int j = cnt - 1; j >= 0; --j) {
-            const uint32_t li = lo - rg.x + (uint32_t)j;
-            const bool in_range = li < last;
-            const uint64_t live = __ballot(in_range);
-            if (live == 0ull) continue;
-            const float4 Wv = s_w[j], Ov = s_o[j];
-            const float2 U = s_u[w][j];
-            const bool interp = __builtin_amdgcn_readfirstlane(__float_as_int(Ov.z)) > 0;
-            AlphaEval e;
-            eval_alpha(Wv, Ov, U, lx, ly, interp, e);
-            const bool contrib = in_range && e.alpha >= kAlphaMin;
-            const uint64_t cm = __ballot(contrib);
-            n_eval += (uint32_t)__popcll(live);
-            n_eval_t += interp ? (uint32_t)__popcll(live) : 0u;
-            if (cm == 0ull) continue;
-            n_con += (uint32_t)__popcll(cm);
-            // every lane runs the update; a non-contributing lane has a = 0 and
-            // dL/dalpha = 0, which leaves T and R as they are and all slots 0
-            const float4 Cc = s_c[j];
-            const float a = contrib ? e.alpha : 0.0f;
-            T = T * __builtin_amdgcn_rcpf(1.0f - a);
-            const float dal_raw = T * ((Cc.x - R0) * g0 + (Cc.y - R1) * g1 + (Cc.z - R2) * g2);
-            const float dal = contrib ? dal_raw : 0.0f;
-            const float aT = a * T;
-            float v[12];
-            v[8] = aT * g0;
-            v[9] = aT * g1;
-            v[10] = aT * g2;
-            R0 = a * Cc.x + (1.0f - a) * R0;
-            R1 = a * Cc.y + (1.0f - a) * R1;
-            R2 = a * Cc.z + (1.0f - a) * R2;
-            float dan = dal, dap = 0.0f;
-            v[11] = 0.0f;
-            if (interp) {
-                dan = (1.0f - Ov.z) * dal;
-                const float dapr = Ov.z * dal;
-                if constexpr (DT) v[11] = (e.apr - e.an) * dal;
-                // d apr / d a_p = (1/K) (1 - a_p)^(1/K - 1) = (1/K) q / (1 - a_p)
-                dap = dapr * Ov.w * (e.q * __builtin_amdgcn_rcpf(1.0f - e.ap));
-            }
-            const float dan_c = e.cn ? 0.0f : dan, dap_c = e.cp ? 0.0f : dap;
-            v[6] = dan_c * e.G;
-            v[7] = dap_c * e.G;
-            const float h = e.G * (dan_c * Ov.x + dap_c * Ov.y);  // G dL/dG
-            const float v1 = fmaf(lyt, Wv.y, lxt * Wv.x), v2 = fmaf(lyt, Wv.w, lxt * Wv.z);
-            v[0] = h;
-            v[1] = h * v1;
-            v[2] = h * v2;
-            v[3] = v[1] * v1;
-            v[4] = v[1] * v2;
-            v[5] = v[2] * v2;
-            const float tot = wave_reduce12<DT>(v, lane);
-            if (writer && tot != 0.0f) {
-                if constexpr (NW == 1) s_g[j][slot] = tot;
-                else atomicAdd(&s_g[j][slot], tot);
+        // each quarter walks, back to front, the entries it may take that lie
+        // before its last contributor; the four quarters of a wave step together
+        const uint32_t base = lo - rg.x;  // list position of entry 0
+        const int lim = qm > base ? (int)min(qm - base, (uint32_t)cnt) : 0;
+        for (int k = (cnt - 1) >> 5; k >= 0; --k) {
+            uint32_t m = s_qm[w][q][k];
+            const int lk = lim - 32 * k;  // entries 32 k + i, i < lk, come before the last contributor
+            m &= lk >= 32 ? ~0u : (lk <= 0 ? 0u : ~((1u << (32 - lk)) - 1u));
+            for (;;) {
+                const bool has = m != 0u;
+                if (__ballot(has) == 0ull) break;
+                const int j = 32 * k + 31 - (has ? __builtin_ctz(m) : 0);
+                m &= m - 1u;
+                const bool in_range = has && base + (uint32_t)j < last;
+                const float4 Wv = s_w[j], Ov = s_o[j];
+                const float2 U = s_u[w][j];
+                const bool interp = Ov.z > 0.0f;
+                AlphaEval e;
+                eval_alpha(Wv, Ov, U, lx, ly, interp, e);
+                const bool contrib = in_range && e.alpha >= kAlphaMin;
+                const uint64_t live = __ballot(in_range);
+                const uint64_t cm = __ballot(contrib);
+                n_eval += (uint32_t)__popcll(live);
+                n_eval_t += (uint32_t)__popcll(__ballot(in_range && interp));
+                if (cm == 0ull) continue;
+                n_con += (uint32_t)__popcll(cm);
+                // every lane runs the update; a non-contributing lane has a = 0 and
+                // dL/dalpha = 0, which leaves T and R as they are and all slots 0
+                const float4 Cc = s_c[j];
+                const float a = contrib ? e.alpha : 0.0f;
+                T = T * __builtin_amdgcn_rcpf(1.0f - a);
+                const float dal_raw = T * ((Cc.x - R0) * g0 + (Cc.y - R1) * g1 + (Cc.z - R2) * g2);
+                const float dal = contrib ? dal_raw : 0.0f;
+                const float aT = a * T;
+                float v[12];
+                v[7] = aT * g0;
+                v[8] = aT * g1;
+                v[9] = aT * g2;
+                R0 = a * Cc.x + (1.0f - a) * R0;
+                R1 = a * Cc.y + (1.0f - a) * R1;
+                R2 = a * Cc.z + (1.0f - a) * R2;
+                float dan = dal, dap = 0.0f;
+                v[11] = 0.0f;
+                if (interp) {
+                    dan = (1.0f - Ov.z) * dal;
+                    const float dapr = Ov.z * dal;
+                    if constexpr (DT) v[11] = (e.apr - e.an) * dal;
+                    // d apr / d a_p = (1/K) (1 - a_p)^(1/K - 1) = (1/K) q / (1 - a_p)
+                    dap = dapr * Ov.w * (e.q * __builtin_amdgcn_rcpf(1.0f - e.ap));
+                }
+                const float dan_c = e.cn ? 0.0f : dan, dap_c = e.cp ? 0.0f : dap;
+                v[5] = dan_c * e.G;
+                v[6] = dap_c * e.G;
+                const float h = e.G * (dan_c * Ov.x + dap_c * Ov.y);  // G dL/dG
+                const float v1 = fmaf(lyt, Wv.y, lxt * Wv.x), v2 = fmaf(lyt, Wv.w, lxt * Wv.z);
+                v[10] = h;
+                v[0] = h * v1;
+                v[1] = h * v2;
+                v[2] = v[0] * v1;
+                v[3] = v[0] * v2;
+                v[4] = v[1] * v2;
+                const float tot = row_reduce12<DT>(v, lane);
+                if (has && slot >= 0 && tot != 0.0f) unsafeAtomicAdd(&s_g[j][slot], (double)tot);
             }
         }
         __syncthreads();
@@ -562,12 +617,11 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
         // 11 screen-space terms (FP64); then the terms of all splats go out
         // as consecutive atomics, row by row
         for (int j = threadIdx.x; j < cnt; j += NT) {
-            const float4 a = *reinterpret_cast<const float4 *>(&s_g[j][0]);
-            const float4 b = *reinterpret_cast<const float4 *>(&s_g[j][4]);
-            const float4 c = *reinterpret_cast<const float4 *>(&s_g[j][8]);
-            // moments about the splat's centre from those about the tile corner
+            const double *g = s_g[j];
+            // moments about the splat's centre from those about the tile's
             const double2 cr = s_ref[j];
-            const double S = a.x, P1 = a.y, P2 = a.z, Q11 = a.w, Q12 = b.x, Q22 = b.y;
+            const double S = g[10];
+            const double P1 = g[0], P2 = g[1], Q11 = g[2], Q12 = g[3], Q22 = g[4];
             const double P[2] = {P1 + cr.x * S, P2 + cr.y * S};
             const double Q[3] = {Q11 + 2.0 * cr.x * P1 + cr.x * cr.x * S,
                                  Q12 + cr.x * P2 + cr.y * P1 + cr.x * cr.y * S,
@@ -576,26 +630,22 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
             screen_grad(s_w[j], P, Q, sc);
             double *d = s_d + j * 11;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) d[q] = sc[q];
-            d[5] = (double)b.z;
-            d[6] = (double)b.w;
-            d[7] = (double)c.x;
-            d[8] = (double)c.y;
-            d[9] = (double)c.z;
-            d[10] = (double)c.w;
+            for (int k = 0; k < 5; ++k) d[k] = sc[k];
+#pragma unroll
+            for (int k = 5; k < 10; ++k) d[k] = g[k];
+            d[10] = g[11];
         }
         __syncthreads();
         for (int idx = threadIdx.x; idx < cnt * 11; idx += NT) {
             const double val = s_d[idx];
-            const int j = idx / 11, q = idx - 11 * j;
-            if (val != 0.0) unsafeAtomicAdd(&sgrad[(size_t)s_id[j] * kG + q], val);
+            const int j = idx / 11, k = idx - 11 * j;
+            if (val != 0.0) unsafeAtomicAdd(&sgrad[(size_t)s_id[j] * kG + k], val);
         }
         __syncthreads();
         hi = lo;
     }
     if (lane == 0) wstats[(size_t)tslot * NW + w] = make_uint4(n_eval, n_eval_t, n_con, 0u);
 }
-
 template <int TW, int TH, int BATCH, bool DT, bool PERSIST>
 __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict__ views, int nv,
                                                       const uint32_t *__restrict__ tile_order,
