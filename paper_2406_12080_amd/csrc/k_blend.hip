@@ -351,21 +351,19 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
 }
 
 // Sum over each row of 16 lanes (one 4x4 quarter of the wave's block) of 12
-// per-lane values v[0..11]: four halvings with DPP inside the row (partners
-// l ^ 8, l ^ 7, l ^ 2 and l ^ 1), each keeping one of the two values of a
-// pair per lane.  Lane l of the row ends with the row's total of value
-// row_slot(l) (-1: a copy of another lane's total).  v[11] is zero unless
-// DT.
-template <bool DT>
-__device__ __forceinline__ float row_reduce12(const float (&v)[12], int lane)
+// per-lane values, taken as six pairs (first, second): four halvings with
+// DPP inside the row (partners l ^ 8, l ^ 7, l ^ 2 and l ^ 1), each keeping
+// one of the two values of a pair per lane.  The caller gives the first
+// halving's operands, chosen per lane by bit 3 of the lane: S1[k] = second
+// if set, else first; S2[k] = the other one.  Lane l of the row ends with the
+// row's total of value row_slot(l) (value 2 k + 1 is the second of pair k;
+// -1: a copy of another lane's total).
+__device__ __forceinline__ float row_reduce12(const float (&S1)[6], const float (&S2)[6], int lane)
 {
-    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+    const bool b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
     float A[6], B[3];
 #pragma unroll
-    for (int k = 0; k < 5; ++k)
-        A[k] = (b3 ? v[2 * k + 1] : v[2 * k]) + dpp_move<0x128>(b3 ? v[2 * k] : v[2 * k + 1]);  // row_ror:8
-    A[5] = DT ? (b3 ? v[11] : v[10]) + dpp_move<0x128>(b3 ? v[10] : v[11])
-              : (b3 ? 0.0f : v[10]) + dpp_move<0x128>(b3 ? v[10] : 0.0f);
+    for (int k = 0; k < 6; ++k) A[k] = S1[k] + dpp_move<0x128>(S2[k]);  // row_ror:8
 #pragma unroll
     for (int m = 0; m < 3; ++m)
         B[m] = (b2 ? A[2 * m + 1] : A[2 * m]) + dpp_move<0x141>(b2 ? A[2 * m] : A[2 * m + 1]);  // half mirror
@@ -384,10 +382,11 @@ constexpr int kG = 12;  // floats per splat in the screen-space gradient
 
 // Per-lane gradient slots of one (pixel, splat) pair, summed over the tile:
 //   0, 1    P'_i = h v_i                  with h = G dL/dG (G the Gaussian)
-//   2..4    Q'_11, Q'_12, Q'_22 = h v_1 v_1, h v_1 v_2, h v_2 v_2
-//   5, 6    dL/dA_n, dL/dA_p (A = kappa |o|)
-//   7..9    dL/d colour
-//   10      S = h
+//   2, 3    Q'_11, Q'_22 = h v_1 v_1, h v_2 v_2
+//   4       Q'_12 = h v_1 v_2
+//   5       S = h
+//   6, 7    dL/dA_n, dL/dA_p (A = kappa |o|)
+//   8..10   dL/d colour
 //   11      dL/dt through alpha (only when the caller asks for dL/dt)
 // Here v = u - c is the pixel's position on the conic's scaled eigen-axes
 // relative to the tile's centre (c, formed in FP64 at staging): v is the
@@ -476,6 +475,7 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
     const float lxt = (float)(px - ox) - 0.5f * (TW - 1), lyt = (float)(py - oy) - 0.5f * (TH - 1);
     const uint2 rg = ranges[tile];
     const int slot = row_slot(lane);
+    const bool b3 = (lane & 8) != 0;  // which value of each pair this lane keeps in the first halving
 
     float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
     uint32_t last = 0;
@@ -488,6 +488,8 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
         g1 = V.dL[3 * p + 1];
         g2 = V.dL[3 * p + 2];
     }
+    // the colour cotangents as the first halving takes them (pairs (0, 1), (2, -))
+    const float ga = b3 ? g1 : g0, gb = b3 ? g0 : g1, g2a = b3 ? 0.0f : g2, g2b = b3 ? g2 : 0.0f;
     if (threadIdx.x == 0) s_max = 0;
     __syncthreads();
     // the quarter's last contributor (rows of 16 lanes), then the tile's
@@ -556,22 +558,26 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
             const int lk = lim - 32 * k;  // entries 32 k + i, i < lk, come before the last contributor
             m &= lk >= 32 ? ~0u : (lk <= 0 ? 0u : ~((1u << (32 - lk)) - 1u));
             for (;;) {
+                // lane masks straight from the compares (no per-lane booleans
+                // carried across the branches)
+                const uint64_t hm = __ballot(m != 0u);
+                if (hm == 0ull) break;
                 const bool has = m != 0u;
-                if (__ballot(has) == 0ull) break;
-                const int j = 32 * k + 31 - (has ? __builtin_ctz(m) : 0);
+                const int j = 32 * k + 31 - __builtin_ctz(m | 0x80000000u);  // entry 32 k when nothing is left
                 m &= m - 1u;
-                const bool in_range = has && base + (uint32_t)j < last;
+                const uint64_t rm = __ballot(base + (uint32_t)j < last);
                 const float4 Wv = s_w[j], Ov = s_o[j];
                 const float2 U = s_u[w][j];
+                const uint64_t tm = __ballot(Ov.z > 0.0f);
                 const bool interp = Ov.z > 0.0f;
                 AlphaEval e;
                 eval_alpha(Wv, Ov, U, lx, ly, interp, e);
-                const bool contrib = in_range && e.alpha >= kAlphaMin;
-                const uint64_t live = __ballot(in_range);
-                const uint64_t cm = __ballot(contrib);
-                n_eval += (uint32_t)__popcll(live);
-                n_eval_t += (uint32_t)__popcll(__ballot(in_range && interp));
+                const uint64_t irm = hm & rm;
+                const uint64_t cm = irm & __ballot(e.alpha >= kAlphaMin);
+                n_eval += (uint32_t)__popcll(irm);
+                n_eval_t += (uint32_t)__popcll(irm & tm);
                 if (cm == 0ull) continue;
+                const bool contrib = has && base + (uint32_t)j < last && e.alpha >= kAlphaMin;
                 n_con += (uint32_t)__popcll(cm);
                 // every lane runs the update; a non-contributing lane has a = 0 and
                 // dL/dalpha = 0, which leaves T and R as they are and all slots 0
@@ -581,34 +587,43 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
                 const float dal_raw = T * ((Cc.x - R0) * g0 + (Cc.y - R1) * g1 + (Cc.z - R2) * g2);
                 const float dal = contrib ? dal_raw : 0.0f;
                 const float aT = a * T;
-                float v[12];
-                v[7] = aT * g0;
-                v[8] = aT * g1;
-                v[9] = aT * g2;
-                R0 = a * Cc.x + (1.0f - a) * R0;
-                R1 = a * Cc.y + (1.0f - a) * R1;
-                R2 = a * Cc.z + (1.0f - a) * R2;
-                float dan = dal, dap = 0.0f;
-                v[11] = 0.0f;
+                R0 = fmaf(a, Cc.x - R0, R0);
+                R1 = fmaf(a, Cc.y - R1, R1);
+                R2 = fmaf(a, Cc.z - R2, R2);
+                float dan = dal, dap = 0.0f, dtv = 0.0f;
                 if (interp) {
                     dan = (1.0f - Ov.z) * dal;
                     const float dapr = Ov.z * dal;
-                    if constexpr (DT) v[11] = (e.apr - e.an) * dal;
+                    if constexpr (DT) dtv = (e.apr - e.an) * dal;
                     // d apr / d a_p = (1/K) (1 - a_p)^(1/K - 1) = (1/K) q / (1 - a_p)
                     dap = dapr * Ov.w * (e.q * __builtin_amdgcn_rcpf(1.0f - e.ap));
                 }
                 const float dan_c = e.cn ? 0.0f : dan, dap_c = e.cp ? 0.0f : dap;
-                v[5] = dan_c * e.G;
-                v[6] = dap_c * e.G;
                 const float h = e.G * (dan_c * Ov.x + dap_c * Ov.y);  // G dL/dG
                 const float v1 = fmaf(lyt, Wv.y, lxt * Wv.x), v2 = fmaf(lyt, Wv.w, lxt * Wv.z);
-                v[10] = h;
-                v[0] = h * v1;
-                v[1] = h * v2;
-                v[2] = v[0] * v1;
-                v[3] = v[0] * v2;
-                v[4] = v[1] * v2;
-                const float tot = row_reduce12<DT>(v, lane);
+                // the six pairs of the slots, as the first halving takes them
+                const float pa = b3 ? v2 : v1, pb = b3 ? v1 : v2;
+                const float ha = h * pa, hb = h * pb, hab = ha * pb;
+                float S1[6], S2[6];
+                S1[0] = ha;                      // P'_1, P'_2
+                S2[0] = hb;
+                S1[1] = ha * pa;                 // Q'_11, Q'_22
+                S2[1] = hb * pb;
+                S1[2] = b3 ? h : hab;            // Q'_12, S
+                S2[2] = b3 ? hab : h;
+                S1[3] = e.G * (b3 ? dap_c : dan_c);  // dL/dA_n, dL/dA_p
+                S2[3] = e.G * (b3 ? dan_c : dap_c);
+                S1[4] = aT * ga;                 // colour 0, 1
+                S2[4] = aT * gb;
+                if constexpr (DT) {              // colour 2, dL/dt
+                    const float c2 = aT * g2;
+                    S1[5] = b3 ? dtv : c2;
+                    S2[5] = b3 ? c2 : dtv;
+                } else {
+                    S1[5] = aT * g2a;
+                    S2[5] = aT * g2b;
+                }
+                const float tot = row_reduce12(S1, S2, lane);
                 if (has && slot >= 0 && tot != 0.0f) unsafeAtomicAdd(&s_g[j][slot], (double)tot);
             }
         }
@@ -620,8 +635,8 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
             const double *g = s_g[j];
             // moments about the splat's centre from those about the tile's
             const double2 cr = s_ref[j];
-            const double S = g[10];
-            const double P1 = g[0], P2 = g[1], Q11 = g[2], Q12 = g[3], Q22 = g[4];
+            const double S = g[5];
+            const double P1 = g[0], P2 = g[1], Q11 = g[2], Q22 = g[3], Q12 = g[4];
             const double P[2] = {P1 + cr.x * S, P2 + cr.y * S};
             const double Q[3] = {Q11 + 2.0 * cr.x * P1 + cr.x * cr.x * S,
                                  Q12 + cr.x * P2 + cr.y * P1 + cr.x * cr.y * S,
@@ -632,8 +647,7 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
 #pragma unroll
             for (int k = 0; k < 5; ++k) d[k] = sc[k];
 #pragma unroll
-            for (int k = 5; k < 10; ++k) d[k] = g[k];
-            d[10] = g[11];
+            for (int k = 5; k < 11; ++k) d[k] = g[k + 1];
         }
         __syncthreads();
         for (int idx = threadIdx.x; idx < cnt * 11; idx += NT) {
