@@ -148,8 +148,7 @@ def optimize_steps(r, h, P, grads, imgs, dL, workload: str, steps: int) -> dict:
     same = all((v.width, v.height) == (o.shape[1], o.shape[0]) for v, o in zip(batches[0], imgs))
     out = imgs if same else [torch.empty((v.height, v.width, 3), device=imgs[0].device) for v in batches[0]]
     cot = dL if same else [torch.randn(o.shape, device=o.device) for o in out]
-    M = {k: torch.zeros_like(t) for k, t in P.items()}
-    V = {k: torch.zeros_like(t) for k, t in P.items()}
+    M, V = r.adam_moments(P)  # one row per interior node
     for g in grads.values():
         g.zero_()
     n_step = 0
@@ -266,8 +265,7 @@ def converge(r, h, views, steps: int) -> dict:
         P["mean"] += noise(P["mean"]) * interior[:, None]
         P["scale"] *= torch.exp(noise(P["scale"]) * interior[:, None])
         P["sh"] += noise(P["sh"]) * interior[:, None]
-    M = {k: torch.zeros_like(t) for k, t in P.items()}
-    V = {k: torch.zeros_like(t) for k, t in P.items()}
+    M, V = r.adam_moments(P)
     grads = {k: torch.zeros_like(t) for k, t in P.items()}
     n_val = sum(t.numel() for t in tgt)
     losses = []

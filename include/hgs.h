@@ -342,14 +342,19 @@ hgs_status hgs_stream_info(hgs_ctx *ctx, hgs_stream_stats *out);
  *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
  *   p -= lr * (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps),
  * and g = 0 afterwards (the next hgs_render_backward accumulates a fresh
- * gradient).  All arrays are device pointers in the parameter layouts of the
- * header (node-major; index 0..4 = mean, scale, rot, opacity, sh), N nodes
- * each; m and v must be zero before step 1.  Leaf entries of every array are
- * left untouched.  Queued on the ctx stream; does not synchronise.  When
- * the step updates the parameters the renderer reads (the bound arrays),
- * the next hgs_render_backward needs a new hgs_render (HGS_ERR_STATE).
+ * gradient).  All arrays are device pointers; index 0..4 = mean, scale,
+ * rot, opacity, sh.  param and grad are in the parameter layouts of the
+ * header (node-major, N nodes each; leaf entries are left untouched); m and
+ * v hold the interior nodes only, node-major by interior rank (row q
+ * belongs to the q-th interior node in ascending id order, as hgs_interior
+ * lists them: n_interior x 3, 3, 4, 1, 48 floats), and must be zero before
+ * step 1.  The arrays of rot and sh must be 16-byte aligned.  Queued on the
+ * ctx stream; does not synchronise.  When the step updates the parameters
+ * the renderer reads (the bound arrays), the next hgs_render_backward needs
+ * a new hgs_render (HGS_ERR_STATE).
  * Errors: HGS_ERR_STATE without a hierarchy, HGS_ERR_INVALID_ARG for a NULL
- * array, step < 1, or a non-finite / out-of-range hyper-parameter. */
+ * or misaligned array, step < 1, or a non-finite / out-of-range
+ * hyper-parameter. */
 typedef struct {
     float *param[5];
     float *grad[5];
@@ -360,6 +365,15 @@ typedef struct {
     int64_t step; /* 1-based, for the bias correction */
 } hgs_adam;
 hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a);
+
+/* The interior nodes (those with children: the ones the optimisation of
+ * Sec. 5.1 updates) of the uploaded or built hierarchy, in ascending id
+ * order: the row order of the optimiser moments of hgs_adam_step.  *count
+ * receives their number; when ids (a device pointer, the caller's) is not
+ * NULL, the first min(cap, count) ids are copied into it, queued on the ctx
+ * stream.  Errors: HGS_ERR_STATE without a hierarchy, HGS_ERR_INVALID_ARG
+ * for a NULL count or a negative cap. */
+hgs_status hgs_interior(hgs_ctx *ctx, int32_t *ids, int64_t cap, int64_t *count);
 
 /* Tuning knobs of the blend stage and its backward (chosen by the
  * autotuner): tile edge tile_w x tile_h in {8x8, 16x8, 16x16, 32x16},

@@ -122,7 +122,7 @@ struct hgs_ctx {
     uint32_t *n_last = nullptr, *n_blend = nullptr;
     double *sgrad = nullptr;     // [visible rank][12] screen-space gradients
     uint32_t *vis_rank = nullptr;  // per cut entry: its visible rank (visible entries only)
-    float *pgrad = nullptr;  // per cut entry, 32 floats
+    float *pgrad = nullptr;  // per cut entry, kPGradFloats floats
     float *cjac = nullptr;   // per cut entry, 12 floats: d colour / d dir, parent - node colour
 
     // state of the last render
@@ -437,7 +437,7 @@ hgs_status ensure_cut_cap(hgs_ctx *ctx, uint32_t cap)
     if ((s = realloc_buf(ctx, ctx->pair_offsets, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->sgrad, (size_t)cap * 12))) return s;
     if ((s = realloc_buf(ctx, ctx->vis_rank, (size_t)cap))) return s;
-    if ((s = realloc_buf(ctx, ctx->pgrad, (size_t)cap * 32))) return s;
+    if ((s = realloc_buf(ctx, ctx->pgrad, (size_t)cap * kPGradFloats))) return s;
     if ((s = realloc_buf(ctx, ctx->cjac, (size_t)cap * 12))) return s;
     ctx->cut_cap = cap;
     const size_t scratch = std::max<size_t>(ctx->cut_cap, ctx->pair_cap);
@@ -774,6 +774,13 @@ hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a)
             return fail(ctx, HGS_ERR_INVALID_ARG, "NULL array of parameter group " + std::to_string(k));
         if (!std::isfinite(a->lr[k]) || a->lr[k] < 0.0f)
             return fail(ctx, HGS_ERR_INVALID_ARG, "bad learning rate of parameter group " + std::to_string(k));
+        // rotation and SH rows are stepped in 16-byte vectors
+        const void *arrs[4] = {a->param[k], a->grad[k], a->m[k], a->v[k]};
+        if (k == 2 || k == 4)
+            for (const void *q : arrs)
+                if (reinterpret_cast<uintptr_t>(q) % 16 != 0)
+                    return fail(ctx, HGS_ERR_INVALID_ARG, "array of parameter group " + std::to_string(k) +
+                                                              " not 16-byte aligned");
     }
     if (a->step < 1 || !(a->beta1 >= 0.0f && a->beta1 < 1.0f) || !(a->beta2 >= 0.0f && a->beta2 < 1.0f) ||
         !(a->eps > 0.0f) || !std::isfinite(a->eps))
@@ -789,6 +796,20 @@ hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a)
         launch_adam(k, ctx->interior, ctx->n_interior, a->param[k], a->grad[k], a->m[k], a->v[k], sc, ctx->stream);
     }
     HIPC(hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_interior(hgs_ctx *ctx, int32_t *ids, int64_t cap, int64_t *count)
+{
+    if (!ctx || !count) return HGS_ERR_INVALID_ARG;
+    if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy uploaded");
+    if (cap < 0) return fail(ctx, HGS_ERR_INVALID_ARG, "negative capacity");
+    *count = ctx->n_interior;
+    if (ids && cap > 0 && ctx->n_interior > 0) {
+        HIPC(hipSetDevice(ctx->device));
+        const size_t n = (size_t)std::min<int64_t>(cap, ctx->n_interior);
+        HIPC(hipMemcpyAsync(ids, ctx->interior, 4 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    }
     return HGS_OK;
 }
 

@@ -281,6 +281,10 @@ void launch_unpack_nodes(const uint32_t *pinfo, const float *box, int64_t N, int
 // over n_pix pixels of all views: dL/dC written to views[v].dL, the mean
 // absolute difference to *loss (device), summed over at most kL1Blocks
 // per-block partials (partial: workspace of that many doubles).
+// Floats per cut entry of the attribute-gradient rows between the
+// preprocess backward and the gradient gather.
+constexpr int kPGradFloats = 20;
+
 constexpr int kL1Blocks = 1024;
 void launch_l1(const DevView *views, int nv, uint32_t n_pix, double *partial, double *loss, hipStream_t st);
 

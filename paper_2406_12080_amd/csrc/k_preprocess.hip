@@ -15,8 +15,10 @@ constexpr int kT = 256;
 constexpr double kAlphaMinD = 1.0 / 255.0;
 // per cut entry, gradient w.r.t. the interpolated attributes: mean 0..2,
 // scale 3..5, raw quaternion 6..9, node opacity 10, parent opacity 11,
-// colour cotangent 12..14, SH basis 15..30, live flag 31
-constexpr int kPG = 32;
+// colour cotangent 12..14, view direction 15..17 (the SH basis follows from
+// it in the gather, as the forward evaluated it), 18 unused, live flag 19
+constexpr int kPG = kPGradFloats;
+static_assert(kPG == 20, "row layout");
 
 __device__ __forceinline__ int view_of(const uint32_t *cut_base, int nv, uint32_t k)
 {
@@ -397,7 +399,7 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
     const uint32_t k = blockIdx.x * kT + threadIdx.x;
     if (k >= total) return;
     float *out = pg + (size_t)k * kPG;
-    float row[kPG];  // the entry's attribute gradient, stored as eight float4
+    float row[kPG];  // the entry's attribute gradient, stored as five float4
     if (ntiles[k] == 0) {
         if (g_dt) g_dt[k] = 0.0f;
         return;
@@ -436,12 +438,10 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
         ddir[2] += gr[c] * (double)cj[3 * c + 2];
         if (use_par) dt += gr[c] * (double)cj[9 + c];
     }
-    {
-        float Y[16];  // stored in FP32, evaluated in FP32
-        sh_eval_f((float)P.dir[0], (float)P.dir[1], (float)P.dir[2], Y);
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) row[15 + kk] = Y[kk];
-    }
+    row[15] = (float)P.dir[0];
+    row[16] = (float)P.dir[1];
+    row[17] = (float)P.dir[2];
+    row[18] = 0.0f;
     row[12] = (float)gr[0];
     row[13] = (float)gr[1];
     row[14] = (float)gr[2];
@@ -622,20 +622,21 @@ __global__ __launch_bounds__(kT, 4) void k_grad_gather(DevHier h, int nv, const 
         const float t = (float)cut_t[pos];
         if (nt == 0 || (op == 11 && !(t > 0.0f))) return;
         const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pos * kPG);
-        const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4], r5 = g4[5], r6 = g4[6], r7 = g4[7];
-        if (r7.w == 0.0f) return;  // no live splat
+        const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4];
+        if (r4.w == 0.0f) return;  // no live splat
         const float w = op == 10 ? 1.0f - t : t;
-        const float g[31] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z,
-                             r2.w, r3.x, r3.y, r3.z, r3.w, r4.x, r4.y, r4.z, r4.w, r5.x, r5.y,
-                             r5.z, r5.w, r6.x, r6.y, r6.z, r6.w, r7.x, r7.y, r7.z};
+        const float g[15] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                             r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z};
 #pragma unroll
         for (int m = 0; m < 10; ++m) a[m] += w * g[m];
         a[10] += op == 10 ? g[10] : g[11];
+        float Y[16];  // the SH basis of the entry's direction, in FP32 as the forward evaluated it
+        sh_eval_f(r3.w, r4.x, r4.y, Y);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float wc = w * g[12 + c];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) ash[3 * k + c] += wc * g[15 + k];
+            for (int k = 0; k < 16; ++k) ash[3 * k + c] += wc * Y[k];
         }
         any = true;
     };

@@ -21,7 +21,7 @@ _NAMES = {0: "HGS_OK", 1: "HGS_ERR_INVALID_ARG", 2: "HGS_ERR_OOM", 3: "HGS_ERR_H
 EXPORTS = ("hgs_create", "hgs_destroy", "hgs_last_error", "hgs_set_stream", "hgs_upload", "hgs_bind_params",
            "hgs_build", "hgs_download", "hgs_cut", "hgs_cut_noalloc", "hgs_compact_mark", "hgs_compact_rebuild", "hgs_render", "hgs_last_render",
            "hgs_render_backward", "hgs_l1_loss", "hgs_stream_begin", "hgs_stream_end", "hgs_stream_cleanup",
-           "hgs_stream_info", "hgs_adam_step", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
+           "hgs_stream_info", "hgs_adam_step", "hgs_interior", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
            "hgs_kernel_time", "hgs_counters")
 COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t", "bwd_evaluated",
                  "bwd_evaluated_t", "bwd_contrib")
@@ -125,6 +125,7 @@ def lib():
         L.hgs_stream_info.argtypes = [vp, P(StreamStats)]
         L.hgs_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.hgs_get_buffer.argtypes = [vp, ctypes.c_int32, P(vp), P(ctypes.c_int64)]
+        L.hgs_interior.argtypes = [vp, vp, ctypes.c_int64, P(ctypes.c_int64)]
         L.hgs_set_profiling.argtypes = [vp, ctypes.c_int32]
         L.hgs_counters.argtypes = [vp, P(ctypes.c_int64), ctypes.c_int32]
         L.hgs_kernel_time.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -445,10 +446,39 @@ class Renderer:
         self._check(self.L.hgs_stream_info(self.h, ctypes.byref(st)))
         return {k: int(getattr(st, k)) for k, _ in StreamStats._fields_}
 
+    def n_interior(self) -> int:
+        """Number of interior nodes of the current hierarchy (``hgs_interior``)."""
+        n = ctypes.c_int64()
+        self._check(self.L.hgs_interior(self.h, None, 0, ctypes.byref(n)))
+        return int(n.value)
+
+    def interior_ids(self):
+        """The interior node ids in ascending order (int32 CUDA tensor): the
+        row order of the optimiser moments."""
+        torch = self.torch
+        n = self.n_interior()
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)[:n]
+        cnt = ctypes.c_int64()
+        self._check(self.L.hgs_interior(self.h, ctypes.c_void_p(out.data_ptr()), n, ctypes.byref(cnt)))
+        return out
+
+    def adam_moments(self, params: dict) -> tuple:
+        """Zeroed first and second moments for ``adam_step``: per parameter
+        group an [n_interior, components] float32 CUDA tensor."""
+        torch = self.torch
+        n = self.n_interior()
+        m, v = {}, {}
+        for k, t in params.items():
+            comp = t.numel() // max(t.shape[0], 1) if t.dim() > 1 else 1
+            m[k] = torch.zeros((n, comp), dtype=torch.float32, device=t.device)
+            v[k] = torch.zeros((n, comp), dtype=torch.float32, device=t.device)
+        return m, v
+
     def adam_step(self, params: dict, grads: dict, m: dict, v: dict, lr, step: int, beta1: float = 0.9,
                   beta2: float = 0.999, eps: float = 1e-15) -> None:
         """One optimiser step on the interior nodes (``hgs_adam_step``); all
-        dicts hold CUDA tensors keyed like the parameters; ``lr`` is one
+        dicts hold CUDA tensors keyed like the parameters, ``m`` and ``v``
+        with one row per interior node (``adam_moments``); ``lr`` is one
         float or a dict per parameter group.  Zeroes ``grads``."""
         a = Adam()
         for k, name in enumerate(PARAM_FIELDS):

@@ -67,8 +67,7 @@ class HierarchyOptimizer:
         self.batch = int(batch)
         self.beta1, self.beta2, self.eps = beta1, beta2, eps
         self.rng = np.random.default_rng(seed)
-        self.m = {k: torch.zeros_like(t) for k, t in params.items()}
-        self.v = {k: torch.zeros_like(t) for k, t in params.items()}
+        self.m, self.v = renderer.adam_moments(params)  # one row per interior node
         self.grads = {k: torch.zeros_like(t) for k, t in params.items()}
         self.t = 0  # Adam's step count
         self._imgs = {}

@@ -420,8 +420,9 @@ def test_adam_step_matches_oracle(hgs_mod, c1):
     N = c1.n_nodes
     inner = np.asarray(c1.child_count) > 0
     gen = np.random.default_rng(21)
-    M = {k: torch.zeros_like(t) for k, t in P.items()}
-    V = {k: torch.zeros_like(t) for k, t in P.items()}
+    M, V = r.adam_moments(P)  # rows by interior rank
+    ids = r.interior_ids().cpu().numpy()
+    assert np.array_equal(ids, np.nonzero(inner)[0]) and r.n_interior() == int(inner.sum())
     oP = {k: t.cpu().numpy().astype(np.float64).reshape(N, -1) for k, t in P.items()}
     oM = {k: np.zeros_like(a) for k, a in oP.items()}
     oV = {k: np.zeros_like(a) for k, a in oP.items()}
@@ -439,8 +440,8 @@ def test_adam_step_matches_oracle(hgs_mod, c1):
         for k in P:
             gp = P[k].cpu().numpy().astype(np.float64).reshape(N, -1)
             assert np.allclose(gp, oP[k], rtol=1e-6, atol=1e-6), (step, k, np.abs(gp - oP[k]).max())
-            assert np.allclose(M[k].cpu().numpy().reshape(N, -1), oM[k], rtol=1e-5, atol=1e-7), (step, k)
-            assert np.allclose(V[k].cpu().numpy().reshape(N, -1), oV[k], rtol=1e-5, atol=1e-9), (step, k)
+            assert np.allclose(M[k].cpu().numpy(), oM[k][ids], rtol=1e-5, atol=1e-7), (step, k)
+            assert np.allclose(V[k].cpu().numpy(), oV[k][ids], rtol=1e-5, atol=1e-9), (step, k)
             gg = G[k].cpu().numpy().reshape(N, -1)
             assert np.all(gg[inner] == 0.0) and np.array_equal(gg[~inner], g[k].reshape(N, -1)[~inner]), (step, k)
             # leaves never move
@@ -448,6 +449,12 @@ def test_adam_step_matches_oracle(hgs_mod, c1):
             assert np.array_equal(gp[~inner], ref[~inner]), (step, k)
     with pytest.raises(H.HgsError) as e:
         r.adam_step(P, G, M, V, lr, 0)
+    assert e.value.status == H.ERR_INVALID_ARG
+    # rotation and SH arrays are stepped in 16-byte vectors: a misaligned one is refused
+    Vbad = dict(V)
+    Vbad["sh"] = torch.zeros(V["sh"].numel() + 1, device="cuda")[1:].view_as(V["sh"])
+    with pytest.raises(H.HgsError) as e:
+        r.adam_step(P, G, M, Vbad, lr, 4, b1, b2, eps)
     assert e.value.status == H.ERR_INVALID_ARG
     # stepping the bound parameters makes the last render stale for backward
     r.bind(*[P[k] for k in H.PARAM_FIELDS])
