@@ -107,6 +107,7 @@ struct hgs_ctx {
     uint32_t *vis_counts = nullptr, *vis_offsets = nullptr;
     uint32_t *skeys = nullptr, *svals = nullptr, *pair_offsets = nullptr;
     uint32_t *pkeys = nullptr, *pvals = nullptr;
+    uint8_t *qbits = nullptr;  // forward quarter records, kMaxBlocks planes of pair_cap bytes
     uint32_t *dup_first = nullptr;  // first splat of every pair-emission block
     uint32_t *k2 = nullptr, *v2 = nullptr;
     uint32_t *hist = nullptr, *hist_scan = nullptr, *partial = nullptr, *scan_total = nullptr;
@@ -453,6 +454,7 @@ hgs_status ensure_pair_cap(hgs_ctx *ctx, uint32_t cap)
     hgs_status s;
     if ((s = realloc_buf(ctx, ctx->pkeys, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->pvals, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->qbits, (size_t)cap * kMaxBlocks))) return s;
     if ((s = realloc_buf(ctx, ctx->dup_first, (size_t)duplicate_blocks(cap) + 1))) return s;
     ctx->pair_cap = cap;
     const size_t scratch = std::max<size_t>(ctx->cut_cap, ctx->pair_cap);
@@ -474,9 +476,9 @@ int bits_for(uint32_t n)
 void enqueue_blend(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st)
 {
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
-    launch_blend(ctx->views_dev, nv, n_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs, ctx->axes, ctx->T_final, ctx->n_last,
-                 ctx->n_blend, ctx->wstats, ctx->ctr, ctx->tile_w, ctx->tile_h, ctx->batch, ctx->persist, ctx->queue,
-                 st);
+    launch_blend(ctx->views_dev, nv, n_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs, ctx->axes, ctx->T_final,
+                 ctx->n_last, ctx->n_blend, ctx->qbits, ctx->pair_cap, ctx->wstats, ctx->ctr, ctx->tile_w,
+                 ctx->tile_h, ctx->batch, ctx->persist, ctx->queue, st);
 }
 
 void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hipEvent_t *ev, bool with_blend)
@@ -605,9 +607,9 @@ void enqueue_backward(hgs_ctx *ctx, int nv, const hgs_grads *out, hipStream_t st
     {
         KernelTimer kt(ctx, 1, st);
         launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs,
-                              ctx->axes, ctx->T_final, ctx->n_last, ctx->vis_rank, ctx->sgrad, ctx->wstats, ctx->ctr,
-                              ctx->r_tw, ctx->r_th, ctx->r_batch, out->dt != nullptr, ctx->r_persist, ctx->queue + 1,
-                              st);
+                              ctx->axes, ctx->T_final, ctx->n_last, ctx->qbits, ctx->pair_cap, ctx->vis_rank,
+                              ctx->sgrad, ctx->wstats, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch,
+                              out->dt != nullptr, ctx->r_persist, ctx->queue + 1, st);
     }
     const DevHier h = dev_hier(ctx);
     {

@@ -220,11 +220,18 @@ void blend_prepare(int tw, int th, int batch);
 // persist: a grid of the chip's resident workgroups takes tile slots from
 // the device-side queue (*queue, cleared by the launch sequence first)
 // instead of one workgroup per tile.
+// Quarter records of the forward, read by the backward: byte b * qstride + p
+// (b < the tile's 8x8 blocks, at most kMaxBlocks; qstride >= the pair count)
+// holds, for the splat at position p of the sorted pair list and block b of
+// its tile, bit q set when some pixel of quarter q of the block blended it
+// or stopped at it (a superset of the blends; the backward's per-pixel test
+// of the last contributor drops the rest).
+constexpr int kMaxBlocks = 8;
 void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *tile_order, const uint2 *ranges,
                   const uint32_t *pair_vals,
                   const SplatRec *recs, const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend,
-                  uint4 *wstats, Counters *ctr, int tw, int th, int batch, bool persist, uint32_t *queue,
-                  hipStream_t st);
+                  uint8_t *qbits, uint32_t qstride, uint4 *wstats, Counters *ctr, int tw, int th, int batch,
+                  bool persist, uint32_t *queue, hipStream_t st);
 
 // ---------------------------------------------------- hierarchy generation
 // Node arrays of the tree under construction (breadth-first ids).
@@ -292,7 +299,8 @@ void launch_l1(const DevView *views, int nv, uint32_t n_pix, double *partial, do
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *tile_order,
                            const uint2 *ranges,
                            const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
-                           const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
+                           const uint32_t *n_last, const uint8_t *qbits, uint32_t qstride, const uint32_t *vis_rank,
+                           double *sgrad, uint4 *wstats,
                            Counters *ctr, int tw, int th, int batch, bool want_dt, bool persist, uint32_t *queue,
                            hipStream_t st);
 void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32_t vis_cap, hipStream_t st);

@@ -181,14 +181,37 @@ __device__ __forceinline__ uint32_t next_run(uint32_t *queue, uint32_t chunk, ui
     return slot;
 }
 
+// Stores the quarter records of one 32-entry word of the batch: `cw` holds,
+// per lane, the entries of the word the lane's pixel blended (or stopped
+// at); OR over each
+// row of 16 lanes (DPP partners l ^ 8, l ^ 7, l ^ 2, l ^ 1) gives the
+// quarter's entries, and lane i writes the byte of entry i (bit q: quarter q
+// blended it) for the n entries of the word, at qbits[p0 + i] (the wave's
+// block's plane of the records).  All lanes take part.
+__device__ __forceinline__ void record_word(uint8_t *__restrict__ qbits, uint32_t cw, uint32_t p0, int n,
+                                            int lane)
+{
+    cw |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)cw, 0x128, 0xF, 0xF, true);
+    cw |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)cw, 0x141, 0xF, 0xF, true);
+    cw |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)cw, 0x4E, 0xF, 0xF, true);
+    cw |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)cw, 0xB1, 0xF, 0xF, true);
+    const uint32_t r0 = __builtin_amdgcn_readlane(cw, 0), r1 = __builtin_amdgcn_readlane(cw, 16);
+    const uint32_t r2 = __builtin_amdgcn_readlane(cw, 32), r3 = __builtin_amdgcn_readlane(cw, 48);
+    if (lane < n) {
+        const uint32_t b = ((r0 >> lane) & 1u) | (((r1 >> lane) & 1u) << 1) | (((r2 >> lane) & 1u) << 2) |
+                           (((r3 >> lane) & 1u) << 3);
+        qbits[p0 + (uint32_t)lane] = (uint8_t)b;
+    }
+}
+
 template <int TW, int TH, int BATCH>
 __device__ __forceinline__ void blend_tile(const DevView *__restrict__ views, int nv,
                                            const uint32_t *__restrict__ tile_order,
                                            const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_vals,
                                            const SplatRec *__restrict__ recs, const double4 *__restrict__ axes,
                                            float *__restrict__ T_final, uint32_t *__restrict__ n_last,
-                                           uint32_t *__restrict__ n_blend, uint4 *__restrict__ wstats,
-                                           uint32_t slot)
+                                           uint32_t *__restrict__ n_blend, uint8_t *__restrict__ qbits,
+                                           uint32_t qstride, uint4 *__restrict__ wstats, uint32_t slot)
 {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;
@@ -274,18 +297,21 @@ __device__ __forceinline__ void blend_tile(const DevView *__restrict__ views, in
         // its pixels are all finished; the four quarters of a wave step together
         for (int k = 0; 32 * k < cnt; ++k) {
             uint32_t m = s_qm[w][q][k];
+            uint32_t cw = 0u;  // entries of this word the lane's pixel blended (or stopped at)
             for (;;) {
                 m = ((alive >> (lane & 48)) & 0xFFFFull) ? m : 0u;  // nothing left for a finished quarter
+                const uint64_t hm = __ballot(m != 0u);
+                if (hm == 0ull) break;
                 const bool has = m != 0u;
-                if (__ballot(has) == 0ull) break;
-                const int j = 32 * k + (has ? __builtin_ctz(m) : 0);
+                const int j = 32 * k + __builtin_ctz(m | 0x80000000u);  // entry 32 k + 31 when nothing is left
                 m &= m - 1u;
                 const bool go = has && T > 0.0f;
                 const float4 Ov = s_o[j];
                 const bool interp = Ov.z > 0.0f;
                 // work counts from the wave's masks (scalar unit only)
-                n_eval += (uint32_t)__popcll(__ballot(go));
-                n_eval_t += (uint32_t)__popcll(__ballot(go && interp));
+                const uint64_t gm = hm & alive;
+                n_eval += (uint32_t)__popcll(gm);
+                n_eval_t += (uint32_t)__popcll(gm & __ballot(Ov.z > 0.0f));
                 AlphaEval e;
                 eval_alpha(s_w[j], Ov, s_u[w][j], lx, ly, interp, e);
                 if (go && e.alpha >= kAlphaMin) {
@@ -298,10 +324,15 @@ __device__ __forceinline__ void blend_tile(const DevView *__restrict__ views, in
                     C2 += Cc.z * wgt;
                     nb += stop ? 0u : 1u;
                     last = stop ? last : jb + (uint32_t)j;
+                    cw |= 1u << (j & 31);  // the splat a pixel stops at too: the backward's range test drops it
                     T = stop ? -T : Tn;
                 }
                 alive = __ballot(T > 0.0f);
             }
+            // the backward takes, per quarter, only the entries it blended here
+            // (entries after the last word walked lie after every pixel's last
+            // contributor, where the backward never looks)
+            record_word(qbits + (size_t)w * qstride, cw, b0 + 32u * (uint32_t)k, min(32, cnt - 32 * k), lane);
             if (alive == 0ull) break;
         }
     }
@@ -329,12 +360,13 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
                                                   const SplatRec *__restrict__ recs,
                                                   const double4 *__restrict__ axes, float *__restrict__ T_final,
                                                   uint32_t *__restrict__ n_last, uint32_t *__restrict__ n_blend,
+                                                  uint8_t *__restrict__ qbits, uint32_t qstride,
                                                   uint4 *__restrict__ wstats, uint32_t n_tiles,
                                                   uint32_t *__restrict__ queue, uint32_t chunk)
 {
     if constexpr (!PERSIST) {
         blend_tile<TW, TH, BATCH>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last, n_blend,
-                                  wstats, blockIdx.x);
+                                  qbits, qstride, wstats, blockIdx.x);
     } else {
         __shared__ uint32_t s_slot;
         for (;;) {
@@ -343,7 +375,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend(const DevView *__restrict__ vi
             const uint32_t last = min(n_tiles, first + chunk);
             for (uint32_t slot = first; slot < last; ++slot) {
                 blend_tile<TW, TH, BATCH>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last,
-                                          n_blend, wstats, slot);
+                                          n_blend, qbits, qstride, wstats, slot);
                 __syncthreads();  // LDS of this tile read by every wave before the next stages
             }
         }
@@ -441,6 +473,7 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
                                                const SplatRec *__restrict__ recs, const double4 *__restrict__ axes,
                                                const float *__restrict__ T_final,
                                                const uint32_t *__restrict__ n_last,
+                                               const uint8_t *__restrict__ qbits, uint32_t qstride,
                                                const uint32_t *__restrict__ vis_rank, double *__restrict__ sgrad,
                                                uint4 *__restrict__ wstats, uint32_t tslot)
 {
@@ -515,15 +548,14 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
                 const SplatRec r = recs[sidx];
                 const double4 W64 = axes[sidx];
                 const float4 W = make_float4((float)W64.x, (float)W64.y, (float)W64.z, (float)W64.w);
-                float2 u[8];
 #pragma unroll
                 for (int bk = 0; bk < NB; ++bk) {
                     float c1, c2, d0, d1;
                     block_offsets(r, W64, ox + (bk % SX) * 8, oy + (bk / SX) * 8, c1, c2, d0, d1);
-                    u[bk] = make_float2(c1, c2);
-                    s_u[bk][j] = u[bk];
+                    s_u[bk][j] = make_float2(c1, c2);
+                    // the quarters of this block that blended the splat in the forward
+                    live |= (uint32_t)qbits[(size_t)bk * qstride + lo + (uint32_t)j] << (4 * bk);
                 }
-                live = quarter_live<NB>(W, u, r.t > 0.0f ? fmaxf(r.An, r.Ap) : r.An);
                 s_id[j] = vis_rank[sidx];  // gradient row
                 s_w[j] = W;
                 s_o[j] = make_float4(r.An, r.Ap, r.t, r.invK);
@@ -549,8 +581,9 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
             }
         }
         __syncthreads();
-        // each quarter walks, back to front, the entries it may take that lie
-        // before its last contributor; the four quarters of a wave step together
+        // each quarter walks, back to front, the entries some pixel of it blended
+        // in the forward (those before its last contributor: later records are
+        // not written); the four quarters of a wave step together
         const uint32_t base = lo - rg.x;  // list position of entry 0
         const int lim = qm > base ? (int)min(qm - base, (uint32_t)cnt) : 0;
         for (int k = (cnt - 1) >> 5; k >= 0; --k) {
@@ -669,6 +702,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                                                       const double4 *__restrict__ axes,
                                                       const float *__restrict__ T_final,
                                                       const uint32_t *__restrict__ n_last,
+                                                      const uint8_t *__restrict__ qbits, uint32_t qstride,
                                                       const uint32_t *__restrict__ vis_rank,
                                                       double *__restrict__ sgrad, uint4 *__restrict__ wstats,
                                                       uint32_t n_tiles, uint32_t *__restrict__ queue,
@@ -676,7 +710,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
 {
     if constexpr (!PERSIST) {
         blend_bwd_tile<TW, TH, BATCH, DT>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last,
-                                          vis_rank, sgrad, wstats, blockIdx.x);
+                                          qbits, qstride, vis_rank, sgrad, wstats, blockIdx.x);
     } else {
         __shared__ uint32_t s_slot;
         for (;;) {
@@ -685,7 +719,7 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
             const uint32_t last = min(n_tiles, first + chunk);
             for (uint32_t slot = first; slot < last; ++slot) {
                 blend_bwd_tile<TW, TH, BATCH, DT>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final,
-                                                  n_last, vis_rank, sgrad, wstats, slot);
+                                                  n_last, qbits, qstride, vis_rank, sgrad, wstats, slot);
                 __syncthreads();  // LDS of this tile read by every wave before the next stages
             }
         }
@@ -756,45 +790,46 @@ uint32_t queue_run(uint32_t n_tiles, uint32_t g)
 template <int TW, int TH, int BATCH>
 void launch_blend_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                     const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, float *T_final,
-                    uint32_t *n_last, uint32_t *n_blend, uint4 *wstats, bool persist, uint32_t *queue,
-                    hipStream_t st)
+                    uint32_t *n_last, uint32_t *n_blend, uint8_t *qbits, uint32_t qstride, uint4 *wstats,
+                    bool persist, uint32_t *queue, hipStream_t st)
 {
     if (persist) {
         auto k = k_blend<TW, TH, BATCH, true>;
         const uint32_t g = std::min(n_tiles, resident_grid(k, TW * TH));
         launch_fill_u32(queue, 0u, 1, st);
         hipLaunchKernelGGL(k, dim3(g), dim3(TW * TH), 0, st, views, nv, order, ranges, pair_vals, recs, axes,
-                           T_final, n_last, n_blend, wstats, n_tiles, queue, queue_run(n_tiles, g));
+                           T_final, n_last, n_blend, qbits, qstride, wstats, n_tiles, queue, queue_run(n_tiles, g));
     } else {
         hipLaunchKernelGGL((k_blend<TW, TH, BATCH, false>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order,
-                           ranges, pair_vals, recs, axes, T_final, n_last, n_blend, wstats, n_tiles, queue, 1u);
+                           ranges, pair_vals, recs, axes, T_final, n_last, n_blend, qbits, qstride, wstats, n_tiles,
+                           queue, 1u);
     }
 }
 
 template <int TW, int TH, int B, bool DT>
 void launch_blend_bwd_dt(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                          const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
-                         const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats, bool persist,
-                         uint32_t *queue, hipStream_t st)
+                         const uint32_t *n_last, const uint8_t *qbits, uint32_t qstride, const uint32_t *vis_rank,
+                         double *sgrad, uint4 *wstats, bool persist, uint32_t *queue, hipStream_t st)
 {
     if (persist) {
         auto k = k_blend_bwd<TW, TH, B, DT, true>;
         const uint32_t g = std::min(n_tiles, resident_grid(k, TW * TH));
         launch_fill_u32(queue, 0u, 1, st);
         hipLaunchKernelGGL(k, dim3(g), dim3(TW * TH), 0, st, views, nv, order, ranges, pair_vals, recs, axes, T_final,
-                           n_last, vis_rank, sgrad, wstats, n_tiles, queue, queue_run(n_tiles, g));
+                           n_last, qbits, qstride, vis_rank, sgrad, wstats, n_tiles, queue, queue_run(n_tiles, g));
     } else {
         hipLaunchKernelGGL((k_blend_bwd<TW, TH, B, DT, false>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order,
-                           ranges, pair_vals, recs, axes, T_final, n_last, vis_rank, sgrad, wstats, n_tiles, queue,
-                           1u);
+                           ranges, pair_vals, recs, axes, T_final, n_last, qbits, qstride, vis_rank, sgrad, wstats,
+                           n_tiles, queue, 1u);
     }
 }
 
 template <int TW, int TH, int BATCH>
 void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                         const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
-                        const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad, uint4 *wstats,
-                        bool want_dt, bool persist, uint32_t *queue, hipStream_t st)
+                        const uint32_t *n_last, const uint8_t *qbits, uint32_t qstride, const uint32_t *vis_rank,
+                        double *sgrad, uint4 *wstats, bool want_dt, bool persist, uint32_t *queue, hipStream_t st)
 {
     // the backward stages at most 32 splats per wave and step: its LDS holds
     // the FP32 partial sums and the FP64 flushed terms of every staged
@@ -803,10 +838,10 @@ void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const ui
     constexpr int B = BATCH < BMAX ? BATCH : BMAX;
     if (want_dt)
         launch_blend_bwd_dt<TW, TH, B, true>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final,
-                                             n_last, vis_rank, sgrad, wstats, persist, queue, st);
+                                             n_last, qbits, qstride, vis_rank, sgrad, wstats, persist, queue, st);
     else
         launch_blend_bwd_dt<TW, TH, B, false>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final,
-                                              n_last, vis_rank, sgrad, wstats, persist, queue, st);
+                                              n_last, qbits, qstride, vis_rank, sgrad, wstats, persist, queue, st);
 }
 
 }  // namespace
@@ -846,42 +881,43 @@ bool blend_supported(int tw, int th, int batch)
 
 static void launch_blend_cfg(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order,
                              const uint2 *ranges, const uint32_t *pair_vals, const SplatRec *recs,
-                             const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend, uint4 *wstats,
-                             int tw, int th, int batch, bool persist, uint32_t *queue, hipStream_t st)
+                             const double4 *axes, float *T_final, uint32_t *n_last, uint32_t *n_blend,
+                             uint8_t *qbits, uint32_t qstride, uint4 *wstats, int tw, int th, int batch, bool persist,
+                             uint32_t *queue, hipStream_t st)
 {
 #define X(a, b, c)                                                                                           \
     if (tw == a && th == b && batch == c)                                                                    \
         return launch_blend_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last, \
-                                       n_blend, wstats, persist, queue, st);
+                                       n_blend, qbits, qstride, wstats, persist, queue, st);
     HGS_BLEND_CASES(X)
 #undef X
 }
 
 void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                   const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, float *T_final,
-                  uint32_t *n_last, uint32_t *n_blend, uint4 *wstats, Counters *ctr, int tw, int th, int batch,
-                  bool persist, uint32_t *queue, hipStream_t st)
+                  uint32_t *n_last, uint32_t *n_blend, uint8_t *qbits, uint32_t qstride, uint4 *wstats,
+                  Counters *ctr, int tw, int th, int batch, bool persist, uint32_t *queue, hipStream_t st)
 {
     if (batch == 0) batch = tw * th;
     if (!n_tiles) return;
     const uint32_t nst = n_tiles * (uint32_t)(tw * th / 64);
-    launch_blend_cfg(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last, n_blend, wstats, tw,
-                     th, batch, persist, queue, st);
+    launch_blend_cfg(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last, n_blend, qbits,
+                     qstride, wstats, tw, th, batch, persist, queue, st);
     hipLaunchKernelGGL(k_stats_reduce, dim3(256), dim3(256), 0, st, wstats, nst, &ctr->evaluated);
 }
 
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order,
                            const uint2 *ranges, const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes,
-                           const float *T_final, const uint32_t *n_last, const uint32_t *vis_rank, double *sgrad,
-                           uint4 *wstats, Counters *ctr, int tw, int th, int batch, bool want_dt, bool persist,
-                           uint32_t *queue, hipStream_t st)
+                           const float *T_final, const uint32_t *n_last, const uint8_t *qbits, uint32_t qstride,
+                           const uint32_t *vis_rank, double *sgrad, uint4 *wstats, Counters *ctr, int tw, int th,
+                           int batch, bool want_dt, bool persist, uint32_t *queue, hipStream_t st)
 {
     if (batch == 0) batch = tw * th;
     if (!n_tiles) return;
 #define X(a, b, c)                                                                                                 \
     if (tw == a && th == b && batch == c) {                                                                        \
         launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last,    \
-                                    vis_rank, sgrad, wstats, want_dt, persist, queue, st);                         \
+                                    qbits, qstride, vis_rank, sgrad, wstats, want_dt, persist, queue, st);         \
         hipLaunchKernelGGL(k_stats_reduce, dim3(256), dim3(256), 0, st, wstats,                                    \
                            n_tiles * (uint32_t)(tw * th / 64), &ctr->bwd_evaluated);                               \
         return;                                                                                                    \
