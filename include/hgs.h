@@ -366,6 +366,20 @@ typedef struct {
 } hgs_adam;
 hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a);
 
+/* Deterministic-reduction mode of hgs_render_backward (a checking aid): with
+ * on = 1 the blend backward uses no floating-point atomics.  Within a tile,
+ * each 4x4 pixel quarter keeps its partial sums in a slot of its own and the
+ * quarters are added in a fixed order; each (tile, splat) pair stores its
+ * 11 screen-space terms at the pair's position in the duplication order,
+ * and every splat's terms are then summed over its tiles in that order.
+ * Gradients are then bit-identical from run to run (in the default mode,
+ * FP64 atomics make the order of the additions vary, which moves results in
+ * their last bits).  Costs 88 bytes of device memory per (tile, splat) pair
+ * (allocated at the next backward) and about one more pass over them; the
+ * blend backward then stages 32 splats per batch, one workgroup per tile.
+ * on = 0 restores the default.  HGS_ERR_INVALID_ARG for other values. */
+hgs_status hgs_set_deterministic(hgs_ctx *ctx, int32_t on);
+
 /* The interior nodes (those with children: the ones the optimisation of
  * Sec. 5.1 updates) of the uploaded or built hierarchy, in ascending id
  * order: the row order of the optimiser moments of hgs_adam_step.  *count

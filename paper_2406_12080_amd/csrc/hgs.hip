@@ -103,6 +103,10 @@ struct hgs_ctx {
     uint32_t *depth_key = nullptr, *ntiles = nullptr;
     uint4 *trec = nullptr;  // per cut entry: tile rectangle and count (visible entries)
     uint2 *rect = nullptr;  // tile rectangles of the visible splats in depth order
+    uint32_t *jrank = nullptr;  // per cut entry: its slot in the depth order of the visible splats
+    double *part = nullptr;     // deterministic backward: 11 doubles per emitted pair
+    uint32_t part_cap = 0;
+    bool deterministic = false;
     uint64_t *vis_mask = nullptr;
     uint32_t *vis_counts = nullptr, *vis_offsets = nullptr;
     uint32_t *skeys = nullptr, *svals = nullptr, *pair_offsets = nullptr;
@@ -429,6 +433,7 @@ hgs_status ensure_cut_cap(hgs_ctx *ctx, uint32_t cap)
     if ((s = realloc_buf(ctx, ctx->depth_key, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->ntiles, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->rect, cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->jrank, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->trec, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->vis_mask, (size_t)cap / 64 + 8))) return s;
     if ((s = realloc_buf(ctx, ctx->vis_counts, (size_t)cap / 256 + 2))) return s;
@@ -519,7 +524,8 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
                       &ctx->ctr->vis_total, ctx->vis_bounds, st);
     launch_radix_sort(ctx->skeys, ctx->svals, ctx->cut_cap, &ctx->ctr->vis_total, 32, sc, st, ctx->vis_bounds, nv);
     mark(3);
-    launch_gather_tiles(ctx->trec, ctx->svals, &ctx->ctr->vis_total, ctx->cut_cap, ctx->pair_offsets, ctx->rect, st);
+    launch_gather_tiles(ctx->trec, ctx->svals, &ctx->ctr->vis_total, ctx->cut_cap, ctx->pair_offsets, ctx->rect,
+                        ctx->jrank, st);
     launch_scan(ctx->pair_offsets, nullptr, ctx->cut_cap, &ctx->ctr->vis_total, ctx->pair_offsets,
                 &ctx->ctr->pair_total, ctx->partial, st);  // in place
     launch_pair_bounds(ctx->vis_bounds, ctx->views_dev, nv, ctx->pair_offsets, &ctx->ctr->vis_total, ctx->cut_cap,
@@ -601,15 +607,23 @@ void drop_hierarchy(hgs_ctx *ctx)
 // for every render of the same forward graph.
 void enqueue_backward(hgs_ctx *ctx, int nv, const hgs_grads *out, hipStream_t st)
 {
-    launch_zero_rows(ctx->sgrad, 12, &ctx->ctr->vis_total, ctx->cut_cap, st);
+    const bool det = ctx->deterministic;
+    if (det)  // every row of the emitted pair list is written or stays zero
+        launch_zero_rows(ctx->part, 11, &ctx->ctr->pair_total, ctx->pair_cap, st);
+    else
+        launch_zero_rows(ctx->sgrad, 12, &ctx->ctr->vis_total, ctx->cut_cap, st);
     launch_fill_u32((uint32_t *)&ctx->ctr->bwd_evaluated, 0u, 6, st);
     const uint32_t *vals = ctx->pairs_in_scratch ? ctx->v2 : ctx->pvals;
     {
         KernelTimer kt(ctx, 1, st);
+        const DetArgs da{ctx->jrank, ctx->pair_offsets, ctx->rect, ctx->part};
         launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs,
                               ctx->axes, ctx->T_final, ctx->n_last, ctx->qbits, ctx->pair_cap, ctx->vis_rank,
-                              ctx->sgrad, ctx->wstats, ctx->ctr, ctx->r_tw, ctx->r_th, ctx->r_batch,
-                              out->dt != nullptr, ctx->r_persist, ctx->queue + 1, st);
+                              ctx->sgrad, det ? &da : nullptr, ctx->wstats, ctx->ctr, ctx->r_tw, ctx->r_th,
+                              ctx->r_batch, out->dt != nullptr, ctx->r_persist, ctx->queue + 1, st);
+        if (det)
+            launch_det_sum(ctx->part, ctx->pair_offsets, ctx->svals, ctx->vis_rank, &ctx->ctr->vis_total,
+                           ctx->cut_cap, &ctx->ctr->pair_total, ctx->pair_cap, ctx->sgrad, st);
     }
     const DevHier h = dev_hier(ctx);
     {
@@ -798,6 +812,15 @@ hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a)
         launch_adam(k, ctx->interior, ctx->n_interior, a->param[k], a->grad[k], a->m[k], a->v[k], sc, ctx->stream);
     }
     HIPC(hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_set_deterministic(hgs_ctx *ctx, int32_t on)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (on != 0 && on != 1) return fail(ctx, HGS_ERR_INVALID_ARG, "on must be 0 or 1");
+    ctx->deterministic = on != 0;
+    ctx->bgraph_valid = false;  // the captured backward follows the mode
     return HGS_OK;
 }
 
@@ -1499,6 +1522,11 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views
         ctx->views_host[v].dL = dL_drgb[v];
     }
     HIPC(hipSetDevice(ctx->device));
+    if (ctx->deterministic && ctx->part_cap < ctx->pair_cap) {
+        if (hgs_status s = realloc_buf(ctx, ctx->part, (size_t)ctx->pair_cap * 11)) return s;
+        ctx->part_cap = ctx->pair_cap;
+        ctx->bgraph_valid = false;
+    }
     const void *outs[6] = {out->mean, out->scale, out->rot, out->opacity, out->sh, out->dt};
     if (ctx->last_graphed) {
         // replay (or capture once) the backward on the library stream, in

@@ -187,7 +187,7 @@ void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_
 // the splat at depth slot i, from trec (per cut entry: rect.x, rect.y,
 // tile count, unused; written for visible entries).
 void launch_gather_tiles(const uint4 *trec, const uint32_t *sorted_vals, const uint32_t *vis_total, uint32_t vis_cap,
-                         uint32_t *counts, uint2 *rect, hipStream_t st);
+                         uint32_t *counts, uint2 *rect, uint32_t *jrank, hipStream_t st);
 // Per view: the depth-order slot of its first visible splat (vis_bounds,
 // nv + 1 entries, the last = visible total).
 void launch_vis_bounds(const uint32_t *cut_base, int nv, const uint64_t *vis_mask, const uint32_t *vis_offsets,
@@ -220,6 +220,24 @@ void blend_prepare(int tw, int th, int batch);
 // persist: a grid of the chip's resident workgroups takes tile slots from
 // the device-side queue (*queue, cleared by the launch sequence first)
 // instead of one workgroup per tile.
+// The deterministic mode of the blend backward (launch_blend_backward with a
+// non-NULL DetArgs): per (tile, splat) pair, the tile's 11 screen-space terms
+// go to part[11 p] by plain stores, p = the pair's position in the list
+// k_duplicate emitted (pair_offsets[j] + the tile's row-major index in the
+// tile rectangle rect[j] of depth-sorted visible splat j = jrank[cut entry]);
+// launch_det_sum then writes each splat's screen gradient as the in-order sum
+// of its pairs' rows.  No floating-point atomics: results are bit-identical
+// from run to run.
+struct DetArgs {
+    const uint32_t *jrank;
+    const uint32_t *pair_offsets;
+    const uint2 *rect;
+    double *part;
+};
+void launch_det_sum(const double *part, const uint32_t *pair_offsets, const uint32_t *sorted_vals,
+                    const uint32_t *vis_rank, const uint32_t *vis_total, uint32_t vis_cap,
+                    const uint32_t *pair_total, uint32_t pair_cap, double *sgrad, hipStream_t st);
+
 // Quarter records of the forward, read by the backward: byte b * qstride + p
 // (b < the tile's 8x8 blocks, at most kMaxBlocks; qstride >= the pair count)
 // holds, for the splat at position p of the sorted pair list and block b of
@@ -300,7 +318,7 @@ void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const
                            const uint2 *ranges,
                            const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                            const uint32_t *n_last, const uint8_t *qbits, uint32_t qstride, const uint32_t *vis_rank,
-                           double *sgrad, uint4 *wstats,
+                           double *sgrad, const DetArgs *det, uint4 *wstats,
                            Counters *ctr, int tw, int th, int batch, bool want_dt, bool persist, uint32_t *queue,
                            hipStream_t st);
 void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32_t vis_cap, hipStream_t st);

@@ -465,7 +465,13 @@ __device__ __forceinline__ double2 centre_offsets(const SplatRec &r, const doubl
     return make_double2(dx * W.x + dy * W.y, dx * W.z + dy * W.w);
 }
 
-template <int TW, int TH, int BATCH, bool DT>
+// DET (the deterministic mode): no floating-point atomics.  Each row of 16
+// lanes stores its FP32 partial sums in a slot of its own, the flush adds the
+// rows in a fixed order (FP64), and the tile's 11 terms for a splat go with
+// plain stores to det.part at the pair's position in the list k_duplicate
+// emitted (the splat's first pair plus the tile's row-major index in its
+// tile rectangle); launch_det_sum then adds each splat's rows in order.
+template <int TW, int TH, int BATCH, bool DT, bool DET>
 __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views, int nv,
                                                const uint32_t *__restrict__ tile_order,
                                                const uint2 *__restrict__ ranges,
@@ -475,7 +481,7 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
                                                const uint32_t *__restrict__ n_last,
                                                const uint8_t *__restrict__ qbits, uint32_t qstride,
                                                const uint32_t *__restrict__ vis_rank, double *__restrict__ sgrad,
-                                               uint4 *__restrict__ wstats, uint32_t tslot)
+                                               const DetArgs det, uint4 *__restrict__ wstats, uint32_t tslot)
 {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;
@@ -486,8 +492,10 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
     __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
     __shared__ float2 s_u[NB][BATCH];  // c1, c2
     __shared__ uint32_t s_id[BATCH];
-    __shared__ __align__(16) double s_g[BATCH][kG];  // the quarters' partial sums, added in FP64
-    __shared__ double s_d[BATCH * 11];  // the flushed terms, splat-major
+    __shared__ __align__(16) double s_g[DET ? 1 : BATCH][kG];  // the quarters' partial sums, added in FP64
+    __shared__ double s_d[DET ? 1 : BATCH * 11];  // the flushed terms, splat-major
+    __shared__ float s_gr[DET ? 4 * NW : 1][DET ? BATCH : 1][kG];  // DET: each row's partial sums
+    __shared__ uint32_t s_pq[DET ? BATCH : 1];  // DET: the pair's position in the emitted list
     __shared__ double2 s_ref[BATCH];    // the tile centre's offsets on the axes (FP64)
     // bit b of word k: quarter q of block bk may take entry 32 k + 31 - b
     // (reversed, so that the lowest set bit is the next entry back to front)
@@ -561,8 +569,18 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
                 s_o[j] = make_float4(r.An, r.Ap, r.t, r.invK);
                 s_c[j] = make_float4(r.r, r.g, r.b, 0.0f);
                 s_ref[j] = centre_offsets<TW, TH>(r, W64, ox, oy);
+                if constexpr (DET) {
+                    for (int row = 0; row < 4 * NW; ++row)
 #pragma unroll
-                for (int k = 0; k < kG; ++k) s_g[j][k] = 0.0;
+                        for (int k = 0; k < kG; ++k) s_gr[row][j][k] = 0.0f;
+                    const uint32_t jr = det.jrank[sidx];
+                    const uint2 rc = det.rect[jr];
+                    const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu;
+                    s_pq[j] = det.pair_offsets[jr] + ((uint32_t)ty - ty0) * (tx1 - tx0 + 1u) + ((uint32_t)tx - tx0);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < kG; ++k) s_g[j][k] = 0.0;
+                }
             } else if (j < BATCH) {  // padding read by quarters with nothing left: alpha = 0
                 s_w[j] = s_o[j] = s_c[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
@@ -657,7 +675,11 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
                     S2[5] = aT * g2b;
                 }
                 const float tot = row_reduce12(S1, S2, lane);
-                if (has && slot >= 0 && tot != 0.0f) unsafeAtomicAdd(&s_g[j][slot], (double)tot);
+                if constexpr (DET) {
+                    if (has && slot >= 0) s_gr[4 * w + q][j][slot] = tot;
+                } else {
+                    if (has && slot >= 0 && tot != 0.0f) unsafeAtomicAdd(&s_g[j][slot], (double)tot);
+                }
             }
         }
         __syncthreads();
@@ -665,7 +687,18 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
         // 11 screen-space terms (FP64); then the terms of all splats go out
         // as consecutive atomics, row by row
         for (int j = threadIdx.x; j < cnt; j += NT) {
-            const double *g = s_g[j];
+            double gd[kG];
+            if constexpr (DET) {
+#pragma unroll
+                for (int k = 0; k < kG; ++k) gd[k] = 0.0;
+                for (int row = 0; row < 4 * NW; ++row)  // rows in a fixed order
+#pragma unroll
+                    for (int k = 0; k < kG; ++k) gd[k] += (double)s_gr[row][j][k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < kG; ++k) gd[k] = s_g[j][k];
+            }
+            const double *g = gd;
             // moments about the splat's centre from those about the tile's
             const double2 cr = s_ref[j];
             const double S = g[5];
@@ -676,24 +709,34 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
                                  Q22 + 2.0 * cr.y * P2 + cr.y * cr.y * S};
             double sc[5];
             screen_grad(s_w[j], P, Q, sc);
-            double *d = s_d + j * 11;
+            double dd[11];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) d[k] = sc[k];
+            for (int k = 0; k < 5; ++k) dd[k] = sc[k];
 #pragma unroll
-            for (int k = 5; k < 11; ++k) d[k] = g[k + 1];
+            for (int k = 5; k < 11; ++k) dd[k] = g[k + 1];
+            if constexpr (DET) {
+                double *o = det.part + (size_t)s_pq[j] * 11;
+#pragma unroll
+                for (int k = 0; k < 11; ++k) o[k] = dd[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 11; ++k) s_d[j * 11 + k] = dd[k];
+            }
         }
         __syncthreads();
-        for (int idx = threadIdx.x; idx < cnt * 11; idx += NT) {
-            const double val = s_d[idx];
-            const int j = idx / 11, k = idx - 11 * j;
-            if (val != 0.0) unsafeAtomicAdd(&sgrad[(size_t)s_id[j] * kG + k], val);
+        if constexpr (!DET) {
+            for (int idx = threadIdx.x; idx < cnt * 11; idx += NT) {
+                const double val = s_d[idx];
+                const int j = idx / 11, k = idx - 11 * j;
+                if (val != 0.0) unsafeAtomicAdd(&sgrad[(size_t)s_id[j] * kG + k], val);
+            }
+            __syncthreads();
         }
-        __syncthreads();
         hi = lo;
     }
     if (lane == 0) wstats[(size_t)tslot * NW + w] = make_uint4(n_eval, n_eval_t, n_con, 0u);
 }
-template <int TW, int TH, int BATCH, bool DT, bool PERSIST>
+template <int TW, int TH, int BATCH, bool DT, bool PERSIST, bool DET>
 __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict__ views, int nv,
                                                       const uint32_t *__restrict__ tile_order,
                                                       const uint2 *__restrict__ ranges,
@@ -704,13 +747,13 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
                                                       const uint32_t *__restrict__ n_last,
                                                       const uint8_t *__restrict__ qbits, uint32_t qstride,
                                                       const uint32_t *__restrict__ vis_rank,
-                                                      double *__restrict__ sgrad, uint4 *__restrict__ wstats,
-                                                      uint32_t n_tiles, uint32_t *__restrict__ queue,
-                                                      uint32_t chunk)
+                                                      double *__restrict__ sgrad, const DetArgs det,
+                                                      uint4 *__restrict__ wstats, uint32_t n_tiles,
+                                                      uint32_t *__restrict__ queue, uint32_t chunk)
 {
     if constexpr (!PERSIST) {
-        blend_bwd_tile<TW, TH, BATCH, DT>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final, n_last,
-                                          qbits, qstride, vis_rank, sgrad, wstats, blockIdx.x);
+        blend_bwd_tile<TW, TH, BATCH, DT, DET>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final,
+                                               n_last, qbits, qstride, vis_rank, sgrad, det, wstats, blockIdx.x);
     } else {
         __shared__ uint32_t s_slot;
         for (;;) {
@@ -718,8 +761,9 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd(const DevView *__restrict_
             if (first >= n_tiles) break;
             const uint32_t last = min(n_tiles, first + chunk);
             for (uint32_t slot = first; slot < last; ++slot) {
-                blend_bwd_tile<TW, TH, BATCH, DT>(views, nv, tile_order, ranges, pair_vals, recs, axes, T_final,
-                                                  n_last, qbits, qstride, vis_rank, sgrad, wstats, slot);
+                blend_bwd_tile<TW, TH, BATCH, DT, DET>(views, nv, tile_order, ranges, pair_vals, recs, axes,
+                                                       T_final, n_last, qbits, qstride, vis_rank, sgrad, det, wstats,
+                                                       slot);
                 __syncthreads();  // LDS of this tile read by every wave before the next stages
             }
         }
@@ -810,18 +854,24 @@ template <int TW, int TH, int B, bool DT>
 void launch_blend_bwd_dt(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                          const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                          const uint32_t *n_last, const uint8_t *qbits, uint32_t qstride, const uint32_t *vis_rank,
-                         double *sgrad, uint4 *wstats, bool persist, uint32_t *queue, hipStream_t st)
+                         double *sgrad, const DetArgs *det, uint4 *wstats, bool persist, uint32_t *queue,
+                         hipStream_t st)
 {
-    if (persist) {
-        auto k = k_blend_bwd<TW, TH, B, DT, true>;
+    if (det) {  // the deterministic mode: one workgroup per tile, 32 splats staged per batch
+        hipLaunchKernelGGL((k_blend_bwd<TW, TH, 32, DT, false, true>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv,
+                           order, ranges, pair_vals, recs, axes, T_final, n_last, qbits, qstride, vis_rank, sgrad,
+                           *det, wstats, n_tiles, queue, 1u);
+    } else if (persist) {
+        auto k = k_blend_bwd<TW, TH, B, DT, true, false>;
         const uint32_t g = std::min(n_tiles, resident_grid(k, TW * TH));
         launch_fill_u32(queue, 0u, 1, st);
         hipLaunchKernelGGL(k, dim3(g), dim3(TW * TH), 0, st, views, nv, order, ranges, pair_vals, recs, axes, T_final,
-                           n_last, qbits, qstride, vis_rank, sgrad, wstats, n_tiles, queue, queue_run(n_tiles, g));
+                           n_last, qbits, qstride, vis_rank, sgrad, DetArgs{}, wstats, n_tiles, queue,
+                           queue_run(n_tiles, g));
     } else {
-        hipLaunchKernelGGL((k_blend_bwd<TW, TH, B, DT, false>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv, order,
-                           ranges, pair_vals, recs, axes, T_final, n_last, qbits, qstride, vis_rank, sgrad, wstats,
-                           n_tiles, queue, 1u);
+        hipLaunchKernelGGL((k_blend_bwd<TW, TH, B, DT, false, false>), dim3(n_tiles), dim3(TW * TH), 0, st, views, nv,
+                           order, ranges, pair_vals, recs, axes, T_final, n_last, qbits, qstride, vis_rank, sgrad,
+                           DetArgs{}, wstats, n_tiles, queue, 1u);
     }
 }
 
@@ -829,7 +879,8 @@ template <int TW, int TH, int BATCH>
 void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order, const uint2 *ranges,
                         const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes, const float *T_final,
                         const uint32_t *n_last, const uint8_t *qbits, uint32_t qstride, const uint32_t *vis_rank,
-                        double *sgrad, uint4 *wstats, bool want_dt, bool persist, uint32_t *queue, hipStream_t st)
+                        double *sgrad, const DetArgs *det, uint4 *wstats, bool want_dt, bool persist,
+                        uint32_t *queue, hipStream_t st)
 {
     // the backward stages at most 32 splats per wave and step: its LDS holds
     // the FP32 partial sums and the FP64 flushed terms of every staged
@@ -838,10 +889,10 @@ void launch_blend_bwd_t(const DevView *views, int nv, uint32_t n_tiles, const ui
     constexpr int B = BATCH < BMAX ? BATCH : BMAX;
     if (want_dt)
         launch_blend_bwd_dt<TW, TH, B, true>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final,
-                                             n_last, qbits, qstride, vis_rank, sgrad, wstats, persist, queue, st);
+                                             n_last, qbits, qstride, vis_rank, sgrad, det, wstats, persist, queue, st);
     else
         launch_blend_bwd_dt<TW, TH, B, false>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final,
-                                              n_last, qbits, qstride, vis_rank, sgrad, wstats, persist, queue, st);
+                                              n_last, qbits, qstride, vis_rank, sgrad, det, wstats, persist, queue, st);
 }
 
 }  // namespace
@@ -856,8 +907,8 @@ void prepare_t()
     constexpr int BMAX = 32 * (TW * TH / 64);
     constexpr int B = BATCH < BMAX ? BATCH : BMAX;
     (void)resident_grid(k_blend<TW, TH, BATCH, true>, TW * TH);
-    (void)resident_grid(k_blend_bwd<TW, TH, B, true, true>, TW * TH);
-    (void)resident_grid(k_blend_bwd<TW, TH, B, false, true>, TW * TH);
+    (void)resident_grid(k_blend_bwd<TW, TH, B, true, true, false>, TW * TH);
+    (void)resident_grid(k_blend_bwd<TW, TH, B, false, true, false>, TW * TH);
 }
 
 void blend_prepare(int tw, int th, int batch)
@@ -909,15 +960,15 @@ void launch_blend(const DevView *views, int nv, uint32_t n_tiles, const uint32_t
 void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const uint32_t *order,
                            const uint2 *ranges, const uint32_t *pair_vals, const SplatRec *recs, const double4 *axes,
                            const float *T_final, const uint32_t *n_last, const uint8_t *qbits, uint32_t qstride,
-                           const uint32_t *vis_rank, double *sgrad, uint4 *wstats, Counters *ctr, int tw, int th,
-                           int batch, bool want_dt, bool persist, uint32_t *queue, hipStream_t st)
+                           const uint32_t *vis_rank, double *sgrad, const DetArgs *det, uint4 *wstats, Counters *ctr,
+                           int tw, int th, int batch, bool want_dt, bool persist, uint32_t *queue, hipStream_t st)
 {
     if (batch == 0) batch = tw * th;
     if (!n_tiles) return;
 #define X(a, b, c)                                                                                                 \
     if (tw == a && th == b && batch == c) {                                                                        \
         launch_blend_bwd_t<a, b, c>(views, nv, n_tiles, order, ranges, pair_vals, recs, axes, T_final, n_last,    \
-                                    qbits, qstride, vis_rank, sgrad, wstats, want_dt, persist, queue, st);         \
+                                    qbits, qstride, vis_rank, sgrad, det, wstats, want_dt, persist, queue, st);    \
         hipLaunchKernelGGL(k_stats_reduce, dim3(256), dim3(256), 0, st, wstats,                                    \
                            n_tiles * (uint32_t)(tw * th / 64), &ctr->bwd_evaluated);                               \
         return;                                                                                                    \

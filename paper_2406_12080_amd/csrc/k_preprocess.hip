@@ -190,18 +190,53 @@ __global__ void k_pair_bounds(const uint32_t *__restrict__ vis_bounds, const Dev
 }
 
 // The tile records of the visible splats in depth order: the one random
-// gather of per-splat data between the depth sort and the pair emission.
+// gather of per-splat data between the depth sort and the pair emission;
+// also each cut entry's depth-order slot (jrank), which the deterministic
+// backward uses to find a pair's position in the emitted list.
 __global__ __launch_bounds__(kT) void k_gather_tiles(const uint4 *__restrict__ trec,
                                                      const uint32_t *__restrict__ sorted_vals,
                                                      const uint32_t *__restrict__ vis_total, uint32_t vis_cap,
-                                                     uint32_t *__restrict__ counts, uint2 *__restrict__ rect)
+                                                     uint32_t *__restrict__ counts, uint2 *__restrict__ rect,
+                                                     uint32_t *__restrict__ jrank)
 {
     const uint32_t n = min(*vis_total, vis_cap);
     const uint32_t i = blockIdx.x * kT + threadIdx.x;
     if (i >= n) return;
-    const uint4 r = trec[sorted_vals[i]];
+    const uint32_t s = sorted_vals[i];
+    const uint4 r = trec[s];
     counts[i] = r.z;
     rect[i] = make_uint2(r.x, r.y);
+    jrank[s] = i;
+}
+
+// Deterministic mode: the screen gradient of depth-sorted visible splat j is
+// the sum, in emission order, of the rows its pairs' tiles stored (every row
+// of the emitted list is written by the backward or zeroed before it).
+__global__ __launch_bounds__(kT) void k_det_sum(const double *__restrict__ part,
+                                                const uint32_t *__restrict__ pair_offsets,
+                                                const uint32_t *__restrict__ sorted_vals,
+                                                const uint32_t *__restrict__ vis_rank,
+                                                const uint32_t *__restrict__ vis_total, uint32_t vis_cap,
+                                                const uint32_t *__restrict__ pair_total, uint32_t pair_cap,
+                                                double *__restrict__ sgrad)
+{
+    const uint32_t n = min(*vis_total, vis_cap);
+    const uint32_t j = blockIdx.x * kT + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t p0 = min(pair_offsets[j], pair_cap);
+    const uint32_t p1 = min(j + 1 < n ? pair_offsets[j + 1] : *pair_total, pair_cap);
+    double acc[11];
+#pragma unroll
+    for (int k = 0; k < 11; ++k) acc[k] = 0.0;
+    for (uint32_t p = p0; p < p1; ++p) {
+        const double *row = part + (size_t)p * 11;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) acc[k] += row[k];
+    }
+    double *o = sgrad + (size_t)vis_rank[sorted_vals[j]] * 12;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) o[k] = acc[k];
+    o[11] = 0.0;
 }
 
 // Pair emission, balanced by pairs: block b writes pairs [b P, (b + 1) P)
@@ -765,12 +800,22 @@ void launch_pair_bounds(const uint32_t *vis_bounds, const DevView *views, int nv
 }
 
 void launch_gather_tiles(const uint4 *trec, const uint32_t *sorted_vals, const uint32_t *vis_total, uint32_t vis_cap,
-                         uint32_t *counts, uint2 *rect, hipStream_t st)
+                         uint32_t *counts, uint2 *rect, uint32_t *jrank, hipStream_t st)
 {
     const uint32_t blocks = (vis_cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_gather_tiles, dim3(blocks), dim3(kT), 0, st, trec, sorted_vals, vis_total, vis_cap, counts,
-                       rect);
+                       rect, jrank);
+}
+
+void launch_det_sum(const double *part, const uint32_t *pair_offsets, const uint32_t *sorted_vals,
+                    const uint32_t *vis_rank, const uint32_t *vis_total, uint32_t vis_cap,
+                    const uint32_t *pair_total, uint32_t pair_cap, double *sgrad, hipStream_t st)
+{
+    const uint32_t blocks = (vis_cap + kT - 1) / kT;
+    if (!blocks) return;
+    hipLaunchKernelGGL(k_det_sum, dim3(blocks), dim3(kT), 0, st, part, pair_offsets, sorted_vals, vis_rank, vis_total,
+                       vis_cap, pair_total, pair_cap, sgrad);
 }
 
 void launch_duplicate(const uint2 *rect, const DevView *views, int nv, const uint32_t *cut_base,

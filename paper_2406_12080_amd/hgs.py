@@ -21,7 +21,7 @@ _NAMES = {0: "HGS_OK", 1: "HGS_ERR_INVALID_ARG", 2: "HGS_ERR_OOM", 3: "HGS_ERR_H
 EXPORTS = ("hgs_create", "hgs_destroy", "hgs_last_error", "hgs_set_stream", "hgs_upload", "hgs_bind_params",
            "hgs_build", "hgs_download", "hgs_cut", "hgs_cut_noalloc", "hgs_compact_mark", "hgs_compact_rebuild", "hgs_render", "hgs_last_render",
            "hgs_render_backward", "hgs_l1_loss", "hgs_stream_begin", "hgs_stream_end", "hgs_stream_cleanup",
-           "hgs_stream_info", "hgs_adam_step", "hgs_interior", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
+           "hgs_stream_info", "hgs_adam_step", "hgs_interior", "hgs_set_deterministic", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
            "hgs_kernel_time", "hgs_counters")
 COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t", "bwd_evaluated",
                  "bwd_evaluated_t", "bwd_contrib")
@@ -126,6 +126,7 @@ def lib():
         L.hgs_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.hgs_get_buffer.argtypes = [vp, ctypes.c_int32, P(vp), P(ctypes.c_int64)]
         L.hgs_interior.argtypes = [vp, vp, ctypes.c_int64, P(ctypes.c_int64)]
+        L.hgs_set_deterministic.argtypes = [vp, ctypes.c_int32]
         L.hgs_set_profiling.argtypes = [vp, ctypes.c_int32]
         L.hgs_counters.argtypes = [vp, P(ctypes.c_int64), ctypes.c_int32]
         L.hgs_kernel_time.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -445,6 +446,11 @@ class Renderer:
         st = StreamStats()
         self._check(self.L.hgs_stream_info(self.h, ctypes.byref(st)))
         return {k: int(getattr(st, k)) for k, _ in StreamStats._fields_}
+
+    def set_deterministic(self, on: bool) -> None:
+        """Deterministic-reduction mode of the backward (``hgs_set_deterministic``):
+        no floating-point atomics, bit-identical gradients from run to run."""
+        self._check(self.L.hgs_set_deterministic(self.h, 1 if on else 0))
 
     def n_interior(self) -> int:
         """Number of interior nodes of the current hierarchy (``hgs_interior``)."""

@@ -200,14 +200,18 @@ def _tunings():
     return CANDIDATES
 
 
-def _grad_case(h, v, seed=0, tuning=(16, 16, 256, 0)):
+def _grad_case(h, v, seed=0, tuning=(16, 16, 256, 0), det=False):
     """GPU backward of one view against the oracle's, in the blend
-    configuration `tuning` = (tile_w, tile_h, batch)."""
+    configuration `tuning` = (tile_w, tile_h, batch); with `det`, in the
+    deterministic-reduction mode, where a second backward of the same render
+    must give the same gradients bit for bit."""
     from paper_2406_12080_amd import hgs as H
     v = PR.safe_tau(h, v)
     r = H.Renderer(0)
     r.upload(h)
     r.set_tuning(*tuning)
+    if det:
+        r.set_deterministic(True)
     P = H.params_to_device(h)
     r.bind(*[P[k] for k in H.PARAM_FIELDS])
     (img,), st = r.render([v])
@@ -223,6 +227,12 @@ def _grad_case(h, v, seed=0, tuning=(16, 16, 256, 0)):
     dt = torch.zeros(len(oids), device="cuda")
     r.backward([w], grads, dt)
     _sync()
+    if det:
+        g2 = {k: torch.zeros_like(P[k]) for k in H.PARAM_FIELDS}
+        dt2 = torch.zeros_like(dt)
+        r.backward([w], g2, dt2)
+        _sync()
+        assert all(torch.equal(grads[k], g2[k]) for k in grads) and torch.equal(dt, dt2), "not repeatable"
     c = r.counters()
     # the backward re-evaluates exactly the pairs the forward blended
     assert c["bwd_contrib"] == st["blended"] == c["blended"], (c, st)
@@ -259,6 +269,31 @@ def test_backward_parity_c2s(hgs_mod, c2s, tuning):
     assert n_near > 100
     PR.assert_grads(res, tuning)
     assert nt > 0 and dt_rel <= PR.GRAD_REL
+
+
+@pytest.mark.parametrize("tuning", [(8, 8, 64, 0), (16, 8, 128, 0), (16, 16, 256, 1), (32, 16, 512, 0)],
+                         ids=lambda t: "%dx%dx%d%s" % (t[:3] + ("p" if t[3] else "",)))
+def test_deterministic_backward_c2s(hgs_mod, c2s, tuning):
+    # the deterministic-reduction mode (no floating-point atomics): two
+    # backwards of one render agree bit for bit, and the result meets the
+    # same bar against the oracle as the default mode
+    v = synth.look_at((0, -40, 1.7), (0, 0, 2.5), (0, 0, 1), 640, 360, 6.0)
+    res, dt_rel, nt, n_near = _grad_case(c2s, v, seed=3, tuning=tuning, det=True)
+    print(tuning, res, dt_rel, nt, n_near)
+    PR.assert_grads(res, tuning)
+    assert nt > 0 and dt_rel <= PR.GRAD_REL
+
+
+def test_deterministic_mode_arguments(hgs_mod):
+    r = hgs_mod.Renderer(0)
+    try:
+        with pytest.raises(hgs_mod.HgsError) as e:
+            r._check(r.L.hgs_set_deterministic(r.h, 2))
+        assert e.value.status == hgs_mod.ERR_INVALID_ARG
+        r.set_deterministic(True)
+        r.set_deterministic(False)
+    finally:
+        r.close()
 
 
 def test_backward_queued_behind_busy_stream(r_c2s, c2s):
