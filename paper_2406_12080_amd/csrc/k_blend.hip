@@ -488,7 +488,7 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
     constexpr int SX = TW / 8;
     constexpr int NB = (TW / 8) * (TH / 8);
     constexpr int NQW = BATCH / 32;  // 32-entry words of a quarter's mask
-    static_assert(BATCH % 32 == 0 && NB <= 8, "tile/batch combination");
+    static_assert(BATCH % 32 == 0 && BATCH <= 32 * NW && NB <= 8, "tile/batch combination");
     __shared__ float4 s_w[BATCH], s_o[BATCH], s_c[BATCH];
     __shared__ float2 s_u[NB][BATCH];  // c1, c2
     __shared__ uint32_t s_id[BATCH];
@@ -548,10 +548,13 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
     for (uint32_t hi = end; hi > rg.x;) {
         const uint32_t lo = hi - rg.x > (uint32_t)BATCH ? hi - BATCH : rg.x;
         const int cnt = (int)(hi - lo);
-        for (int j0 = 0; j0 < BATCH; j0 += NT) {
-            const int j = j0 + (int)threadIdx.x;
+        {
+            // wave w stages entries 32 w .. 32 w + 31 on its lanes 0-31 (the
+            // batch holds at most 32 entries per wave), so that the staging
+            // work is spread over the waves of the tile
+            const int j = 32 * w + lane;
             uint32_t live = 0u;
-            if (j < cnt) {
+            if (lane < 32 && j < cnt) {
                 const uint32_t sidx = pair_vals[lo + j];
                 const SplatRec r = recs[sidx];
                 const double4 W64 = axes[sidx];
@@ -581,20 +584,16 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
 #pragma unroll
                     for (int k = 0; k < kG; ++k) s_g[j][k] = 0.0;
                 }
-            } else if (j < BATCH) {  // padding read by quarters with nothing left: alpha = 0
+            } else if (lane < 32 && j < BATCH) {  // padding read by quarters with nothing left: alpha = 0
                 s_w[j] = s_o[j] = s_c[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
                 for (int bk = 0; bk < NB; ++bk) s_u[bk][j] = make_float2(0.0f, 0.0f);
             }
-            const int e0 = j0 + 64 * w;  // first entry of this wave's 64
-            if (e0 < BATCH) {
+            if (32 * w < BATCH) {  // this wave's word of the quarter masks
 #pragma unroll
                 for (int bq = 0; bq < 4 * NB; ++bq) {
                     const uint64_t m = __ballot((live >> bq) & 1u);
-                    if (lane == 0) {
-                        s_qm[bq >> 2][bq & 3][e0 >> 5] = __builtin_bitreverse32((uint32_t)m);
-                        if (e0 + 32 < BATCH) s_qm[bq >> 2][bq & 3][(e0 >> 5) + 1] = __builtin_bitreverse32((uint32_t)(m >> 32));
-                    }
+                    if (lane == 0) s_qm[bq >> 2][bq & 3][w] = __builtin_bitreverse32((uint32_t)m);
                 }
             }
         }
@@ -686,7 +685,7 @@ __device__ __forceinline__ void blend_bwd_tile(const DevView *__restrict__ views
         // flush: one lane per splat turns the tile's partial sums into the
         // 11 screen-space terms (FP64); then the terms of all splats go out
         // as consecutive atomics, row by row
-        for (int j = threadIdx.x; j < cnt; j += NT) {
+        if (const int j = 32 * w + lane; lane < 32 && j < cnt) {  // wave w: entries 32 w .. 32 w + 31
             double gd[kG];
             if constexpr (DET) {
 #pragma unroll
