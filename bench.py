@@ -135,9 +135,11 @@ ADAM_LR = dict(mean=1.6e-4, scale=5e-3, rot=1e-3, opacity=5e-2, sh=2.5e-3)
 def optimize_steps(r, h, P, grads, imgs, dL, workload: str, steps: int) -> dict:
     """Time `steps` steps of the hierarchy optimisation: per step a new batch
     of eyes with tau log-uniform over the workload's range (config 5: 32
-    views of 1920x1080, tau in [3, 15] px), render, backward with a fixed
-    synthetic cotangent, and one Adam step on the interior nodes (which also
-    zeroes their gradients).  Cameras are drawn before the timed region."""
+    views of 1920x1080, tau in [3, 15] px), render, and the backward with a
+    fixed synthetic cotangent with the Adam step on the interior nodes fused
+    into its gradient gather (hgs_backward_adam_step).  The same steps with
+    the backward into gradient arrays followed by the separate Adam step are
+    timed beside it.  Cameras are drawn before the timed region."""
     import torch
     from paper_2406_12080_amd import synth
     cfg = WORKLOADS[workload]["config"]
@@ -153,24 +155,33 @@ def optimize_steps(r, h, P, grads, imgs, dL, workload: str, steps: int) -> dict:
         g.zero_()
     n_step = 0
 
-    def one(views):
+    def one(views, fused=True):
         nonlocal n_step
         n_step += 1
         r.render(views, out=out)
-        r.backward(cot, grads)
-        r.adam_step(P, grads, M, V, ADAM_LR, n_step)
+        if fused:
+            r.backward_adam_step(cot, P, M, V, ADAM_LR, n_step)
+        else:
+            r.backward(cot, grads)
+            r.adam_step(P, grads, M, V, ADAM_LR, n_step)
 
-    for s in range(warm):
-        one(batches[s])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(warm, warm + steps):
-        one(batches[s])
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+    def timed(fused, n):
+        for s in range(warm):
+            one(batches[s], fused)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(warm, warm + n):
+            one(batches[s], fused)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    dt = timed(True, steps)
+    n_sep = min(steps, 20)
+    dt_sep = timed(False, n_sep)
     taus = [v.tau for b in batches[warm:] for v in b]
     nv = len(batches[0])
-    log(f"[bench] optimisation: {steps} steps, {dt * 1e3:.2f} ms/step")
+    log(f"[bench] optimisation: {steps} steps, {dt * 1e3:.2f} ms/step (backward and Adam separate: "
+        f"{dt_sep * 1e3:.2f} ms/step over {n_sep} steps)")
     # the Adam step alone (HBM-bound): per interior node and parameter the
     # parameter, gradient and both moments are read and written once
     n_adam = 10
@@ -187,7 +198,9 @@ def optimize_steps(r, h, P, grads, imgs, dL, workload: str, steps: int) -> dict:
     log(f"[bench] Adam step alone: {ms_adam:.3f} ms, {gbs:.0f} GB/s")
     return dict(steps=steps, warmup=warm, ms_per_step=round(dt * 1e3, 3), views_per_s=round(nv / dt, 3),
                 views_per_step=nv, tau_min=round(min(taus), 3), tau_max=round(max(taus), 3),
-                step="new eyes and tau per step; render + backward + Adam on the interior nodes",
+                step="new eyes and tau per step; render + backward with Adam on the interior nodes fused into "
+                     "the gradient gather",
+                ms_per_step_separate=round(dt_sep * 1e3, 3),
                 adam=dict(ms=round(ms_adam, 4), bytes=int(adam_bytes), gb_per_s=round(gbs, 1),
                           frac_hbm=round(gbs / 8000.0, 4), launches_per_step=len(P),
                           bytes_per_node=per_node * 32))
@@ -266,7 +279,6 @@ def converge(r, h, views, steps: int) -> dict:
         P["scale"] *= torch.exp(noise(P["scale"]) * interior[:, None])
         P["sh"] += noise(P["sh"]) * interior[:, None]
     M, V = r.adam_moments(P)
-    grads = {k: torch.zeros_like(t) for k, t in P.items()}
     n_val = sum(t.numel() for t in tgt)
     losses = []
     t0 = time.perf_counter()
@@ -278,8 +290,7 @@ def converge(r, h, views, steps: int) -> dict:
             dL = [torch.sign(d) / n_val for d in diffs]
         if s == steps:
             break
-        r.backward(dL, grads)
-        r.adam_step(P, grads, M, V, CONVERGE_LR, s + 1)
+        r.backward_adam_step(dL, P, M, V, CONVERGE_LR, s + 1)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(steps, 1)
     marks = sorted({0, steps} | {steps * k // 10 for k in range(1, 10)})

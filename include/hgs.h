@@ -366,6 +366,21 @@ typedef struct {
 } hgs_adam;
 hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a);
 
+/* The backward of render render_id with the optimiser step of Sec. 5.1
+ * applied right away: the same parameters, moments and errors as
+ * hgs_render_backward into gradient arrays that hold zero, followed by
+ * hgs_adam_step on them (bit for bit), but the gradient of each interior
+ * node goes from the gather's registers into its Adam update and is never
+ * stored.  a->grad is not used (may be NULL); a->param, a->m and a->v as for
+ * hgs_adam_step (interior nodes stepped, leaves untouched, every interior
+ * node stepped, with gradient zero where no cut entry reached it); no dL/dt
+ * output.  Arguments are checked as by the two calls (argument errors
+ * change nothing).  Queued on the ctx stream; does not synchronise; when
+ * the step updates the parameters the renderer reads, the state kept for
+ * the backward is stale afterwards, as after hgs_adam_step. */
+hgs_status hgs_backward_adam_step(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const float *const *dL_drgb,
+                                  const hgs_adam *a);
+
 /* Deterministic-reduction mode of hgs_render_backward (a checking aid): with
  * on = 1 the blend backward uses no floating-point atomics.  Within a tile,
  * each 4x4 pixel quarter keeps its partial sums in a slot of its own and the

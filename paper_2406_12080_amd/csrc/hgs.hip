@@ -151,7 +151,8 @@ struct hgs_ctx {
     // gradient outputs its launches name
     hipGraphExec_t bexec = nullptr;
     RenderKey bkey;
-    const void *bkey_out[6] = {};
+    const void *bkey_out[21] = {};  // gradient outputs, or the fused step's parameters and moments
+    AdamScalars *adam_sc = nullptr;  // device: the fused optimiser step's scalars, one record per group
     bool bgraph_valid = false;
     bool last_graphed = false;  // the last render ran through the forward graph
 
@@ -182,17 +183,18 @@ hgs_status fail(hgs_ctx *c, hgs_status s, const std::string &msg)
             return fail(ctx, HGS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
     } while (0)
 
-// Queues the copy of the first n host view records to views_dev on st.  The
-// DMA reads a pinned staging slot, not views_host: the copy may run long
-// after this returns (behind earlier work on st), and the host records may
-// change meanwhile.  A slot is reused only once its previous copy has run.
-hgs_status stage_copy(hgs_ctx *ctx, const DevView *src, int n, DevView *dst, hipStream_t st)
+// Queues the copy of `bytes` host bytes (at most the size of kMaxViews view
+// records) to dst on st.  The DMA reads a pinned staging slot, not src: the
+// copy may run long after this returns (behind earlier work on st), and the
+// host bytes may change meanwhile.  A slot is reused only once its previous
+// copy has run.
+hgs_status stage_copy(hgs_ctx *ctx, const void *src, size_t bytes, void *dst, hipStream_t st)
 {
     const int k = ctx->stage_next;
     ctx->stage_next = (k + 1) % kStageRing;
     if (ctx->stage_used[k]) HIPC(hipEventSynchronize(ctx->stage_ev[k]));
-    memcpy(ctx->stage[k], src, sizeof(DevView) * (size_t)n);
-    HIPC(hipMemcpyAsync(dst, ctx->stage[k], sizeof(DevView) * (size_t)n, hipMemcpyHostToDevice, st));
+    memcpy(ctx->stage[k], src, bytes);
+    HIPC(hipMemcpyAsync(dst, ctx->stage[k], bytes, hipMemcpyHostToDevice, st));
     HIPC(hipEventRecord(ctx->stage_ev[k], st));
     ctx->stage_used[k] = true;
     return HGS_OK;
@@ -200,7 +202,7 @@ hgs_status stage_copy(hgs_ctx *ctx, const DevView *src, int n, DevView *dst, hip
 
 hgs_status push_views(hgs_ctx *ctx, int n, hipStream_t st)
 {
-    return stage_copy(ctx, ctx->views_host, n, ctx->views_dev, st);
+    return stage_copy(ctx, ctx->views_host, sizeof(DevView) * (size_t)n, ctx->views_dev, st);
 }
 
 hgs_status dalloc(hgs_ctx *ctx, void **p, size_t bytes)
@@ -605,7 +607,9 @@ void drop_hierarchy(hgs_ctx *ctx)
 // the gradient outputs.  Every size it launches with is a capacity or a
 // count the kernels read on the device, so that a captured copy stays valid
 // for every render of the same forward graph.
-void enqueue_backward(hgs_ctx *ctx, int nv, const hgs_grads *out, hipStream_t st)
+// With `fused` the gather applies the optimiser step instead of writing
+// gradients (out is then unused).
+void enqueue_backward(hgs_ctx *ctx, int nv, const hgs_grads *out, const AdamRows *fused, hipStream_t st)
 {
     const bool det = ctx->deterministic;
     if (det)  // every row of the emitted pair list is written or stays zero
@@ -620,7 +624,7 @@ void enqueue_backward(hgs_ctx *ctx, int nv, const hgs_grads *out, hipStream_t st
         launch_blend_backward(ctx->views_dev, nv, ctx->last_tiles, ctx->tile_sorted, ctx->ranges, vals, ctx->recs,
                               ctx->axes, ctx->T_final, ctx->n_last, ctx->qbits, ctx->pair_cap, ctx->vis_rank,
                               ctx->sgrad, det ? &da : nullptr, ctx->wstats, ctx->ctr, ctx->r_tw, ctx->r_th,
-                              ctx->r_batch, out->dt != nullptr, ctx->r_persist, ctx->queue + 1, st);
+                              ctx->r_batch, out && out->dt != nullptr, ctx->r_persist, ctx->queue + 1, st);
         if (det)
             launch_det_sum(ctx->part, ctx->pair_offsets, ctx->svals, ctx->vis_rank, &ctx->ctr->vis_total,
                            ctx->cut_cap, &ctx->ctr->pair_total, ctx->pair_cap, ctx->sgrad, st);
@@ -631,8 +635,10 @@ void enqueue_backward(hgs_ctx *ctx, int nv, const hgs_grads *out, hipStream_t st
         launch_preprocess_backward(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t,
                                    &ctx->ctr->cut_total, ctx->cut_cap, ctx->ntiles, ctx->recs, ctx->cjac,
                                    ctx->vis_rank, ctx->sgrad, ctx->pgrad, ctx->masks, (ctx->n + 63) / 64,
-                                   ctx->word_off, ctx->interior, ctx->n_interior, out->mean, out->scale, out->rot,
-                                   out->opacity, out->sh, out->dt, st);
+                                   ctx->word_off, ctx->interior, ctx->n_interior, out ? out->mean : nullptr,
+                                   out ? out->scale : nullptr, out ? out->rot : nullptr,
+                                   out ? out->opacity : nullptr, out ? out->sh : nullptr, out ? out->dt : nullptr,
+                                   fused, st);
     }
 }
 
@@ -733,6 +739,7 @@ hgs_status hgs_create(hgs_ctx **out, int device, void *hip_stream)
         if ((s = dalloc(ctx, (void **)&ctx->seg_tile_base, sizeof(uint32_t) * kMaxViews))) break;
         if ((s = dalloc(ctx, (void **)&ctx->queue, sizeof(uint32_t) * 2))) break;
         if ((s = dalloc(ctx, (void **)&ctx->l1_partial, sizeof(double) * kL1Blocks))) break;
+        if ((s = dalloc(ctx, (void **)&ctx->adam_sc, sizeof(AdamScalars) * 5))) break;
         if ((s = scratch_init(ctx))) break;
     } while (0);
     if (s != HGS_OK) {
@@ -779,19 +786,20 @@ hgs_status hgs_set_stream(hgs_ctx *ctx, void *hip_stream)
     return HGS_OK;
 }
 
-hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a)
+// Checks the optimiser arguments (the gradient arrays only when `grads`)
+// and fills the scalars of the five groups.
+static hgs_status check_adam(hgs_ctx *ctx, const hgs_adam *a, bool grads, AdamScalars sc[5])
 {
-    if (!ctx) return HGS_ERR_INVALID_ARG;
     if (!ctx->has_hier) return fail(ctx, HGS_ERR_STATE, "no hierarchy uploaded");
     if (ctx->streaming) return fail(ctx, HGS_ERR_STATE, "no optimiser step while rendering out of core");
     if (!a) return fail(ctx, HGS_ERR_INVALID_ARG, "NULL optimiser arguments");
     for (int k = 0; k < 5; ++k) {
-        if (!a->param[k] || !a->grad[k] || !a->m[k] || !a->v[k])
+        if (!a->param[k] || (grads && !a->grad[k]) || !a->m[k] || !a->v[k])
             return fail(ctx, HGS_ERR_INVALID_ARG, "NULL array of parameter group " + std::to_string(k));
         if (!std::isfinite(a->lr[k]) || a->lr[k] < 0.0f)
             return fail(ctx, HGS_ERR_INVALID_ARG, "bad learning rate of parameter group " + std::to_string(k));
         // rotation and SH rows are stepped in 16-byte vectors
-        const void *arrs[4] = {a->param[k], a->grad[k], a->m[k], a->v[k]};
+        const void *arrs[4] = {a->param[k], grads ? a->grad[k] : nullptr, a->m[k], a->v[k]};
         if (k == 2 || k == 4)
             for (const void *q : arrs)
                 if (reinterpret_cast<uintptr_t>(q) % 16 != 0)
@@ -801,16 +809,29 @@ hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a)
     if (a->step < 1 || !(a->beta1 >= 0.0f && a->beta1 < 1.0f) || !(a->beta2 >= 0.0f && a->beta2 < 1.0f) ||
         !(a->eps > 0.0f) || !std::isfinite(a->eps))
         return fail(ctx, HGS_ERR_INVALID_ARG, "bad step, beta1, beta2 or eps");
-    HIPC(hipSetDevice(ctx->device));
-    // stepping the parameters the renderer reads makes the last render stale
-    for (int k = 0; k < 5; ++k)
-        if (a->param[k] == (ctx->use_bound ? ctx->bound[k] : ctx->own[k])) ctx->have_render = false;
     const double bc1 = 1.0 / (1.0 - std::pow((double)a->beta1, (double)a->step));
     const double bc2 = 1.0 / (1.0 - std::pow((double)a->beta2, (double)a->step));
-    for (int k = 0; k < 5; ++k) {
-        const AdamScalars sc{a->lr[k], a->beta1, a->beta2, a->eps, (float)bc1, (float)bc2};
-        launch_adam(k, ctx->interior, ctx->n_interior, a->param[k], a->grad[k], a->m[k], a->v[k], sc, ctx->stream);
-    }
+    for (int k = 0; k < 5; ++k) sc[k] = AdamScalars{a->lr[k], a->beta1, a->beta2, a->eps, (float)bc1, (float)bc2};
+    return HGS_OK;
+}
+
+// stepping the parameters the renderer reads makes the last render stale
+static void adam_stepped(hgs_ctx *ctx, const hgs_adam *a)
+{
+    for (int k = 0; k < 5; ++k)
+        if (a->param[k] == (ctx->use_bound ? ctx->bound[k] : ctx->own[k])) ctx->have_render = false;
+}
+
+hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    AdamScalars sc[5];
+    if (hgs_status s = check_adam(ctx, a, true, sc)) return s;
+    HIPC(hipSetDevice(ctx->device));
+    adam_stepped(ctx, a);
+    for (int k = 0; k < 5; ++k)
+        launch_adam(k, ctx->interior, ctx->n_interior, a->param[k], a->grad[k], a->m[k], a->v[k], sc[k],
+                    ctx->stream);
     HIPC(hipGetLastError());
     return HGS_OK;
 }
@@ -1499,10 +1520,10 @@ hgs_status hgs_last_render(hgs_ctx *ctx, uint64_t *render_id, int32_t *n_views)
     return HGS_OK;
 }
 
-hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const float *const *dL_drgb,
-                               hgs_grads *out)
+// Checks the arguments of a backward of render `render_id` and puts the
+// cotangent pointers into the host view records.
+static hgs_status check_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const float *const *dL_drgb)
 {
-    if (!ctx) return HGS_ERR_INVALID_ARG;
     if (ctx->streaming) return fail(ctx, HGS_ERR_STATE, "no backward while rendering out of core");
     if (!ctx->have_render || ctx->render_param_gen != ctx->param_gen)
         return fail(ctx, HGS_ERR_STATE, "render_backward needs a render with the current parameters");
@@ -1514,20 +1535,39 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views
         return fail(ctx, HGS_ERR_INVALID_ARG, "render " + std::to_string(render_id) + " has " +
                                                   std::to_string(ctx->last_nv) + " views, not " +
                                                   std::to_string(n_views));
-    if (!dL_drgb || !out || !out->mean || !out->scale || !out->rot || !out->opacity || !out->sh)
-        return fail(ctx, HGS_ERR_INVALID_ARG, "bad gradient arguments");
-    const int nv = ctx->last_nv;
-    for (int v = 0; v < nv; ++v) {
+    if (!dL_drgb) return fail(ctx, HGS_ERR_INVALID_ARG, "bad gradient arguments");
+    for (int v = 0; v < ctx->last_nv; ++v) {
         if (!dL_drgb[v]) return fail(ctx, HGS_ERR_INVALID_ARG, "dL_drgb[" + std::to_string(v) + "] is NULL");
         ctx->views_host[v].dL = dL_drgb[v];
     }
+    return HGS_OK;
+}
+
+// Queues the backward of the last render into `out`, or, with `fused`,
+// with the optimiser step applied in the gather (scalars: 5 host records).
+// A render of several views replays a captured graph, keyed by the render's
+// graph and every output array.
+static hgs_status run_backward(hgs_ctx *ctx, const hgs_grads *out, const AdamRows *fused, const AdamScalars *scalars)
+{
+    const int nv = ctx->last_nv;
     HIPC(hipSetDevice(ctx->device));
     if (ctx->deterministic && ctx->part_cap < ctx->pair_cap) {
         if (hgs_status s = realloc_buf(ctx, ctx->part, (size_t)ctx->pair_cap * 11)) return s;
         ctx->part_cap = ctx->pair_cap;
         ctx->bgraph_valid = false;
     }
-    const void *outs[6] = {out->mean, out->scale, out->rot, out->opacity, out->sh, out->dt};
+    const void *outs[21] = {};
+    if (fused) {
+        for (int k = 0; k < 5; ++k) {
+            outs[6 + k] = fused->p[k];
+            outs[11 + k] = fused->m[k];
+            outs[16 + k] = fused->v[k];
+        }
+    } else {
+        const void *g[6] = {out->mean, out->scale, out->rot, out->opacity, out->sh, out->dt};
+        memcpy(outs, g, sizeof g);
+    }
+    hipStream_t st = ctx->last_graphed ? ctx->gstream : ctx->stream;
     if (ctx->last_graphed) {
         // replay (or capture once) the backward on the library stream, in
         // order with the caller's stream on both sides
@@ -1538,9 +1578,9 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views
                 ctx->bexec = nullptr;
             }
             hipGraph_t g = nullptr;
-            HIPC(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
-            enqueue_backward(ctx, nv, out, ctx->gstream);
-            HIPC(hipStreamEndCapture(ctx->gstream, &g));
+            HIPC(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            enqueue_backward(ctx, nv, out, fused, st);
+            HIPC(hipStreamEndCapture(st, &g));
             hipError_t e = hipGraphInstantiate(&ctx->bexec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess)
@@ -1550,19 +1590,50 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views
             ctx->bgraph_valid = true;
         }
         HIPC(hipEventRecord(ctx->ev_in, ctx->stream));
-        HIPC(hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
-        if (hgs_status s = push_views(ctx, nv, ctx->gstream)) return s;
-        HIPC(hipGraphLaunch(ctx->bexec, ctx->gstream));
-        HIPC(hipEventRecord(ctx->ev_out, ctx->gstream));
+        HIPC(hipStreamWaitEvent(st, ctx->ev_in, 0));
+    }
+    if (hgs_status s = push_views(ctx, nv, st)) return s;
+    if (fused)
+        if (hgs_status s = stage_copy(ctx, scalars, sizeof(AdamScalars) * 5, ctx->adam_sc, st)) return s;
+    if (ctx->last_graphed) {
+        HIPC(hipGraphLaunch(ctx->bexec, st));
+        HIPC(hipEventRecord(ctx->ev_out, st));
         HIPC(hipStreamWaitEvent(ctx->stream, ctx->ev_out, 0));
     } else {
-        hipStream_t st = ctx->stream;
-        if (hgs_status s = push_views(ctx, nv, st)) return s;
-        enqueue_backward(ctx, nv, out, st);
+        enqueue_backward(ctx, nv, out, fused, st);
     }
     HIPC(hipGetLastError());
     // host copy of views keeps dL for nothing else
     for (int v = 0; v < nv; ++v) ctx->views_host[v].dL = nullptr;
+    return HGS_OK;
+}
+
+hgs_status hgs_render_backward(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const float *const *dL_drgb,
+                               hgs_grads *out)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (hgs_status s = check_backward(ctx, render_id, n_views, dL_drgb)) return s;
+    if (!out || !out->mean || !out->scale || !out->rot || !out->opacity || !out->sh)
+        return fail(ctx, HGS_ERR_INVALID_ARG, "bad gradient arguments");
+    return run_backward(ctx, out, nullptr, nullptr);
+}
+
+hgs_status hgs_backward_adam_step(hgs_ctx *ctx, uint64_t render_id, int32_t n_views, const float *const *dL_drgb,
+                                  const hgs_adam *a)
+{
+    if (!ctx) return HGS_ERR_INVALID_ARG;
+    if (hgs_status s = check_backward(ctx, render_id, n_views, dL_drgb)) return s;
+    AdamScalars sc[5];
+    if (hgs_status s = check_adam(ctx, a, false, sc)) return s;
+    AdamRows rows{};
+    for (int k = 0; k < 5; ++k) {
+        rows.p[k] = a->param[k];
+        rows.m[k] = a->m[k];
+        rows.v[k] = a->v[k];
+    }
+    rows.sc = ctx->adam_sc;
+    if (hgs_status s = run_backward(ctx, nullptr, &rows, sc)) return s;
+    adam_stepped(ctx, a);
     return HGS_OK;
 }
 

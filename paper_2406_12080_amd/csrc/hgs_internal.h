@@ -321,20 +321,43 @@ void launch_blend_backward(const DevView *views, int nv, uint32_t n_tiles, const
                            double *sgrad, const DetArgs *det, uint4 *wstats,
                            Counters *ctr, int tw, int th, int batch, bool want_dt, bool persist, uint32_t *queue,
                            hipStream_t st);
-void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32_t vis_cap, hipStream_t st);
-void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
-                                const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
-                                const uint32_t *ntiles, const SplatRec *recs, const float *cjac,
-                                const uint32_t *vis_rank, const double *sgrad, float *pg, const uint64_t *masks, int64_t words, const uint32_t *word_off,
-                                const int32_t *interior, int64_t n_interior, float *g_mean, float *g_scale,
-                                float *g_rot, float *g_opacity, float *g_sh, float *g_dt, hipStream_t st);
-
 // optimiser step (Adam) over the interior nodes of one parameter group
 // (0 mean, 1 scale, 2 rotation, 3 opacity, 4 SH); bc1 = 1 / (1 - beta1^t),
 // bc2 = 1 / (1 - beta2^t)
 struct AdamScalars {
     float lr, beta1, beta2, eps, bc1, bc2;
 };
+
+// One Adam update of one element (the step of 3D Gaussian Splatting's
+// optimiser, bias-corrected): the separate optimiser step and the one fused
+// into the gradient gather both call it, so that they agree bit for bit.
+// The fused multiply-adds are written out and no other contraction is
+// allowed: left to the compiler, the choice of which product to fuse
+// differed between the two kernels.
+__device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, const AdamScalars &s)
+{
+#pragma clang fp contract(off)
+    m = fmaf(s.beta1, m, (1.0f - s.beta1) * g);
+    v = fmaf(s.beta2, v, ((1.0f - s.beta2) * g) * g);
+    p -= s.lr * (m * s.bc1) / (sqrtf(v * s.bc2) + s.eps);
+}
+
+// The optimiser step fused into the backward's gradient gather: per group
+// the parameters (node-major) and both moments (by interior rank), and the
+// group's scalars in device memory (5 records, written before each launch).
+struct AdamRows {
+    float *p[5], *m[5], *v[5];
+    const AdamScalars *sc;
+};
+void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32_t vis_cap, hipStream_t st);
+void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
+                                const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
+                                const uint32_t *ntiles, const SplatRec *recs, const float *cjac,
+                                const uint32_t *vis_rank, const double *sgrad, float *pg, const uint64_t *masks, int64_t words, const uint32_t *word_off,
+                                const int32_t *interior, int64_t n_interior, float *g_mean, float *g_scale,
+                                float *g_rot, float *g_opacity, float *g_sh, float *g_dt, const AdamRows *fused,
+                                hipStream_t st);
+
 void launch_adam(int group, const int32_t *interior, int64_t n_interior, float *p, float *g, float *m, float *v,
                  const AdamScalars &s, hipStream_t st);
 

@@ -14,14 +14,6 @@ namespace {
 
 constexpr int kT = 256;
 
-__device__ __forceinline__ float adam_one(float &p, float g, float &m, float &v, const AdamScalars &s)
-{
-    m = s.beta1 * m + (1.0f - s.beta1) * g;
-    v = s.beta2 * v + (1.0f - s.beta2) * g * g;
-    p -= s.lr * (m * s.bc1) / (sqrtf(v * s.bc2) + s.eps);
-    return p;
-}
-
 // One thread per element of a group with COMP components per node (the
 // rows of the moments are contiguous, element e = q COMP + c).
 template <int COMP>

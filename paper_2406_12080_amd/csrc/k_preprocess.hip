@@ -623,8 +623,109 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
 // cut are consecutive cut entries, so one or two mask words give all of
 // them at once.  The mask words of kGatherViews views are loaded together;
 // positions and entries are read only for the views that hold one.
+//
+// FUSED: instead of adding the sum to the gradient arrays, the thread
+// applies the optimiser step to its node right away (every interior node,
+// those with no contribution too, whose gradient is zero): the gradient is
+// never written, re-read or cleared.
 constexpr int kGatherViews = 8;
 
+// The fused optimiser step of one block: thread t holds the gathered
+// gradient of interior node q0 + t (node id `node`; zero past the end).  The
+// rows go through LDS so that the update walks the moments contiguously and
+// each parameter row with consecutive lanes, as the separate step does:
+// first the 11 floats of mean, scale, rotation and opacity of all rows, then
+// the 48 SH floats of 64 rows at a time.  The separate step reads 0 + sum
+// from a cleared gradient array; the same value is formed here (it turns -0
+// into +0), and the arithmetic is the same function, so both agree bit for
+// bit.  Every thread of the block calls it (barriers).
+constexpr int kAdamLds = 64 * 48;  // floats of the staging buffer (>= kT x 11)
+static_assert(kT * 11 <= kAdamLds && kT % 64 == 0, "staging buffer");
+
+__device__ __forceinline__ void adam_block(const AdamRows &ad, const int32_t *__restrict__ interior,
+                                           int64_t n_interior, int64_t q0, int32_t node, const float (&a)[11],
+                                           const float (&ash)[48])
+{
+    __shared__ float s_g[kAdamLds];
+    __shared__ int32_t s_node[kT];
+    const int t = threadIdx.x;
+    const int rows = (int)min<int64_t>(kT, n_interior - q0);  // >= 1: the block holds an interior node
+    s_node[t] = node;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) s_g[11 * t + k] = a[k];
+    __syncthreads();
+    // mean and scale: 3 floats per row
+#pragma unroll
+    for (int grp = 0; grp < 2; ++grp) {
+        const AdamScalars s = ad.sc[grp];
+        float *p = ad.p[grp], *m = ad.m[grp] + 3 * q0, *v = ad.v[grp] + 3 * q0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int e = t + kT * k, r = e / 3, c = e - 3 * r;
+            if (r < rows) {
+                const int64_t pi = 3 * (int64_t)s_node[r] + c;
+                float pk = p[pi], mk = m[e], vk = v[e];
+                adam_one(pk, 0.0f + s_g[11 * r + 3 * grp + c], mk, vk, s);
+                p[pi] = pk;
+                m[e] = mk;
+                v[e] = vk;
+            }
+        }
+    }
+    if (t < rows) {
+        // rotation: one 16-byte row per thread; opacity: one float
+        const AdamScalars s = ad.sc[2];
+        float4 *p4 = reinterpret_cast<float4 *>(ad.p[2]) + node, *m4 = reinterpret_cast<float4 *>(ad.m[2]) + q0 + t,
+               *v4 = reinterpret_cast<float4 *>(ad.v[2]) + q0 + t;
+        float4 pk = *p4, mk = *m4, vk = *v4;
+        adam_one(pk.x, 0.0f + a[6], mk.x, vk.x, s);
+        adam_one(pk.y, 0.0f + a[7], mk.y, vk.y, s);
+        adam_one(pk.z, 0.0f + a[8], mk.z, vk.z, s);
+        adam_one(pk.w, 0.0f + a[9], mk.w, vk.w, s);
+        *p4 = pk;
+        *m4 = mk;
+        *v4 = vk;
+        const AdamScalars so = ad.sc[3];
+        float po = ad.p[3][node], mo = ad.m[3][q0 + t], vo = ad.v[3][q0 + t];
+        adam_one(po, 0.0f + a[10], mo, vo, so);
+        ad.p[3][node] = po;
+        ad.m[3][q0 + t] = mo;
+        ad.v[3][q0 + t] = vo;
+    }
+    // SH: 64 rows of 12 float4 at a time
+    const AdamScalars s = ad.sc[4];
+    float4 *p4 = reinterpret_cast<float4 *>(ad.p[4]);
+    float4 *m4 = reinterpret_cast<float4 *>(ad.m[4]) + 12 * q0, *v4 = reinterpret_cast<float4 *>(ad.v[4]) + 12 * q0;
+    float4 *g4 = reinterpret_cast<float4 *>(s_g);
+#pragma unroll 1
+    for (int r0 = 0; r0 < rows; r0 += 64) {
+        __syncthreads();  // the previous contents read
+        if (t >= r0 && t < r0 + 64)
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                g4[12 * (t - r0) + k] = make_float4(ash[4 * k], ash[4 * k + 1], ash[4 * k + 2], ash[4 * k + 3]);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int e = t + kT * k, r = e / 12, c = e - 12 * r;  // row r0 + r, vector c
+            if (r0 + r < rows) {
+                const int64_t pi = 12 * (int64_t)s_node[r0 + r] + c;
+                const int64_t mi = 12 * (int64_t)r0 + e;
+                const float4 g = g4[e];
+                float4 pk = p4[pi], mk = m4[mi], vk = v4[mi];
+                adam_one(pk.x, 0.0f + g.x, mk.x, vk.x, s);
+                adam_one(pk.y, 0.0f + g.y, mk.y, vk.y, s);
+                adam_one(pk.z, 0.0f + g.z, mk.z, vk.z, s);
+                adam_one(pk.w, 0.0f + g.w, mk.w, vk.w, s);
+                p4[pi] = pk;
+                m4[mi] = mk;
+                v4[mi] = vk;
+            }
+        }
+    }
+}
+
+template <bool FUSED>
 __global__ __launch_bounds__(kT, 4) void k_grad_gather(DevHier h, int nv, const uint64_t *__restrict__ masks,
                                                     int64_t words, const uint32_t *__restrict__ word_off,
                                                     const uint32_t *__restrict__ cut_total, uint32_t cap,
@@ -633,13 +734,12 @@ __global__ __launch_bounds__(kT, 4) void k_grad_gather(DevHier h, int nv, const 
                                                     const int32_t *__restrict__ interior, int64_t n_interior,
                                                     float *__restrict__ g_mean, float *__restrict__ g_scale,
                                                     float *__restrict__ g_rot, float *__restrict__ g_op,
-                                                    float *__restrict__ g_sh)
+                                                    float *__restrict__ g_sh, AdamRows ad)
 {
     const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (q >= n_interior) return;
-    const uint32_t total = min(*cut_total, cap);
-    const int64_t i = interior[q];
-    const int64_t c0 = h.child_begin[i], c1 = c0 + h.child_count[i];  // children [c0, c1)
+    const bool valid = q < n_interior;  // the fused step's threads past the end still help in its update
+    if (!FUSED && !valid) return;
+    const int64_t i = valid ? interior[q] : 0;
     float a[11];  // mean 3, scale 3, rotation 4, opacity
     float ash[48];
 #pragma unroll
@@ -647,78 +747,86 @@ __global__ __launch_bounds__(kT, 4) void k_grad_gather(DevHier h, int nv, const 
 #pragma unroll
     for (int m = 0; m < 48; ++m) ash[m] = 0.0f;
     bool any = false;
-    // adds the attribute gradient of entry pos, weighted 1 - t as the node's
-    // own entry (op 10: node opacity term) or t as a child's entry (op 11:
-    // parent opacity term; none when t = 0).  The row (all eight vectors at
-    // once) is read only for a visible entry that contributes.
-    auto take = [&](uint32_t pos, int op) {
-        if (pos >= total) return;
-        const uint32_t nt = ntiles[pos];
-        const float t = (float)cut_t[pos];
-        if (nt == 0 || (op == 11 && !(t > 0.0f))) return;
-        const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pos * kPG);
-        const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4];
-        if (r4.w == 0.0f) return;  // no live splat
-        const float w = op == 10 ? 1.0f - t : t;
-        const float g[15] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
-                             r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z};
-#pragma unroll
-        for (int m = 0; m < 10; ++m) a[m] += w * g[m];
-        a[10] += op == 10 ? g[10] : g[11];
-        float Y[16];  // the SH basis of the entry's direction, in FP32 as the forward evaluated it
-        sh_eval_f(r3.w, r4.x, r4.y, Y);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float wc = w * g[12 + c];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) ash[3 * k + c] += wc * Y[k];
-        }
-        any = true;
-    };
-    const int64_t wi = i >> 6, wa = c0 >> 6, wb = (c1 - 1) >> 6;
-    const uint64_t below_i = (1ull << (i & 63)) - 1ull, own_bit = 1ull << (i & 63);
-    // the children's bits in their first word (wa) and last word (wb)
-    const int lo = (int)(c0 & 63), hi = (int)((c1 - 1) & 63);
-    const uint64_t k_lo = ~((1ull << lo) - 1ull), k_hi = hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull);
-    const uint64_t ka = wa == wb ? (k_lo & k_hi) : k_lo, kb = wa == wb ? 0ull : k_hi;
-    const bool wide = wb - wa > 1;  // children over more than two words: every view is looked at
-#pragma unroll 1
-    for (int v0 = 0; v0 < nv; v0 += kGatherViews) {
-        // the views of this group that hold the node or one of its children
-        // (their mask words loaded together)
-        uint32_t hit = 0;
-        if (wide) {
-            hit = (1u << min(kGatherViews, nv - v0)) - 1u;
-        } else {
-#pragma unroll
-            for (int u = 0; u < kGatherViews; ++u) {
-                const int v = v0 + u;
-                if (v < nv) {
-                    const uint64_t *mv = masks + (int64_t)v * words;
-                    const uint64_t mo = mv[wi], ma = mv[wa], mb = kb ? mv[wb] : 0ull;
-                    hit |= ((mo & own_bit) || (ma & ka) || (mb & kb)) ? 1u << u : 0u;
+    if (valid) {
+        const uint32_t total = min(*cut_total, cap);
+        const int64_t c0 = h.child_begin[i], c1 = c0 + h.child_count[i];  // children [c0, c1)
+        // adds the attribute gradient of entry pos, weighted 1 - t as the node's
+        // own entry (op 10: node opacity term) or t as a child's entry (op 11:
+        // parent opacity term; none when t = 0).  The row (all eight vectors at
+        // once) is read only for a visible entry that contributes.
+        auto take = [&](uint32_t pos, int op) {
+            if (pos >= total) return;
+            const uint32_t nt = ntiles[pos];
+            const float t = (float)cut_t[pos];
+            if (nt == 0 || (op == 11 && !(t > 0.0f))) return;
+            const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pos * kPG);
+            const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4];
+            if (r4.w == 0.0f) return;  // no live splat
+            const float w = op == 10 ? 1.0f - t : t;
+            const float g[15] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                                 r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z};
+    #pragma unroll
+            for (int m = 0; m < 10; ++m) a[m] += w * g[m];
+            a[10] += op == 10 ? g[10] : g[11];
+            float Y[16];  // the SH basis of the entry's direction, in FP32 as the forward evaluated it
+            sh_eval_f(r3.w, r4.x, r4.y, Y);
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float wc = w * g[12 + c];
+    #pragma unroll
+                for (int k = 0; k < 16; ++k) ash[3 * k + c] += wc * Y[k];
+            }
+            any = true;
+        };
+        const int64_t wi = i >> 6, wa = c0 >> 6, wb = (c1 - 1) >> 6;
+        const uint64_t below_i = (1ull << (i & 63)) - 1ull, own_bit = 1ull << (i & 63);
+        // the children's bits in their first word (wa) and last word (wb)
+        const int lo = (int)(c0 & 63), hi = (int)((c1 - 1) & 63);
+        const uint64_t k_lo = ~((1ull << lo) - 1ull), k_hi = hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull);
+        const uint64_t ka = wa == wb ? (k_lo & k_hi) : k_lo, kb = wa == wb ? 0ull : k_hi;
+        const bool wide = wb - wa > 1;  // children over more than two words: every view is looked at
+    #pragma unroll 1
+        for (int v0 = 0; v0 < nv; v0 += kGatherViews) {
+            // the views of this group that hold the node or one of its children
+            // (their mask words loaded together)
+            uint32_t hit = 0;
+            if (wide) {
+                hit = (1u << min(kGatherViews, nv - v0)) - 1u;
+            } else {
+    #pragma unroll
+                for (int u = 0; u < kGatherViews; ++u) {
+                    const int v = v0 + u;
+                    if (v < nv) {
+                        const uint64_t *mv = masks + (int64_t)v * words;
+                        const uint64_t mo = mv[wi], ma = mv[wa], mb = kb ? mv[wb] : 0ull;
+                        hit |= ((mo & own_bit) || (ma & ka) || (mb & kb)) ? 1u << u : 0u;
+                    }
                 }
             }
-        }
-        while (hit) {
-            const int v = v0 + __ffs(hit) - 1;
-            hit &= hit - 1u;
-            const uint64_t *mv = masks + (int64_t)v * words;
-            const uint32_t *ov = word_off + (int64_t)v * words;
-            // own entry
-            const uint64_t mo = mv[wi];
-            if (mo & own_bit) take(ov[wi] + (uint32_t)__popcll(mo & below_i), 10);
-            // children: the selected ones among [c0, c1) are consecutive entries from p0
-            uint32_t p0 = ~0u, nsel = 0;
-            for (int64_t w = wa; w <= wb; ++w) {
-                const uint64_t mw = mv[w];
-                const uint64_t m = mw & (w == wa ? k_lo : ~0ull) & (w == wb ? k_hi : ~0ull);
-                if (!m) continue;
-                if (p0 == ~0u) p0 = ov[w] + (uint32_t)__popcll(mw & ((m & (~m + 1ull)) - 1ull));
-                nsel += (uint32_t)__popcll(m);
+            while (hit) {
+                const int v = v0 + __ffs(hit) - 1;
+                hit &= hit - 1u;
+                const uint64_t *mv = masks + (int64_t)v * words;
+                const uint32_t *ov = word_off + (int64_t)v * words;
+                // own entry
+                const uint64_t mo = mv[wi];
+                if (mo & own_bit) take(ov[wi] + (uint32_t)__popcll(mo & below_i), 10);
+                // children: the selected ones among [c0, c1) are consecutive entries from p0
+                uint32_t p0 = ~0u, nsel = 0;
+                for (int64_t w = wa; w <= wb; ++w) {
+                    const uint64_t mw = mv[w];
+                    const uint64_t m = mw & (w == wa ? k_lo : ~0ull) & (w == wb ? k_hi : ~0ull);
+                    if (!m) continue;
+                    if (p0 == ~0u) p0 = ov[w] + (uint32_t)__popcll(mw & ((m & (~m + 1ull)) - 1ull));
+                    nsel += (uint32_t)__popcll(m);
+                }
+                for (uint32_t k = 0; k < nsel; ++k) take(p0 + k, 11);
             }
-            for (uint32_t k = 0; k < nsel; ++k) take(p0 + k, 11);
         }
+    }
+    if constexpr (FUSED) {
+        adam_block(ad, interior, n_interior, (int64_t)blockIdx.x * kT, (int32_t)i, a, ash);
+        return;
     }
     if (!any) return;
     // node-major records: vector read-modify-write
@@ -866,17 +974,22 @@ void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, 
                                 const uint32_t *vis_rank, const double *sgrad, float *pg, const uint64_t *masks,
                                 int64_t words, const uint32_t *word_off, const int32_t *interior, int64_t n_interior,
                                 float *g_mean, float *g_scale, float *g_rot, float *g_opacity, float *g_sh,
-                                float *g_dt, hipStream_t st)
+                                float *g_dt, const AdamRows *fused, hipStream_t st)
 {
     const uint32_t blocks = (cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(kT), 0, st, h, views, nv, cut_base, cut_ids, cut_t,
                        cut_total, cap, ntiles, recs, cjac, vis_rank, sgrad, pg, g_dt);
     const int64_t gblocks = (n_interior + kT - 1) / kT;
-    if (gblocks)
-        hipLaunchKernelGGL(k_grad_gather, dim3((uint32_t)gblocks), dim3(kT), 0, st, h, nv, masks, words, word_off,
-                           cut_total, cap, cut_t, ntiles, pg, interior, n_interior, g_mean, g_scale, g_rot,
-                           g_opacity, g_sh);
+    if (!gblocks) return;
+    if (fused)
+        hipLaunchKernelGGL(k_grad_gather<true>, dim3((uint32_t)gblocks), dim3(kT), 0, st, h, nv, masks, words,
+                           word_off, cut_total, cap, cut_t, ntiles, pg, interior, n_interior, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, *fused);
+    else
+        hipLaunchKernelGGL(k_grad_gather<false>, dim3((uint32_t)gblocks), dim3(kT), 0, st, h, nv, masks, words,
+                           word_off, cut_total, cap, cut_t, ntiles, pg, interior, n_interior, g_mean, g_scale, g_rot,
+                           g_opacity, g_sh, AdamRows{});
 }
 
 }  // namespace hgs

@@ -21,7 +21,7 @@ _NAMES = {0: "HGS_OK", 1: "HGS_ERR_INVALID_ARG", 2: "HGS_ERR_OOM", 3: "HGS_ERR_H
 EXPORTS = ("hgs_create", "hgs_destroy", "hgs_last_error", "hgs_set_stream", "hgs_upload", "hgs_bind_params",
            "hgs_build", "hgs_download", "hgs_cut", "hgs_cut_noalloc", "hgs_compact_mark", "hgs_compact_rebuild", "hgs_render", "hgs_last_render",
            "hgs_render_backward", "hgs_l1_loss", "hgs_stream_begin", "hgs_stream_end", "hgs_stream_cleanup",
-           "hgs_stream_info", "hgs_adam_step", "hgs_interior", "hgs_set_deterministic", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
+           "hgs_stream_info", "hgs_adam_step", "hgs_backward_adam_step", "hgs_interior", "hgs_set_deterministic", "hgs_set_tuning", "hgs_get_buffer", "hgs_set_profiling",
            "hgs_kernel_time", "hgs_counters")
 COUNTER_NAMES = ("cut", "visible", "pairs", "evaluated", "blended", "evaluated_t", "bwd_evaluated",
                  "bwd_evaluated_t", "bwd_contrib")
@@ -119,6 +119,7 @@ def lib():
         L.hgs_render_backward.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, P(vp), P(Grads)]
         L.hgs_l1_loss.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, P(vp), P(vp), vp]
         L.hgs_adam_step.argtypes = [vp, P(Adam)]
+        L.hgs_backward_adam_step.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, P(vp), P(Adam)]
         L.hgs_stream_begin.argtypes = [vp, ctypes.c_int64]
         L.hgs_stream_end.argtypes = [vp]
         L.hgs_stream_cleanup.argtypes = [vp, ctypes.c_int32]
@@ -372,17 +373,9 @@ class Renderer:
         ``dL`` holds one float32 [H, W, 3] CUDA tensor per view of that
         render; ``dt`` (optional) room for dL/dt of every cut entry."""
         torch = self.torch
-        if self._last is None:
-            raise HgsError(ERR_STATE, "no render on this renderer")
-        rid = self._last[0] if render_id is None else int(render_id)
+        rid = self._check_cotangents(dL, render_id)
         if rid == self._last[0]:
-            shapes, n_cut = self._last[1], self._last[2]
-            if len(dL) != len(shapes):
-                raise HgsError(ERR_INVALID_ARG, f"{len(dL)} cotangents for a render of {len(shapes)} views")
-            for k, (g, shp) in enumerate(zip(dL, shapes)):
-                if not (g.is_cuda and g.dtype == torch.float32 and tuple(g.shape) == shp):
-                    raise HgsError(ERR_INVALID_ARG, f"dL[{k}] must be a float32 CUDA tensor of shape {shp}, "
-                                                    f"not {g.dtype} {tuple(g.shape)}")
+            n_cut = self._last[2]
             if dt is not None and not (dt.is_cuda and dt.dtype == torch.float32 and dt.numel() >= n_cut):
                 raise HgsError(ERR_INVALID_ARG, f"dt must be a float32 CUDA tensor of at least {n_cut} entries")
         comp = dict(mean=3, scale=3, rot=4, opacity=1, sh=48)
@@ -400,6 +393,23 @@ class Renderer:
         g.dt = dt.data_ptr() if dt is not None else None
         self._keep = dL
         self._check(self.L.hgs_render_backward(self.h, rid, len(dL), ptrs, ctypes.byref(g)))
+
+    def _check_cotangents(self, dL, render_id):
+        """The render id a backward names; checks the cotangents' shapes
+        when it is this renderer's last render (the library rejects any
+        other id)."""
+        if self._last is None:
+            raise HgsError(ERR_STATE, "no render on this renderer")
+        rid = self._last[0] if render_id is None else int(render_id)
+        if rid == self._last[0]:
+            shapes = self._last[1]
+            if len(dL) != len(shapes):
+                raise HgsError(ERR_INVALID_ARG, f"{len(dL)} cotangents for a render of {len(shapes)} views")
+            for k, (g, shp) in enumerate(zip(dL, shapes)):
+                if not (g.is_cuda and g.dtype == self.torch.float32 and tuple(g.shape) == shp):
+                    raise HgsError(ERR_INVALID_ARG, f"dL[{k}] must be a float32 CUDA tensor of shape {shp}, "
+                                                    f"not {g.dtype} {tuple(g.shape)}")
+        return rid
 
     def l1_loss(self, targets, dL=None, loss=None):
         """``hgs_l1_loss`` of this renderer's last render against ``targets``
@@ -486,15 +496,40 @@ class Renderer:
         dicts hold CUDA tensors keyed like the parameters, ``m`` and ``v``
         with one row per interior node (``adam_moments``); ``lr`` is one
         float or a dict per parameter group.  Zeroes ``grads``."""
+        a = self._adam_args(params, grads, m, v, lr, step, beta1, beta2, eps)
+        self._check(self.L.hgs_adam_step(self.h, ctypes.byref(a)))
+
+    def _adam_args(self, params, grads, m, v, lr, step, beta1, beta2, eps):
         a = Adam()
+        comp = dict(mean=3, scale=3, rot=4, opacity=1, sh=48)
+        n_int = self.n_interior()
         for k, name in enumerate(PARAM_FIELDS):
-            for arr, d in ((a.param, params), (a.grad, grads), (a.m, m), (a.v, v)):
+            for arr, d, rows in ((a.param, params, self.n_nodes), (a.grad, grads, self.n_nodes), (a.m, m, n_int),
+                                 (a.v, v, n_int)):
+                if d is None:
+                    continue
                 t = d[name]
-                assert t.is_cuda and t.is_contiguous() and t.dtype == self.torch.float32
+                if not (t.is_cuda and t.is_contiguous() and t.dtype == self.torch.float32 and
+                        t.numel() == comp[name] * rows):
+                    raise HgsError(ERR_INVALID_ARG, f"{name}: optimiser arrays must be contiguous float32 CUDA "
+                                                    f"tensors of {rows} x {comp[name]} entries")
                 arr[k] = t.data_ptr()
             a.lr[k] = float(lr[name] if isinstance(lr, dict) else lr)
         a.beta1, a.beta2, a.eps, a.step = float(beta1), float(beta2), float(eps), int(step)
-        self._check(self.L.hgs_adam_step(self.h, ctypes.byref(a)))
+        return a
+
+    def backward_adam_step(self, dL, params: dict, m: dict, v: dict, lr, step: int, beta1: float = 0.9,
+                           beta2: float = 0.999, eps: float = 1e-15, render_id: int | None = None) -> None:
+        """The backward of a render with the optimiser step applied in the
+        gradient gather (``hgs_backward_adam_step``): the result of
+        ``backward`` into zeroed gradients followed by ``adam_step``, with no
+        gradient arrays.  Arguments as for those two calls."""
+        rid = self._check_cotangents(dL, render_id)
+        dL = [g.contiguous() for g in dL]
+        ptrs = (ctypes.c_void_p * len(dL))(*[g.data_ptr() for g in dL])
+        a = self._adam_args(params, None, m, v, lr, step, beta1, beta2, eps)
+        self._keep = dL
+        self._check(self.L.hgs_backward_adam_step(self.h, rid, len(dL), ptrs, ctypes.byref(a)))
 
     def counters(self) -> dict:
         out = (ctypes.c_int64 * len(COUNTER_NAMES))()

@@ -12,9 +12,12 @@ over the range (uniform in log tau); the loss is the L1 image distance and
 the optimiser Adam on the interior nodes.
 
 Every step runs in the library: ``hgs_render`` (cut, interpolation and
-splatting of the batch), ``hgs_l1_loss`` (loss and cotangent),
-``hgs_render_backward`` and ``hgs_adam_step``.  This module only draws the
-views and passes pointers; nothing of a step is computed in Python.
+splatting of the batch), ``hgs_l1_loss`` (loss and cotangent) and
+``hgs_backward_adam_step`` (the backward with the Adam update applied in its
+gradient gather; ``fused=False`` takes ``hgs_render_backward`` into gradient
+arrays and ``hgs_adam_step`` instead, with the same result bit for bit).
+This module only draws the views and passes pointers; nothing of a step is
+computed in Python.
 """
 from __future__ import annotations
 
@@ -46,12 +49,13 @@ class HierarchyOptimizer:
     training cameras (``synth.View``-like); targets: one float32 [H, W, 3]
     CUDA tensor per training view.  Each step draws ``batch`` distinct
     training views (all of them when there are fewer), gives each a tau
-    drawn log-uniform over ``tau_range`` and takes one Adam step.
+    drawn log-uniform over ``tau_range`` and takes one Adam step (fused
+    into the backward unless ``fused`` is False).
     """
 
     def __init__(self, renderer: hgs.Renderer, params: dict, train_views, targets, lr=None,
                  tau_range=(3.0, 15.0), batch: int = 32, beta1: float = 0.9, beta2: float = 0.999,
-                 eps: float = 1e-15, seed: int = 0):
+                 eps: float = 1e-15, seed: int = 0, fused: bool = True):
         import torch
         if len(train_views) != len(targets) or not train_views:
             raise ValueError("one target image per training view, at least one view")
@@ -68,7 +72,8 @@ class HierarchyOptimizer:
         self.beta1, self.beta2, self.eps = beta1, beta2, eps
         self.rng = np.random.default_rng(seed)
         self.m, self.v = renderer.adam_moments(params)  # one row per interior node
-        self.grads = {k: torch.zeros_like(t) for k, t in params.items()}
+        self.fused = bool(fused)
+        self.grads = None if self.fused else {k: torch.zeros_like(t) for k, t in params.items()}
         self.t = 0  # Adam's step count
         self._imgs = {}
         self._dl = {}
@@ -107,8 +112,12 @@ class HierarchyOptimizer:
         self.r.render(views, out=imgs)
         loss = self.loss.clone()
         self.r.l1_loss([self.targets[i] for i in idx], dL, loss)
-        self.r.backward(dL, self.grads)
         self.t += 1
-        self.r.adam_step(self.params, self.grads, self.m, self.v, self.lr, self.t, self.beta1, self.beta2,
-                         self.eps)
+        if self.fused:
+            self.r.backward_adam_step(dL, self.params, self.m, self.v, self.lr, self.t, self.beta1, self.beta2,
+                                      self.eps)
+        else:
+            self.r.backward(dL, self.grads)
+            self.r.adam_step(self.params, self.grads, self.m, self.v, self.lr, self.t, self.beta1, self.beta2,
+                             self.eps)
         return loss, (idx, views)

@@ -124,3 +124,69 @@ def test_optimizer_steps_match_oracle(case):
             assert np.linalg.norm(du_o) > 0 and rel <= 1e-2, (k, rel)
     finally:
         r.close()
+
+
+@pytest.mark.parametrize("nv", [1, 3])
+def test_fused_backward_adam_step_equals_separate(nv):
+    """hgs_backward_adam_step against hgs_render_backward into zeroed
+    gradients followed by hgs_adam_step: parameters and both moments equal
+    bit for bit over three steps (the backward in its deterministic mode, so
+    that both runs gather the same sums), for one view (stages launched one
+    by one) and for three (the captured graph)."""
+    from paper_2406_12080_amd import hgs
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    h = synth.make_scene(2, n_leaves=60_000)
+    rng = np.random.default_rng(5)
+    r = hgs.Renderer(0)
+    try:
+        r.upload(h)
+        P = hgs.params_to_device(h)
+        r.bind(*[P[k] for k in hgs.PARAM_FIELDS])
+        r.set_deterministic(True)
+        PA = {k: t.clone() for k, t in P.items()}
+        PB = {k: t.clone() for k, t in P.items()}
+        MA, VA = r.adam_moments(P)
+        MB, VB = r.adam_moments(P)
+        G = {k: torch.zeros_like(t) for k, t in P.items()}
+        lr = {k: _f32(x) for k, x in LR.items()}
+        inner = torch.from_numpy(np.asarray(h.child_count) > 0).cuda()
+        for step in range(1, 4):
+            views = [synth.look_at((40 * np.cos(a), 40 * np.sin(a), 1.7), (0, 0, 2.5), (0, 0, 1), 320, 180,
+                                   float(rng.uniform(3.0, 15.0)))
+                     for a in rng.uniform(0, 2 * np.pi, nv)]
+            r.render(views)
+            dL = [torch.from_numpy(rng.normal(scale=1e-3, size=(v.height, v.width, 3)).astype(np.float32)).cuda()
+                  for v in views]
+            r.backward(dL, G)
+            r.adam_step(PA, G, MA, VA, lr, step, _f32(B1), _f32(B2), _f32(EPS))
+            r.backward_adam_step(dL, PB, MB, VB, lr, step, _f32(B1), _f32(B2), _f32(EPS))
+            torch.cuda.synchronize()
+            print(f"nv={nv} step {step}: compared", flush=True)
+            for k in hgs.PARAM_FIELDS:
+                assert torch.equal(PA[k], PB[k]), (step, k)
+                assert torch.equal(MA[k], MB[k]) and torch.equal(VA[k], VB[k]), (step, k)
+                assert not bool(torch.any(G[k] != 0)), (step, k)
+                moved = (PA[k] != P[k]).reshape(h.n_nodes, -1).any(dim=1)
+                assert bool(moved.any()) and not bool((moved & ~inner).any()), (step, k)
+        # argument errors change nothing
+        before = {k: t.clone() for k, t in PB.items()}
+        with pytest.raises(hgs.HgsError) as e:
+            r.backward_adam_step(dL, PB, MB, VB, lr, 0)
+        assert e.value.status == hgs.ERR_INVALID_ARG
+        Vbad = dict(VB)
+        Vbad["rot"] = torch.zeros(VB["rot"].numel() + 1, device="cuda")[1:].view_as(VB["rot"])
+        with pytest.raises(hgs.HgsError) as e:
+            r.backward_adam_step(dL, PB, MB, Vbad, lr, 4)
+        assert e.value.status == hgs.ERR_INVALID_ARG
+        with pytest.raises(hgs.HgsError) as e:
+            r.backward_adam_step(dL, PB, MB, VB, lr, 4, render_id=r.last_render()[0] + 1)
+        assert e.value.status == hgs.ERR_STATE
+        torch.cuda.synchronize()
+        assert all(torch.equal(before[k], PB[k]) for k in PB)
+        # stepping the bound parameters makes the render stale for a backward
+        r.backward_adam_step(dL, P, MB, VB, lr, 4)
+        with pytest.raises(hgs.HgsError) as e:
+            r.backward(dL, G)
+        assert e.value.status == hgs.ERR_STATE
+    finally:
+        r.close()
