@@ -79,10 +79,23 @@ __global__ __launch_bounds__(kT, 5) void k_preprocess(DevHier h, const DevView *
                     r.ay = (int32_t)fv;
                     r.fx = (float)(P.u - fu);
                     r.fy = (float)(P.v - fv);
-                    // eigen-axes of the conic [[ca, cb], [cb, cc]]
+                    // eigen-axes of the conic [[ca, cb], [cb, cc]]: the major axis at
+                    // angle th with (cos 2th, sin 2th) = (ca - cc, 2 cb) / r, its cosine
+                    // and sine by the half-angle formulas (each from the better
+                    // conditioned one), th in (-pi/2, pi/2]; any direction for a circle
                     const double ca = P.conic[0], cb = P.conic[1], cc = P.conic[2];
-                    const double th = 0.5 * atan2(2.0 * cb, ca - cc);
-                    const double cs = cos(th), sn = sin(th);
+                    const double dx = ca - cc, dy = 2.0 * cb, rr = sqrt(dx * dx + dy * dy);
+                    double cs = 1.0, sn = 0.0;
+                    if (rr > 0.0) {
+                        const double c2 = dx / rr, s2 = dy / rr;
+                        if (c2 >= 0.0) {
+                            cs = sqrt(0.5 * (1.0 + c2));
+                            sn = s2 / (2.0 * cs);
+                        } else {
+                            sn = copysign(sqrt(0.5 * (1.0 - c2)), s2);
+                            cs = s2 / (2.0 * sn);
+                        }
+                    }
                     const double l1 = ca * cs * cs + 2.0 * cb * sn * cs + cc * sn * sn;
                     const double l2 = ca * sn * sn - 2.0 * cb * sn * cs + cc * cs * cs;
                     const double s1 = sqrt(fmax(l1, 0.0) * kHalfLog2e), s2 = sqrt(fmax(l2, 0.0) * kHalfLog2e);
