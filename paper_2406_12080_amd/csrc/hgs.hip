@@ -127,6 +127,7 @@ struct hgs_ctx {
     uint32_t *n_last = nullptr, *n_blend = nullptr;
     double *sgrad = nullptr;     // [visible rank][12] screen-space gradients
     uint32_t *vis_rank = nullptr;  // per cut entry: its visible rank (visible entries only)
+    uint32_t *vis_entry = nullptr;  // per visible rank: its cut entry
     float *pgrad = nullptr;  // per cut entry, kPGradFloats floats
     float *cjac = nullptr;   // per cut entry, 12 floats: d colour / d dir, parent - node colour
 
@@ -445,6 +446,7 @@ hgs_status ensure_cut_cap(hgs_ctx *ctx, uint32_t cap)
     if ((s = realloc_buf(ctx, ctx->pair_offsets, cap))) return s;
     if ((s = realloc_buf(ctx, ctx->sgrad, (size_t)cap * 12))) return s;
     if ((s = realloc_buf(ctx, ctx->vis_rank, (size_t)cap))) return s;
+    if ((s = realloc_buf(ctx, ctx->vis_entry, (size_t)cap))) return s;
     if ((s = realloc_buf(ctx, ctx->pgrad, (size_t)cap * kPGradFloats))) return s;
     if ((s = realloc_buf(ctx, ctx->cjac, (size_t)cap * 12))) return s;
     ctx->cut_cap = cap;
@@ -516,7 +518,7 @@ void enqueue_forward(hgs_ctx *ctx, int nv, uint32_t n_tiles, hipStream_t st, hip
     const uint32_t vblocks = (ctx->cut_cap + 255) / 256;
     launch_scan(ctx->vis_counts, nullptr, vblocks, nullptr, ctx->vis_offsets, &ctx->ctr->vis_total, ctx->partial, st);
     launch_compact_visible(ctx->vis_mask, ctx->vis_offsets, &ctx->ctr->cut_total, ctx->cut_cap, ctx->depth_key,
-                           ctx->skeys, ctx->svals, ctx->vis_rank, st);
+                           ctx->skeys, ctx->svals, ctx->vis_rank, ctx->vis_entry, st);
     // the visible splats keep the cut's view-major order: each view's run is
     // sorted by depth on its own (4 passes, in place), so that its pairs are
     // emitted as one run, which the tile sort then orders by the view's own
@@ -634,7 +636,8 @@ void enqueue_backward(hgs_ctx *ctx, int nv, const hgs_grads *out, const AdamRows
         KernelTimer kt(ctx, 2, st);
         launch_preprocess_backward(h, ctx->views_dev, nv, ctx->cut_base, ctx->cut_ids, ctx->cut_t,
                                    &ctx->ctr->cut_total, ctx->cut_cap, ctx->ntiles, ctx->recs, ctx->cjac,
-                                   ctx->vis_rank, ctx->sgrad, ctx->pgrad, ctx->masks, (ctx->n + 63) / 64,
+                                   ctx->vis_entry, &ctx->ctr->vis_total, ctx->sgrad, ctx->pgrad, ctx->masks,
+                                   (ctx->n + 63) / 64,
                                    ctx->word_off, ctx->interior, ctx->n_interior, out ? out->mean : nullptr,
                                    out ? out->scale : nullptr, out ? out->rot : nullptr,
                                    out ? out->opacity : nullptr, out ? out->sh : nullptr, out ? out->dt : nullptr,

@@ -181,7 +181,7 @@ void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uin
 // row of its screen-space gradient).
 void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
                             uint32_t cap, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals,
-                            uint32_t *vis_rank, hipStream_t st);
+                            uint32_t *vis_rank, uint32_t *vis_entry, hipStream_t st);
 // Tile records of the visible splats in depth order (one gather through
 // the sorted values): counts[i] = tile count and rect[i] = tile rectangle of
 // the splat at depth slot i, from trec (per cut entry: rect.x, rect.y,
@@ -353,7 +353,8 @@ void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
                                 const uint32_t *ntiles, const SplatRec *recs, const float *cjac,
-                                const uint32_t *vis_rank, const double *sgrad, float *pg, const uint64_t *masks, int64_t words, const uint32_t *word_off,
+                                const uint32_t *vis_entry, const uint32_t *vis_total, const double *sgrad, float *pg,
+                                const uint64_t *masks, int64_t words, const uint32_t *word_off,
                                 const int32_t *interior, int64_t n_interior, float *g_mean, float *g_scale,
                                 float *g_rot, float *g_opacity, float *g_sh, float *g_dt, const AdamRows *fused,
                                 hipStream_t st);

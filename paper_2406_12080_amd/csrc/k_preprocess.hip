@@ -141,7 +141,8 @@ __global__ __launch_bounds__(kT) void k_compact_visible(const uint64_t *__restri
                                                         const uint32_t *__restrict__ cut_total, uint32_t cap,
                                                         const uint32_t *__restrict__ depth_key,
                                                         uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                        uint32_t *__restrict__ vis_rank)
+                                                        uint32_t *__restrict__ vis_rank,
+                                                        uint32_t *__restrict__ vis_entry)
 {
     const uint32_t total = min(*cut_total, cap);
     const uint32_t k = blockIdx.x * kT + threadIdx.x;
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(kT) void k_compact_visible(const uint64_t *__restri
         keys[pos] = depth_key[k];
         vals[pos] = k;
         vis_rank[k] = pos;
+        vis_entry[pos] = k;
     }
 }
 
@@ -431,6 +433,11 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
 }
 
 // ------------------------------------------------------------------ backward
+// Thread v takes the v-th visible cut entry (vis_entry lists them in cut
+// order, so that every wave holds visible entries only) and writes its
+// attribute-gradient row at the entry's cut position; rows of entries that
+// are not visible are never read.  With g_dt, thread k also clears dL/dt of
+// cut entry k when it is not visible.
 __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevView *__restrict__ views, int nv,
                                                        const uint32_t *__restrict__ cut_base,
                                                        const int32_t *__restrict__ cut_ids,
@@ -439,20 +446,20 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
                                                        const uint32_t *__restrict__ ntiles,
                                                        const SplatRec *__restrict__ recs,
                                                        const float *__restrict__ cjac,
-                                                       const uint32_t *__restrict__ vis_rank,
+                                                       const uint32_t *__restrict__ vis_entry,
+                                                       const uint32_t *__restrict__ vis_total,
                                                        const double *__restrict__ sgrad, float *__restrict__ pg,
                                                        float *__restrict__ g_dt)
 {
     const uint32_t total = min(*cut_total, cap);
-    const uint32_t k = blockIdx.x * kT + threadIdx.x;
-    if (k >= total) return;
+    const uint32_t vis = min(*vis_total, total);
+    const uint32_t tid = blockIdx.x * kT + threadIdx.x;
+    if (g_dt && tid < total && ntiles[tid] == 0) g_dt[tid] = 0.0f;
+    if (tid >= vis) return;
+    const uint32_t k = vis_entry[tid];
     float *out = pg + (size_t)k * kPG;
     float row[kPG];  // the entry's attribute gradient, stored as five float4
-    if (ntiles[k] == 0) {
-        if (g_dt) g_dt[k] = 0.0f;
-        return;
-    }
-    const double *sg = sgrad + (size_t)vis_rank[k] * 12;
+    const double *sg = sgrad + (size_t)tid * 12;  // screen-gradient rows by visible rank
     const double du = sg[0], dv = sg[1], dAn = sg[5], dAp = sg[6];
     const double drgb[3] = {sg[7], sg[8], sg[9]};
     double dt = sg[10];
@@ -888,12 +895,12 @@ void launch_preprocess(const DevHier &h, const DevView *views, int nv, const uin
 
 void launch_compact_visible(const uint64_t *vis_mask, const uint32_t *vis_block_offsets, const uint32_t *cut_total,
                             uint32_t cap, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals,
-                            uint32_t *vis_rank, hipStream_t st)
+                            uint32_t *vis_rank, uint32_t *vis_entry, hipStream_t st)
 {
     const uint32_t blocks = (cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_compact_visible, dim3(blocks), dim3(kT), 0, st, vis_mask, vis_block_offsets, cut_total, cap,
-                       depth_key, keys, vals, vis_rank);
+                       depth_key, keys, vals, vis_rank, vis_entry);
 }
 
 void launch_zero_rows(double *rows, int width, const uint32_t *vis_total, uint32_t vis_cap, hipStream_t st)
@@ -984,15 +991,16 @@ void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st)
 void launch_preprocess_backward(const DevHier &h, const DevView *views, int nv, const uint32_t *cut_base,
                                 const int32_t *cut_ids, const double *cut_t, const uint32_t *cut_total, uint32_t cap,
                                 const uint32_t *ntiles, const SplatRec *recs, const float *cjac,
-                                const uint32_t *vis_rank, const double *sgrad, float *pg, const uint64_t *masks,
-                                int64_t words, const uint32_t *word_off, const int32_t *interior, int64_t n_interior,
+                                const uint32_t *vis_entry, const uint32_t *vis_total, const double *sgrad, float *pg,
+                                const uint64_t *masks, int64_t words, const uint32_t *word_off,
+                                const int32_t *interior, int64_t n_interior,
                                 float *g_mean, float *g_scale, float *g_rot, float *g_opacity, float *g_sh,
                                 float *g_dt, const AdamRows *fused, hipStream_t st)
 {
     const uint32_t blocks = (cap + kT - 1) / kT;
     if (!blocks) return;
     hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(kT), 0, st, h, views, nv, cut_base, cut_ids, cut_t,
-                       cut_total, cap, ntiles, recs, cjac, vis_rank, sgrad, pg, g_dt);
+                       cut_total, cap, ntiles, recs, cjac, vis_entry, vis_total, sgrad, pg, g_dt);
     const int64_t gblocks = (n_interior + kT - 1) / kT;
     if (!gblocks) return;
     if (fused)
