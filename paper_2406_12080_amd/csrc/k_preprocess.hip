@@ -770,33 +770,57 @@ __global__ __launch_bounds__(kT, 4) void k_grad_gather(DevHier h, int nv, const 
     if (valid) {
         const uint32_t total = min(*cut_total, cap);
         const int64_t c0 = h.child_begin[i], c1 = c0 + h.child_count[i];  // children [c0, c1)
-        // adds the attribute gradient of entry pos, weighted 1 - t as the node's
-        // own entry (op 10: node opacity term) or t as a child's entry (op 11:
-        // parent opacity term; none when t = 0).  The row (all eight vectors at
-        // once) is read only for a visible entry that contributes.
-        auto take = [&](uint32_t pos, int op) {
-            if (pos >= total) return;
-            const uint32_t nt = ntiles[pos];
-            const float t = (float)cut_t[pos];
-            if (nt == 0 || (op == 11 && !(t > 0.0f))) return;
-            const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pos * kPG);
-            const float4 r0 = g4[0], r1 = g4[1], r2 = g4[2], r3 = g4[3], r4 = g4[4];
-            if (r4.w == 0.0f) return;  // no live splat
+        // adds the attribute gradient of a contributing entry (row r), weighted
+        // 1 - t as the node's own entry (op 10: node opacity term) or t as a
+        // child's entry (op 11: parent opacity term)
+        auto add = [&](const float4 (&r)[5], float t, int op) {
             const float w = op == 10 ? 1.0f - t : t;
-            const float g[15] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
-                                 r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z};
-    #pragma unroll
+            const float g[15] = {r[0].x, r[0].y, r[0].z, r[0].w, r[1].x, r[1].y, r[1].z, r[1].w,
+                                 r[2].x, r[2].y, r[2].z, r[2].w, r[3].x, r[3].y, r[3].z};
+#pragma unroll
             for (int m = 0; m < 10; ++m) a[m] += w * g[m];
             a[10] += op == 10 ? g[10] : g[11];
             float Y[16];  // the SH basis of the entry's direction, in FP32 as the forward evaluated it
-            sh_eval_f(r3.w, r4.x, r4.y, Y);
-    #pragma unroll
+            sh_eval_f(r[3].w, r[4].x, r[4].y, Y);
+#pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const float wc = w * g[12 + c];
-    #pragma unroll
+#pragma unroll
                 for (int k = 0; k < 16; ++k) ash[3 * k + c] += wc * Y[k];
             }
             any = true;
+        };
+        // the entries at cut positions pa (op oa) and pb (op ob; ~0u: none),
+        // added in that order: their tile counts and t first, then the rows
+        // of those that are visible and contribute (a child's entry only with
+        // t > 0; a row without a live splat adds nothing), the two entries'
+        // loads in flight together
+        auto take2 = [&](uint32_t pa, int oa, uint32_t pb, int ob) {
+            const bool va = pa < total, vb = pb < total;
+            uint32_t nta = 0, ntb = 0;
+            float ta = 0.0f, tb = 0.0f;
+            if (va) {
+                nta = ntiles[pa];
+                ta = (float)cut_t[pa];
+            }
+            if (vb) {
+                ntb = ntiles[pb];
+                tb = (float)cut_t[pb];
+            }
+            const bool ua = nta != 0 && (oa == 10 || ta > 0.0f), ub = ntb != 0 && (ob == 10 || tb > 0.0f);
+            float4 ra[5], rb[5];
+            if (ua) {
+                const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pa * kPG);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) ra[q] = g4[q];
+            }
+            if (ub) {
+                const float4 *g4 = reinterpret_cast<const float4 *>(pg + (size_t)pb * kPG);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) rb[q] = g4[q];
+            }
+            if (ua && ra[4].w != 0.0f) add(ra, ta, oa);
+            if (ub && rb[4].w != 0.0f) add(rb, tb, ob);
         };
         const int64_t wi = i >> 6, wa = c0 >> 6, wb = (c1 - 1) >> 6;
         const uint64_t below_i = (1ull << (i & 63)) - 1ull, own_bit = 1ull << (i & 63);
@@ -830,7 +854,7 @@ __global__ __launch_bounds__(kT, 4) void k_grad_gather(DevHier h, int nv, const 
                 const uint32_t *ov = word_off + (int64_t)v * words;
                 // own entry
                 const uint64_t mo = mv[wi];
-                if (mo & own_bit) take(ov[wi] + (uint32_t)__popcll(mo & below_i), 10);
+                const uint32_t own = (mo & own_bit) ? ov[wi] + (uint32_t)__popcll(mo & below_i) : ~0u;
                 // children: the selected ones among [c0, c1) are consecutive entries from p0
                 uint32_t p0 = ~0u, nsel = 0;
                 for (int64_t w = wa; w <= wb; ++w) {
@@ -840,7 +864,13 @@ __global__ __launch_bounds__(kT, 4) void k_grad_gather(DevHier h, int nv, const 
                     if (p0 == ~0u) p0 = ov[w] + (uint32_t)__popcll(mw & ((m & (~m + 1ull)) - 1ull));
                     nsel += (uint32_t)__popcll(m);
                 }
-                for (uint32_t k = 0; k < nsel; ++k) take(p0 + k, 11);
+                // the own entry, then the children's, two at a time
+                uint32_t k = 0;
+                if (own != ~0u) {
+                    take2(own, 10, nsel ? p0 : ~0u, 11);
+                    k = 1;
+                }
+                for (; k < nsel; k += 2) take2(p0 + k, 11, k + 1 < nsel ? p0 + k + 1 : ~0u, 11);
             }
         }
     }
