@@ -31,6 +31,18 @@ __device__ __forceinline__ int view_of(const uint32_t *cut_base, int nv, uint32_
     return lo;
 }
 
+// view_of for the lanes of a wave whose entries are close together: one
+// search with the first active lane's entry (a wave-uniform value, so its
+// loads go through the scalar cache), and a search of its own only for a
+// lane whose entry lies outside that view
+__device__ __forceinline__ int view_of_wave(const uint32_t *cut_base, int nv, uint32_t k)
+{
+    const uint32_t kf = __builtin_amdgcn_readfirstlane(k);
+    const int vf = view_of(cut_base, nv, kf);
+    const uint32_t b0 = cut_base[vf], b1 = vf + 1 < nv ? cut_base[vf + 1] : 0xFFFFFFFFu;
+    return k >= b0 && k < b1 ? vf : view_of(cut_base, nv, k);
+}
+
 __global__ __launch_bounds__(kT, 5) void k_preprocess(DevHier h, const DevView *__restrict__ views, int nv,
                                                    const uint32_t *__restrict__ cut_base,
                                                    const int32_t *__restrict__ cut_ids,
@@ -50,7 +62,7 @@ __global__ __launch_bounds__(kT, 5) void k_preprocess(DevHier h, const DevView *
     bool vis = false;
     uint32_t nt = 0;
     if (k < total) {
-        const int vi = view_of(cut_base, nv, k);
+        const int vi = view_of_wave(cut_base, nv, k);
         const DevView &V = views[vi];
         Proj P;
         project_splat(h, V, (uint32_t)cut_ids[k], cut_t[k], P);
@@ -463,7 +475,7 @@ __global__ __launch_bounds__(kT, 3) void k_preprocess_bwd(DevHier h, const DevVi
     const double du = sg[0], dv = sg[1], dAn = sg[5], dAp = sg[6];
     const double drgb[3] = {sg[7], sg[8], sg[9]};
     double dt = sg[10];
-    const int vi = view_of(cut_base, nv, k);
+    const int vi = view_of_wave(cut_base, nv, k);
     const DevView &V = views[vi];
     Proj P;
     project_splat(h, V, (uint32_t)cut_ids[k], cut_t[k], P);
