@@ -188,8 +188,8 @@ hgs_status fail(hgs_ctx *c, hgs_status s, const std::string &msg)
 // records) to dst on st.  The DMA reads a pinned staging slot, not src: the
 // copy may run long after this returns (behind earlier work on st), and the
 // host bytes may change meanwhile.  A slot is reused only once its previous
-// copy has run.
-hgs_status stage_copy(hgs_ctx *ctx, const void *src, size_t bytes, void *dst, hipStream_t st)
+// copy has run.  Called through stage_records, which counts in records.
+hgs_status stage_bytes(hgs_ctx *ctx, const void *src, size_t bytes, void *dst, hipStream_t st)
 {
     const int k = ctx->stage_next;
     ctx->stage_next = (k + 1) % kStageRing;
@@ -201,9 +201,17 @@ hgs_status stage_copy(hgs_ctx *ctx, const void *src, size_t bytes, void *dst, hi
     return HGS_OK;
 }
 
+// stage_bytes for n records of type T
+template <typename T>
+hgs_status stage_records(hgs_ctx *ctx, const T *src, size_t n, T *dst, hipStream_t st)
+{
+    static_assert(sizeof(T) <= sizeof(DevView) * kMaxViews, "staging slot");
+    return stage_bytes(ctx, src, sizeof(T) * n, dst, st);
+}
+
 hgs_status push_views(hgs_ctx *ctx, int n, hipStream_t st)
 {
-    return stage_copy(ctx, ctx->views_host, sizeof(DevView) * (size_t)n, ctx->views_dev, st);
+    return stage_records(ctx, ctx->views_host, (size_t)n, ctx->views_dev, st);
 }
 
 hgs_status dalloc(hgs_ctx *ctx, void **p, size_t bytes)
@@ -1325,7 +1333,7 @@ hgs_status hgs_cut_noalloc(hgs_ctx *ctx, const hgs_view *view, int32_t *out_ids,
     DevView hv;
     fill_dev_view(*view, ctx->tile_w, ctx->tile_h, hv);
     hgs_status s;
-    if ((s = stage_copy(ctx, &hv, 1, dview, st))) return s;
+    if ((s = stage_records(ctx, &hv, 1, dview, st))) return s;
     const DevHier h = dev_hier(ctx);
     const int nb = cut_blocks(ctx->n);
     launch_fill_u32((uint32_t *)ctr, 0u, sizeof(Counters) / 4, st);
@@ -1597,7 +1605,7 @@ static hgs_status run_backward(hgs_ctx *ctx, const hgs_grads *out, const AdamRow
     }
     if (hgs_status s = push_views(ctx, nv, st)) return s;
     if (fused)
-        if (hgs_status s = stage_copy(ctx, scalars, sizeof(AdamScalars) * 5, ctx->adam_sc, st)) return s;
+        if (hgs_status s = stage_records(ctx, scalars, 5, ctx->adam_sc, st)) return s;
     if (ctx->last_graphed) {
         HIPC(hipGraphLaunch(ctx->bexec, st));
         HIPC(hipEventRecord(ctx->ev_out, st));
