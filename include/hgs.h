@@ -369,9 +369,11 @@ hgs_status hgs_adam_step(hgs_ctx *ctx, const hgs_adam *a);
 /* The backward of render render_id with the optimiser step of Sec. 5.1
  * applied right away: the same parameters, moments and errors as
  * hgs_render_backward into gradient arrays that hold zero, followed by
- * hgs_adam_step on them (bit for bit), but the gradient of each interior
- * node goes from the gather's registers into its Adam update and is never
- * stored.  a->grad is not used (may be NULL); a->param, a->m and a->v as for
+ * hgs_adam_step on them, but the gradient of each interior node goes from
+ * the gather's registers into its Adam update and is never stored.  Bit for
+ * bit the same when both backwards form the same sums: always in the
+ * deterministic mode (hgs_set_deterministic); by default the screen-space
+ * sums are atomic and may differ in their last bits from run to run.  a->grad is not used (may be NULL); a->param, a->m and a->v as for
  * hgs_adam_step (interior nodes stepped, leaves untouched, every interior
  * node stepped, with gradient zero where no cut entry reached it); no dL/dt
  * output.  Arguments are checked as by the two calls (argument errors

@@ -15,7 +15,8 @@ Every step runs in the library: ``hgs_render`` (cut, interpolation and
 splatting of the batch), ``hgs_l1_loss`` (loss and cotangent) and
 ``hgs_backward_adam_step`` (the backward with the Adam update applied in its
 gradient gather; ``fused=False`` takes ``hgs_render_backward`` into gradient
-arrays and ``hgs_adam_step`` instead, with the same result bit for bit).
+arrays and ``hgs_adam_step`` instead, with the same result; bit for bit in
+the backward's deterministic mode).
 This module only draws the views and passes pointers; nothing of a step is
 computed in Python.
 """
