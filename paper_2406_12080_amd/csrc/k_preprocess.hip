@@ -664,22 +664,22 @@ constexpr int kGatherViews = 8;
 
 // The fused optimiser step of one block: thread t holds the gathered
 // gradient of interior node q0 + t (node id `node`; zero past the end).  The
-// rows go through LDS so that the update walks the moments contiguously and
-// each parameter row with consecutive lanes, as the separate step does:
-// first the 11 floats of mean, scale, rotation and opacity of all rows, then
-// the 48 SH floats of 64 rows at a time.  The separate step reads 0 + sum
+// mean and scale rows (3 floats each) and the SH rows (48 floats, 64 rows at
+// a time) go through LDS, so that the update walks the moments contiguously
+// and each parameter row with consecutive lanes, as the separate step does;
+// rotation (one 16-byte row) and opacity are stepped by the row's own
+// thread from its registers.  The separate step reads 0 + sum
 // from a cleared gradient array; the same value is formed here (it turns -0
 // into +0), and the arithmetic is the same function, so both agree bit for
 // bit.  Every thread of the block calls it (barriers).
 constexpr int kAdamLds = 64 * 48;  // floats of the staging buffer (>= kT x 11)
 static_assert(kT * 11 <= kAdamLds && kT % 64 == 0, "staging buffer");
 
-__device__ __forceinline__ void adam_block(const AdamRows &ad, const int32_t *__restrict__ interior,
-                                           int64_t n_interior, int64_t q0, int32_t node, const float (&a)[11],
-                                           const float (&ash)[48])
+__device__ __forceinline__ void adam_block(const AdamRows &ad, int64_t n_interior, int64_t q0, int32_t node,
+                                           const float (&a)[11], const float (&ash)[48])
 {
     __shared__ float s_g[kAdamLds];
-    __shared__ int32_t s_node[kT];
+    __shared__ int32_t s_node[kT];  // the block's node ids
     const int t = threadIdx.x;
     const int rows = (int)min<int64_t>(kT, n_interior - q0);  // >= 1: the block holds an interior node
     s_node[t] = node;
@@ -887,7 +887,7 @@ __global__ __launch_bounds__(kT, 4) void k_grad_gather(DevHier h, int nv, const 
         }
     }
     if constexpr (FUSED) {
-        adam_block(ad, interior, n_interior, (int64_t)blockIdx.x * kT, (int32_t)i, a, ash);
+        adam_block(ad, n_interior, (int64_t)blockIdx.x * kT, (int32_t)i, a, ash);
         return;
     }
     if (!any) return;
